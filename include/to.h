@@ -1,0 +1,160 @@
+/*
+ * to.h -- C ABI of the MI355X (gfx950) voxel hex8 topology-optimisation hot
+ * path: the SIMP-weighted linear-elasticity state solve, compliance and its
+ * sensitivity, the density/sensitivity filters and the density -> signed
+ * distance transfer of Jezek et al., "Sequential topology optimization: SIMP
+ * initialization for level-set boundary refinement".
+ *
+ * Conventions for every call:
+ *  - Plain C types only.  "d_" pointers are device (HBM) memory, "h_" pointers
+ *    are host memory.  The caller owns every array; the library never frees
+ *    caller memory.  The library owns the opaque context (and, when no
+ *    workspace is passed to to_create, the device workspace it allocates).
+ *  - Grid: nelx x nely x nelz cubic voxels of edge h.
+ *      node     n = i + (nelx+1) * (j + (nely+1) * k)
+ *      element  e = i + nelx * (j + nely * k)   (lower corner at node (i,j,k))
+ *      DOF      3*n + c, c = 0:x 1:y 2:z (interleaved)
+ *    nel = nelx*nely*nelz, nn = (nelx+1)(nely+1)(nelz+1), ndof = 3*nn.
+ *  - Streams: all work is queued on the context's HIP stream (passed as a
+ *    void* holding a hipStream_t; NULL = the default stream).  Calls that
+ *    return host values (h_c, info, status of a solve) synchronise that stream.
+ *  - Errors: every call returns a to_status.  Invalid arguments are rejected
+ *    before anything is queued.  to_last_error(ctx) gives a message; with a
+ *    NULL ctx it gives the calling thread's last error.  The context stays
+ *    usable after any error.  One context per thread (not thread-safe).
+ */
+#ifndef TO_H_
+#define TO_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct to_ctx to_ctx;
+
+typedef enum {
+  TO_OK = 0,
+  TO_E_INVALID = -1,    /* bad argument (sizes, NULL required pointer, x outside [0,1]) */
+  TO_E_OOM = -2,        /* workspace too small or device allocation failed            */
+  TO_E_HIP = -3,        /* a HIP runtime call failed                                  */
+  TO_E_NOCONV = -4,     /* iteration cap reached; outputs hold the last iterate        */
+  TO_E_NONFINITE = -5,  /* NaN/Inf in an input or produced during a solve             */
+  TO_E_SINGULAR = -6,   /* CG breakdown (p^T K p <= 0): singular or indefinite system  */
+  TO_E_BUSY = -7        /* serving: no slot or memory for the request right now        */
+} to_status;
+
+typedef enum { TO_BC_CANTILEVER = 0, TO_BC_MBB = 1, TO_BC_CUSTOM = 2 } to_bc;
+
+/* Arithmetic of the state solve.  FP64: Jacobi-PCG in float64 throughout.
+ * FP32_REFINE: inner Jacobi-PCG with float32 vectors and float32 element
+ * arithmetic, outer iterative refinement whose residual f - K u, norms and
+ * solution update are float64.  FP32_REFINE_BF16: as FP32_REFINE with the CG
+ * search direction stored in bfloat16 (the same rounded direction is used in
+ * the product and in the solution update). */
+typedef enum { TO_PREC_FP64 = 0, TO_PREC_FP32_REFINE = 1, TO_PREC_FP32_REFINE_BF16 = 2 } to_prec;
+
+typedef enum { TO_FILTER_DENS = 0, TO_FILTER_DENS_T = 1, TO_FILTER_SENS = 2 } to_filter_mode;
+
+/* Statement of the state problem K(x) u = F (paper Sec. 2.1.1, Eq. 2) with the
+ * modified SIMP modulus E_e = Emin + x_e^penal (E0 - Emin) (Eq. 1).
+ * Built-in boundary conditions (z is the vertical axis):
+ *   CANTILEVER: all DOFs fixed on the x = 0 face; total load -load_total in z
+ *     along the bottom edge (i = nelx, k = 0) of the opposite face, as the
+ *     consistent nodal shares of a uniform line load (end nodes carry half an
+ *     interior node's share: -(load_total*w)/nely with w = 0.5 or 1).
+ *   MBB: u_x = 0 on x = 0 (symmetry), u_z = 0 on the edge i = nelx, k = 0,
+ *     u_y = 0 at node (0,0,0); the same line load on the edge i = 0, k = nelz.
+ *   CUSTOM: fixed_mask (ndof bytes, nonzero = fixed) and load (ndof doubles)
+ *     are host arrays read once by to_create.
+ * Loads on fixed DOFs are ignored. */
+typedef struct {
+  int32_t nelx, nely, nelz;    /* voxels per axis, each >= 1                      */
+  double h;                    /* voxel edge, > 0                                 */
+  double E0, Emin, nu, penal;  /* E0 > 0, 0 <= Emin < E0, -1 < nu < 0.5, penal>=1 */
+  int32_t bc;                  /* to_bc                                           */
+  const uint8_t *fixed_mask;   /* CUSTOM only, host, ndof                         */
+  const double *load;          /* CUSTOM only, host, ndof                         */
+  double load_total;           /* built-in BCs: magnitude of the total load       */
+  int32_t precision;           /* to_prec                                         */
+  double rtol;                 /* stop when ||f - K u||_2 <= rtol ||f||_2 (float64) */
+  int32_t max_iters;           /* cap on the total number of inner CG iterations  */
+} to_problem;
+
+typedef struct {
+  int32_t outer_iters;   /* float64 residual evaluations after the first       */
+  int32_t inner_iters;   /* CG iterations summed over all inner solves         */
+  double rel_res;        /* final ||f - K u||_2 / ||f||_2, computed in float64  */
+  double ms;             /* wall time of the call on the host, milliseconds     */
+} to_solve_info;
+
+/* Device workspace (bytes) a context for this problem needs.  Lets the caller
+ * allocate it (e.g. as a torch uint8 tensor) and admit work by footprint. */
+to_status to_workspace_size(const to_problem *prob, size_t *bytes);
+
+/* Create a context.  d_workspace: caller-owned device memory of at least
+ * to_workspace_size() bytes, 256-byte aligned, or NULL to let the library
+ * allocate (and free, in to_destroy) its own.  stream: hipStream_t or NULL.
+ * Precomputes the fixed-DOF mask and the load vector on the device. */
+to_status to_create(const to_problem *prob, void *d_workspace, size_t bytes, void *stream,
+                    to_ctx **out);
+void to_destroy(to_ctx *ctx);                 /* NULL-safe */
+const char *to_last_error(const to_ctx *ctx); /* valid until the next call on ctx */
+
+/* State solve (Eq. 2): u = K(x)^{-1} F by Jacobi-preconditioned CG in the
+ * context's precision, to rtol.  d_x: [nel] densities in [0,1] (Eq. 1 maps
+ * them to moduli).  d_u0: [ndof] warm start or NULL (zero start).  d_u: [ndof]
+ * output; fixed DOFs are exactly 0.  info: host, may be NULL.
+ * Returns TO_E_NOCONV (d_u = last iterate, info filled) when max_iters is hit,
+ * TO_E_SINGULAR on CG breakdown, TO_E_NONFINITE on NaN/Inf, TO_E_INVALID when
+ * some x_e lies outside [0,1]. */
+to_status to_solve(to_ctx *ctx, const double *d_x, const double *d_u0, double *d_u,
+                   to_solve_info *info);
+
+/* Compliance and its sensitivity (Eq. 2 and Eq. 3):
+ *   h_c = F^T u  (host scalar, float64, deterministic reduction),
+ *   d_dc[e] = -penal x_e^(penal-1) (E0 - Emin) u_e^T k0 u_e  (float64, [nel]),
+ * with k0 the unit-modulus element stiffness.  d_dc may be NULL. */
+to_status to_compliance_sensitivity(to_ctx *ctx, const double *d_x, const double *d_u, double *h_c,
+                                     double *d_dc);
+
+/* Filters (Sec. 2.1.3, Eq. 4), radius rmin in element units (> 0), weights
+ * H = max(0, rmin - distance) over element centroids at distance < rmin,
+ * truncated at the domain boundary and normalised per element:
+ *   DENS   : out_e = sum_i H_ei V x_i / sum_i H_ei V            (d_in = x)
+ *   DENS_T : out_j = sum_e H_ej V in_e / sum_i H_ei V           (adjoint of DENS)
+ *   SENS   : out_e = sum_i (x_i/V) H_ei in_i / ((max(x_e,1e-3)/V) sum_i H_ei)  (Eq. 4;
+ *            in = dc, d_x = densities, required)
+ * d_x is ignored for DENS and DENS_T.  d_out must not alias d_in. */
+to_status to_filter(to_ctx *ctx, double rmin, int32_t mode, const double *d_x, const double *d_in,
+                    double *d_out);
+
+/* Density -> signed distance (Secs. 3.2-3.4, Eqs. 25-30):
+ *   rho_n : nodal densities; on a voxel grid the paper's local linear
+ *           least-squares map (Eqs. 25-27, with its fallbacks) is the mean of
+ *           the adjacent elements, summed in increasing element order;
+ *   iso-surface rho_n = rho_t by marching tetrahedra on the six-tet (Kuhn)
+ *           split of every voxel (a node is inside when rho_n >= rho_t);
+ *   d      : exact minimum distance from every node to the triangles (Eqs. 28-29);
+ *   phi    : -d where rho_n >= rho_t, +d elsewhere (Eq. 30); +/-inf when the
+ *           surface is empty.
+ *   vf     : per element, the volume fraction where the piecewise-linear
+ *           interpolant of phi on the same split is < 0 (ersatz weight).
+ * d_phi [nn] required; d_rho_nodes [nn] and d_vf [nel] may be NULL. */
+to_status to_density_to_sdf(to_ctx *ctx, const double *d_x, double rho_t, double *d_phi,
+                            double *d_rho_nodes, double *d_vf);
+
+/* Matrix-free operator of Eq. 2, y = K(x) u with the fixed DOFs zeroed on
+ * input and identity rows on output (y_fixed = u_fixed), float64.
+ * d_u, d_y: [ndof], must not alias. */
+to_status to_matvec(to_ctx *ctx, const double *d_x, const double *d_u, double *d_y);
+/* The same operator with float32 vectors, float32 moduli and float32 element
+ * arithmetic (the inner-CG product of TO_PREC_FP32_REFINE). */
+to_status to_matvec_f32(to_ctx *ctx, const double *d_x, const float *d_u, float *d_y);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TO_H_ */

@@ -134,3 +134,33 @@ def full_solve(nelx, nely, nelz, x, *, h=1.0, E0=1.0, Emin=1e-9, nu=0.3, penal=3
     s = element_energy(nelx, nely, nelz, K0, u)
     dc = sensitivity(x, s, E0, Emin, penal)
     return u, compliance(f, u), dc, info
+
+
+def apply_rows(nelx, nely, nelz, E, K0, u, fixed, nodes):
+    """Rows of the masked operator at the given nodes, straight from the
+    definition y_n = sum over the elements e around n of E_e (K0 u_e)[node n]
+    (fixed DOFs zero on input, identity rows on output).  Returns (len(nodes), 3).
+    Used to check the operator on grids too large to assemble."""
+    u = np.asarray(u, dtype=np.float64)
+    u0 = np.where(fixed, 0.0, u)
+    out = np.zeros((len(nodes), 3))
+    NX, NY = nelx + 1, nely + 1
+    for r, n in enumerate(nodes):
+        i, j, k = n % NX, (n // NX) % NY, n // (NX * NY)
+        acc = np.zeros(3)
+        for bz in (0, 1):
+            for by in (0, 1):
+                for bx in (0, 1):
+                    ei, ej, ek = i - 1 + bx, j - 1 + by, k - 1 + bz
+                    if not (0 <= ei < nelx and 0 <= ej < nely and 0 <= ek < nelz):
+                        continue
+                    e = ei + nelx * (ej + nely * ek)
+                    a = (1 - bx) + 2 * (1 - by) + 4 * (1 - bz)     # corner of e at node n
+                    dofs = []
+                    for b in range(8):
+                        nb = grid.node_index(nelx, nely, ei + (b & 1), ej + ((b >> 1) & 1), ek + (b >> 2))
+                        dofs.extend([3 * nb, 3 * nb + 1, 3 * nb + 2])
+                    acc += E[e] * (K0[3 * a:3 * a + 3, :] @ u0[dofs])
+        for c in range(3):
+            out[r, c] = u[3 * n + c] if fixed[3 * n + c] else acc[c]
+    return out

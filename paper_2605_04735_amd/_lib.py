@@ -1,0 +1,74 @@
+"""ctypes declarations of the C ABI in include/to.h.
+
+Loading fails loudly when the built library is missing: there is no fallback.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtopo_mi355x.so")
+
+TO_OK, TO_E_INVALID, TO_E_OOM, TO_E_HIP, TO_E_NOCONV, TO_E_NONFINITE, TO_E_SINGULAR, TO_E_BUSY = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+STATUS_NAMES = {0: "TO_OK", -1: "TO_E_INVALID", -2: "TO_E_OOM", -3: "TO_E_HIP",
+                -4: "TO_E_NOCONV", -5: "TO_E_NONFINITE", -6: "TO_E_SINGULAR", -7: "TO_E_BUSY"}
+BC_CANTILEVER, BC_MBB, BC_CUSTOM = 0, 1, 2
+PREC_FP64, PREC_FP32_REFINE, PREC_FP32_REFINE_BF16 = 0, 1, 2
+FILTER_DENS, FILTER_DENS_T, FILTER_SENS = 0, 1, 2
+
+
+class ToProblem(ctypes.Structure):
+    _fields_ = [
+        ("nelx", ctypes.c_int32), ("nely", ctypes.c_int32), ("nelz", ctypes.c_int32),
+        ("h", ctypes.c_double), ("E0", ctypes.c_double), ("Emin", ctypes.c_double),
+        ("nu", ctypes.c_double), ("penal", ctypes.c_double),
+        ("bc", ctypes.c_int32),
+        ("fixed_mask", ctypes.POINTER(ctypes.c_uint8)),
+        ("load", ctypes.POINTER(ctypes.c_double)),
+        ("load_total", ctypes.c_double),
+        ("precision", ctypes.c_int32),
+        ("rtol", ctypes.c_double),
+        ("max_iters", ctypes.c_int32),
+    ]
+
+
+class ToSolveInfo(ctypes.Structure):
+    _fields_ = [("outer_iters", ctypes.c_int32), ("inner_iters", ctypes.c_int32),
+                ("rel_res", ctypes.c_double), ("ms", ctypes.c_double)]
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_D = ctypes.c_double
+_SIGS = {
+    "to_workspace_size": (ctypes.c_int, [ctypes.POINTER(ToProblem), ctypes.POINTER(ctypes.c_size_t)]),
+    "to_create": (ctypes.c_int, [ctypes.POINTER(ToProblem), _P, ctypes.c_size_t, _P,
+                                 ctypes.POINTER(_P)]),
+    "to_destroy": (None, [_P]),
+    "to_last_error": (ctypes.c_char_p, [_P]),
+    "to_solve": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(ToSolveInfo)]),
+    "to_compliance_sensitivity": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(_D), _P]),
+    "to_filter": (ctypes.c_int, [_P, _D, ctypes.c_int32, _P, _P, _P]),
+    "to_density_to_sdf": (ctypes.c_int, [_P, _P, _D, _P, _P, _P]),
+    "to_matvec": (ctypes.c_int, [_P, _P, _P, _P]),
+    "to_matvec_f32": (ctypes.c_int, [_P, _P, _P, _P]),
+    "to_last_energy_sum": (_D, [_P]),
+    "to_last_triangle_count": (ctypes.c_int32, [_P]),
+}
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("HIP library %s is missing: run __graft_entry__.build() "
+                               "(or python paper_2605_04735_amd/build.py) first" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib

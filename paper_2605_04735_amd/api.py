@@ -1,0 +1,232 @@
+"""Python binding of the C ABI with the same call names.
+
+Argument marshalling only: torch tensors supply device memory and the current
+HIP stream; every step of the computation runs in the HIP library.
+"""
+import ctypes
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from ._lib import (BC_CANTILEVER, BC_MBB, BC_CUSTOM, PREC_FP64, PREC_FP32_REFINE,  # noqa: F401
+                   PREC_FP32_REFINE_BF16, FILTER_DENS, FILTER_DENS_T, FILTER_SENS)
+
+
+class TopoError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s: %s" % (L.STATUS_NAMES.get(status, status), message))
+        self.status = status
+        self.message = message
+
+
+@dataclass
+class Problem:
+    nelx: int
+    nely: int
+    nelz: int
+    h: float = 1.0
+    E0: float = 1.0
+    Emin: float = 1e-9
+    nu: float = 0.3
+    penal: float = 3.0
+    bc: int = L.BC_CANTILEVER
+    fixed_mask: Optional[np.ndarray] = None   # CUSTOM: (ndof,) bool/uint8
+    load: Optional[np.ndarray] = None         # CUSTOM: (ndof,) float64
+    load_total: float = 1.0
+    precision: int = L.PREC_FP64
+    rtol: float = 1e-8
+    max_iters: int = 200000
+    _keep: list = field(default_factory=list, repr=False)
+
+    @property
+    def nel(self):
+        return self.nelx * self.nely * self.nelz
+
+    @property
+    def nn(self):
+        return (self.nelx + 1) * (self.nely + 1) * (self.nelz + 1)
+
+    @property
+    def ndof(self):
+        return 3 * self.nn
+
+    def to_c(self):
+        p = L.ToProblem()
+        for name in ("nelx", "nely", "nelz", "bc", "precision", "max_iters"):
+            setattr(p, name, int(getattr(self, name)))
+        for name in ("h", "E0", "Emin", "nu", "penal", "load_total", "rtol"):
+            setattr(p, name, float(getattr(self, name)))
+        self._keep = []
+        if self.bc == L.BC_CUSTOM and self.fixed_mask is not None and self.load is not None:
+            m = np.ascontiguousarray(np.asarray(self.fixed_mask).astype(np.uint8).ravel())
+            f = np.ascontiguousarray(np.asarray(self.load, dtype=np.float64).ravel())
+            if m.size != self.ndof or f.size != self.ndof:
+                raise ValueError("CUSTOM mask/load must have ndof entries")
+            self._keep = [m, f]
+            p.fixed_mask = m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+            p.load = f.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        return p
+
+
+def _err(ctx_handle=None):
+    msg = L.lib().to_last_error(ctx_handle)
+    return msg.decode() if msg else ""
+
+
+def _check(status, ctx_handle=None):
+    if status != L.TO_OK:
+        raise TopoError(status, _err(ctx_handle))
+
+
+def _dev(t, dtype, numel, name):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype or not t.is_contiguous() or t.numel() != numel:
+        raise TypeError("%s must be a contiguous %s tensor with %d elements" % (name, dtype, numel))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def to_workspace_size(prob: Problem) -> int:
+    n = ctypes.c_size_t(0)
+    cp = prob.to_c()
+    _check(L.lib().to_workspace_size(ctypes.byref(cp), ctypes.byref(n)))
+    return n.value
+
+
+class Context:
+    """Owns the opaque to_ctx and (when the binding allocated it) the
+    workspace tensor."""
+
+    def __init__(self, prob: Problem, workspace=None, stream=None, device="cuda"):
+        self.prob = prob
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        nbytes = to_workspace_size(prob)
+        if workspace is None:
+            workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        ptr = workspace.data_ptr()
+        aligned = (ptr + 255) & ~255
+        self.workspace = workspace
+        self.ws_bytes = nbytes
+        h = ctypes.c_void_p(0)
+        cp = prob.to_c()
+        _check(L.lib().to_create(ctypes.byref(cp), ctypes.c_void_p(aligned),
+                                 ctypes.c_size_t(workspace.numel() - (aligned - ptr)),
+                                 _stream(self.stream), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            L.lib().to_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def last_error(self):
+        return _err(self.handle)
+
+
+def to_create(prob: Problem, workspace=None, stream=None) -> Context:
+    return Context(prob, workspace, stream)
+
+
+def to_destroy(ctx: Context):
+    ctx.close()
+
+
+def to_solve(ctx: Context, x, u0=None, u=None, raise_on_error=True):
+    """Returns (u, info, status)."""
+    p = ctx.prob
+    if u is None:
+        u = torch.empty(p.ndof, dtype=torch.float64, device=x.device)
+    info = L.ToSolveInfo()
+    st = L.lib().to_solve(ctx.handle, _dev(x, torch.float64, p.nel, "x"),
+                          _dev(u0, torch.float64, p.ndof, "u0"), _dev(u, torch.float64, p.ndof, "u"),
+                          ctypes.byref(info))
+    if raise_on_error:
+        _check(st, ctx.handle)
+    return u, {"outer_iters": info.outer_iters, "inner_iters": info.inner_iters,
+               "rel_res": info.rel_res, "ms": info.ms}, st
+
+
+def to_compliance_sensitivity(ctx: Context, x, u, dc=None, want_dc=True):
+    """Returns (c, dc)."""
+    p = ctx.prob
+    if dc is None and want_dc:
+        dc = torch.empty(p.nel, dtype=torch.float64, device=x.device)
+    c = ctypes.c_double(0.0)
+    _check(L.lib().to_compliance_sensitivity(ctx.handle, _dev(x, torch.float64, p.nel, "x"),
+                                             _dev(u, torch.float64, p.ndof, "u"), ctypes.byref(c),
+                                             _dev(dc, torch.float64, p.nel, "dc")), ctx.handle)
+    return c.value, dc
+
+
+def last_energy_sum(ctx: Context) -> float:
+    return L.lib().to_last_energy_sum(ctx.handle)
+
+
+def to_filter(ctx: Context, rmin, mode, inp, x=None, out=None):
+    p = ctx.prob
+    if out is None:
+        out = torch.empty(p.nel, dtype=torch.float64, device=inp.device)
+    _check(L.lib().to_filter(ctx.handle, float(rmin), int(mode), _dev(x, torch.float64, p.nel, "x"),
+                             _dev(inp, torch.float64, p.nel, "in"),
+                             _dev(out, torch.float64, p.nel, "out")), ctx.handle)
+    return out
+
+
+def to_density_to_sdf(ctx: Context, x, rho_t=0.5, phi=None, rho_nodes=None, vf=None,
+                      want_rho=True, want_vf=True):
+    """Returns (phi, rho_nodes, vf)."""
+    p = ctx.prob
+    dev = x.device
+    if phi is None:
+        phi = torch.empty(p.nn, dtype=torch.float64, device=dev)
+    if rho_nodes is None and want_rho:
+        rho_nodes = torch.empty(p.nn, dtype=torch.float64, device=dev)
+    if vf is None and want_vf:
+        vf = torch.empty(p.nel, dtype=torch.float64, device=dev)
+    _check(L.lib().to_density_to_sdf(ctx.handle, _dev(x, torch.float64, p.nel, "x"), float(rho_t),
+                                     _dev(phi, torch.float64, p.nn, "phi"),
+                                     _dev(rho_nodes, torch.float64, p.nn, "rho_nodes"),
+                                     _dev(vf, torch.float64, p.nel, "vf")), ctx.handle)
+    return phi, rho_nodes, vf
+
+
+def last_triangle_count(ctx: Context) -> int:
+    return L.lib().to_last_triangle_count(ctx.handle)
+
+
+def to_matvec(ctx: Context, x, u, y=None):
+    p = ctx.prob
+    if y is None:
+        y = torch.empty(p.ndof, dtype=torch.float64, device=u.device)
+    _check(L.lib().to_matvec(ctx.handle, _dev(x, torch.float64, p.nel, "x"),
+                             _dev(u, torch.float64, p.ndof, "u"),
+                             _dev(y, torch.float64, p.ndof, "y")), ctx.handle)
+    return y
+
+
+def to_matvec_f32(ctx: Context, x, u, y=None):
+    p = ctx.prob
+    if y is None:
+        y = torch.empty(p.ndof, dtype=torch.float32, device=u.device)
+    _check(L.lib().to_matvec_f32(ctx.handle, _dev(x, torch.float64, p.nel, "x"),
+                                 _dev(u, torch.float32, p.ndof, "u"),
+                                 _dev(y, torch.float32, p.ndof, "y")), ctx.handle)
+    return y

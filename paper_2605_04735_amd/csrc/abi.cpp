@@ -1,0 +1,623 @@
+// C ABI (include/to.h) and the host-side solver driver: Jacobi-PCG with
+// float64 outer iterative refinement, compliance/sensitivity, filters and the
+// density -> SDF transfer.  Every arithmetic step runs in the HIP kernels; the
+// host only validates, sequences launches and polls small device flags.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "to.h"
+
+using namespace topo;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+constexpr int MAXOFS = 1024;        // filter stencil capacity (rmin <= 6)
+constexpr double MAX_RMIN = 6.0;
+
+struct Layout {
+  size_t off = 0;
+  template <typename T>
+  size_t take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    const size_t at = off;
+    off += count * sizeof(T);
+    return at;
+  }
+};
+
+}  // namespace
+
+struct to_ctx {
+  to_problem p{};
+  Grid g{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  bool owns_ws = false;
+
+  double *E64 = nullptr, *dinv64 = nullptr, *f = nullptr, *r64 = nullptr;
+  float *E32 = nullptr, *dinv32 = nullptr;
+  uint8_t *mask = nullptr;
+  double *v64[6] = {};  // d, r, z, pA, pB, q  (float64 inner)
+  float *v32[6] = {};   // d, r, z, pA, pB, q  (float32 inner)
+  double *part = nullptr, *scal = nullptr;
+  int *flags = nullptr;
+  double *ftmp = nullptr, *fw = nullptr;
+  int *fofs = nullptr;
+  double *rho_scratch = nullptr;
+  int *cnt = nullptr, *toff = nullptr, *bsums = nullptr;
+
+  double *tri = nullptr;  // triangles, grown on demand by to_density_to_sdf
+  size_t tri_cap = 0;
+
+  double *h_scal = nullptr;
+  int *h_flags = nullptr;
+
+  Coef<double> k64{};
+  Coef<float> k32{};
+  double kd = 0.0;
+  double fnorm = 0.0;
+  int kz = 4;
+  double last_rmin = -1.0;
+  int nofs = 0;
+  double eta = 1e-2;   // inner relative tolerance of the float32 refinement
+  int chunk = 32;      // CG iterations queued between host polls
+  int last_tri = 0;    // triangles of the last density -> SDF transfer
+  std::string err;
+};
+
+namespace {
+
+to_status fail(to_ctx *c, to_status s, const std::string &msg) {
+  g_last_error = msg;
+  if (c) c->err = msg;
+  return s;
+}
+
+#define HIPCHK(call)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail(c, TO_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_));  \
+  } while (0)
+
+bool validate_problem(const to_problem *p, std::string *why) {
+  if (!p) { *why = "problem is NULL"; return false; }
+  if (p->nelx < 1 || p->nely < 1 || p->nelz < 1) { *why = "grid sizes must be >= 1"; return false; }
+  const double nn = double(p->nelx + 1) * (p->nely + 1) * (p->nelz + 1);
+  if (nn * 3 > 2.0e9) { *why = "grid too large"; return false; }
+  if (!(p->h > 0) || !std::isfinite(p->h)) { *why = "h must be > 0"; return false; }
+  if (!(p->E0 > 0) || !std::isfinite(p->E0)) { *why = "E0 must be > 0"; return false; }
+  if (!(p->Emin >= 0) || !(p->Emin < p->E0)) { *why = "need 0 <= Emin < E0"; return false; }
+  if (!(p->nu > -1.0 && p->nu < 0.5)) { *why = "need -1 < nu < 0.5"; return false; }
+  if (!(p->penal >= 1.0) || !std::isfinite(p->penal)) { *why = "need penal >= 1"; return false; }
+  if (p->bc < 0 || p->bc > 2) { *why = "unknown bc"; return false; }
+  if (p->bc == TO_BC_CUSTOM && (!p->fixed_mask || !p->load)) {
+    *why = "CUSTOM bc needs fixed_mask and load"; return false;
+  }
+  if (p->bc != TO_BC_CUSTOM && !std::isfinite(p->load_total)) { *why = "bad load_total"; return false; }
+  if (p->precision < 0 || p->precision > 2) { *why = "unknown precision"; return false; }
+  if (p->precision == TO_PREC_FP32_REFINE_BF16) {
+    *why = "bfloat16 direction storage is not available in this build"; return false;
+  }
+  if (!(p->rtol > 0) || !(p->rtol < 1)) { *why = "need 0 < rtol < 1"; return false; }
+  if (p->max_iters < 1) { *why = "max_iters must be >= 1"; return false; }
+  return true;
+}
+
+Grid make_grid(const to_problem *p) {
+  Grid g;
+  g.nelx = p->nelx;
+  g.nely = p->nely;
+  g.nelz = p->nelz;
+  g.nel = (size_t)p->nelx * p->nely * p->nelz;
+  g.nn = (size_t)(p->nelx + 1) * (p->nely + 1) * (p->nelz + 1);
+  g.ndof = 3 * g.nn;
+  return g;
+}
+
+// Carves (or sizes, when base == nullptr) the workspace.
+size_t carve(to_ctx *c, const Grid &g, int precision, char *base) {
+  Layout L;
+  const size_t oE64 = L.take<double>(g.nel), oE32 = L.take<float>(g.nel);
+  const size_t oD64 = L.take<double>(g.nn), oD32 = L.take<float>(g.nn);
+  const size_t oMask = L.take<uint8_t>(g.nn);
+  const size_t oF = L.take<double>(g.ndof), oR64 = L.take<double>(g.ndof);
+  size_t ov[6];
+  if (precision == TO_PREC_FP64)
+    for (int i = 0; i < 6; ++i) ov[i] = L.take<double>(g.ndof);
+  else
+    for (int i = 0; i < 6; ++i) ov[i] = L.take<float>(g.ndof);
+  const size_t oPart = L.take<double>(2 * (size_t)MAXB);
+  const size_t oScal = L.take<double>(S_COUNT);
+  const size_t oFlags = L.take<int>(F_COUNT);
+  const size_t oFtmp = L.take<double>(g.nel);
+  const size_t oFw = L.take<double>(MAXOFS), oFofs = L.take<int>(3 * MAXOFS);
+  const size_t oRho = L.take<double>(g.nn);
+  const size_t oCnt = L.take<int>(g.nel), oToff = L.take<int>(g.nel);
+  const size_t oBs = L.take<int>(g.nel / 1024 + 4);
+  const size_t total = (L.off + 255) & ~size_t(255);
+  if (base) {
+    c->E64 = (double *)(base + oE64);
+    c->E32 = (float *)(base + oE32);
+    c->dinv64 = (double *)(base + oD64);
+    c->dinv32 = (float *)(base + oD32);
+    c->mask = (uint8_t *)(base + oMask);
+    c->f = (double *)(base + oF);
+    c->r64 = (double *)(base + oR64);
+    for (int i = 0; i < 6; ++i) {
+      if (precision == TO_PREC_FP64) c->v64[i] = (double *)(base + ov[i]);
+      else c->v32[i] = (float *)(base + ov[i]);
+    }
+    c->part = (double *)(base + oPart);
+    c->scal = (double *)(base + oScal);
+    c->flags = (int *)(base + oFlags);
+    c->ftmp = (double *)(base + oFtmp);
+    c->fw = (double *)(base + oFw);
+    c->fofs = (int *)(base + oFofs);
+    c->rho_scratch = (double *)(base + oRho);
+    c->cnt = (int *)(base + oCnt);
+    c->toff = (int *)(base + oToff);
+    c->bsums = (int *)(base + oBs);
+  }
+  return total;
+}
+
+template <typename T>
+Coef<T> make_coef(double nu, double h) {
+  const double lam = nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+  const double mu = 1.0 / (2.0 * (1.0 + nu));
+  const double F = h / 32.0;
+  Coef<T> k;
+  k.L2 = (T)(2.0 * lam * F);
+  k.M4 = (T)(4.0 * mu * F);
+  k.M2 = (T)(2.0 * mu * F);
+  k.L2_3 = (T)(2.0 * lam * F / 3.0);
+  k.M2_3 = (T)(2.0 * mu * F / 3.0);
+  k.B9 = (T)((2.0 * lam + 8.0 * mu) / 9.0 * F);
+  return k;
+}
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+to_status sync_read(to_ctx *c) {
+  HIPCHK(hipMemcpyAsync(c->h_scal, c->scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost,
+                        c->stream));
+  HIPCHK(hipMemcpyAsync(c->h_flags, c->flags, F_COUNT * sizeof(int), hipMemcpyDeviceToHost,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return TO_OK;
+}
+
+to_status prepare_moduli(to_ctx *c, const double *d_x, bool check) {
+  HIPCHK(launch_fill(c->flags, F_COUNT * sizeof(int), c->stream));
+  HIPCHK(launch_modulus(c->g, d_x, c->p.E0, c->p.Emin, c->p.penal, c->E64, c->E32, c->flags,
+                        c->stream));
+  if (check) {
+    to_status s = sync_read(c);
+    if (s != TO_OK) return s;
+    if (c->h_flags[F_BADX] & 2) return fail(c, TO_E_NONFINITE, "x holds NaN or Inf");
+    if (c->h_flags[F_BADX] & 1) return fail(c, TO_E_INVALID, "x outside [0,1]");
+  }
+  return TO_OK;
+}
+
+// One inner Jacobi-PCG solve of K d = r64 / ||r64|| in precision T.
+template <typename T>
+to_status inner_pcg(to_ctx *c, T *const v[6], const T *E, const T *dinv, const Coef<T> &k,
+                    double eta, int cap, int *iters, int *status) {
+  const Grid &g = c->g;
+  T *d = v[0], *r = v[1], *z = v[2], *pA = v[3], *pB = v[4], *q = v[5];
+  int nb_init = 0;
+  HIPCHK(launch_cg_init<T>(g, c->r64, c->scal, d, r, z, pA, dinv, c->mask, c->part, &nb_init,
+                           c->stream));
+  HIPCHK(launch_finish_init(c->part, nb_init, eta * eta, c->scal, c->flags, c->stream));
+  MvArgs<T> a{};
+  a.nelx = g.nelx;
+  a.nely = g.nely;
+  a.nelz = g.nelz;
+  a.kz = c->kz;
+  a.E = E;
+  a.mask = c->mask;
+  a.part = c->part;
+  a.scal = c->scal;
+  a.flags = c->flags;
+  a.k = k;
+  a.out = q;
+  a.in = z;
+  int launched = 0;
+  *iters = 0;
+  *status = 0;
+  for (;;) {
+    const int n = std::min(c->chunk, cap - launched);
+    for (int it = 0; it < n; ++it) {
+      const int par = (launched + it) & 1;
+      a.pold = par ? pB : pA;
+      a.pout = par ? pA : pB;
+      int nb = 0, nbu = 0;
+      HIPCHK((launch_matvec<T, MV_CG>(a, &nb, c->stream)));
+      HIPCHK(launch_finish_alpha(c->part, nb, c->scal, c->flags, c->stream));
+      HIPCHK(launch_cg_update<T>(g, d, a.pout, q, r, z, dinv, c->mask, c->scal, c->flags, c->part,
+                                 &nbu, c->stream));
+      HIPCHK(launch_finish_beta(c->part, nbu, c->scal, c->flags, c->stream));
+    }
+    launched += n;
+    to_status s = sync_read(c);
+    if (s != TO_OK) return s;
+    *iters = c->h_flags[F_ITERS];
+    *status = c->h_flags[F_STATUS];
+    if (c->h_flags[F_DONE] || launched >= cap) break;
+  }
+  return TO_OK;
+}
+
+template <typename T>
+to_status axpy_correction(to_ctx *c, double *u, const T *d) {
+  HIPCHK(launch_axpy_out<T>(c->g, u, d, c->scal, c->stream));
+  return TO_OK;
+}
+
+to_status residual64(to_ctx *c, const double *u) {
+  MvArgs<double> a{};
+  a.nelx = c->g.nelx;
+  a.nely = c->g.nely;
+  a.nelz = c->g.nelz;
+  a.kz = c->kz;
+  a.E = c->E64;
+  a.in = u;
+  a.out = c->r64;
+  a.f = c->f;
+  a.mask = c->mask;
+  a.part = c->part;
+  a.k = c->k64;
+  int nb = 0;
+  HIPCHK((launch_matvec<double, MV_RESID>(a, &nb, c->stream)));
+  HIPCHK(launch_finish_sum(c->part, nb, 0, c->scal, S_NORM2, c->stream));
+  HIPCHK(launch_set_scale(c->scal, c->stream));
+  return TO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+to_status to_workspace_size(const to_problem *prob, size_t *bytes) {
+  std::string why;
+  if (!bytes) return fail(nullptr, TO_E_INVALID, "bytes is NULL");
+  if (!validate_problem(prob, &why)) return fail(nullptr, TO_E_INVALID, why);
+  *bytes = carve(nullptr, make_grid(prob), prob->precision, nullptr);
+  return TO_OK;
+}
+
+to_status to_create(const to_problem *prob, void *d_workspace, size_t bytes, void *stream,
+                    to_ctx **out) {
+  std::string why;
+  if (!out) return fail(nullptr, TO_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!validate_problem(prob, &why)) return fail(nullptr, TO_E_INVALID, why);
+  if (d_workspace && ((uintptr_t)d_workspace & 255u))
+    return fail(nullptr, TO_E_INVALID, "workspace must be 256-byte aligned");
+  to_ctx *c = new to_ctx();
+  c->p = *prob;
+  c->p.fixed_mask = nullptr;
+  c->p.load = nullptr;
+  c->g = make_grid(prob);
+  c->stream = (hipStream_t)stream;
+  if (const char *e = std::getenv("TOPO_INNER_ETA")) c->eta = std::atof(e);
+  if (const char *e = std::getenv("TOPO_CHUNK")) c->chunk = std::max(1, std::atoi(e));
+  auto bail = [&](to_status s, const std::string &m) {
+    to_status r = fail(nullptr, s, m);
+    to_destroy(c);
+    return r;
+  };
+  if (hipGetDevice(&c->device) != hipSuccess) return bail(TO_E_HIP, "hipGetDevice failed");
+  const size_t need = carve(nullptr, c->g, prob->precision, nullptr);
+  if (d_workspace) {
+    if (bytes < need) return bail(TO_E_OOM, "workspace smaller than to_workspace_size()");
+    c->ws = (char *)d_workspace;
+    c->ws_bytes = bytes;
+  } else {
+    if (hipMalloc((void **)&c->ws, need) != hipSuccess) return bail(TO_E_OOM, "hipMalloc failed");
+    c->owns_ws = true;
+    c->ws_bytes = need;
+  }
+  carve(c, c->g, prob->precision, c->ws);
+  if (hipHostMalloc((void **)&c->h_scal, S_COUNT * sizeof(double), hipHostMallocDefault) !=
+          hipSuccess ||
+      hipHostMalloc((void **)&c->h_flags, F_COUNT * sizeof(int), hipHostMallocDefault) != hipSuccess)
+    return bail(TO_E_OOM, "hipHostMalloc failed");
+  c->k64 = make_coef<double>(prob->nu, prob->h);
+  c->k32 = make_coef<float>(prob->nu, prob->h);
+  {
+    const double lam = prob->nu / ((1.0 + prob->nu) * (1.0 - 2.0 * prob->nu));
+    const double mu = 1.0 / (2.0 * (1.0 + prob->nu));
+    c->kd = prob->h * (lam + 4.0 * mu) / 9.0;
+  }
+  c->kz = matvec_kz(c->g);
+  if (matvec_blocks(c->g, c->kz) > MAXB) {
+    // bigger z chunks until the partial-sum array fits
+    while (matvec_blocks(c->g, c->kz) > MAXB) c->kz *= 2;
+  }
+  hipStream_t s = c->stream;
+  if (prob->bc == TO_BC_CUSTOM) {
+    // host arrays -> device: the per-DOF mask goes through the triangle
+    // scratch (int array of nel >= ... may be small), so use a temporary
+    uint8_t *dm = nullptr;
+    if (hipMalloc((void **)&dm, c->g.ndof) != hipSuccess) return bail(TO_E_OOM, "hipMalloc failed");
+    bool ok = hipMemcpy(dm, prob->fixed_mask, c->g.ndof, hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(c->f, prob->load, c->g.ndof * sizeof(double), hipMemcpyHostToDevice) ==
+                  hipSuccess &&
+              launch_mask_custom(c->g, dm, c->mask, c->f, s) == hipSuccess &&
+              hipStreamSynchronize(s) == hipSuccess;
+    hipFree(dm);
+    if (!ok) return bail(TO_E_HIP, "uploading the custom mask/load failed");
+  } else {
+    if (launch_mask_builtin(c->g, prob->bc, c->mask, s) != hipSuccess ||
+        launch_load_builtin(c->g, prob->bc, prob->load_total, c->mask, c->f, s) != hipSuccess)
+      return bail(TO_E_HIP, "building the mask/load failed");
+  }
+  // ||f||
+  int nb = 0;
+  if (launch_dot(c->f, c->f, c->g.ndof, c->part, &nb, s) != hipSuccess ||
+      launch_finish_sum(c->part, nb, 0, c->scal, S_TMP, s) != hipSuccess)
+    return bail(TO_E_HIP, "norm of f failed");
+  if (sync_read(c) != TO_OK) return bail(TO_E_HIP, "sync failed");
+  c->fnorm = std::sqrt(c->h_scal[S_TMP]);
+  *out = c;
+  return TO_OK;
+}
+
+void to_destroy(to_ctx *c) {
+  if (!c) return;
+  if (c->stream) hipStreamSynchronize(c->stream);
+  else hipDeviceSynchronize();
+  if (c->owns_ws && c->ws) hipFree(c->ws);
+  if (c->tri) hipFree(c->tri);
+  if (c->h_scal) hipHostFree(c->h_scal);
+  if (c->h_flags) hipHostFree(c->h_flags);
+  delete c;
+}
+
+const char *to_last_error(const to_ctx *c) {
+  if (c) return c->err.c_str();
+  return g_last_error.c_str();
+}
+
+to_status to_solve(to_ctx *c, const double *d_x, const double *d_u0, double *d_u,
+                   to_solve_info *info) {
+  if (!c) return fail(nullptr, TO_E_INVALID, "ctx is NULL");
+  if (!d_x || !d_u) return fail(c, TO_E_INVALID, "d_x and d_u are required");
+  const double t0 = now_ms();
+  HIPCHK(hipSetDevice(c->device));
+  const Grid &g = c->g;
+  to_status st = prepare_moduli(c, d_x, false);
+  if (st != TO_OK) return st;
+  HIPCHK(launch_diag(g, c->E64, c->kd, c->mask, c->dinv64, c->dinv32, c->stream));
+  if (d_u0 && d_u0 != d_u)
+    HIPCHK(hipMemcpyAsync(d_u, d_u0, g.ndof * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  else if (!d_u0)
+    HIPCHK(launch_fill(d_u, g.ndof * sizeof(double), c->stream));
+  st = sync_read(c);
+  if (st != TO_OK) return st;
+  if (c->h_flags[F_BADX] & 2) return fail(c, TO_E_NONFINITE, "x holds NaN or Inf");
+  if (c->h_flags[F_BADX] & 1) return fail(c, TO_E_INVALID, "x outside [0,1]");
+
+  const bool fp64 = c->p.precision == TO_PREC_FP64;
+  int outer = 0, total_inner = 0;
+  double rel = 0.0;
+  to_status result = TO_OK;
+  std::string msg;
+  if (c->fnorm == 0.0) {
+    HIPCHK(launch_fill(d_u, g.ndof * sizeof(double), c->stream));
+  } else {
+    for (;;) {
+      st = residual64(c, d_u);
+      if (st != TO_OK) return st;
+      st = sync_read(c);
+      if (st != TO_OK) return st;
+      rel = std::sqrt(c->h_scal[S_NORM2]) / c->fnorm;
+      if (!std::isfinite(rel)) { result = TO_E_NONFINITE; msg = "non-finite residual"; break; }
+      if (rel <= c->p.rtol) break;
+      if (total_inner >= c->p.max_iters || outer >= 200) {
+        result = TO_E_NOCONV;
+        msg = "iteration cap reached";
+        break;
+      }
+      // inner relative tolerance: the whole remaining reduction in float64,
+      // eta (or the remaining reduction if smaller) in float32
+      const double need = 0.5 * c->p.rtol / rel;
+      const double eta = fp64 ? need : std::max(c->eta, need);
+      int it = 0, status = 0;
+      const int cap = c->p.max_iters - total_inner;
+      if (fp64) {
+        st = inner_pcg<double>(c, c->v64, c->E64, c->dinv64, c->k64, eta, cap, &it, &status);
+        if (st != TO_OK) return st;
+        st = axpy_correction<double>(c, d_u, c->v64[0]);
+      } else {
+        st = inner_pcg<float>(c, c->v32, c->E32, c->dinv32, c->k32, eta, cap, &it, &status);
+        if (st != TO_OK) return st;
+        st = axpy_correction<float>(c, d_u, c->v32[0]);
+      }
+      if (st != TO_OK) return st;
+      total_inner += it;
+      ++outer;
+      if (status == 1) { result = TO_E_SINGULAR; msg = "CG breakdown: p^T K p <= 0"; }
+      if (status == 2) { result = TO_E_NONFINITE; msg = "non-finite value in CG"; }
+      if (result != TO_OK) {
+        st = residual64(c, d_u);
+        if (st == TO_OK) st = sync_read(c);
+        if (st == TO_OK) rel = std::sqrt(c->h_scal[S_NORM2]) / c->fnorm;
+        break;
+      }
+    }
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (info) {
+    info->outer_iters = outer;
+    info->inner_iters = total_inner;
+    info->rel_res = rel;
+    info->ms = now_ms() - t0;
+  }
+  if (result != TO_OK) return fail(c, result, msg);
+  return TO_OK;
+}
+
+to_status to_compliance_sensitivity(to_ctx *c, const double *d_x, const double *d_u, double *h_c,
+                                    double *d_dc) {
+  if (!c) return fail(nullptr, TO_E_INVALID, "ctx is NULL");
+  if (!d_x || !d_u || !h_c) return fail(c, TO_E_INVALID, "d_x, d_u and h_c are required");
+  HIPCHK(hipSetDevice(c->device));
+  to_status st = prepare_moduli(c, d_x, false);
+  if (st != TO_OK) return st;
+  int nb = 0;
+  HIPCHK(launch_energy_sens(c->g, d_x, d_u, c->E64, c->k64, c->p.E0, c->p.Emin, c->p.penal, d_dc,
+                            c->part, &nb, c->stream));
+  HIPCHK(launch_finish_sum(c->part, nb, 0, c->scal, S_ES, c->stream));
+  HIPCHK(launch_dot(c->f, d_u, c->g.ndof, c->part, &nb, c->stream));
+  HIPCHK(launch_finish_sum(c->part, nb, 0, c->scal, S_C, c->stream));
+  st = sync_read(c);
+  if (st != TO_OK) return st;
+  if (c->h_flags[F_BADX] & 2) return fail(c, TO_E_NONFINITE, "x holds NaN or Inf");
+  if (c->h_flags[F_BADX] & 1) return fail(c, TO_E_INVALID, "x outside [0,1]");
+  *h_c = c->h_scal[S_C];
+  if (!std::isfinite(*h_c)) return fail(c, TO_E_NONFINITE, "non-finite compliance");
+  return TO_OK;
+}
+
+double to_last_energy_sum(const to_ctx *c) { return c ? c->h_scal[S_ES] : 0.0; }
+
+to_status to_filter(to_ctx *c, double rmin, int32_t mode, const double *d_x, const double *d_in,
+                    double *d_out) {
+  if (!c) return fail(nullptr, TO_E_INVALID, "ctx is NULL");
+  if (!(rmin > 0.0) || !(rmin <= MAX_RMIN)) return fail(c, TO_E_INVALID, "need 0 < rmin <= 6");
+  if (mode < 0 || mode > 2) return fail(c, TO_E_INVALID, "unknown filter mode");
+  if (!d_in || !d_out) return fail(c, TO_E_INVALID, "d_in and d_out are required");
+  if (d_in == d_out) return fail(c, TO_E_INVALID, "d_out must not alias d_in");
+  if (mode == TO_FILTER_SENS && !d_x) return fail(c, TO_E_INVALID, "SENS mode needs d_x");
+  HIPCHK(hipSetDevice(c->device));
+  if (rmin != c->last_rmin) {
+    // offsets with distance < rmin in (dz, dy, dx) lexicographic order
+    std::vector<int> ofs;
+    std::vector<double> w;
+    const int m = (int)std::ceil(rmin);
+    for (int dz = -m; dz <= m; ++dz)
+      for (int dy = -m; dy <= m; ++dy)
+        for (int dx = -m; dx <= m; ++dx) {
+          const double d = std::sqrt((double)(dx * dx + dy * dy + dz * dz));
+          if (d < rmin) {
+            ofs.push_back(dx);
+            ofs.push_back(dy);
+            ofs.push_back(dz);
+            w.push_back(rmin - d);
+          }
+        }
+    if ((int)w.size() > MAXOFS) return fail(c, TO_E_INVALID, "filter stencil too large");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(c->fofs, ofs.data(), ofs.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->fw, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice));
+    c->nofs = (int)w.size();
+    c->last_rmin = rmin;
+  }
+  const double V = c->p.h * c->p.h * c->p.h;
+  HIPCHK(launch_filter(c->g, mode, c->nofs, c->fofs, c->fw, V, d_x, d_in, c->ftmp, d_out,
+                       c->stream));
+  return TO_OK;
+}
+
+to_status to_density_to_sdf(to_ctx *c, const double *d_x, double rho_t, double *d_phi,
+                            double *d_rho_nodes, double *d_vf) {
+  if (!c) return fail(nullptr, TO_E_INVALID, "ctx is NULL");
+  if (!d_x || !d_phi) return fail(c, TO_E_INVALID, "d_x and d_phi are required");
+  if (!std::isfinite(rho_t)) return fail(c, TO_E_INVALID, "rho_t must be finite");
+  HIPCHK(hipSetDevice(c->device));
+  const Grid &g = c->g;
+  double *rho = d_rho_nodes ? d_rho_nodes : c->rho_scratch;
+  HIPCHK(launch_node_mean(g, d_x, rho, c->stream));
+  HIPCHK(launch_mt_count(g, rho, rho_t, c->cnt, c->stream));
+  HIPCHK(launch_scan(c->cnt, c->toff, g.nel, c->bsums, c->stream));
+  const int nt = (int)((g.nel + 1023) / 1024);
+  HIPCHK(hipMemcpyAsync(c->h_flags + F_COUNT - 1, c->bsums + nt, sizeof(int),
+                        hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  const int total = c->h_flags[F_COUNT - 1];
+  c->last_tri = total;
+  if (total < 0) return fail(c, TO_E_INVALID, "triangle count overflow");
+  if (total > 0) {
+    const size_t need = (size_t)total * 9;
+    if (need > c->tri_cap) {
+      if (c->tri) HIPCHK(hipFree(c->tri));
+      c->tri = nullptr;
+      c->tri_cap = 0;
+      const size_t cap = need + need / 4;
+      if (hipMalloc((void **)&c->tri, cap * sizeof(double)) != hipSuccess)
+        return fail(c, TO_E_OOM, "cannot allocate the triangle buffer");
+      c->tri_cap = cap;
+    }
+    HIPCHK(launch_mt_emit(g, rho, rho_t, c->p.h, c->toff, c->cnt, c->tri, c->stream));
+    HIPCHK(launch_udist(g, c->p.h, c->cnt, c->toff, c->tri, rho, rho_t, d_phi, c->stream));
+  } else {
+    HIPCHK(launch_sign_inf(g, rho, rho_t, d_phi, c->stream));
+  }
+  if (d_vf) HIPCHK(launch_vf(g, d_phi, d_vf, c->stream));
+  return TO_OK;
+}
+
+int32_t to_last_triangle_count(const to_ctx *c) { return c ? c->last_tri : 0; }
+
+to_status to_matvec(to_ctx *c, const double *d_x, const double *d_u, double *d_y) {
+  if (!c) return fail(nullptr, TO_E_INVALID, "ctx is NULL");
+  if (!d_x || !d_u || !d_y) return fail(c, TO_E_INVALID, "d_x, d_u and d_y are required");
+  if (d_u == d_y) return fail(c, TO_E_INVALID, "d_y must not alias d_u");
+  HIPCHK(hipSetDevice(c->device));
+  to_status st = prepare_moduli(c, d_x, false);
+  if (st != TO_OK) return st;
+  MvArgs<double> a{};
+  a.nelx = c->g.nelx;
+  a.nely = c->g.nely;
+  a.nelz = c->g.nelz;
+  a.kz = c->kz;
+  a.E = c->E64;
+  a.in = d_u;
+  a.out = d_y;
+  a.mask = c->mask;
+  a.k = c->k64;
+  HIPCHK((launch_matvec<double, MV_APPLY>(a, nullptr, c->stream)));
+  return TO_OK;
+}
+
+to_status to_matvec_f32(to_ctx *c, const double *d_x, const float *d_u, float *d_y) {
+  if (!c) return fail(nullptr, TO_E_INVALID, "ctx is NULL");
+  if (!d_x || !d_u || !d_y) return fail(c, TO_E_INVALID, "d_x, d_u and d_y are required");
+  if ((const void *)d_u == (const void *)d_y) return fail(c, TO_E_INVALID, "d_y must not alias d_u");
+  HIPCHK(hipSetDevice(c->device));
+  to_status st = prepare_moduli(c, d_x, false);
+  if (st != TO_OK) return st;
+  MvArgs<float> a{};
+  a.nelx = c->g.nelx;
+  a.nely = c->g.nely;
+  a.nelz = c->g.nelz;
+  a.kz = c->kz;
+  a.E = c->E32;
+  a.in = d_u;
+  a.out = d_y;
+  a.mask = c->mask;
+  a.k = c->k32;
+  HIPCHK((launch_matvec<float, MV_APPLY>(a, nullptr, c->stream)));
+  return TO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,140 @@
+// Internal declarations shared by the HIP kernels and the C-ABI driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace topo {
+
+// ---------------------------------------------------------------- device scalars
+// Float64 scalars of a running solve live in one small device array so that
+// consecutive kernels hand them over without a host round trip.
+enum Scal {
+  S_RZ = 0,     // r^T z of the current CG iterate
+  S_ALPHA,      // CG step length
+  S_BETA,       // CG direction update factor
+  S_RR,         // ||r||^2 over free DOFs (recursive residual)
+  S_TOL2,       // stop when S_RR <= S_TOL2
+  S_PQ,         // p^T K p
+  S_NORM2,      // ||f - K u||^2 of the outer residual
+  S_SCALE,      // 1/||f - K u||: scaling of the inner right-hand side
+  S_C,          // compliance f^T u
+  S_ES,         // sum_e E_e u_e^T k0 u_e
+  S_TMP,
+  S_COUNT = 16
+};
+enum Flag {
+  F_DONE = 0,   // inner CG finished (converged, broke down or non-finite)
+  F_STATUS,     // 0 ok, 1 breakdown (p^T K p <= 0), 2 non-finite
+  F_ITERS,      // inner CG iterations of the current inner solve
+  F_BADX,       // bit 0: some x outside [0,1]; bit 1: some x non-finite
+  F_COUNT = 8
+};
+
+constexpr int MAXB = 8192;         // capacity of the per-block partial-sum array
+constexpr int RED_THREADS = 256;
+
+// Element tile of the matrix-free product: 16 x 16 elements per z layer, one
+// thread each; the tile owns the 15 x 15 nodes whose all adjacent elements lie
+// in it, and marches up a z range of node planes.
+constexpr int TE = 16;
+constexpr int TN = TE - 1;
+constexpr int TP = TE + 1;
+constexpr int MV_THREADS = TE * TE;
+
+enum MvMode { MV_APPLY = 0, MV_CG = 1, MV_RESID = 2 };
+
+// Unit-modulus coefficients of the factored hex8 stiffness (see k_matvec.hip),
+// already multiplied by h/32.
+template <typename T>
+struct Coef {
+  T L2, M4, M2, L2_3, M2_3, B9;
+};
+
+template <typename T>
+struct MvArgs {
+  int nelx, nely, nelz, kz;
+  const T *E;            // [nel] moduli
+  const T *in;           // APPLY/RESID: u; CG: z
+  const T *pold;         // CG: previous search direction
+  T *pout;               // CG: new search direction (owned nodes)
+  T *out;                // APPLY: y; CG: q = K p; RESID: r = f - K u
+  const double *f;       // RESID: load vector
+  const uint8_t *mask;   // [nn] bit c set = DOF c fixed
+  double *part;          // [nblocks] partial sums (CG: p^T q; RESID: ||r||^2)
+  const double *scal;    // CG: reads S_BETA
+  const int *flags;      // CG: early exit when flags[F_DONE]
+  Coef<T> k;
+};
+
+struct Grid {
+  int nelx, nely, nelz;
+  size_t nel, nn, ndof;
+};
+
+// ---------------------------------------------------------------- launchers
+template <typename T, int MODE>
+hipError_t launch_matvec(const MvArgs<T> &a, int *nblocks, hipStream_t s);
+int matvec_kz(const Grid &g);
+int matvec_blocks(const Grid &g, int kz);
+
+hipError_t launch_modulus(const Grid &g, const double *x, double E0, double Emin, double penal,
+                          double *E64, float *E32, int *flags, hipStream_t s);
+hipError_t launch_diag(const Grid &g, const double *E64, double kd, const uint8_t *mask,
+                       double *dinv64, float *dinv32, hipStream_t s);
+hipError_t launch_mask_builtin(const Grid &g, int bc, uint8_t *mask, hipStream_t s);
+hipError_t launch_load_builtin(const Grid &g, int bc, double load_total, const uint8_t *mask,
+                               double *f, hipStream_t s);
+hipError_t launch_mask_custom(const Grid &g, const uint8_t *dof_mask, uint8_t *mask, double *f,
+                              hipStream_t s);
+
+int vec_blocks(size_t nn);
+template <typename T>
+hipError_t launch_cg_init(const Grid &g, const double *b, const double *scal, T *x, T *r, T *z,
+                          T *p, const T *dinv, const uint8_t *mask, double *part, int *nb,
+                          hipStream_t s);
+template <typename T>
+hipError_t launch_cg_update(const Grid &g, T *x, const T *p, const T *q, T *r, T *z,
+                            const T *dinv, const uint8_t *mask, const double *scal,
+                            const int *flags, double *part, int *nb, hipStream_t s);
+template <typename T>
+hipError_t launch_axpy_out(const Grid &g, double *u, const T *d, const double *scal,
+                           hipStream_t s);
+
+hipError_t launch_finish_init(const double *part, int nb, double tol2_rel, double *scal,
+                              int *flags, hipStream_t s);
+hipError_t launch_finish_alpha(const double *part, int nb, double *scal, int *flags,
+                               hipStream_t s);
+hipError_t launch_finish_beta(const double *part, int nb, double *scal, int *flags,
+                              hipStream_t s);
+hipError_t launch_finish_sum(const double *part, int nb, int comp, double *scal, int idx,
+                             hipStream_t s);
+hipError_t launch_fill(void *p, size_t bytes, hipStream_t s);
+hipError_t launch_set_scale(double *scal, hipStream_t s);
+hipError_t launch_dot(const double *a, const double *b, size_t n, double *part, int *nb,
+                      hipStream_t s);
+
+hipError_t launch_energy_sens(const Grid &g, const double *x, const double *u, const double *E64,
+                              Coef<double> k, double E0, double Emin, double penal, double *dc,
+                              double *part, int *nb, hipStream_t s);
+
+hipError_t launch_filter(const Grid &g, int mode, int nofs, const int *ofs, const double *w,
+                         double V, const double *x, const double *in, double *tmp, double *out,
+                         hipStream_t s);
+
+// SDF
+hipError_t launch_node_mean(const Grid &g, const double *x, double *rho, hipStream_t s);
+hipError_t launch_mt_count(const Grid &g, const double *rho, double rho_t, int *count,
+                           hipStream_t s);
+hipError_t launch_scan(const int *in, int *out, size_t n, int *block_sums, hipStream_t s);
+hipError_t launch_mt_emit(const Grid &g, const double *rho, double rho_t, double h,
+                          const int *offset, const int *count, double *tri, hipStream_t s);
+hipError_t launch_udist(const Grid &g, double h, const int *count, const int *offset,
+                        const double *tri, const double *rho, double rho_t, double *phi,
+                        hipStream_t s);
+hipError_t launch_vf(const Grid &g, const double *phi, double *vf, hipStream_t s);
+hipError_t launch_sign_inf(const Grid &g, const double *rho, double rho_t, double *phi,
+                           hipStream_t s);
+
+}  // namespace topo

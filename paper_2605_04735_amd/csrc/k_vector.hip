@@ -1,0 +1,463 @@
+// Element/node set-up kernels (Eq. 1 moduli, Jacobi diagonal, boundary mask,
+// load vector) and the streaming kernels of Jacobi-preconditioned CG with
+// deterministic two-stage reductions.
+#include "common.h"
+
+namespace topo {
+
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 0; i < nw; ++i) r += sh[i];
+  }
+  __syncthreads();
+  return r;
+}
+
+// ---------------------------------------------------------------- Eq. 1
+__global__ void k_modulus(size_t nel, const double *__restrict__ x, double E0, double Emin,
+                          double penal, double *__restrict__ E64, float *__restrict__ E32,
+                          int *__restrict__ flags) {
+  int bad = 0;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < nel;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const double xe = x[e];
+    if (!isfinite(xe)) bad |= 2;
+    else if (xe < 0.0 || xe > 1.0) bad |= 1;
+    const double E = Emin + pow(xe, penal) * (E0 - Emin);
+    E64[e] = E;
+    E32[e] = (float)E;
+  }
+  if (bad) atomicOr(&flags[F_BADX], bad);
+}
+
+hipError_t launch_modulus(const Grid &g, const double *x, double E0, double Emin, double penal,
+                          double *E64, float *E32, int *flags, hipStream_t s) {
+  int blocks = (int)((g.nel + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_modulus, dim3(blocks), dim3(256), 0, s, g.nel, x, E0, Emin, penal, E64,
+                     E32, flags);
+  return hipGetLastError();
+}
+
+// Jacobi diagonal: every diagonal entry of the unit-modulus k0 equals kd, so
+// diag(K) at node n is kd * sum of the moduli of its (up to 8) elements.
+__global__ void k_diag(int nelx, int nely, int nelz, const double *__restrict__ E64, double kd,
+                       const uint8_t *__restrict__ mask, double *__restrict__ dinv64,
+                       float *__restrict__ dinv32) {
+  const int NX = nelx + 1, NY = nely + 1, NZ = nelz + 1;
+  const size_t nn = (size_t)NX * NY * NZ;
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < nn;
+       n += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(n % NX), j = (int)((n / NX) % NY), k = (int)(n / ((size_t)NX * NY));
+    double s = 0.0;
+    for (int bz = 0; bz < 2; ++bz)
+      for (int by = 0; by < 2; ++by)
+        for (int bx = 0; bx < 2; ++bx) {
+          const int ei = i - 1 + bx, ej = j - 1 + by, ek = k - 1 + bz;
+          if (ei >= 0 && ei < nelx && ej >= 0 && ej < nely && ek >= 0 && ek < nelz)
+            s += E64[(size_t)ei + (size_t)nelx * ((size_t)ej + (size_t)nely * ek)];
+        }
+    const double d = (s > 0.0) ? 1.0 / (kd * s) : 0.0;
+    dinv64[n] = d;
+    dinv32[n] = (float)d;
+  }
+}
+
+hipError_t launch_diag(const Grid &g, const double *E64, double kd, const uint8_t *mask,
+                       double *dinv64, float *dinv32, hipStream_t s) {
+  int blocks = (int)((g.nn + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_diag, dim3(blocks), dim3(256), 0, s, g.nelx, g.nely, g.nelz, E64, kd, mask,
+                     dinv64, dinv32);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- BCs, load
+__global__ void k_mask_builtin(int nelx, int nely, int nelz, int bc, uint8_t *__restrict__ mask) {
+  const int NX = nelx + 1, NY = nely + 1, NZ = nelz + 1;
+  const size_t nn = (size_t)NX * NY * NZ;
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < nn;
+       n += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(n % NX), j = (int)((n / NX) % NY), k = (int)(n / ((size_t)NX * NY));
+    unsigned m = 0;
+    if (bc == 0) {  // cantilever: clamp x = 0
+      if (i == 0) m = 7u;
+    } else {        // MBB half beam
+      if (i == 0) m |= 1u;
+      if (i == nelx && k == 0) m |= 4u;
+      if (i == 0 && j == 0 && k == 0) m |= 2u;
+    }
+    mask[n] = (uint8_t)m;
+  }
+}
+
+hipError_t launch_mask_builtin(const Grid &g, int bc, uint8_t *mask, hipStream_t s) {
+  int blocks = (int)((g.nn + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_mask_builtin, dim3(blocks), dim3(256), 0, s, g.nelx, g.nely, g.nelz, bc,
+                     mask);
+  return hipGetLastError();
+}
+
+__global__ void k_load_builtin(int nelx, int nely, int nelz, int bc, double load_total,
+                               const uint8_t *__restrict__ mask, double *__restrict__ f) {
+  const int NX = nelx + 1, NY = nely + 1, NZ = nelz + 1;
+  const size_t nn = (size_t)NX * NY * NZ;
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < nn;
+       n += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(n % NX), j = (int)((n / NX) % NY), k = (int)(n / ((size_t)NX * NY));
+    double fz = 0.0;
+    const bool on_edge = (bc == 0) ? (i == nelx && k == 0) : (i == 0 && k == nelz);
+    if (on_edge) {
+      const double w = (j == 0 || j == nely) ? 0.5 : 1.0;
+      fz = -(load_total * w) / (double)nely;
+    }
+    const unsigned m = mask[n];
+    f[3 * n + 0] = 0.0;
+    f[3 * n + 1] = 0.0;
+    f[3 * n + 2] = (m & 4u) ? 0.0 : fz;
+  }
+}
+
+hipError_t launch_load_builtin(const Grid &g, int bc, double load_total, const uint8_t *mask,
+                               double *f, hipStream_t s) {
+  int blocks = (int)((g.nn + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_load_builtin, dim3(blocks), dim3(256), 0, s, g.nelx, g.nely, g.nelz, bc,
+                     load_total, mask, f);
+  return hipGetLastError();
+}
+
+// CUSTOM: per-DOF byte mask (device copy) -> per-node bits; zero f on fixed DOFs
+__global__ void k_mask_custom(size_t nn, const uint8_t *__restrict__ dof_mask,
+                              uint8_t *__restrict__ mask, double *__restrict__ f) {
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < nn;
+       n += (size_t)gridDim.x * blockDim.x) {
+    unsigned m = 0;
+    for (int c = 0; c < 3; ++c)
+      if (dof_mask[3 * n + c]) {
+        m |= 1u << c;
+        f[3 * n + c] = 0.0;
+      }
+    mask[n] = (uint8_t)m;
+  }
+}
+
+hipError_t launch_mask_custom(const Grid &g, const uint8_t *dof_mask, uint8_t *mask, double *f,
+                              hipStream_t s) {
+  int blocks = (int)((g.nn + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_mask_custom, dim3(blocks), dim3(256), 0, s, g.nn, dof_mask, mask, f);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- CG streams
+int vec_blocks(size_t nn) {
+  size_t b = (nn + 255) / 256;
+  if (b > 2048) b = 2048;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+// b (float64) scaled by scal[S_SCALE] -> r; x = 0; z = D r; p = 0.
+// Partial sums: part[blk] = r^T z, part[MAXB + blk] = ||r||^2.
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_init(size_t nn, const double *__restrict__ b,
+                                                 const double *__restrict__ scal, T *__restrict__ x,
+                                                 T *__restrict__ r, T *__restrict__ z,
+                                                 T *__restrict__ p, const T *__restrict__ dinv,
+                                                 const uint8_t *__restrict__ mask,
+                                                 double *__restrict__ part) {
+  __shared__ double sh[4];
+  const double sc = scal[S_SCALE];
+  double rz = 0.0, rr = 0.0;
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < nn;
+       n += (size_t)gridDim.x * blockDim.x) {
+    const unsigned m = mask[n];
+    const T di = dinv[n];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const size_t i = 3 * n + c;
+      const T rv = ((m >> c) & 1u) ? T(0) : (T)(b[i] * sc);
+      const T zv = di * rv;
+      x[i] = 0;
+      r[i] = rv;
+      z[i] = zv;
+      p[i] = 0;
+      rz += (double)rv * (double)zv;
+      rr += (double)rv * (double)rv;
+    }
+  }
+  const double s1 = block_sum(rz, sh);
+  const double s2 = block_sum(rr, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = s1;
+    part[MAXB + blockIdx.x] = s2;
+  }
+}
+
+template <typename T>
+hipError_t launch_cg_init(const Grid &g, const double *b, const double *scal, T *x, T *r, T *z,
+                          T *p, const T *dinv, const uint8_t *mask, double *part, int *nb,
+                          hipStream_t s) {
+  const int blocks = vec_blocks(g.nn);
+  *nb = blocks;
+  hipLaunchKernelGGL(k_cg_init<T>, dim3(blocks), dim3(256), 0, s, g.nn, b, scal, x, r, z, p, dinv,
+                     mask, part);
+  return hipGetLastError();
+}
+
+// x += alpha p; r -= alpha q; z = D r (fixed DOFs 0).
+// Partial sums: part[blk] = r^T z, part[MAXB + blk] = ||r||^2.
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_update(size_t nn, T *__restrict__ x,
+                                                   const T *__restrict__ p,
+                                                   const T *__restrict__ q, T *__restrict__ r,
+                                                   T *__restrict__ z, const T *__restrict__ dinv,
+                                                   const uint8_t *__restrict__ mask,
+                                                   const double *__restrict__ scal,
+                                                   const int *__restrict__ flags,
+                                                   double *__restrict__ part) {
+  if (flags[F_DONE]) return;
+  __shared__ double sh[4];
+  const T alpha = (T)scal[S_ALPHA];
+  double rz = 0.0, rr = 0.0;
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < nn;
+       n += (size_t)gridDim.x * blockDim.x) {
+    const unsigned m = mask[n];
+    const T di = dinv[n];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const size_t i = 3 * n + c;
+      x[i] = x[i] + alpha * p[i];
+      const T rv = ((m >> c) & 1u) ? T(0) : r[i] - alpha * q[i];
+      const T zv = di * rv;
+      r[i] = rv;
+      z[i] = zv;
+      rz += (double)rv * (double)zv;
+      rr += (double)rv * (double)rv;
+    }
+  }
+  const double s1 = block_sum(rz, sh);
+  const double s2 = block_sum(rr, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = s1;
+    part[MAXB + blockIdx.x] = s2;
+  }
+}
+
+template <typename T>
+hipError_t launch_cg_update(const Grid &g, T *x, const T *p, const T *q, T *r, T *z,
+                            const T *dinv, const uint8_t *mask, const double *scal,
+                            const int *flags, double *part, int *nb, hipStream_t s) {
+  const int blocks = vec_blocks(g.nn);
+  *nb = blocks;
+  hipLaunchKernelGGL(k_cg_update<T>, dim3(blocks), dim3(256), 0, s, g.nn, x, p, q, r, z, dinv,
+                     mask, scal, flags, part);
+  return hipGetLastError();
+}
+
+// u += d / scal[S_SCALE]  (float64 solution update of the outer refinement)
+template <typename T>
+__global__ void k_axpy_out(size_t ndof, double *__restrict__ u, const T *__restrict__ d,
+                           const double *__restrict__ scal) {
+  const double a = 1.0 / scal[S_SCALE];
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ndof;
+       i += (size_t)gridDim.x * blockDim.x)
+    u[i] += a * (double)d[i];
+}
+
+template <typename T>
+hipError_t launch_axpy_out(const Grid &g, double *u, const T *d, const double *scal,
+                           hipStream_t s) {
+  int blocks = (int)((g.ndof + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_axpy_out<T>, dim3(blocks), dim3(256), 0, s, g.ndof, u, d, scal);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- reductions
+// One block sums nb partials in a fixed order (strided per thread, then a
+// fixed tree), so every reduction is reproducible run to run.
+__device__ double fixed_order_sum(const double *v, int nb) {
+  __shared__ double sh[RED_THREADS];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += RED_THREADS) s += v[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_finish_init(const double *part, int nb,
+                                                             double tol2_rel, double *scal,
+                                                             int *flags) {
+  const double rz = fixed_order_sum(part, nb);
+  const double rr = fixed_order_sum(part + MAXB, nb);
+  if (threadIdx.x == 0) {
+    scal[S_RZ] = rz;
+    scal[S_RR] = rr;
+    scal[S_BETA] = 0.0;
+    scal[S_TOL2] = tol2_rel * rr;
+    flags[F_ITERS] = 0;
+    flags[F_STATUS] = 0;
+    int done = (rr == 0.0) ? 1 : 0;
+    if (!isfinite(rr) || !isfinite(rz)) {
+      flags[F_STATUS] = 2;
+      done = 1;
+    }
+    flags[F_DONE] = done;
+  }
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_finish_alpha(const double *part, int nb,
+                                                              double *scal, int *flags) {
+  if (flags[F_DONE]) return;
+  const double pq = fixed_order_sum(part, nb);
+  if (threadIdx.x == 0) {
+    scal[S_PQ] = pq;
+    if (!isfinite(pq)) {
+      flags[F_STATUS] = 2;
+      flags[F_DONE] = 1;
+    } else if (!(pq > 0.0)) {
+      flags[F_STATUS] = 1;
+      flags[F_DONE] = 1;
+    } else {
+      scal[S_ALPHA] = scal[S_RZ] / pq;
+    }
+  }
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_finish_beta(const double *part, int nb,
+                                                             double *scal, int *flags) {
+  if (flags[F_DONE]) return;
+  const double rz = fixed_order_sum(part, nb);
+  const double rr = fixed_order_sum(part + MAXB, nb);
+  if (threadIdx.x == 0) {
+    flags[F_ITERS] += 1;
+    if (!isfinite(rz) || !isfinite(rr)) {
+      flags[F_STATUS] = 2;
+      flags[F_DONE] = 1;
+    } else {
+      scal[S_BETA] = rz / scal[S_RZ];
+      scal[S_RZ] = rz;
+      scal[S_RR] = rr;
+      if (rr <= scal[S_TOL2]) flags[F_DONE] = 1;
+    }
+  }
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_finish_sum(const double *part, int nb, double *scal,
+                                                            int idx) {
+  const double s = fixed_order_sum(part, nb);
+  if (threadIdx.x == 0) scal[idx] = s;
+}
+
+hipError_t launch_finish_init(const double *part, int nb, double tol2_rel, double *scal,
+                              int *flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish_init, dim3(1), dim3(RED_THREADS), 0, s, part, nb, tol2_rel, scal,
+                     flags);
+  return hipGetLastError();
+}
+hipError_t launch_finish_alpha(const double *part, int nb, double *scal, int *flags,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_finish_alpha, dim3(1), dim3(RED_THREADS), 0, s, part, nb, scal, flags);
+  return hipGetLastError();
+}
+hipError_t launch_finish_beta(const double *part, int nb, double *scal, int *flags,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_finish_beta, dim3(1), dim3(RED_THREADS), 0, s, part, nb, scal, flags);
+  return hipGetLastError();
+}
+hipError_t launch_finish_sum(const double *part, int nb, int comp, double *scal, int idx,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_finish_sum, dim3(1), dim3(RED_THREADS), 0, s, part + (size_t)comp * MAXB,
+                     nb, scal, idx);
+  return hipGetLastError();
+}
+
+// After the outer residual: S_SCALE = 1/||r||.
+__global__ void k_set_scale(double *scal) {
+  if (threadIdx.x == 0) {
+    const double n2 = scal[S_NORM2];
+    scal[S_SCALE] = (n2 > 0.0) ? 1.0 / sqrt(n2) : 1.0;
+  }
+}
+
+// Byte fill with zeros: a kernel rather than a memset so that a captured
+// graph replays it faithfully.
+__global__ void k_fill(uint32_t *p, size_t nwords) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nwords;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+hipError_t launch_fill(void *p, size_t bytes, hipStream_t s) {
+  const size_t nw = bytes / 4;
+  int blocks = (int)((nw + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, s, (uint32_t *)p, nw);
+  return hipGetLastError();
+}
+
+// partial sums of a^T b
+__global__ __launch_bounds__(256) void k_dot(const double *__restrict__ a,
+                                             const double *__restrict__ b, size_t n,
+                                             double *__restrict__ part) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    s += a[i] * b[i];
+  const double t = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+hipError_t launch_dot(const double *a, const double *b, size_t n, double *part, int *nb,
+                      hipStream_t s) {
+  int blocks = (int)((n + 255) / 256);
+  if (blocks > 2048) blocks = 2048;
+  if (blocks < 1) blocks = 1;
+  *nb = blocks;
+  hipLaunchKernelGGL(k_dot, dim3(blocks), dim3(256), 0, s, a, b, n, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_scale(double *scal, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_scale, dim3(1), dim3(64), 0, s, scal);
+  return hipGetLastError();
+}
+
+template hipError_t launch_cg_init<double>(const Grid &, const double *, const double *, double *,
+                                           double *, double *, double *, const double *,
+                                           const uint8_t *, double *, int *, hipStream_t);
+template hipError_t launch_cg_init<float>(const Grid &, const double *, const double *, float *,
+                                          float *, float *, float *, const float *,
+                                          const uint8_t *, double *, int *, hipStream_t);
+template hipError_t launch_cg_update<double>(const Grid &, double *, const double *,
+                                             const double *, double *, double *, const double *,
+                                             const uint8_t *, const double *, const int *,
+                                             double *, int *, hipStream_t);
+template hipError_t launch_cg_update<float>(const Grid &, float *, const float *, const float *,
+                                            float *, float *, const float *, const uint8_t *,
+                                            const double *, const int *, double *, int *,
+                                            hipStream_t);
+template hipError_t launch_axpy_out<double>(const Grid &, double *, const double *,
+                                            const double *, hipStream_t);
+template hipError_t launch_axpy_out<float>(const Grid &, double *, const float *, const double *,
+                                           hipStream_t);
+
+}  // namespace topo

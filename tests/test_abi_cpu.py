@@ -1,0 +1,62 @@
+"""Host-side checks of the C ABI that need no GPU: the built library loads,
+exports every function include/to.h declares, and validates problems."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2605_04735_amd import _lib as L
+from paper_2605_04735_amd import api as A
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "to.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(to_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared()
+    assert "to_solve" in names and "to_density_to_sdf" in names
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (to_[a-z0-9_]+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    lib = L.lib()
+    for n in names:
+        assert getattr(lib, n) is not None
+
+
+def test_workspace_size_validates_problem():
+    assert A.to_workspace_size(A.Problem(24, 12, 6)) > 0
+    big = A.to_workspace_size(A.Problem(96, 48, 48))
+    assert big > 0.69e6 * 6 * 8
+    mixed = A.to_workspace_size(A.Problem(96, 48, 48, precision=A.PREC_FP32_REFINE))
+    assert mixed < big
+    bad = [dict(nelx=0), dict(h=0.0), dict(nu=0.5), dict(Emin=2.0), dict(penal=0.5),
+           dict(bc=7), dict(rtol=0.0), dict(max_iters=0), dict(precision=9)]
+    for kw in bad:
+        args = dict(nelx=4, nely=3, nelz=2)
+        args.update(kw)
+        with pytest.raises(A.TopoError) as e:
+            A.to_workspace_size(A.Problem(**args))
+        assert e.value.status == L.TO_E_INVALID
+    with pytest.raises(A.TopoError):
+        A.to_workspace_size(A.Problem(4, 3, 2, bc=A.BC_CUSTOM))
+
+
+def test_struct_layout_matches_header():
+    # int32 x3, pad, 5 doubles, int32 + pad, 2 pointers, double, int32 + pad, double, int32 + pad
+    assert ctypes.sizeof(L.ToProblem) == 104
+    assert ctypes.sizeof(L.ToSolveInfo) == 24
+
+
+def test_last_error_without_context():
+    with pytest.raises(A.TopoError):
+        A.to_workspace_size(A.Problem(-1, 3, 2))
+    assert "grid" in A.L.lib().to_last_error(None).decode()

@@ -175,3 +175,18 @@ def test_load_shares_sum_to_total():
     for bc in (grid.BC_CANTILEVER, grid.BC_MBB):
         f = grid.load_vector(7, 5, 3, bc, 2.5)
         assert abs(f[2::3].sum() + 2.5) < 1e-15 and not f[0::3].any() and not f[1::3].any()
+
+
+def test_apply_rows_matches_assembled_operator():
+    nelx, nely, nelz = 5, 4, 3
+    rng = np.random.default_rng(4)
+    E = rng.uniform(0.1, 1.0, nelx * nely * nelz)
+    K0 = element.k0(0.3, 1.0)
+    K = fem.assemble(nelx, nely, nelz, E, K0)
+    for bc in (grid.BC_CANTILEVER, grid.BC_MBB):
+        fixed, _ = fem.problem_arrays(nelx, nely, nelz, bc)
+        u = rng.standard_normal(fixed.size)
+        y = fem.apply_masked(K, fixed, u).reshape(-1, 3)
+        nodes = np.arange(y.shape[0])
+        yr = fem.apply_rows(nelx, nely, nelz, E, K0, u, fixed, nodes)
+        assert np.max(np.abs(y - yr)) < 1e-14
