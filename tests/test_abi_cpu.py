@@ -50,10 +50,21 @@ def test_workspace_size_validates_problem():
         A.to_workspace_size(A.Problem(4, 3, 2, bc=A.BC_CUSTOM))
 
 
-def test_struct_layout_matches_header():
-    # int32 x3, pad, 5 doubles, int32 + pad, 2 pointers, double, int32 + pad, double, int32 + pad
-    assert ctypes.sizeof(L.ToProblem) == 104
-    assert ctypes.sizeof(L.ToSolveInfo) == 24
+def test_struct_layout_matches_header(tmp_path):
+    """ctypes field offsets equal the C compiler's for include/to.h."""
+    fields = [f for f, _ in L.ToProblem._fields_]
+    src = tmp_path / "lay.c"
+    body = "".join('printf("%%zu ", offsetof(to_problem, %s));' % f for f in fields)
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "to.h"\n'
+                   'int main(void){ %s printf("%%zu %%zu\\n", sizeof(to_problem), '
+                   'sizeof(to_solve_info)); return 0; }' % body)
+    exe = tmp_path / "lay"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                           check=True).stdout.split()]
+    assert vals[:-2] == [getattr(L.ToProblem, f).offset for f in fields]
+    assert vals[-2] == ctypes.sizeof(L.ToProblem)
+    assert vals[-1] == ctypes.sizeof(L.ToSolveInfo)
 
 
 def test_last_error_without_context():
