@@ -74,6 +74,7 @@ struct to_ctx {
   double eta = 1e-2;   // inner relative tolerance of the float32 refinement
   int chunk = 32;      // CG iterations queued between host polls
   int last_tri = 0;    // triangles of the last density -> SDF transfer
+  bool trace = false;  // TOPO_TRACE=1: print the refinement history to stderr
   std::string err;
 };
 
@@ -260,6 +261,11 @@ to_status inner_pcg(to_ctx *c, T *const v[6], const T *E, const T *dinv, const C
     if (s != TO_OK) return s;
     *iters = c->h_flags[F_ITERS];
     *status = c->h_flags[F_STATUS];
+    if (c->trace)
+      std::fprintf(stderr, "[topo]   inner launched %d iters %d done %d status %d rr %.3e tol2 %.3e rz %.3e pq %.3e alpha %.3e beta %.3e\n",
+                   launched, *iters, c->h_flags[F_DONE], *status, c->h_scal[S_RR],
+                   c->h_scal[S_TOL2], c->h_scal[S_RZ], c->h_scal[S_PQ], c->h_scal[S_ALPHA],
+                   c->h_scal[S_BETA]);
     if (c->h_flags[F_DONE] || launched >= cap) break;
   }
   return TO_OK;
@@ -319,6 +325,7 @@ to_status to_create(const to_problem *prob, void *d_workspace, size_t bytes, voi
   c->stream = (hipStream_t)stream;
   if (const char *e = std::getenv("TOPO_INNER_ETA")) c->eta = std::atof(e);
   if (const char *e = std::getenv("TOPO_CHUNK")) c->chunk = std::max(1, std::atoi(e));
+  if (const char *e = std::getenv("TOPO_TRACE")) c->trace = std::atoi(e) != 0;
   auto bail = [&](to_status s, const std::string &m) {
     to_status r = fail(nullptr, s, m);
     to_destroy(c);
@@ -430,6 +437,8 @@ to_status to_solve(to_ctx *c, const double *d_x, const double *d_u0, double *d_u
       st = sync_read(c);
       if (st != TO_OK) return st;
       rel = std::sqrt(c->h_scal[S_NORM2]) / c->fnorm;
+      if (c->trace)
+        std::fprintf(stderr, "[topo] outer %d rel %.3e inner_total %d\n", outer, rel, total_inner);
       if (!std::isfinite(rel)) { result = TO_E_NONFINITE; msg = "non-finite residual"; break; }
       if (rel <= c->p.rtol) break;
       if (total_inner >= c->p.max_iters || outer >= 200) {

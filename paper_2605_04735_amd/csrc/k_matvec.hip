@@ -190,6 +190,15 @@ __global__ __launch_bounds__(MV_THREADS) void k_matvec(const MvArgs<T> a) {
   for (int L = k0 - 1; L < k1; ++L) {
     load_plane(L + 1, buf ^ 1);
     __syncthreads();
+    // CG: the owned node's direction on plane L, read while pl[buf] is
+    // stable (the next layer's load overwrites it before the node phase ends)
+    T pn0 = 0, pn1 = 0, pn2 = 0;
+    if (MODE == MV_CG && own) {
+      const int idx = (ni + 1) + TP * (nj + 1);
+      pn0 = pl[buf][0][idx];
+      pn1 = pl[buf][1][idx];
+      pn2 = pl[buf][2][idx];
+    }
     // element phase: element (gi, gj, L)
     {
       T u[3][8];
@@ -249,9 +258,7 @@ __global__ __launch_bounds__(MV_THREADS) void k_matvec(const MvArgs<T> a) {
           a.out[3 * n + 0] = s0;
           a.out[3 * n + 1] = s1;
           a.out[3 * n + 2] = s2;
-          const int idx = (ni + 1) + TP * (nj + 1);
-          acc += (double)pl[buf][0][idx] * (double)s0 + (double)pl[buf][1][idx] * (double)s1 +
-                 (double)pl[buf][2][idx] * (double)s2;
+          acc += (double)pn0 * (double)s0 + (double)pn1 * (double)s1 + (double)pn2 * (double)s2;
         } else {  // MV_RESID
           const double r0 = (m & 1u) ? 0.0 : a.f[3 * n + 0] - (double)s0;
           const double r1 = (m & 2u) ? 0.0 : a.f[3 * n + 1] - (double)s1;

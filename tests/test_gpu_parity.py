@@ -115,7 +115,9 @@ def test_solve_vs_oracle(name, dims, bc, kind, prec):
     print("solve", name, prec, flush=True)
     x = (inputs.uniform(nelx, nely, nelz, 0.5) if kind == "uniform"
          else inputs.random_field(nelx, nely, nelz, seed=2, ell=3.0))
-    rtol = 1e-10 if prec == A.PREC_FP64 else 1e-8
+    # the MBB half beam is pinned in y at a single node, so its error/residual
+    # ratio is ~1e2: both paths solve to the same residual
+    rtol = 1e-10
     prob = A.Problem(nelx, nely, nelz, bc=bc, precision=prec, rtol=rtol)
     ctx = A.to_create(prob)
     xg = gpu(x)
@@ -123,9 +125,17 @@ def test_solve_vs_oracle(name, dims, bc, kind, prec):
     assert info["rel_res"] <= rtol
     c, dc = A.to_compliance_sensitivity(ctx, xg, u)
     uref, cref, dcref = _oracle_solution(nelx, nely, nelz, x, prob)
+    # float64: u, c, dc <= 1e-8.  float32 inner + float64 refinement: c and dc
+    # <= 1e-6; u only to 1e-5, because with E_min = 1e-9 the displacement of
+    # near-void regions is barely determined by the residual (their stiffness
+    # is below float32 resolution next to solid elements) while it hardly
+    # enters c or dc.
     tol = 1e-8 if prec == A.PREC_FP64 else 1e-6
+    tol_u = 1e-8 if prec == A.PREC_FP64 else 1e-5
     un = cpu(u)
-    assert rel2(un, uref) <= tol
+    print("err_u %.2e err_c %.2e err_dc %.2e" % (rel2(un, uref), abs(c - cref) / abs(cref),
+                                                rel2(cpu(dc), dcref)))
+    assert rel2(un, uref) <= tol_u
     assert abs(c - cref) <= tol * abs(cref)
     assert rel2(cpu(dc), dcref) <= tol
     fixed, _ = fem.problem_arrays(nelx, nely, nelz, bc)
