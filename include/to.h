@@ -148,11 +148,24 @@ to_status to_density_to_sdf(to_ctx *ctx, const double *d_x, double rho_t, double
 
 /* Matrix-free operator of Eq. 2, y = K(x) u with the fixed DOFs zeroed on
  * input and identity rows on output (y_fixed = u_fixed), float64.
- * d_u, d_y: [ndof], must not alias. */
+ * d_u, d_y: [ndof], must not alias.  d_x NULL reuses the moduli of the
+ * previous call on this context (one kernel launch, for timing). */
 to_status to_matvec(to_ctx *ctx, const double *d_x, const double *d_u, double *d_y);
 /* The same operator with float32 vectors, float32 moduli and float32 element
  * arithmetic (the inner-CG product of TO_PREC_FP32_REFINE). */
 to_status to_matvec_f32(to_ctx *ctx, const double *d_x, const float *d_u, float *d_y);
+
+/* Diagnostics.
+ * to_last_energy_sum: sum_e E_e u_e^T k0 u_e of the last
+ *   to_compliance_sensitivity call (equals F^T u at an exact solution).
+ * to_last_triangle_count: triangles of the last to_density_to_sdf call.
+ * to_profile: returns the accumulated HIP-event time (ms) and count of the
+ *   inner-CG product launches recorded since the previous to_profile call,
+ *   then resets them and turns recording on (enable != 0) or off.  Recording
+ *   brackets each such launch with events on the context stream. */
+double to_last_energy_sum(const to_ctx *ctx);
+int32_t to_last_triangle_count(const to_ctx *ctx);
+to_status to_profile(to_ctx *ctx, int32_t enable, double *h_ms, int64_t *h_count);
 
 #ifdef __cplusplus
 }

@@ -55,6 +55,8 @@ _SIGS = {
     "to_matvec_f32": (ctypes.c_int, [_P, _P, _P, _P]),
     "to_last_energy_sum": (_D, [_P]),
     "to_last_triangle_count": (ctypes.c_int32, [_P]),
+    "to_profile": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(_D),
+                                  ctypes.POINTER(ctypes.c_int64)]),
 }
 
 

@@ -212,7 +212,16 @@ def last_triangle_count(ctx: Context) -> int:
     return L.lib().to_last_triangle_count(ctx.handle)
 
 
+def to_profile(ctx: Context, enable: bool):
+    """(ms, count) of inner-CG product launches since the previous call."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _check(L.lib().to_profile(ctx.handle, int(enable), ctypes.byref(ms), ctypes.byref(n)), ctx.handle)
+    return ms.value, n.value
+
+
 def to_matvec(ctx: Context, x, u, y=None):
+    """x = None reuses the moduli of the previous product on ctx."""
     p = ctx.prob
     if y is None:
         y = torch.empty(p.ndof, dtype=torch.float64, device=u.device)
@@ -223,6 +232,7 @@ def to_matvec(ctx: Context, x, u, y=None):
 
 
 def to_matvec_f32(ctx: Context, x, u, y=None):
+    """x = None reuses the moduli of the previous product on ctx."""
     p = ctx.prob
     if y is None:
         y = torch.empty(p.ndof, dtype=torch.float32, device=u.device)

@@ -75,6 +75,12 @@ struct to_ctx {
   int chunk = 32;      // CG iterations queued between host polls
   int last_tri = 0;    // triangles of the last density -> SDF transfer
   bool trace = false;  // TOPO_TRACE=1: print the refinement history to stderr
+  // optional HIP-event timing of every CG-mode product launch
+  bool prof = false;
+  std::vector<hipEvent_t> ev;  // start/stop pairs
+  size_t ev_used = 0;
+  double prof_ms = 0.0;
+  long long prof_count = 0;
   std::string err;
 };
 
@@ -204,6 +210,29 @@ to_status sync_read(to_ctx *c) {
   return TO_OK;
 }
 
+// Accumulates the elapsed times of the recorded event pairs (the stream has
+// been synchronised) and recycles the events.
+void prof_collect(to_ctx *c) {
+  for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]) == hipSuccess) {
+      c->prof_ms += ms;
+      c->prof_count += 1;
+    }
+  }
+  c->ev_used = 0;
+}
+
+hipError_t prof_mark(to_ctx *c) {
+  if (c->ev_used == c->ev.size()) {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    c->ev.push_back(e);
+  }
+  return hipEventRecord(c->ev[c->ev_used++], c->stream);
+}
+
 to_status prepare_moduli(to_ctx *c, const double *d_x, bool check) {
   HIPCHK(launch_fill(c->flags, F_COUNT * sizeof(int), c->stream));
   HIPCHK(launch_modulus(c->g, d_x, c->p.E0, c->p.Emin, c->p.penal, c->E64, c->E32, c->flags,
@@ -250,7 +279,9 @@ to_status inner_pcg(to_ctx *c, T *const v[6], const T *E, const T *dinv, const C
       a.pold = par ? pB : pA;
       a.pout = par ? pA : pB;
       int nb = 0, nbu = 0;
+      if (c->prof) HIPCHK(prof_mark(c));
       HIPCHK((launch_matvec<T, MV_CG>(a, &nb, c->stream)));
+      if (c->prof) HIPCHK(prof_mark(c));
       HIPCHK(launch_finish_alpha(c->part, nb, c->scal, c->flags, c->stream));
       HIPCHK(launch_cg_update<T>(g, d, a.pout, q, r, z, dinv, c->mask, c->scal, c->flags, c->part,
                                  &nbu, c->stream));
@@ -259,6 +290,7 @@ to_status inner_pcg(to_ctx *c, T *const v[6], const T *E, const T *dinv, const C
     launched += n;
     to_status s = sync_read(c);
     if (s != TO_OK) return s;
+    if (c->prof) prof_collect(c);
     *iters = c->h_flags[F_ITERS];
     *status = c->h_flags[F_STATUS];
     if (c->trace)
@@ -392,6 +424,7 @@ void to_destroy(to_ctx *c) {
   if (!c) return;
   if (c->stream) hipStreamSynchronize(c->stream);
   else hipDeviceSynchronize();
+  for (hipEvent_t e : c->ev) hipEventDestroy(e);
   if (c->owns_ws && c->ws) hipFree(c->ws);
   if (c->tri) hipFree(c->tri);
   if (c->h_scal) hipHostFree(c->h_scal);
@@ -589,11 +622,13 @@ int32_t to_last_triangle_count(const to_ctx *c) { return c ? c->last_tri : 0; }
 
 to_status to_matvec(to_ctx *c, const double *d_x, const double *d_u, double *d_y) {
   if (!c) return fail(nullptr, TO_E_INVALID, "ctx is NULL");
-  if (!d_x || !d_u || !d_y) return fail(c, TO_E_INVALID, "d_x, d_u and d_y are required");
+  if (!d_u || !d_y) return fail(c, TO_E_INVALID, "d_u and d_y are required");
   if (d_u == d_y) return fail(c, TO_E_INVALID, "d_y must not alias d_u");
   HIPCHK(hipSetDevice(c->device));
-  to_status st = prepare_moduli(c, d_x, false);
-  if (st != TO_OK) return st;
+  if (d_x) {
+    to_status st = prepare_moduli(c, d_x, false);
+    if (st != TO_OK) return st;
+  }
   MvArgs<double> a{};
   a.nelx = c->g.nelx;
   a.nely = c->g.nely;
@@ -610,11 +645,13 @@ to_status to_matvec(to_ctx *c, const double *d_x, const double *d_u, double *d_y
 
 to_status to_matvec_f32(to_ctx *c, const double *d_x, const float *d_u, float *d_y) {
   if (!c) return fail(nullptr, TO_E_INVALID, "ctx is NULL");
-  if (!d_x || !d_u || !d_y) return fail(c, TO_E_INVALID, "d_x, d_u and d_y are required");
+  if (!d_u || !d_y) return fail(c, TO_E_INVALID, "d_u and d_y are required");
   if ((const void *)d_u == (const void *)d_y) return fail(c, TO_E_INVALID, "d_y must not alias d_u");
   HIPCHK(hipSetDevice(c->device));
-  to_status st = prepare_moduli(c, d_x, false);
-  if (st != TO_OK) return st;
+  if (d_x) {
+    to_status st = prepare_moduli(c, d_x, false);
+    if (st != TO_OK) return st;
+  }
   MvArgs<float> a{};
   a.nelx = c->g.nelx;
   a.nely = c->g.nely;
@@ -626,6 +663,17 @@ to_status to_matvec_f32(to_ctx *c, const double *d_x, const float *d_u, float *d
   a.mask = c->mask;
   a.k = c->k32;
   HIPCHK((launch_matvec<float, MV_APPLY>(a, nullptr, c->stream)));
+  return TO_OK;
+}
+
+to_status to_profile(to_ctx *c, int32_t enable, double *h_ms, int64_t *h_count) {
+  if (!c) return fail(nullptr, TO_E_INVALID, "ctx is NULL");
+  if (h_ms) *h_ms = c->prof_ms;
+  if (h_count) *h_count = c->prof_count;
+  c->prof = enable != 0;
+  c->prof_ms = 0.0;
+  c->prof_count = 0;
+  c->ev_used = 0;
   return TO_OK;
 }
 
