@@ -82,10 +82,11 @@ def main():
                                                     kappa=2.0)).to(dev)
 
     # ---------------------------------------------------------- calibration
-    ref_ctx = A.to_create(problem(A.PREC_FP64, 1e-12))
+    ref_ctx = A.to_create(problem(A.PREC_FP64, 1e-11))
 
     def reference(x):
-        u, info, _ = A.to_solve(ref_ctx, x)
+        u, info, st = A.to_solve(ref_ctx, x, raise_on_error=False)
+        assert info["rel_res"] <= 1e-10, info
         c, dc = A.to_compliance_sensitivity(ref_ctx, x, u)
         return u.cpu().numpy(), c, dc.cpu().numpy(), info
 
@@ -217,7 +218,7 @@ def main():
                         "dc_max": float(np.abs(dc_m - dcref).max() / np.abs(dcref).max())},
         "fp64": {"u": rel2(u_d, uref), "c": abs(c_d - cref) / abs(cref), "dc": rel2(dc_d, dcref),
                  "dc_max": float(np.abs(dc_d - dcref).max() / np.abs(dcref).max())},
-        "reference": "float64 GPU solve to rel. residual 1e-12 (validated against the oracle "
+        "reference": "float64 GPU solve to rel. residual 1e-11 (validated against the oracle "
                      "on smaller grids by the parity tests)"}
 
     sps_m = args.steps / res_m["sec"]

@@ -58,6 +58,13 @@ struct to_ctx {
   double *rho_scratch = nullptr;
   int *cnt = nullptr, *toff = nullptr, *bsums = nullptr;
 
+  // batched inner-CG tables for this single design
+  void *desc = nullptr;          // CgDesc<T> (T by precision)
+  int2 *bmap_mv = nullptr, *bmap_up = nullptr;
+  unsigned *arrive = nullptr;    // arrival counters of the two CG kernels
+  int nb_mv = 0, nb_up = 0;
+  int parity = 0;
+
   double *tri = nullptr;  // triangles, grown on demand by to_density_to_sdf
   size_t tri_cap = 0;
 
@@ -154,6 +161,10 @@ size_t carve(to_ctx *c, const Grid &g, int precision, char *base) {
   const size_t oRho = L.take<double>(g.nn);
   const size_t oCnt = L.take<int>(g.nel), oToff = L.take<int>(g.nel);
   const size_t oBs = L.take<int>(g.nel / 1024 + 4);
+  const int nbm = matvec_blocks(g, matvec_kz(g)), nbu = update_blocks(g.nn);
+  const size_t oDesc = L.take<char>(std::max(sizeof(CgDesc<double>), sizeof(CgDesc<float>)));
+  const size_t oBm = L.take<int2>(nbm), oBu = L.take<int2>(nbu);
+  const size_t oCnt2 = L.take<unsigned>(4);
   const size_t total = (L.off + 255) & ~size_t(255);
   if (base) {
     c->E64 = (double *)(base + oE64);
@@ -177,6 +188,12 @@ size_t carve(to_ctx *c, const Grid &g, int precision, char *base) {
     c->cnt = (int *)(base + oCnt);
     c->toff = (int *)(base + oToff);
     c->bsums = (int *)(base + oBs);
+    c->desc = (void *)(base + oDesc);
+    c->bmap_mv = (int2 *)(base + oBm);
+    c->bmap_up = (int2 *)(base + oBu);
+    c->arrive = (unsigned *)(base + oCnt2);
+    c->nb_mv = nbm;
+    c->nb_up = nbu;
   }
   return total;
 }
@@ -246,46 +263,59 @@ to_status prepare_moduli(to_ctx *c, const double *d_x, bool check) {
   return TO_OK;
 }
 
-// One inner Jacobi-PCG solve of K d = r64 / ||r64|| in precision T.
 template <typename T>
-to_status inner_pcg(to_ctx *c, T *const v[6], const T *E, const T *dinv, const Coef<T> &k,
-                    double eta, int cap, int *iters, int *status) {
+CgDesc<T> make_desc(to_ctx *c, T *const v[6], const T *E, const T *dinv, const Coef<T> &k) {
   const Grid &g = c->g;
-  T *d = v[0], *r = v[1], *z = v[2], *pA = v[3], *pB = v[4], *q = v[5];
+  CgDesc<T> d{};
+  d.nelx = g.nelx;
+  d.nely = g.nely;
+  d.nelz = g.nelz;
+  d.kz = c->kz;
+  d.tx = (g.nelx + 1 + TN - 1) / TN;
+  d.ty = (g.nely + 1 + TN - 1) / TN;
+  d.nb_mv = c->nb_mv;
+  d.nb_up = c->nb_up;
+  d.nn = (long long)g.nn;
+  d.k = k;
+  d.E = E;
+  d.dinv = dinv;
+  d.mask = c->mask;
+  d.x = v[0];
+  d.r = v[1];
+  d.z = v[2];
+  d.p[0] = v[3];
+  d.p[1] = v[4];
+  d.q = v[5];
+  d.part = c->part;
+  d.scal = c->scal;
+  d.flags = c->flags;
+  d.cnt = c->arrive;
+  return d;
+}
+
+// One inner Jacobi-PCG solve of K d = r64 / ||r64|| in precision T, run as
+// the batch-of-one case of the batched CG kernels (two launches per
+// iteration; the reductions finish in the last block of each kernel).
+template <typename T>
+to_status inner_pcg(to_ctx *c, T *const v[6], const T *dinv, double eta, int cap, int *iters,
+                    int *status) {
+  const Grid &g = c->g;
   int nb_init = 0;
-  HIPCHK(launch_cg_init<T>(g, c->r64, c->scal, d, r, z, pA, dinv, c->mask, c->part, &nb_init,
-                           c->stream));
-  HIPCHK(launch_finish_init(c->part, nb_init, eta * eta, c->scal, c->flags, c->stream));
-  MvArgs<T> a{};
-  a.nelx = g.nelx;
-  a.nely = g.nely;
-  a.nelz = g.nelz;
-  a.kz = c->kz;
-  a.E = E;
-  a.mask = c->mask;
-  a.part = c->part;
-  a.scal = c->scal;
-  a.flags = c->flags;
-  a.k = k;
-  a.out = q;
-  a.in = z;
+  HIPCHK(launch_cg_init<T>(g, c->r64, c->scal, v[0], v[1], v[2], v[3], v[4], dinv, c->mask,
+                           c->part, &nb_init, c->stream));
+  HIPCHK(launch_finish_init(c->part, nb_init, eta * eta, cap, c->scal, c->flags, c->stream));
+  const CgDesc<T> *desc = (const CgDesc<T> *)c->desc;
   int launched = 0;
   *iters = 0;
   *status = 0;
   for (;;) {
     const int n = std::min(c->chunk, cap - launched);
     for (int it = 0; it < n; ++it) {
-      const int par = (launched + it) & 1;
-      a.pold = par ? pB : pA;
-      a.pout = par ? pA : pB;
-      int nb = 0, nbu = 0;
       if (c->prof) HIPCHK(prof_mark(c));
-      HIPCHK((launch_matvec<T, MV_CG>(a, &nb, c->stream)));
+      HIPCHK(launch_cg_matvec<T>(desc, c->bmap_mv, c->nb_mv, c->parity, c->stream));
       if (c->prof) HIPCHK(prof_mark(c));
-      HIPCHK(launch_finish_alpha(c->part, nb, c->scal, c->flags, c->stream));
-      HIPCHK(launch_cg_update<T>(g, d, a.pout, q, r, z, dinv, c->mask, c->scal, c->flags, c->part,
-                                 &nbu, c->stream));
-      HIPCHK(launch_finish_beta(c->part, nbu, c->scal, c->flags, c->stream));
+      HIPCHK(launch_cg_update<T>(desc, c->bmap_up, c->nb_up, c->parity, c->stream));
+      c->parity ^= 1;
     }
     launched += n;
     to_status s = sync_read(c);
@@ -294,10 +324,9 @@ to_status inner_pcg(to_ctx *c, T *const v[6], const T *E, const T *dinv, const C
     *iters = c->h_flags[F_ITERS];
     *status = c->h_flags[F_STATUS];
     if (c->trace)
-      std::fprintf(stderr, "[topo]   inner launched %d iters %d done %d status %d rr %.3e tol2 %.3e rz %.3e pq %.3e alpha %.3e beta %.3e\n",
+      std::fprintf(stderr, "[topo]   inner launched %d iters %d done %d status %d rr %.3e tol2 %.3e\n",
                    launched, *iters, c->h_flags[F_DONE], *status, c->h_scal[S_RR],
-                   c->h_scal[S_TOL2], c->h_scal[S_RZ], c->h_scal[S_PQ], c->h_scal[S_ALPHA],
-                   c->h_scal[S_BETA]);
+                   c->h_scal[S_TOL2]);
     if (c->h_flags[F_DONE] || launched >= cap) break;
   }
   return TO_OK;
@@ -387,11 +416,26 @@ to_status to_create(const to_problem *prob, void *d_workspace, size_t bytes, voi
     c->kd = prob->h * (lam + 4.0 * mu) / 9.0;
   }
   c->kz = matvec_kz(c->g);
-  if (matvec_blocks(c->g, c->kz) > MAXB) {
-    // bigger z chunks until the partial-sum array fits
-    while (matvec_blocks(c->g, c->kz) > MAXB) c->kz *= 2;
-  }
   hipStream_t s = c->stream;
+  {
+    // single-design tables of the batched CG kernels
+    std::vector<int2> bm(c->nb_mv), bu(c->nb_up);
+    for (int b = 0; b < c->nb_mv; ++b) bm[b] = make_int2(0, b);
+    for (int b = 0; b < c->nb_up; ++b) bu[b] = make_int2(0, b);
+    bool ok = hipMemcpy(c->bmap_mv, bm.data(), bm.size() * sizeof(int2), hipMemcpyHostToDevice) ==
+                  hipSuccess &&
+              hipMemcpy(c->bmap_up, bu.data(), bu.size() * sizeof(int2), hipMemcpyHostToDevice) ==
+                  hipSuccess &&
+              launch_fill(c->arrive, 4 * sizeof(unsigned), s) == hipSuccess;
+    if (prob->precision == TO_PREC_FP64) {
+      const CgDesc<double> d = make_desc<double>(c, c->v64, c->E64, c->dinv64, c->k64);
+      ok = ok && hipMemcpy(c->desc, &d, sizeof(d), hipMemcpyHostToDevice) == hipSuccess;
+    } else {
+      const CgDesc<float> d = make_desc<float>(c, c->v32, c->E32, c->dinv32, c->k32);
+      ok = ok && hipMemcpy(c->desc, &d, sizeof(d), hipMemcpyHostToDevice) == hipSuccess;
+    }
+    if (!ok) return bail(TO_E_HIP, "uploading the CG tables failed");
+  }
   if (prob->bc == TO_BC_CUSTOM) {
     // host arrays -> device: the per-DOF mask goes through the triangle
     // scratch (int array of nel >= ... may be small), so use a temporary
@@ -458,7 +502,7 @@ to_status to_solve(to_ctx *c, const double *d_x, const double *d_u0, double *d_u
 
   const bool fp64 = c->p.precision == TO_PREC_FP64;
   int outer = 0, total_inner = 0;
-  double rel = 0.0;
+  double rel = 0.0, best = INFINITY, hist[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
   to_status result = TO_OK;
   std::string msg;
   if (c->fnorm == 0.0) {
@@ -479,6 +523,15 @@ to_status to_solve(to_ctx *c, const double *d_x, const double *d_u0, double *d_u
         msg = "iteration cap reached";
         break;
       }
+      // attainable accuracy: stop when four refinement passes have not halved
+      // the float64 residual
+      hist[outer % 4] = rel;
+      if (outer >= 4 && rel > 0.5 * hist[(outer + 1) % 4] && rel > 0.5 * best) {
+        result = TO_E_NOCONV;
+        msg = "residual stagnated above rtol (attainable accuracy reached)";
+        break;
+      }
+      best = std::min(best, rel);
       // inner relative tolerance: the whole remaining reduction in float64,
       // eta (or the remaining reduction if smaller) in float32
       const double need = 0.5 * c->p.rtol / rel;
@@ -486,11 +539,11 @@ to_status to_solve(to_ctx *c, const double *d_x, const double *d_u0, double *d_u
       int it = 0, status = 0;
       const int cap = c->p.max_iters - total_inner;
       if (fp64) {
-        st = inner_pcg<double>(c, c->v64, c->E64, c->dinv64, c->k64, eta, cap, &it, &status);
+        st = inner_pcg<double>(c, c->v64, c->dinv64, eta, cap, &it, &status);
         if (st != TO_OK) return st;
         st = axpy_correction<double>(c, d_u, c->v64[0]);
       } else {
-        st = inner_pcg<float>(c, c->v32, c->E32, c->dinv32, c->k32, eta, cap, &it, &status);
+        st = inner_pcg<float>(c, c->v32, c->dinv32, eta, cap, &it, &status);
         if (st != TO_OK) return st;
         st = axpy_correction<float>(c, d_u, c->v32[0]);
       }

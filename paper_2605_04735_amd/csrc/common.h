@@ -29,6 +29,7 @@ enum Flag {
   F_STATUS,     // 0 ok, 1 breakdown (p^T K p <= 0), 2 non-finite
   F_ITERS,      // inner CG iterations of the current inner solve
   F_BADX,       // bit 0: some x outside [0,1]; bit 1: some x non-finite
+  F_CAP,        // the inner CG stops (done) after this many iterations
   F_COUNT = 8
 };
 
@@ -68,6 +69,26 @@ struct MvArgs {
   Coef<T> k;
 };
 
+// One design of a batched inner CG solve (device resident).  The product
+// kernel reads p[parity] as the previous direction and writes p[parity ^ 1].
+template <typename T>
+struct CgDesc {
+  int nelx, nely, nelz, kz;
+  int tx, ty;           // product tiles along x and y (blocks: tx * ty * tz)
+  int nb_mv, nb_up;     // blocks of this design in the product / update kernels
+  long long nn;
+  Coef<T> k;
+  const T *E;
+  const T *dinv;
+  const uint8_t *mask;
+  T *x, *r, *z, *q;
+  T *p[2];
+  double *part;         // [2 * MAXB]
+  double *scal;         // [S_COUNT]
+  int *flags;           // [F_COUNT]
+  unsigned *cnt;        // [2] arrival counters of the two kernels (kept at 0 between launches)
+};
+
 struct Grid {
   int nelx, nely, nelz;
   size_t nel, nn, ndof;
@@ -92,22 +113,24 @@ hipError_t launch_mask_custom(const Grid &g, const uint8_t *dof_mask, uint8_t *m
 int vec_blocks(size_t nn);
 template <typename T>
 hipError_t launch_cg_init(const Grid &g, const double *b, const double *scal, T *x, T *r, T *z,
-                          T *p, const T *dinv, const uint8_t *mask, double *part, int *nb,
+                          T *pA, T *pB, const T *dinv, const uint8_t *mask, double *part, int *nb,
                           hipStream_t s);
+// One CG iteration for every design of a batch is the product kernel (with
+// its last-block step length) followed by the update kernel (last-block beta
+// and convergence test).  blockmaps: (design, local block) per block.
 template <typename T>
-hipError_t launch_cg_update(const Grid &g, T *x, const T *p, const T *q, T *r, T *z,
-                            const T *dinv, const uint8_t *mask, const double *scal,
-                            const int *flags, double *part, int *nb, hipStream_t s);
+hipError_t launch_cg_matvec(const CgDesc<T> *descs, const int2 *bmap_mv, int nb_mv, int parity,
+                            hipStream_t s);
+template <typename T>
+hipError_t launch_cg_update(const CgDesc<T> *descs, const int2 *bmap_up, int nb_up, int parity,
+                            hipStream_t s);
+int update_blocks(size_t nn);
 template <typename T>
 hipError_t launch_axpy_out(const Grid &g, double *u, const T *d, const double *scal,
                            hipStream_t s);
 
-hipError_t launch_finish_init(const double *part, int nb, double tol2_rel, double *scal,
+hipError_t launch_finish_init(const double *part, int nb, double tol2_rel, int cap, double *scal,
                               int *flags, hipStream_t s);
-hipError_t launch_finish_alpha(const double *part, int nb, double *scal, int *flags,
-                               hipStream_t s);
-hipError_t launch_finish_beta(const double *part, int nb, double *scal, int *flags,
-                              hipStream_t s);
 hipError_t launch_finish_sum(const double *part, int nb, int comp, double *scal, int idx,
                              hipStream_t s);
 hipError_t launch_fill(void *p, size_t bytes, hipStream_t s);

@@ -130,163 +130,365 @@ __device__ __forceinline__ double block_sum_d(double v, double *sh) {
   return r;
 }
 
-template <typename T, int MODE>
-__global__ __launch_bounds__(MV_THREADS) void k_matvec(const MvArgs<T> a) {
-  if (MODE == MV_CG && a.flags[F_DONE]) return;
-  __shared__ T pl[2][3][TP * TP];
-  __shared__ T eo[24][MV_THREADS];
-  __shared__ double red[MV_THREADS / 64];
+// Value of lane + 1 within each row of 16 lanes (0 for the last lane of a
+// row): the DPP row shift, no LDS traffic.
+__device__ __forceinline__ float from_next_lane(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x101, 0xF, 0xF, true));
+}
+__device__ __forceinline__ double from_next_lane(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x101, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x101, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
 
+// One block of the product: the 16 x 16 element tile (bx, by) marching over
+// node planes [bz kz, bz kz + kz).  Returns the block's partial sum (CG:
+// p^T q, RESID: ||r||^2) in thread 0.
+//
+// Per element layer L the block holds node planes L and L+1 in LDS; plane
+// L+2 is already being fetched into registers while layer L is computed.
+// Element outputs are combined without an LDS round trip of all 24 values:
+// along x by a DPP lane shift (node i gets element i-1's ax=1 corner and
+// element i's ax=0 corner from the next lane), along y through a 6-value LDS
+// exchange with the next row of the tile, along z through a register carry.
+// The summation order is fixed, so the result is deterministic.
+template <typename T, int MODE>
+__device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int by, int bz, T beta,
+                                               T (*pl)[3][TP * TP], T (*ex)[MV_THREADS],
+                                               double *red) {
   const int tid = threadIdx.x;
   const int NX = a.nelx + 1, NY = a.nely + 1, NZ = a.nelz + 1;
-  const int i0 = blockIdx.x * TN, j0 = blockIdx.y * TN;
-  const int k0 = blockIdx.z * a.kz;
+  const int i0 = bx * TN, j0 = by * TN;
+  const int k0 = bz * a.kz;
   const int k1 = min(k0 + a.kz, NZ);
-  const T beta = (MODE == MV_CG) ? (T)a.scal[S_BETA] : T(0);
 
   const int ei = tid % TE, ej = tid / TE;
   const int gi = i0 - 1 + ei, gj = j0 - 1 + ej;
   const bool e_xy = gi >= 0 && gi < a.nelx && gj >= 0 && gj < a.nely;
+  // the node owned by this lane: (i0 + ei, j0 + ej), interior of the tile
+  const int gni = i0 + ei, gnj = j0 + ej;
+  const bool own = ei < TN && ej < TN && gni < NX && gnj < NY;
+  const size_t plane = (size_t)NX * NY;
 
-  const int ni = tid % TN, nj = tid / TN;
-  const int gni = i0 + ni, gnj = j0 + nj;
-  const bool own = tid < TN * TN && gni < NX && gnj < NY;
-
-  // Stage node plane kp (17 x 17 nodes around the tile) into pl[buf]; fixed
-  // DOFs read as zero.  In CG mode the plane is the new direction
-  // p = z + beta p_old, written back for the owned nodes.
-  auto load_plane = [&](int kp, int buf) {
-    for (int idx = tid; idx < TP * TP; idx += MV_THREADS) {
+  // register staging of one node plane (17 x 17 nodes, two slots per lane)
+  T rin[2][3], rpo[2][3];
+  unsigned rm[2];
+  bool rv[2];
+  auto fetch = [&](int kp) {
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      const int idx = tid + sl * MV_THREADS;
       const int li = idx % TP, lj = idx / TP;
       const int gx = i0 - 1 + li, gy = j0 - 1 + lj;
-      T v0 = 0, v1 = 0, v2 = 0;
-      if (kp >= 0 && kp < NZ && gx >= 0 && gx < NX && gy >= 0 && gy < NY) {
-        const size_t n = (size_t)gx + (size_t)NX * ((size_t)gy + (size_t)NY * kp);
+      rv[sl] = idx < TP * TP && kp >= 0 && kp < NZ && gx >= 0 && gx < NX && gy >= 0 && gy < NY;
+      rm[sl] = 7u;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        rin[sl][c] = 0;
+        rpo[sl][c] = 0;
+      }
+      if (rv[sl]) {
+        const size_t n = (size_t)gx + (size_t)NX * gy + plane * kp;
+        rm[sl] = a.mask[n];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          rin[sl][c] = a.in[3 * n + c];
+          if (MODE == MV_CG) rpo[sl][c] = a.pold[3 * n + c];
+        }
+      }
+    }
+  };
+  auto stage = [&](int kp) {
+    T(*dst)[TP * TP] = pl[kp & 1];
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      const int idx = tid + sl * MV_THREADS;
+      if (idx >= TP * TP) continue;
+      T v[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const bool fx = (rm[sl] >> c) & 1u;
+        v[c] = fx ? T(0) : rin[sl][c];
+        if (MODE == MV_CG) v[c] = fx ? T(0) : v[c] + beta * rpo[sl][c];
+        dst[c][idx] = v[c];
+      }
+      if (MODE == MV_CG && rv[sl]) {
+        const int li = idx % TP, lj = idx / TP;
+        if (li >= 1 && li <= TN && lj >= 1 && lj <= TN && kp >= k0 && kp < k1) {
+          const size_t n = (size_t)(i0 - 1 + li) + (size_t)NX * (j0 - 1 + lj) + plane * kp;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) a.pout[3 * n + c] = v[c];
+        }
+      }
+    }
+  };
+  auto modulus = [&](int L) -> T {
+    return (e_xy && L >= 0 && L < a.nelz)
+               ? a.E[(size_t)gi + (size_t)a.nelx * ((size_t)gj + (size_t)a.nely * L)]
+               : T(0);
+  };
+
+  T carry[3] = {0, 0, 0};
+  double acc = 0.0;
+  fetch(k0 - 1);
+  stage(k0 - 1);
+  fetch(k0);
+  T Ecur = modulus(k0 - 1);
+  for (int L = k0 - 1; L < k1; ++L) {
+    stage(L + 1);
+    if (L + 2 <= k1) fetch(L + 2);
+    const T Enext = modulus(L + 1);
+    __syncthreads();
+    T(*lo)[TP * TP] = pl[L & 1];
+    T(*hi)[TP * TP] = pl[(L + 1) & 1];
+    T pn[3] = {0, 0, 0};
+    if (MODE == MV_CG && own) {
+      const int idx = (ei + 1) + TP * (ej + 1);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) pn[c] = lo[c][idx];
+    }
+    T u[3][8];
+#pragma unroll
+    for (int an = 0; an < 8; ++an) {
+      const int idx = (ei + (an & 1)) + TP * (ej + ((an >> 1) & 1));
+#pragma unroll
+      for (int c = 0; c < 3; ++c) u[c][an] = (an >> 2) ? hi[c][idx] : lo[c][idx];
+    }
+    hex8_apply(u, Ecur, a.k);
+    // x: xc[ay][az][c] for the node at this lane's (ei, ej)
+    T xc[2][2][3];
+#pragma unroll
+    for (int ay = 0; ay < 2; ++ay)
+#pragma unroll
+      for (int az = 0; az < 2; ++az)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          xc[ay][az][c] = u[c][1 + 2 * ay + 4 * az] + from_next_lane(u[c][2 * ay + 4 * az]);
+    // y: the next tile row needs this row's ay = 0 corners
+#pragma unroll
+    for (int az = 0; az < 2; ++az)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) ex[3 * az + c][tid] = xc[0][az][c];
+    __syncthreads();
+    if (own) {
+      T bot[3], top[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        bot[c] = carry[c] + (xc[1][0][c] + ex[c][tid + TE]);
+        top[c] = xc[1][1][c] + ex[3 + c][tid + TE];
+        carry[c] = top[c];
+      }
+      if (L >= k0) {
+        const size_t n = (size_t)gni + (size_t)NX * gnj + plane * L;
         const unsigned m = a.mask[n];
-        v0 = (m & 1u) ? T(0) : a.in[3 * n + 0];
-        v1 = (m & 2u) ? T(0) : a.in[3 * n + 1];
-        v2 = (m & 4u) ? T(0) : a.in[3 * n + 2];
-        if (MODE == MV_CG) {
-          v0 = (m & 1u) ? T(0) : v0 + beta * a.pold[3 * n + 0];
-          v1 = (m & 2u) ? T(0) : v1 + beta * a.pold[3 * n + 1];
-          v2 = (m & 4u) ? T(0) : v2 + beta * a.pold[3 * n + 2];
-          if (li >= 1 && li <= TN && lj >= 1 && lj <= TN && kp >= k0 && kp < k1) {
-            a.pout[3 * n + 0] = v0;
-            a.pout[3 * n + 1] = v1;
-            a.pout[3 * n + 2] = v2;
+        if (MODE == MV_APPLY) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) a.out[3 * n + c] = ((m >> c) & 1u) ? a.in[3 * n + c] : bot[c];
+        } else if (MODE == MV_CG) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const T q = ((m >> c) & 1u) ? T(0) : bot[c];
+            a.out[3 * n + c] = q;
+            acc += (double)pn[c] * (double)q;
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const double r = ((m >> c) & 1u) ? 0.0 : a.f[3 * n + c] - (double)bot[c];
+            a.out[3 * n + c] = (T)r;
+            acc += r * r;
           }
         }
       }
-      pl[buf][0][idx] = v0;
-      pl[buf][1][idx] = v1;
-      pl[buf][2][idx] = v2;
     }
-  };
-
-  T carry0 = 0, carry1 = 0, carry2 = 0;
-  double acc = 0.0;
-  int buf = 0;
-  load_plane(k0 - 1, 0);
-  for (int L = k0 - 1; L < k1; ++L) {
-    load_plane(L + 1, buf ^ 1);
-    __syncthreads();
-    // CG: the owned node's direction on plane L, read while pl[buf] is
-    // stable (the next layer's load overwrites it before the node phase ends)
-    T pn0 = 0, pn1 = 0, pn2 = 0;
-    if (MODE == MV_CG && own) {
-      const int idx = (ni + 1) + TP * (nj + 1);
-      pn0 = pl[buf][0][idx];
-      pn1 = pl[buf][1][idx];
-      pn2 = pl[buf][2][idx];
-    }
-    // element phase: element (gi, gj, L)
-    {
-      T u[3][8];
-      T E = 0;
-      const bool valid = e_xy && L >= 0 && L < a.nelz;
-      if (valid) E = a.E[(size_t)gi + (size_t)a.nelx * ((size_t)gj + (size_t)a.nely * L)];
-#pragma unroll
-      for (int an = 0; an < 8; ++an) {
-        const int ax = an & 1, ay = (an >> 1) & 1, az = an >> 2;
-        const int idx = (ei + ax) + TP * (ej + ay);
-        const int b = az ? (buf ^ 1) : buf;
-        u[0][an] = pl[b][0][idx];
-        u[1][an] = pl[b][1][idx];
-        u[2][an] = pl[b][2][idx];
-      }
-      hex8_apply(u, E, a.k);
-#pragma unroll
-      for (int an = 0; an < 8; ++an) {
-        eo[3 * an + 0][tid] = u[0][an];
-        eo[3 * an + 1][tid] = u[1][an];
-        eo[3 * an + 2][tid] = u[2][an];
-      }
-    }
-    __syncthreads();
-    // node phase: owned node (gni, gnj) on plane L gets carry + bottom
-    // corners of layer L; the top corners of layer L become the new carry.
-    if (own) {
-      T s0 = carry0, s1 = carry1, s2 = carry2;
-      T t0 = 0, t1 = 0, t2 = 0;
-#pragma unroll
-      for (int dy = 0; dy < 2; ++dy)
-#pragma unroll
-        for (int dx = 0; dx < 2; ++dx) {
-          const int e = (ni + dx) + TE * (nj + dy);
-          const int cb = (1 - dx) + 2 * (1 - dy);  // corner a = ax + 2 ay (+ 4 az)
-          s0 += eo[3 * cb + 0][e];
-          s1 += eo[3 * cb + 1][e];
-          s2 += eo[3 * cb + 2][e];
-          t0 += eo[3 * (cb + 4) + 0][e];
-          t1 += eo[3 * (cb + 4) + 1][e];
-          t2 += eo[3 * (cb + 4) + 2][e];
-        }
-      carry0 = t0;
-      carry1 = t1;
-      carry2 = t2;
-      if (L >= k0) {
-        const size_t n = (size_t)gni + (size_t)NX * ((size_t)gnj + (size_t)NY * L);
-        const unsigned m = a.mask[n];
-        if (MODE == MV_APPLY) {
-          a.out[3 * n + 0] = (m & 1u) ? a.in[3 * n + 0] : s0;
-          a.out[3 * n + 1] = (m & 2u) ? a.in[3 * n + 1] : s1;
-          a.out[3 * n + 2] = (m & 4u) ? a.in[3 * n + 2] : s2;
-        } else if (MODE == MV_CG) {
-          s0 = (m & 1u) ? T(0) : s0;
-          s1 = (m & 2u) ? T(0) : s1;
-          s2 = (m & 4u) ? T(0) : s2;
-          a.out[3 * n + 0] = s0;
-          a.out[3 * n + 1] = s1;
-          a.out[3 * n + 2] = s2;
-          acc += (double)pn0 * (double)s0 + (double)pn1 * (double)s1 + (double)pn2 * (double)s2;
-        } else {  // MV_RESID
-          const double r0 = (m & 1u) ? 0.0 : a.f[3 * n + 0] - (double)s0;
-          const double r1 = (m & 2u) ? 0.0 : a.f[3 * n + 1] - (double)s1;
-          const double r2 = (m & 4u) ? 0.0 : a.f[3 * n + 2] - (double)s2;
-          a.out[3 * n + 0] = (T)r0;
-          a.out[3 * n + 1] = (T)r1;
-          a.out[3 * n + 2] = (T)r2;
-          acc += r0 * r0 + r1 * r1 + r2 * r2;
-        }
-      }
-    }
-    buf ^= 1;
+    Ecur = Enext;
   }
-  if (MODE != MV_APPLY) {
-    const double s = block_sum_d(acc, red);
-    if (tid == 0) a.part[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = s;
+  if (MODE != MV_APPLY) return block_sum_d(acc, red);
+  return 0.0;
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(MV_THREADS) void k_matvec(const MvArgs<T> a) {
+  __shared__ T pl[2][3][TP * TP];
+  __shared__ T ex[6][MV_THREADS];
+  __shared__ double red[MV_THREADS / 64];
+  const double s = matvec_block<T, MODE>(a, blockIdx.x, blockIdx.y, blockIdx.z, T(0), pl, ex, red);
+  if (MODE != MV_APPLY && threadIdx.x == 0)
+    a.part[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = s;
+}
+
+// Partial sums cross blocks (possibly on different XCDs, each with its own
+// L2) through agent-scope atomic stores and loads, which go to the coherence
+// point without writing back or invalidating whole caches.
+__device__ __forceinline__ void publish(double *p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double collect(const double *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Fixed-order sum of n published values by one block (strided per thread,
+// then a fixed tree): the same result whichever block runs it.
+__device__ double block_fixed_sum(const double *v, int n, double *sh) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += collect(v + i);
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// Thread 0 has published this block's partials; returns true in every thread
+// of the block that arrives last for its design (which then owns the second
+// reduction stage).  The wait makes the published stores complete before the
+// arrival is counted.
+__device__ bool arrive_last(unsigned *cnt, int nb, int *flag_sh) {
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_s_waitcnt(0);
+    const unsigned prev = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *flag_sh = (prev == (unsigned)nb - 1u) ? 1 : 0;
+  }
+  __syncthreads();
+  return *flag_sh != 0;
+}
+
+// Batched inner-CG product over a table of designs: blockmap[b] = (design,
+// local block).  Per design: p = z + beta p_old, q = K p, and the last block
+// to finish turns p^T q into the step length alpha (or flags a breakdown).
+template <typename T>
+__global__ __launch_bounds__(MV_THREADS) void k_cg_matvec(const CgDesc<T> *descs,
+                                                          const int2 *blockmap, int parity) {
+  __shared__ T pl[2][3][TP * TP];
+  __shared__ T ex[6][MV_THREADS];
+  __shared__ double red[MV_THREADS];
+  __shared__ int last_sh;
+  const int2 bm = blockmap[blockIdx.x];
+  const CgDesc<T> &d = descs[bm.x];
+  if (d.flags[F_DONE]) return;
+  MvArgs<T> a;
+  a.nelx = d.nelx;
+  a.nely = d.nely;
+  a.nelz = d.nelz;
+  a.kz = d.kz;
+  a.E = d.E;
+  a.in = d.z;
+  a.pold = d.p[parity];
+  a.pout = d.p[parity ^ 1];
+  a.out = d.q;
+  a.mask = d.mask;
+  a.k = d.k;
+  const int lb = bm.y;
+  const int bx = lb % d.tx, by = (lb / d.tx) % d.ty, bz = lb / (d.tx * d.ty);
+  const T beta = (T)d.scal[S_BETA];
+  const double s = matvec_block<T, MV_CG>(a, bx, by, bz, beta, pl, ex, red);
+  if (threadIdx.x == 0) publish(d.part + lb, s);
+  if (!arrive_last(d.cnt, d.nb_mv, &last_sh)) return;
+  const double pq = block_fixed_sum(d.part, d.nb_mv, red);
+  if (threadIdx.x == 0) {
+    d.cnt[0] = 0u;
+    d.scal[S_PQ] = pq;
+    if (!isfinite(pq)) {
+      d.flags[F_STATUS] = 2;
+      d.flags[F_DONE] = 1;
+    } else if (!(pq > 0.0)) {
+      d.flags[F_STATUS] = 1;
+      d.flags[F_DONE] = 1;
+    } else {
+      d.scal[S_ALPHA] = d.scal[S_RZ] / pq;
+    }
+  }
+}
+
+// Batched CG vector update: x += alpha p; r -= alpha q; z = D r (fixed DOFs
+// 0); the last block of each design forms beta and tests convergence.
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_update(const CgDesc<T> *descs, const int2 *blockmap,
+                                                   int parity) {
+  __shared__ double red[256];
+  __shared__ int last_sh;
+  const int2 bm = blockmap[blockIdx.x];
+  const CgDesc<T> &d = descs[bm.x];
+  if (d.flags[F_DONE]) return;
+  const T alpha = (T)d.scal[S_ALPHA];
+  const T *__restrict__ p = d.p[parity ^ 1];
+  T *__restrict__ x = d.x;
+  T *__restrict__ r = d.r;
+  T *__restrict__ z = d.z;
+  const T *__restrict__ q = d.q;
+  const T *__restrict__ dinv = d.dinv;
+  const uint8_t *__restrict__ mask = d.mask;
+  const size_t nn = (size_t)d.nn;
+  const size_t stride = (size_t)d.nb_up * 256;
+  double rz = 0.0, rr = 0.0;
+  for (size_t n = (size_t)bm.y * 256 + threadIdx.x; n < nn; n += stride) {
+    const unsigned m = mask[n];
+    const T di = dinv[n];
+    T xv[3], pv[3], rv[3], qv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      xv[c] = x[3 * n + c];
+      pv[c] = p[3 * n + c];
+      rv[c] = r[3 * n + c];
+      qv[c] = q[3 * n + c];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T xn = xv[c] + alpha * pv[c];
+      const T rn = ((m >> c) & 1u) ? T(0) : rv[c] - alpha * qv[c];
+      const T zn = di * rn;
+      x[3 * n + c] = xn;
+      r[3 * n + c] = rn;
+      z[3 * n + c] = zn;
+      rz += (double)rn * (double)zn;
+      rr += (double)rn * (double)rn;
+    }
+  }
+  const double s1 = block_sum_d(rz, red);
+  __syncthreads();
+  const double s2 = block_sum_d(rr, red);
+  if (threadIdx.x == 0) {
+    publish(d.part + bm.y, s1);
+    publish(d.part + MAXB + bm.y, s2);
+  }
+  if (!arrive_last(d.cnt + 1, d.nb_up, &last_sh)) return;
+  const double rzn = block_fixed_sum(d.part, d.nb_up, red);
+  const double rrn = block_fixed_sum(d.part + MAXB, d.nb_up, red);
+  if (threadIdx.x == 0) {
+    d.cnt[1] = 0u;
+    d.flags[F_ITERS] += 1;
+    if (!isfinite(rzn) || !isfinite(rrn)) {
+      d.flags[F_STATUS] = 2;
+      d.flags[F_DONE] = 1;
+    } else {
+      d.scal[S_BETA] = rzn / d.scal[S_RZ];
+      d.scal[S_RZ] = rzn;
+      d.scal[S_RR] = rrn;
+      if (rrn <= d.scal[S_TOL2] || d.flags[F_ITERS] >= d.flags[F_CAP]) d.flags[F_DONE] = 1;
+    }
   }
 }
 
 int matvec_kz(const Grid &g) {
   const int NX = g.nelx + 1, NY = g.nely + 1, NZ = g.nelz + 1;
   const int tiles = ((NX + TN - 1) / TN) * ((NY + TN - 1) / TN);
-  // aim for >= ~2048 blocks (8 per CU) while keeping the z-halo recompute
-  // (kz + 1)/kz modest
-  int chunks = (2048 + tiles - 1) / tiles;
+  if (const char *e = getenv("TOPO_KZ")) {
+    int v = atoi(e);
+    if (v >= 1) {
+      while (tiles * ((NZ + v - 1) / v) > MAXB) ++v;
+      return v;
+    }
+  }
+  // about 4 blocks per CU while keeping the z recompute (kz + 1)/kz small
+  int chunks = (1024 + tiles - 1) / tiles;
   int kz = (NZ + chunks - 1) / chunks;
-  if (kz < 4) kz = 4;
-  if (kz > 64) kz = 64;
+  if (kz < 2) kz = 2;
+  if (kz > 32) kz = 32;
+  while (tiles * ((NZ + kz - 1) / kz) > MAXB) ++kz;  // partial sums must fit
   return kz;
 }
 
@@ -306,11 +508,31 @@ hipError_t launch_matvec(const MvArgs<T> &a, int *nblocks, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_cg_matvec(const CgDesc<T> *descs, const int2 *bmap_mv, int nb_mv, int parity,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_matvec<T>, dim3(nb_mv), dim3(MV_THREADS), 0, s, descs, bmap_mv, parity);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cg_update(const CgDesc<T> *descs, const int2 *bmap_up, int nb_up, int parity,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_update<T>, dim3(nb_up), dim3(256), 0, s, descs, bmap_up, parity);
+  return hipGetLastError();
+}
+
 template hipError_t launch_matvec<double, MV_APPLY>(const MvArgs<double> &, int *, hipStream_t);
-template hipError_t launch_matvec<double, MV_CG>(const MvArgs<double> &, int *, hipStream_t);
 template hipError_t launch_matvec<double, MV_RESID>(const MvArgs<double> &, int *, hipStream_t);
 template hipError_t launch_matvec<float, MV_APPLY>(const MvArgs<float> &, int *, hipStream_t);
-template hipError_t launch_matvec<float, MV_CG>(const MvArgs<float> &, int *, hipStream_t);
+template hipError_t launch_cg_matvec<double>(const CgDesc<double> *, const int2 *, int, int,
+                                             hipStream_t);
+template hipError_t launch_cg_matvec<float>(const CgDesc<float> *, const int2 *, int, int,
+                                            hipStream_t);
+template hipError_t launch_cg_update<double>(const CgDesc<double> *, const int2 *, int, int,
+                                             hipStream_t);
+template hipError_t launch_cg_update<float>(const CgDesc<float> *, const int2 *, int, int,
+                                            hipStream_t);
 
 // ---------------------------------------------------------------- energies
 // s_e = u_e^T k0 u_e (float64) with the same factored apply, dc_e of Eq. 3,

@@ -159,6 +159,14 @@ hipError_t launch_mask_custom(const Grid &g, const uint8_t *dof_mask, uint8_t *m
 }
 
 // ---------------------------------------------------------------- CG streams
+// blocks of the batched update kernel for one design (grid-stride beyond)
+int update_blocks(size_t nn) {
+  size_t b = (nn + 255) / 256;
+  if (b > 1024) b = 1024;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
 int vec_blocks(size_t nn) {
   size_t b = (nn + 255) / 256;
   if (b > 2048) b = 2048;
@@ -172,7 +180,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_cg_init(size_t nn, const double *__restrict__ b,
                                                  const double *__restrict__ scal, T *__restrict__ x,
                                                  T *__restrict__ r, T *__restrict__ z,
-                                                 T *__restrict__ p, const T *__restrict__ dinv,
+                                                 T *__restrict__ p, T *__restrict__ p2,
+                                                 const T *__restrict__ dinv,
                                                  const uint8_t *__restrict__ mask,
                                                  double *__restrict__ part) {
   __shared__ double sh[4];
@@ -191,6 +200,7 @@ __global__ __launch_bounds__(256) void k_cg_init(size_t nn, const double *__rest
       r[i] = rv;
       z[i] = zv;
       p[i] = 0;
+      p2[i] = 0;
       rz += (double)rv * (double)zv;
       rr += (double)rv * (double)rv;
     }
@@ -205,62 +215,12 @@ __global__ __launch_bounds__(256) void k_cg_init(size_t nn, const double *__rest
 
 template <typename T>
 hipError_t launch_cg_init(const Grid &g, const double *b, const double *scal, T *x, T *r, T *z,
-                          T *p, const T *dinv, const uint8_t *mask, double *part, int *nb,
+                          T *pA, T *pB, const T *dinv, const uint8_t *mask, double *part, int *nb,
                           hipStream_t s) {
   const int blocks = vec_blocks(g.nn);
   *nb = blocks;
-  hipLaunchKernelGGL(k_cg_init<T>, dim3(blocks), dim3(256), 0, s, g.nn, b, scal, x, r, z, p, dinv,
-                     mask, part);
-  return hipGetLastError();
-}
-
-// x += alpha p; r -= alpha q; z = D r (fixed DOFs 0).
-// Partial sums: part[blk] = r^T z, part[MAXB + blk] = ||r||^2.
-template <typename T>
-__global__ __launch_bounds__(256) void k_cg_update(size_t nn, T *__restrict__ x,
-                                                   const T *__restrict__ p,
-                                                   const T *__restrict__ q, T *__restrict__ r,
-                                                   T *__restrict__ z, const T *__restrict__ dinv,
-                                                   const uint8_t *__restrict__ mask,
-                                                   const double *__restrict__ scal,
-                                                   const int *__restrict__ flags,
-                                                   double *__restrict__ part) {
-  if (flags[F_DONE]) return;
-  __shared__ double sh[4];
-  const T alpha = (T)scal[S_ALPHA];
-  double rz = 0.0, rr = 0.0;
-  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < nn;
-       n += (size_t)gridDim.x * blockDim.x) {
-    const unsigned m = mask[n];
-    const T di = dinv[n];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const size_t i = 3 * n + c;
-      x[i] = x[i] + alpha * p[i];
-      const T rv = ((m >> c) & 1u) ? T(0) : r[i] - alpha * q[i];
-      const T zv = di * rv;
-      r[i] = rv;
-      z[i] = zv;
-      rz += (double)rv * (double)zv;
-      rr += (double)rv * (double)rv;
-    }
-  }
-  const double s1 = block_sum(rz, sh);
-  const double s2 = block_sum(rr, sh);
-  if (threadIdx.x == 0) {
-    part[blockIdx.x] = s1;
-    part[MAXB + blockIdx.x] = s2;
-  }
-}
-
-template <typename T>
-hipError_t launch_cg_update(const Grid &g, T *x, const T *p, const T *q, T *r, T *z,
-                            const T *dinv, const uint8_t *mask, const double *scal,
-                            const int *flags, double *part, int *nb, hipStream_t s) {
-  const int blocks = vec_blocks(g.nn);
-  *nb = blocks;
-  hipLaunchKernelGGL(k_cg_update<T>, dim3(blocks), dim3(256), 0, s, g.nn, x, p, q, r, z, dinv,
-                     mask, scal, flags, part);
+  hipLaunchKernelGGL(k_cg_init<T>, dim3(blocks), dim3(256), 0, s, g.nn, b, scal, x, r, z, pA, pB,
+                     dinv, mask, part);
   return hipGetLastError();
 }
 
@@ -302,8 +262,8 @@ __device__ double fixed_order_sum(const double *v, int nb) {
 }
 
 __global__ __launch_bounds__(RED_THREADS) void k_finish_init(const double *part, int nb,
-                                                             double tol2_rel, double *scal,
-                                                             int *flags) {
+                                                             double tol2_rel, int cap,
+                                                             double *scal, int *flags) {
   const double rz = fixed_order_sum(part, nb);
   const double rr = fixed_order_sum(part + MAXB, nb);
   if (threadIdx.x == 0) {
@@ -313,6 +273,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_finish_init(const double *part,
     scal[S_TOL2] = tol2_rel * rr;
     flags[F_ITERS] = 0;
     flags[F_STATUS] = 0;
+    flags[F_CAP] = cap;
     int done = (rr == 0.0) ? 1 : 0;
     if (!isfinite(rr) || !isfinite(rz)) {
       flags[F_STATUS] = 2;
@@ -322,63 +283,16 @@ __global__ __launch_bounds__(RED_THREADS) void k_finish_init(const double *part,
   }
 }
 
-__global__ __launch_bounds__(RED_THREADS) void k_finish_alpha(const double *part, int nb,
-                                                              double *scal, int *flags) {
-  if (flags[F_DONE]) return;
-  const double pq = fixed_order_sum(part, nb);
-  if (threadIdx.x == 0) {
-    scal[S_PQ] = pq;
-    if (!isfinite(pq)) {
-      flags[F_STATUS] = 2;
-      flags[F_DONE] = 1;
-    } else if (!(pq > 0.0)) {
-      flags[F_STATUS] = 1;
-      flags[F_DONE] = 1;
-    } else {
-      scal[S_ALPHA] = scal[S_RZ] / pq;
-    }
-  }
-}
-
-__global__ __launch_bounds__(RED_THREADS) void k_finish_beta(const double *part, int nb,
-                                                             double *scal, int *flags) {
-  if (flags[F_DONE]) return;
-  const double rz = fixed_order_sum(part, nb);
-  const double rr = fixed_order_sum(part + MAXB, nb);
-  if (threadIdx.x == 0) {
-    flags[F_ITERS] += 1;
-    if (!isfinite(rz) || !isfinite(rr)) {
-      flags[F_STATUS] = 2;
-      flags[F_DONE] = 1;
-    } else {
-      scal[S_BETA] = rz / scal[S_RZ];
-      scal[S_RZ] = rz;
-      scal[S_RR] = rr;
-      if (rr <= scal[S_TOL2]) flags[F_DONE] = 1;
-    }
-  }
-}
-
 __global__ __launch_bounds__(RED_THREADS) void k_finish_sum(const double *part, int nb, double *scal,
                                                             int idx) {
   const double s = fixed_order_sum(part, nb);
   if (threadIdx.x == 0) scal[idx] = s;
 }
 
-hipError_t launch_finish_init(const double *part, int nb, double tol2_rel, double *scal,
+hipError_t launch_finish_init(const double *part, int nb, double tol2_rel, int cap, double *scal,
                               int *flags, hipStream_t s) {
-  hipLaunchKernelGGL(k_finish_init, dim3(1), dim3(RED_THREADS), 0, s, part, nb, tol2_rel, scal,
-                     flags);
-  return hipGetLastError();
-}
-hipError_t launch_finish_alpha(const double *part, int nb, double *scal, int *flags,
-                               hipStream_t s) {
-  hipLaunchKernelGGL(k_finish_alpha, dim3(1), dim3(RED_THREADS), 0, s, part, nb, scal, flags);
-  return hipGetLastError();
-}
-hipError_t launch_finish_beta(const double *part, int nb, double *scal, int *flags,
-                              hipStream_t s) {
-  hipLaunchKernelGGL(k_finish_beta, dim3(1), dim3(RED_THREADS), 0, s, part, nb, scal, flags);
+  hipLaunchKernelGGL(k_finish_init, dim3(1), dim3(RED_THREADS), 0, s, part, nb, tol2_rel, cap,
+                     scal, flags);
   return hipGetLastError();
 }
 hipError_t launch_finish_sum(const double *part, int nb, int comp, double *scal, int idx,
@@ -442,19 +356,11 @@ hipError_t launch_set_scale(double *scal, hipStream_t s) {
 }
 
 template hipError_t launch_cg_init<double>(const Grid &, const double *, const double *, double *,
-                                           double *, double *, double *, const double *,
+                                           double *, double *, double *, double *, const double *,
                                            const uint8_t *, double *, int *, hipStream_t);
 template hipError_t launch_cg_init<float>(const Grid &, const double *, const double *, float *,
-                                          float *, float *, float *, const float *,
+                                          float *, float *, float *, float *, const float *,
                                           const uint8_t *, double *, int *, hipStream_t);
-template hipError_t launch_cg_update<double>(const Grid &, double *, const double *,
-                                             const double *, double *, double *, const double *,
-                                             const uint8_t *, const double *, const int *,
-                                             double *, int *, hipStream_t);
-template hipError_t launch_cg_update<float>(const Grid &, float *, const float *, const float *,
-                                            float *, float *, const float *, const uint8_t *,
-                                            const double *, const int *, double *, int *,
-                                            hipStream_t);
 template hipError_t launch_axpy_out<double>(const Grid &, double *, const double *,
                                             const double *, hipStream_t);
 template hipError_t launch_axpy_out<float>(const Grid &, double *, const float *, const double *,
