@@ -162,7 +162,8 @@ to_status to_matvec_f32(to_ctx *ctx, const double *d_x, const float *d_u, float 
  * to_profile: returns the accumulated HIP-event time (ms) and count of the
  *   inner-CG product launches recorded since the previous to_profile call,
  *   then resets them and turns recording on (enable != 0) or off.  Recording
- *   brackets each such launch with events on the context stream. */
+ *   brackets one in every 16 such launches with events on the context stream
+ *   (the events slow the launch stream down; sampling keeps that small). */
 double to_last_energy_sum(const to_ctx *ctx);
 int32_t to_last_triangle_count(const to_ctx *ctx);
 to_status to_profile(to_ctx *ctx, int32_t enable, double *h_ms, int64_t *h_count);

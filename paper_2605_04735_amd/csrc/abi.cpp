@@ -61,7 +61,7 @@ struct to_ctx {
   // batched inner-CG tables for this single design
   void *desc = nullptr;          // CgDesc<T> (T by precision)
   int2 *bmap_mv = nullptr, *bmap_up = nullptr;
-  unsigned *arrive = nullptr;    // arrival counters of the two CG kernels
+  double *cgp = nullptr;         // block partials of the batched CG kernels
   int nb_mv = 0, nb_up = 0;
   int parity = 0;
 
@@ -78,7 +78,7 @@ struct to_ctx {
   int kz = 4;
   double last_rmin = -1.0;
   int nofs = 0;
-  double eta = 1e-2;   // inner relative tolerance of the float32 refinement
+  double eta = 1e-4;   // inner relative tolerance of the float32 refinement
   int chunk = 32;      // CG iterations queued between host polls
   int last_tri = 0;    // triangles of the last density -> SDF transfer
   bool trace = false;  // TOPO_TRACE=1: print the refinement history to stderr
@@ -88,6 +88,7 @@ struct to_ctx {
   size_t ev_used = 0;
   double prof_ms = 0.0;
   long long prof_count = 0;
+  int prof_every = 16;  // bracket one product launch in this many
   std::string err;
 };
 
@@ -164,7 +165,7 @@ size_t carve(to_ctx *c, const Grid &g, int precision, char *base) {
   const int nbm = matvec_blocks(g, matvec_kz(g)), nbu = update_blocks(g.nn);
   const size_t oDesc = L.take<char>(std::max(sizeof(CgDesc<double>), sizeof(CgDesc<float>)));
   const size_t oBm = L.take<int2>(nbm), oBu = L.take<int2>(nbu);
-  const size_t oCnt2 = L.take<unsigned>(4);
+  const size_t oCgp = L.take<double>(CGP_SIZE);
   const size_t total = (L.off + 255) & ~size_t(255);
   if (base) {
     c->E64 = (double *)(base + oE64);
@@ -191,7 +192,7 @@ size_t carve(to_ctx *c, const Grid &g, int precision, char *base) {
     c->desc = (void *)(base + oDesc);
     c->bmap_mv = (int2 *)(base + oBm);
     c->bmap_up = (int2 *)(base + oBu);
-    c->arrive = (unsigned *)(base + oCnt2);
+    c->cgp = (double *)(base + oCgp);
     c->nb_mv = nbm;
     c->nb_up = nbu;
   }
@@ -286,10 +287,9 @@ CgDesc<T> make_desc(to_ctx *c, T *const v[6], const T *E, const T *dinv, const C
   d.p[0] = v[3];
   d.p[1] = v[4];
   d.q = v[5];
-  d.part = c->part;
+  d.cgp = c->cgp;
   d.scal = c->scal;
   d.flags = c->flags;
-  d.cnt = c->arrive;
   return d;
 }
 
@@ -300,10 +300,11 @@ template <typename T>
 to_status inner_pcg(to_ctx *c, T *const v[6], const T *dinv, double eta, int cap, int *iters,
                     int *status) {
   const Grid &g = c->g;
-  int nb_init = 0;
-  HIPCHK(launch_cg_init<T>(g, c->r64, c->scal, v[0], v[1], v[2], v[3], v[4], dinv, c->mask,
-                           c->part, &nb_init, c->stream));
-  HIPCHK(launch_finish_init(c->part, nb_init, eta * eta, cap, c->scal, c->flags, c->stream));
+  // the first product runs with parity c->parity and reads partial set parity ^ 1
+  const int slot = c->parity ^ 1;
+  HIPCHK(launch_cg_init<T>(g, c->r64, c->scal, v[0], v[1], v[2], v[3], v[4], dinv, c->mask, c->cgp,
+                           slot, c->nb_up, c->stream));
+  HIPCHK(launch_finish_init(c->cgp, c->nb_up, slot, eta * eta, cap, c->scal, c->flags, c->stream));
   const CgDesc<T> *desc = (const CgDesc<T> *)c->desc;
   int launched = 0;
   *iters = 0;
@@ -311,9 +312,10 @@ to_status inner_pcg(to_ctx *c, T *const v[6], const T *dinv, double eta, int cap
   for (;;) {
     const int n = std::min(c->chunk, cap - launched);
     for (int it = 0; it < n; ++it) {
-      if (c->prof) HIPCHK(prof_mark(c));
+      const bool mark = c->prof && ((launched + it) % c->prof_every == 0);
+      if (mark) HIPCHK(prof_mark(c));
       HIPCHK(launch_cg_matvec<T>(desc, c->bmap_mv, c->nb_mv, c->parity, c->stream));
-      if (c->prof) HIPCHK(prof_mark(c));
+      if (mark) HIPCHK(prof_mark(c));
       HIPCHK(launch_cg_update<T>(desc, c->bmap_up, c->nb_up, c->parity, c->stream));
       c->parity ^= 1;
     }
@@ -387,6 +389,7 @@ to_status to_create(const to_problem *prob, void *d_workspace, size_t bytes, voi
   if (const char *e = std::getenv("TOPO_INNER_ETA")) c->eta = std::atof(e);
   if (const char *e = std::getenv("TOPO_CHUNK")) c->chunk = std::max(1, std::atoi(e));
   if (const char *e = std::getenv("TOPO_TRACE")) c->trace = std::atoi(e) != 0;
+  if (const char *e = std::getenv("TOPO_PROF_EVERY")) c->prof_every = std::max(1, std::atoi(e));
   auto bail = [&](to_status s, const std::string &m) {
     to_status r = fail(nullptr, s, m);
     to_destroy(c);
@@ -425,8 +428,7 @@ to_status to_create(const to_problem *prob, void *d_workspace, size_t bytes, voi
     bool ok = hipMemcpy(c->bmap_mv, bm.data(), bm.size() * sizeof(int2), hipMemcpyHostToDevice) ==
                   hipSuccess &&
               hipMemcpy(c->bmap_up, bu.data(), bu.size() * sizeof(int2), hipMemcpyHostToDevice) ==
-                  hipSuccess &&
-              launch_fill(c->arrive, 4 * sizeof(unsigned), s) == hipSuccess;
+                  hipSuccess;
     if (prob->precision == TO_PREC_FP64) {
       const CgDesc<double> d = make_desc<double>(c, c->v64, c->E64, c->dinv64, c->k64);
       ok = ok && hipMemcpy(c->desc, &d, sizeof(d), hipMemcpyHostToDevice) == hipSuccess;
@@ -663,7 +665,9 @@ to_status to_density_to_sdf(to_ctx *c, const double *d_x, double rho_t, double *
       c->tri_cap = cap;
     }
     HIPCHK(launch_mt_emit(g, rho, rho_t, c->p.h, c->toff, c->cnt, c->tri, c->stream));
-    HIPCHK(launch_udist(g, c->p.h, c->cnt, c->toff, c->tri, rho, rho_t, d_phi, c->stream));
+    // the coarse occupancy grid reuses the filter scratch (nel doubles >= nel/64 ints)
+    HIPCHK(launch_udist(g, c->p.h, c->cnt, c->toff, c->tri, (int *)c->ftmp, rho, rho_t, d_phi,
+                        c->stream));
   } else {
     HIPCHK(launch_sign_inf(g, rho, rho_t, d_phi, c->stream));
   }

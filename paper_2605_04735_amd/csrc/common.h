@@ -22,6 +22,8 @@ enum Scal {
   S_C,          // compliance f^T u
   S_ES,         // sum_e E_e u_e^T k0 u_e
   S_TMP,
+  S_RZ0,        // r^T z of the partial-sum set of parity 0 / 1 (batched CG)
+  S_RZ1,
   S_COUNT = 16
 };
 enum Flag {
@@ -83,11 +85,18 @@ struct CgDesc {
   const uint8_t *mask;
   T *x, *r, *z, *q;
   T *p[2];
-  double *part;         // [2 * MAXB]
+  double *cgp;          // [CGP_SIZE] block partials: p^T q, then r^T z and ||r||^2 by parity
   double *scal;         // [S_COUNT]
   int *flags;           // [F_COUNT]
-  unsigned *cnt;        // [2] arrival counters of the two kernels (kept at 0 between launches)
 };
+
+// Layout of CgDesc::cgp.  The product kernel of parity P reads the r^T z and
+// ||r||^2 partials of set P^1 and writes the p^T q partials; the update
+// kernel of parity P reads those and writes set P.
+constexpr int CGP_PQ = 0;
+constexpr int CGP_RZ = MAXB;          // + P * MAXB
+constexpr int CGP_RR = 3 * MAXB;      // + P * MAXB
+constexpr int CGP_SIZE = 5 * MAXB;
 
 struct Grid {
   int nelx, nely, nelz;
@@ -111,10 +120,13 @@ hipError_t launch_mask_custom(const Grid &g, const uint8_t *dof_mask, uint8_t *m
                               hipStream_t s);
 
 int vec_blocks(size_t nn);
+// Start of an inner solve: r = b * scal[S_SCALE] (fixed DOFs 0), x = 0,
+// z = D r, both directions 0, with the r^T z / ||r||^2 partials written
+// (nb_up blocks, as the update kernel) to parity set `slot` of cgp.
 template <typename T>
 hipError_t launch_cg_init(const Grid &g, const double *b, const double *scal, T *x, T *r, T *z,
-                          T *pA, T *pB, const T *dinv, const uint8_t *mask, double *part, int *nb,
-                          hipStream_t s);
+                          T *pA, T *pB, const T *dinv, const uint8_t *mask, double *cgp, int slot,
+                          int nb_up, hipStream_t s);
 // One CG iteration for every design of a batch is the product kernel (with
 // its last-block step length) followed by the update kernel (last-block beta
 // and convergence test).  blockmaps: (design, local block) per block.
@@ -129,8 +141,8 @@ template <typename T>
 hipError_t launch_axpy_out(const Grid &g, double *u, const T *d, const double *scal,
                            hipStream_t s);
 
-hipError_t launch_finish_init(const double *part, int nb, double tol2_rel, int cap, double *scal,
-                              int *flags, hipStream_t s);
+hipError_t launch_finish_init(const double *cgp, int nb_up, int slot, double tol2_rel, int cap,
+                              double *scal, int *flags, hipStream_t s);
 hipError_t launch_finish_sum(const double *part, int nb, int comp, double *scal, int idx,
                              hipStream_t s);
 hipError_t launch_fill(void *p, size_t bytes, hipStream_t s);
@@ -153,8 +165,9 @@ hipError_t launch_mt_count(const Grid &g, const double *rho, double rho_t, int *
 hipError_t launch_scan(const int *in, int *out, size_t n, int *block_sums, hipStream_t s);
 hipError_t launch_mt_emit(const Grid &g, const double *rho, double rho_t, double h,
                           const int *offset, const int *count, double *tri, hipStream_t s);
+// occ: scratch of ceil(nelx/4) ceil(nely/4) ceil(nelz/4) ints
 hipError_t launch_udist(const Grid &g, double h, const int *count, const int *offset,
-                        const double *tri, const double *rho, double rho_t, double *phi,
+                        const double *tri, int *occ, const double *rho, double rho_t, double *phi,
                         hipStream_t s);
 hipError_t launch_vf(const Grid &g, const double *phi, double *vf, hipStream_t s);
 hipError_t launch_sign_inf(const Grid &g, const double *rho, double rho_t, double *phi,

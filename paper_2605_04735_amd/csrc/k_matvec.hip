@@ -317,59 +317,67 @@ __global__ __launch_bounds__(MV_THREADS) void k_matvec(const MvArgs<T> a) {
     a.part[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = s;
 }
 
-// Partial sums cross blocks (possibly on different XCDs, each with its own
-// L2) through agent-scope atomic stores and loads, which go to the coherence
-// point without writing back or invalidating whole caches.
-__device__ __forceinline__ void publish(double *p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double collect(const double *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Fixed-order sum of n published values by one block (strided per thread,
-// then a fixed tree): the same result whichever block runs it.
+// Fixed-order sum of n block partials written by the previous kernel, done
+// by every block that needs it: the loads are independent batches per thread
+// (latency overlapped), followed by a fixed shuffle/wave tree, so each block
+// gets the bit-identical value and no block waits for another.
 __device__ double block_fixed_sum(const double *v, int n, double *sh) {
+  constexpr int K = 4;
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) s += collect(v + i);
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
+  for (int base = 0; base < n; base += K * (int)blockDim.x) {
+    double t[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = base + k * (int)blockDim.x + (int)threadIdx.x;
+      t[k] = (i < n) ? v[i] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) s += t[k];
   }
-  const double r = sh[0];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   __syncthreads();
+  if (lane == 0) sh[w] = s;
+  __syncthreads();
+  double r = 0.0;
+  const int nw = (blockDim.x + 63) >> 6;
+  for (int i = 0; i < nw; ++i) r += sh[i];
   return r;
 }
 
-// Thread 0 has published this block's partials; returns true in every thread
-// of the block that arrives last for its design (which then owns the second
-// reduction stage).  The wait makes the published stores complete before the
-// arrival is counted.
-__device__ bool arrive_last(unsigned *cnt, int nb, int *flag_sh) {
-  if (threadIdx.x == 0) {
-    __builtin_amdgcn_s_waitcnt(0);
-    const unsigned prev = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    *flag_sh = (prev == (unsigned)nb - 1u) ? 1 : 0;
-  }
-  __syncthreads();
-  return *flag_sh != 0;
-}
-
 // Batched inner-CG product over a table of designs: blockmap[b] = (design,
-// local block).  Per design: p = z + beta p_old, q = K p, and the last block
-// to finish turns p^T q into the step length alpha (or flags a breakdown).
+// local block).  Every block first completes the reduction of the previous
+// update (r^T z and ||r||^2, partial set parity^1): converged designs stop
+// here; otherwise beta = (r^T z)_new / (r^T z)_old, p = z + beta p_old,
+// q = K p, and the block's p^T q partial is written for the update kernel.
 template <typename T>
 __global__ __launch_bounds__(MV_THREADS) void k_cg_matvec(const CgDesc<T> *descs,
                                                           const int2 *blockmap, int parity) {
   __shared__ T pl[2][3][TP * TP];
   __shared__ T ex[6][MV_THREADS];
-  __shared__ double red[MV_THREADS];
-  __shared__ int last_sh;
+  __shared__ double red[MV_THREADS / 64];
   const int2 bm = blockmap[blockIdx.x];
   const CgDesc<T> &d = descs[bm.x];
   if (d.flags[F_DONE]) return;
+  const int lb = bm.y;
+  const double rz = block_fixed_sum(d.cgp + CGP_RZ + (parity ^ 1) * MAXB, d.nb_up, red);
+  const double rr = block_fixed_sum(d.cgp + CGP_RR + (parity ^ 1) * MAXB, d.nb_up, red);
+  const double rz_old = d.scal[S_RZ0 + parity];
+  const int iters = d.flags[F_ITERS];
+  const bool bad = !isfinite(rz) || !isfinite(rr);
+  if (bad || rr <= d.scal[S_TOL2] || iters >= d.flags[F_CAP]) {
+    if (lb == 0 && threadIdx.x == 0) {
+      if (bad) d.flags[F_STATUS] = 2;
+      d.scal[S_RR] = rr;
+      d.flags[F_DONE] = 1;
+    }
+    return;
+  }
+  if (lb == 0 && threadIdx.x == 0) {
+    d.scal[S_RZ0 + (parity ^ 1)] = rz;
+    d.scal[S_RR] = rr;
+  }
   MvArgs<T> a;
   a.nelx = d.nelx;
   a.nely = d.nely;
@@ -382,39 +390,34 @@ __global__ __launch_bounds__(MV_THREADS) void k_cg_matvec(const CgDesc<T> *descs
   a.out = d.q;
   a.mask = d.mask;
   a.k = d.k;
-  const int lb = bm.y;
   const int bx = lb % d.tx, by = (lb / d.tx) % d.ty, bz = lb / (d.tx * d.ty);
-  const T beta = (T)d.scal[S_BETA];
+  const T beta = (T)(rz / rz_old);
   const double s = matvec_block<T, MV_CG>(a, bx, by, bz, beta, pl, ex, red);
-  if (threadIdx.x == 0) publish(d.part + lb, s);
-  if (!arrive_last(d.cnt, d.nb_mv, &last_sh)) return;
-  const double pq = block_fixed_sum(d.part, d.nb_mv, red);
-  if (threadIdx.x == 0) {
-    d.cnt[0] = 0u;
-    d.scal[S_PQ] = pq;
-    if (!isfinite(pq)) {
-      d.flags[F_STATUS] = 2;
-      d.flags[F_DONE] = 1;
-    } else if (!(pq > 0.0)) {
-      d.flags[F_STATUS] = 1;
-      d.flags[F_DONE] = 1;
-    } else {
-      d.scal[S_ALPHA] = d.scal[S_RZ] / pq;
-    }
-  }
+  if (threadIdx.x == 0) d.cgp[CGP_PQ + lb] = s;
 }
 
-// Batched CG vector update: x += alpha p; r -= alpha q; z = D r (fixed DOFs
-// 0); the last block of each design forms beta and tests convergence.
+// Batched CG vector update: every block completes the p^T q reduction of the
+// product, alpha = (r^T z) / (p^T q), then x += alpha p; r -= alpha q;
+// z = D r (fixed DOFs 0) and the block's r^T z and ||r||^2 partials go to set
+// `parity` for the next product.
 template <typename T>
 __global__ __launch_bounds__(256) void k_cg_update(const CgDesc<T> *descs, const int2 *blockmap,
                                                    int parity) {
-  __shared__ double red[256];
-  __shared__ int last_sh;
+  __shared__ double red[4];
   const int2 bm = blockmap[blockIdx.x];
   const CgDesc<T> &d = descs[bm.x];
   if (d.flags[F_DONE]) return;
-  const T alpha = (T)d.scal[S_ALPHA];
+  const double pq = block_fixed_sum(d.cgp + CGP_PQ, d.nb_mv, red);
+  if (!(pq > 0.0) || !isfinite(pq)) {
+    if (bm.y == 0 && threadIdx.x == 0) {
+      d.scal[S_PQ] = pq;
+      d.flags[F_STATUS] = isfinite(pq) ? 1 : 2;
+      d.flags[F_DONE] = 1;
+    }
+    return;
+  }
+  const double rz = d.scal[S_RZ0 + (parity ^ 1)];
+  const T alpha = (T)(rz / pq);
   const T *__restrict__ p = d.p[parity ^ 1];
   T *__restrict__ x = d.x;
   T *__restrict__ r = d.r;
@@ -424,7 +427,7 @@ __global__ __launch_bounds__(256) void k_cg_update(const CgDesc<T> *descs, const
   const uint8_t *__restrict__ mask = d.mask;
   const size_t nn = (size_t)d.nn;
   const size_t stride = (size_t)d.nb_up * 256;
-  double rz = 0.0, rr = 0.0;
+  double rzs = 0.0, rrs = 0.0;
   for (size_t n = (size_t)bm.y * 256 + threadIdx.x; n < nn; n += stride) {
     const unsigned m = mask[n];
     const T di = dinv[n];
@@ -444,31 +447,20 @@ __global__ __launch_bounds__(256) void k_cg_update(const CgDesc<T> *descs, const
       x[3 * n + c] = xn;
       r[3 * n + c] = rn;
       z[3 * n + c] = zn;
-      rz += (double)rn * (double)zn;
-      rr += (double)rn * (double)rn;
+      rzs += (double)rn * (double)zn;
+      rrs += (double)rn * (double)rn;
     }
   }
-  const double s1 = block_sum_d(rz, red);
+  const double s1 = block_sum_d(rzs, red);
   __syncthreads();
-  const double s2 = block_sum_d(rr, red);
+  const double s2 = block_sum_d(rrs, red);
   if (threadIdx.x == 0) {
-    publish(d.part + bm.y, s1);
-    publish(d.part + MAXB + bm.y, s2);
-  }
-  if (!arrive_last(d.cnt + 1, d.nb_up, &last_sh)) return;
-  const double rzn = block_fixed_sum(d.part, d.nb_up, red);
-  const double rrn = block_fixed_sum(d.part + MAXB, d.nb_up, red);
-  if (threadIdx.x == 0) {
-    d.cnt[1] = 0u;
-    d.flags[F_ITERS] += 1;
-    if (!isfinite(rzn) || !isfinite(rrn)) {
-      d.flags[F_STATUS] = 2;
-      d.flags[F_DONE] = 1;
-    } else {
-      d.scal[S_BETA] = rzn / d.scal[S_RZ];
-      d.scal[S_RZ] = rzn;
-      d.scal[S_RR] = rrn;
-      if (rrn <= d.scal[S_TOL2] || d.flags[F_ITERS] >= d.flags[F_CAP]) d.flags[F_DONE] = 1;
+    d.cgp[CGP_RZ + parity * MAXB + bm.y] = s1;
+    d.cgp[CGP_RR + parity * MAXB + bm.y] = s2;
+    if (bm.y == 0) {
+      d.scal[S_PQ] = pq;
+      d.scal[S_ALPHA] = rz / pq;
+      d.flags[F_ITERS] = d.flags[F_ITERS] + 1;
     }
   }
 }
@@ -483,8 +475,8 @@ int matvec_kz(const Grid &g) {
       return v;
     }
   }
-  // about 4 blocks per CU while keeping the z recompute (kz + 1)/kz small
-  int chunks = (1024 + tiles - 1) / tiles;
+  // about 8 blocks per CU while keeping the z recompute (kz + 1)/kz small
+  int chunks = (2048 + tiles - 1) / tiles;
   int kz = (NZ + chunks - 1) / chunks;
   if (kz < 2) kz = 2;
   if (kz > 32) kz = 32;

@@ -11,13 +11,15 @@
 //  scan       exclusive prefix sum of the counts (triangle offsets)
 //  mt_emit    triangle vertices, each voxel's triangles stored contiguously
 //  udist      per node, the exact minimum distance to the triangles (Eq. 29):
-//             voxels are visited in rings of growing Chebyshev gap r from the
-//             node; every triangle lies in the voxel that produced it and no
-//             point of ring r is closer than r h, so the search stops after
-//             ring r once the best distance is <= (r + 1) h
+//             every triangle lies in the voxel that produced it, so voxels
+//             (and 4^3 coarse cells of them) can be skipped whenever their
+//             box is farther than the best distance found so far; the search
+//             grows outwards and stops when nothing unvisited can be closer
 //  sign       Eq. 30: phi = -d if rho >= rho_t else +d
 //  vf         per voxel, the volume fraction of {phi_lin < 0} over the same
 //             six tets, in closed form from the edge crossing fractions
+#include <algorithm>
+
 #include "common.h"
 
 namespace topo {
@@ -302,47 +304,108 @@ __device__ double tri_dist2(const double *p, const double *a, const double *b, c
   return dot3(q, q);
 }
 
+constexpr int CB = 4;  // coarse cell edge (voxels) of the occupancy grid
+
+// occupancy of the CB^3 coarse cells: 1 when any voxel in it has triangles
+__global__ void k_occ(int nelx, int nely, int nelz, const int *__restrict__ count,
+                      int *__restrict__ occ) {
+  const int cx = (nelx + CB - 1) / CB, cy = (nely + CB - 1) / CB, cz = (nelz + CB - 1) / CB;
+  const size_t nc = (size_t)cx * cy * cz;
+  for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < nc;
+       c += (size_t)gridDim.x * blockDim.x) {
+    const int ci = (int)(c % cx), cj = (int)((c / cx) % cy), ck = (int)(c / ((size_t)cx * cy));
+    int any = 0;
+    for (int k = ck * CB; k < min((ck + 1) * CB, nelz) && !any; ++k)
+      for (int j = cj * CB; j < min((cj + 1) * CB, nely) && !any; ++j)
+        for (int i = ci * CB; i < min((ci + 1) * CB, nelx); ++i)
+          if (count[(size_t)i + (size_t)nelx * ((size_t)j + (size_t)nely * k)]) {
+            any = 1;
+            break;
+          }
+    occ[c] = any;
+  }
+}
+
+__device__ __forceinline__ int axis_gap(int lo, int hi, int i) {  // voxels [lo, hi) vs node i
+  return max(0, max(lo - i, i - hi));
+}
+
+__device__ __forceinline__ void scan_voxel(int vi, int vj, int vk, int nelx, int nely,
+                                           const int *__restrict__ count,
+                                           const int *__restrict__ offset,
+                                           const double *__restrict__ tri, const double *p,
+                                           double &best) {
+  const size_t e = (size_t)vi + (size_t)nelx * ((size_t)vj + (size_t)nely * vk);
+  const int c = count[e];
+  if (c == 0) return;
+  const double *t = tri + 9 * (size_t)offset[e];
+  for (int q = 0; q < c; ++q, t += 9) best = fmin(best, tri_dist2(p, t, t + 3, t + 6));
+}
+
+// Exact Eq. 29 distance per node.  Phase 1 scans the voxels at Chebyshev gap
+// 0 and 1 from the node (no point of a voxel at gap g is closer than g h, so
+// a best distance <= 2 h is final).  Phase 2 scans rings of coarse cells
+// around the node's cell, skipping empty cells and cells or voxels whose box
+// is already farther than the best distance; after coarse ring R every
+// unvisited cell is farther than R CB h, which gives the stop rule.
 __global__ void k_udist(int nelx, int nely, int nelz, double h, const int *__restrict__ count,
                         const int *__restrict__ offset, const double *__restrict__ tri,
-                        const double *__restrict__ rho, double rho_t, double *__restrict__ phi) {
+                        const int *__restrict__ occ, const double *__restrict__ rho, double rho_t,
+                        double *__restrict__ phi) {
   const int NX = nelx + 1, NY = nely + 1, NZ = nelz + 1;
   const size_t nn = (size_t)NX * NY * NZ;
-  const int rmax = max(nelx, max(nely, nelz));
+  const int cx = (nelx + CB - 1) / CB, cy = (nely + CB - 1) / CB, cz = (nelz + CB - 1) / CB;
+  const int Rmax = max(cx, max(cy, cz));
   for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < nn;
        n += (size_t)gridDim.x * blockDim.x) {
     const int i = (int)(n % NX), j = (int)((n / NX) % NY), k = (int)(n / ((size_t)NX * NY));
     const double p[3] = {(double)i * h, (double)j * h, (double)k * h};
     double best = INFINITY;
-    for (int r = 0; r <= rmax; ++r) {
-      // voxels with per-axis gap <= r and = r on some axis; along one axis the
-      // voxels with gap g are i + g and i - 1 - g
-      for (int gz = -r - 1; gz <= r; ++gz) {
-        const int vk = k + gz;
-        if (vk < 0 || vk >= nelz) continue;
-        const int az = (gz >= 0) ? gz : -gz - 1;
-        for (int gy = -r - 1; gy <= r; ++gy) {
-          const int vj = j + gy;
-          if (vj < 0 || vj >= nely) continue;
-          const int ay = (gy >= 0) ? gy : -gy - 1;
-          const bool edge_yz = (az == r) || (ay == r);
-          for (int gx = -r - 1; gx <= r; ++gx) {
-            const int ax = (gx >= 0) ? gx : -gx - 1;
-            if (!edge_yz && ax != r) {  // interior of the ring: jump to the far side
-              gx = r - 1;
-              continue;
+    // phase 1: voxels i-2 .. i+1 (gaps 0 and 1) per axis
+    for (int vk = max(k - 2, 0); vk <= min(k + 1, nelz - 1); ++vk)
+      for (int vj = max(j - 2, 0); vj <= min(j + 1, nely - 1); ++vj)
+        for (int vi = max(i - 2, 0); vi <= min(i + 1, nelx - 1); ++vi)
+          scan_voxel(vi, vj, vk, nelx, nely, count, offset, tri, p, best);
+    if (!(best <= 4.0 * h * h)) {
+      const int c0i = min(i / CB, cx - 1), c0j = min(j / CB, cy - 1), c0k = min(k / CB, cz - 1);
+      for (int R = 0; R <= Rmax; ++R) {
+        for (int ck = c0k - R; ck <= c0k + R; ++ck) {
+          if (ck < 0 || ck >= cz) continue;
+          const bool zs = (ck == c0k - R) || (ck == c0k + R);
+          const int gz = axis_gap(ck * CB, min((ck + 1) * CB, nelz), k);
+          for (int cj = c0j - R; cj <= c0j + R; ++cj) {
+            if (cj < 0 || cj >= cy) continue;
+            const bool ys = zs || (cj == c0j - R) || (cj == c0j + R);
+            const int gy = axis_gap(cj * CB, min((cj + 1) * CB, nely), j);
+            for (int ci = c0i - R; ci <= c0i + R; ++ci) {
+              if (!ys && ci != c0i - R && ci != c0i + R) {  // ring interior: far side only
+                ci = c0i + R - 1;
+                continue;
+              }
+              if (ci < 0 || ci >= cx) continue;
+              const int gx = axis_gap(ci * CB, min((ci + 1) * CB, nelx), i);
+              const double cd = ((double)gx * gx + (double)gy * gy + (double)gz * gz) * h * h;
+              if (cd >= best) continue;
+              if (!occ[(size_t)ci + (size_t)cx * ((size_t)cj + (size_t)cy * ck)]) continue;
+              for (int vk = ck * CB; vk < min((ck + 1) * CB, nelz); ++vk) {
+                const int vz = axis_gap(vk, vk + 1, k);
+                for (int vj = cj * CB; vj < min((cj + 1) * CB, nely); ++vj) {
+                  const int vy = axis_gap(vj, vj + 1, j);
+                  for (int vi = ci * CB; vi < min((ci + 1) * CB, nelx); ++vi) {
+                    const int vx = axis_gap(vi, vi + 1, i);
+                    if (vx <= 1 && vy <= 1 && vz <= 1) continue;  // done in phase 1
+                    const double vd = ((double)vx * vx + (double)vy * vy + (double)vz * vz) * h * h;
+                    if (vd >= best) continue;
+                    scan_voxel(vi, vj, vk, nelx, nely, count, offset, tri, p, best);
+                  }
+                }
+              }
             }
-            const int vi = i + gx;
-            if (vi < 0 || vi >= nelx) continue;
-            const size_t e = (size_t)vi + (size_t)nelx * ((size_t)vj + (size_t)nely * vk);
-            const int c = count[e];
-            if (c == 0) continue;
-            const double *t = tri + 9 * (size_t)offset[e];
-            for (int q = 0; q < c; ++q, t += 9) best = fmin(best, tri_dist2(p, t, t + 3, t + 6));
           }
         }
+        const double lim = (double)R * CB * h;
+        if (best <= lim * lim) break;
       }
-      const double lim = (double)(r + 1) * h;
-      if (best <= lim * lim) break;
     }
     const double d = sqrt(best);
     phi[n] = (rho[n] >= rho_t) ? -d : d;
@@ -350,12 +413,16 @@ __global__ void k_udist(int nelx, int nely, int nelz, double h, const int *__res
 }
 
 hipError_t launch_udist(const Grid &g, double h, const int *count, const int *offset,
-                        const double *tri, const double *rho, double rho_t, double *phi,
+                        const double *tri, int *occ, const double *rho, double rho_t, double *phi,
                         hipStream_t s) {
+  const int cx = (g.nelx + CB - 1) / CB, cy = (g.nely + CB - 1) / CB, cz = (g.nelz + CB - 1) / CB;
+  const size_t nc = (size_t)cx * cy * cz;
+  hipLaunchKernelGGL(k_occ, dim3((unsigned)std::min<size_t>((nc + 255) / 256, 8192)), dim3(256), 0,
+                     s, g.nelx, g.nely, g.nelz, count, occ);
   int blocks = (int)((g.nn + 127) / 128);
   if (blocks > 65535) blocks = 65535;
   hipLaunchKernelGGL(k_udist, dim3(blocks), dim3(128), 0, s, g.nelx, g.nely, g.nelz, h, count,
-                     offset, tri, rho, rho_t, phi);
+                     offset, tri, occ, rho, rho_t, phi);
   return hipGetLastError();
 }
 

@@ -161,8 +161,14 @@ hipError_t launch_mask_custom(const Grid &g, const uint8_t *dof_mask, uint8_t *m
 // ---------------------------------------------------------------- CG streams
 // blocks of the batched update kernel for one design (grid-stride beyond)
 int update_blocks(size_t nn) {
-  size_t b = (nn + 255) / 256;
-  if (b > 1024) b = 1024;
+  size_t cap = 512;
+  if (const char *e = getenv("TOPO_UPB")) cap = (size_t)atoi(e);
+  if (cap < 1) cap = 1;
+  if (cap > (size_t)MAXB) cap = MAXB;
+  size_t b = (nn + 1023) / 1024;
+  if (b < 64) b = 64;
+  if (b > cap) b = cap;
+  if (b > (nn + 255) / 256) b = (nn + 255) / 256;
   if (b < 1) b = 1;
   return (int)b;
 }
@@ -174,8 +180,6 @@ int vec_blocks(size_t nn) {
   return (int)b;
 }
 
-// b (float64) scaled by scal[S_SCALE] -> r; x = 0; z = D r; p = 0.
-// Partial sums: part[blk] = r^T z, part[MAXB + blk] = ||r||^2.
 template <typename T>
 __global__ __launch_bounds__(256) void k_cg_init(size_t nn, const double *__restrict__ b,
                                                  const double *__restrict__ scal, T *__restrict__ x,
@@ -183,7 +187,7 @@ __global__ __launch_bounds__(256) void k_cg_init(size_t nn, const double *__rest
                                                  T *__restrict__ p, T *__restrict__ p2,
                                                  const T *__restrict__ dinv,
                                                  const uint8_t *__restrict__ mask,
-                                                 double *__restrict__ part) {
+                                                 double *__restrict__ rzp, double *__restrict__ rrp) {
   __shared__ double sh[4];
   const double sc = scal[S_SCALE];
   double rz = 0.0, rr = 0.0;
@@ -208,19 +212,17 @@ __global__ __launch_bounds__(256) void k_cg_init(size_t nn, const double *__rest
   const double s1 = block_sum(rz, sh);
   const double s2 = block_sum(rr, sh);
   if (threadIdx.x == 0) {
-    part[blockIdx.x] = s1;
-    part[MAXB + blockIdx.x] = s2;
+    rzp[blockIdx.x] = s1;
+    rrp[blockIdx.x] = s2;
   }
 }
 
 template <typename T>
 hipError_t launch_cg_init(const Grid &g, const double *b, const double *scal, T *x, T *r, T *z,
-                          T *pA, T *pB, const T *dinv, const uint8_t *mask, double *part, int *nb,
-                          hipStream_t s) {
-  const int blocks = vec_blocks(g.nn);
-  *nb = blocks;
-  hipLaunchKernelGGL(k_cg_init<T>, dim3(blocks), dim3(256), 0, s, g.nn, b, scal, x, r, z, pA, pB,
-                     dinv, mask, part);
+                          T *pA, T *pB, const T *dinv, const uint8_t *mask, double *cgp, int slot,
+                          int nb_up, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_init<T>, dim3(nb_up), dim3(256), 0, s, g.nn, b, scal, x, r, z, pA, pB,
+                     dinv, mask, cgp + CGP_RZ + slot * MAXB, cgp + CGP_RR + slot * MAXB);
   return hipGetLastError();
 }
 
@@ -261,13 +263,15 @@ __device__ double fixed_order_sum(const double *v, int nb) {
   return r;
 }
 
-__global__ __launch_bounds__(RED_THREADS) void k_finish_init(const double *part, int nb,
+__global__ __launch_bounds__(RED_THREADS) void k_finish_init(const double *cgp, int nb, int slot,
                                                              double tol2_rel, int cap,
                                                              double *scal, int *flags) {
-  const double rz = fixed_order_sum(part, nb);
-  const double rr = fixed_order_sum(part + MAXB, nb);
+  const double rz = fixed_order_sum(cgp + CGP_RZ + slot * MAXB, nb);
+  const double rr = fixed_order_sum(cgp + CGP_RR + slot * MAXB, nb);
   if (threadIdx.x == 0) {
     scal[S_RZ] = rz;
+    scal[S_RZ0] = rz;   // both generations: the first product's beta multiplies p = 0
+    scal[S_RZ1] = rz;
     scal[S_RR] = rr;
     scal[S_BETA] = 0.0;
     scal[S_TOL2] = tol2_rel * rr;
@@ -289,10 +293,10 @@ __global__ __launch_bounds__(RED_THREADS) void k_finish_sum(const double *part, 
   if (threadIdx.x == 0) scal[idx] = s;
 }
 
-hipError_t launch_finish_init(const double *part, int nb, double tol2_rel, int cap, double *scal,
-                              int *flags, hipStream_t s) {
-  hipLaunchKernelGGL(k_finish_init, dim3(1), dim3(RED_THREADS), 0, s, part, nb, tol2_rel, cap,
-                     scal, flags);
+hipError_t launch_finish_init(const double *cgp, int nb_up, int slot, double tol2_rel, int cap,
+                              double *scal, int *flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish_init, dim3(1), dim3(RED_THREADS), 0, s, cgp, nb_up, slot, tol2_rel,
+                     cap, scal, flags);
   return hipGetLastError();
 }
 hipError_t launch_finish_sum(const double *part, int nb, int comp, double *scal, int idx,
@@ -357,10 +361,10 @@ hipError_t launch_set_scale(double *scal, hipStream_t s) {
 
 template hipError_t launch_cg_init<double>(const Grid &, const double *, const double *, double *,
                                            double *, double *, double *, double *, const double *,
-                                           const uint8_t *, double *, int *, hipStream_t);
+                                           const uint8_t *, double *, int, int, hipStream_t);
 template hipError_t launch_cg_init<float>(const Grid &, const double *, const double *, float *,
                                           float *, float *, float *, float *, const float *,
-                                          const uint8_t *, double *, int *, hipStream_t);
+                                          const uint8_t *, double *, int, int, hipStream_t);
 template hipError_t launch_axpy_out<double>(const Grid &, double *, const double *,
                                             const double *, hipStream_t);
 template hipError_t launch_axpy_out<float>(const Grid &, double *, const float *, const double *,

@@ -195,11 +195,12 @@ def _sdf_case(kind, dims, seed):
                                    solid_fraction=0.4)
     c = grid.element_centroids(nelx, nely, nelz, 1.0)
     r = np.linalg.norm(c - np.array([nelx / 2 + 0.1, nely / 2 - 0.2, nelz / 2 + 0.15]), axis=1)
-    return 1.0 / (1.0 + np.exp(r - 0.35 * min(dims)))
+    radius = 0.35 * min(dims) if kind == "sphere" else 4.3      # "ball": far-field nodes
+    return 1.0 / (1.0 + np.exp(r - radius))
 
 
 @pytest.mark.parametrize("kind,dims,seed", [("field", (17, 13, 11), 1), ("field", (24, 8, 6), 2),
-                                            ("sphere", (14, 14, 14), 0)])
+                                            ("sphere", (14, 14, 14), 0), ("ball", (40, 36, 33), 0)])
 def test_density_to_sdf_vs_bruteforce(kind, dims, seed):
     nelx, nely, nelz = dims
     print("sdf", kind, dims, flush=True)
