@@ -423,7 +423,7 @@ to_status to_create(const to_problem *prob, void *d_workspace, size_t bytes, voi
   {
     // single-design tables of the batched CG kernels
     std::vector<int2> bm(c->nb_mv), bu(c->nb_up);
-    for (int b = 0; b < c->nb_mv; ++b) bm[b] = make_int2(0, b);
+    for (int b = 0; b < c->nb_mv; ++b) bm[b] = make_int2(0, xcd_local(b, c->nb_mv));
     for (int b = 0; b < c->nb_up; ++b) bu[b] = make_int2(0, b);
     bool ok = hipMemcpy(c->bmap_mv, bm.data(), bm.size() * sizeof(int2), hipMemcpyHostToDevice) ==
                   hipSuccess &&

@@ -98,6 +98,17 @@ constexpr int CGP_RZ = MAXB;          // + P * MAXB
 constexpr int CGP_RR = 3 * MAXB;      // + P * MAXB
 constexpr int CGP_SIZE = 5 * MAXB;
 
+// Workgroups are dispatched to the 8 XCDs (each with its own L2) round-robin
+// by block index.  xcd_local maps block b of nb to a local tile index such
+// that every XCD gets one contiguous range of tiles: neighbouring tiles,
+// which share halo node planes and elements, then share an L2.
+constexpr int NXCD = 8;
+__host__ __device__ inline int xcd_local(int b, int nb) {
+  const int x = b % NXCD, slot = b / NXCD;
+  const int base = nb / NXCD, extra = nb % NXCD;
+  return x * base + (x < extra ? x : extra) + slot;
+}
+
 struct Grid {
   int nelx, nely, nelz;
   size_t nel, nn, ndof;

@@ -308,13 +308,14 @@ __device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int b
 }
 
 template <typename T, int MODE>
-__global__ __launch_bounds__(MV_THREADS) void k_matvec(const MvArgs<T> a) {
+__global__ __launch_bounds__(MV_THREADS) void k_matvec(const MvArgs<T> a, int tx, int ty) {
   __shared__ T pl[2][3][TP * TP];
   __shared__ T ex[6][MV_THREADS];
   __shared__ double red[MV_THREADS / 64];
-  const double s = matvec_block<T, MODE>(a, blockIdx.x, blockIdx.y, blockIdx.z, T(0), pl, ex, red);
-  if (MODE != MV_APPLY && threadIdx.x == 0)
-    a.part[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = s;
+  const int lb = xcd_local(blockIdx.x, gridDim.x);
+  const double s = matvec_block<T, MODE>(a, lb % tx, (lb / tx) % ty, lb / (tx * ty), T(0), pl, ex,
+                                         red);
+  if (MODE != MV_APPLY && threadIdx.x == 0) a.part[lb] = s;
 }
 
 // Fixed-order sum of n block partials written by the previous kernel, done
@@ -492,11 +493,11 @@ int matvec_blocks(const Grid &g, int kz) {
 template <typename T, int MODE>
 hipError_t launch_matvec(const MvArgs<T> &a, int *nblocks, hipStream_t s) {
   const int NX = a.nelx + 1, NY = a.nely + 1, NZ = a.nelz + 1;
-  dim3 grid((NX + TN - 1) / TN, (NY + TN - 1) / TN, (NZ + a.kz - 1) / a.kz);
-  const int nb = grid.x * grid.y * grid.z;
+  const int tx = (NX + TN - 1) / TN, ty = (NY + TN - 1) / TN, tz = (NZ + a.kz - 1) / a.kz;
+  const int nb = tx * ty * tz;
   if (nblocks) *nblocks = nb;
   if (MODE != MV_APPLY && nb > MAXB) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((k_matvec<T, MODE>), grid, dim3(MV_THREADS), 0, s, a);
+  hipLaunchKernelGGL((k_matvec<T, MODE>), dim3(nb), dim3(MV_THREADS), 0, s, a, tx, ty);
   return hipGetLastError();
 }
 
