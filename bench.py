@@ -97,6 +97,26 @@ def probe(kind):
     log("product probe done")
 
 
+def measured_traffic(summary, section_kernel):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, or
+    None when the kernel source changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(os.path.join(ROOT, "profiles", summary)).read()
+    except OSError:
+        return None
+    src = os.path.join(ROOT, "paper_2605_04735_amd", "csrc", "k_matvec.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for sec in text.split("## ")[1:]:
+        if ("kernel: " + section_kernel) not in sec:
+            continue
+        fields = dict(l.split(": ", 1) for l in sec.splitlines() if ": " in l)
+        if sha not in fields.get("source", ""):
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    return None
+
+
 def rel2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
@@ -237,9 +257,11 @@ def main():
             cl = A.to_create(pl)
             us, g = product_rate(cl, pl, f32, reps=50)
             byt = (24 if f32 else 48) * pl.nn + (4 if f32 else 8) * pl.nel
+            tr = measured_traffic("pmc_product_256x128x128.txt",
+                                  "void topo::k_matvec<%s, 0>" % ("float" if f32 else "double"))
             products["256x128x128_%s" % ("f32" if f32 else "f64")] = {
                 "us": us, "gdofs": g, "algorithmic_GBs": byt / (us * 1e-6) / 1e9,
-                "frac_hbm": byt / (us * 1e-6) / 1e9 / HBM_PEAK_GBS}
+                "frac_hbm": byt / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, "traffic_bytes": tr}
             cl.close()
             del cl
             torch.cuda.empty_cache()
@@ -253,8 +275,10 @@ def main():
     mv_us = 1e3 * res_m["mv_ms"] / max(res_m["mv_n"], 1)
     bytes_launch = 48 * nn + 4 * nel
     achieved = bytes_launch / (mv_us * 1e-6) / 1e9
+    traffic = measured_traffic("pmc_cg_matvec_f32_cantilever_96x48x48.txt",
+                               "void topo::k_cg_matvec<float>")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_matvec<float, MV_CG>", "avg_us": round(mv_us, 3),
                 "bytes_per_launch": bytes_launch}
 
