@@ -155,6 +155,37 @@ to_status to_matvec(to_ctx *ctx, const double *d_x, const double *d_u, double *d
  * arithmetic (the inner-CG product of TO_PREC_FP32_REFINE). */
 to_status to_matvec_f32(to_ctx *ctx, const double *d_x, const float *d_u, float *d_y);
 
+/* Serving (continuous batching).  A server owns one device allocation of
+ * hbm_budget_bytes (an arena for per-request state), a private HIP stream of
+ * default priority and a worker thread.  Requests are compliance +
+ * sensitivity solves (TO_PREC_FP32_REFINE, built-in BCs, any grid size) that
+ * are admitted in arrival order as soon as a slot (max_slots) and arena space
+ * for the request's footprint are free; all admitted designs that are in an
+ * inner CG solve advance together, one batched product launch and one
+ * batched update launch per iteration.  A request's results do not depend on
+ * which other requests share the batch.
+ *   to_server_submit: h_x [nel] is copied; h_dc_out [nel] (may be NULL) must
+ *     stay valid until the request is returned by to_server_poll.  Returns
+ *     TO_E_OOM if the footprint can never fit the budget, TO_E_BUSY if the
+ *     queue is full, TO_E_INVALID for other precisions or CUSTOM BCs.
+ *   to_server_poll: non-blocking; returns up to cap finished requests (tag,
+ *     compliance F^T u, status, latency from submit to completion in ms).
+ *   to_server_wait_idle: blocks until nothing is queued or live, or the
+ *     timeout passes (then TO_E_BUSY).
+ *   Thread-safe: submit, poll, wait and stats may be called from any thread. */
+typedef struct to_server to_server;
+to_status to_server_create(size_t hbm_budget_bytes, int32_t max_slots, void *stream_unused,
+                           to_server **out);
+to_status to_server_submit(to_server *srv, const to_problem *prob, const double *h_x,
+                           double *h_dc_out, uint64_t tag);
+to_status to_server_poll(to_server *srv, uint64_t *tags, double *c, int32_t *status,
+                         double *latency_ms, int32_t cap, int32_t *n);
+to_status to_server_wait_idle(to_server *srv, double timeout_ms);
+to_status to_server_stats(to_server *srv, int32_t *live, int32_t *queued, int64_t *ticks,
+                          size_t *free_bytes);
+const char *to_server_last_error(const to_server *srv);
+void to_server_destroy(to_server *srv); /* NULL-safe; waits for the worker to stop */
+
 /* Diagnostics.
  * to_last_energy_sum: sum_e E_e u_e^T k0 u_e of the last
  *   to_compliance_sensitivity call (equals F^T u at an exact solution).

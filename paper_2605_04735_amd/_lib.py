@@ -57,6 +57,17 @@ _SIGS = {
     "to_last_triangle_count": (ctypes.c_int32, [_P]),
     "to_profile": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(_D),
                                   ctypes.POINTER(ctypes.c_int64)]),
+    "to_server_create": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int32, _P, ctypes.POINTER(_P)]),
+    "to_server_submit": (ctypes.c_int, [_P, ctypes.POINTER(ToProblem), _P, _P, ctypes.c_uint64]),
+    "to_server_poll": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int32,
+                                      ctypes.POINTER(ctypes.c_int32)]),
+    "to_server_wait_idle": (ctypes.c_int, [_P, _D]),
+    "to_server_stats": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_size_t)]),
+    "to_server_last_error": (ctypes.c_char_p, [_P]),
+    "to_server_destroy": (None, [_P]),
 }
 
 

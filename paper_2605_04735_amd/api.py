@@ -240,3 +240,78 @@ def to_matvec_f32(ctx: Context, x, u, y=None):
                                  _dev(u, torch.float32, p.ndof, "u"),
                                  _dev(y, torch.float32, p.ndof, "y")), ctx.handle)
     return y
+
+
+class Server:
+    """Continuous-batching compliance + sensitivity server (to_server_*).
+
+    submit() copies the densities; the sensitivity lands in a host array kept
+    here until the request is returned by poll()."""
+
+    def __init__(self, hbm_budget_bytes, max_slots=64):
+        h = ctypes.c_void_p(0)
+        st = L.lib().to_server_create(ctypes.c_size_t(int(hbm_budget_bytes)), int(max_slots), None,
+                                      ctypes.byref(h))
+        if st != L.TO_OK:
+            raise TopoError(st, L.lib().to_server_last_error(None).decode())
+        self.handle = h
+        self._pending = {}
+
+    def _err(self):
+        m = L.lib().to_server_last_error(self.handle)
+        return m.decode() if m else ""
+
+    def submit(self, prob: Problem, x, tag, want_dc=True):
+        x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+        if x.size != prob.nel:
+            raise ValueError("x must have nel entries")
+        dc = np.empty(prob.nel, dtype=np.float64) if want_dc else None
+        cp = prob.to_c()
+        st = L.lib().to_server_submit(self.handle, ctypes.byref(cp), ctypes.c_void_p(x.ctypes.data),
+                                      None if dc is None else ctypes.c_void_p(dc.ctypes.data),
+                                      ctypes.c_uint64(int(tag)))
+        if st != L.TO_OK:
+            raise TopoError(st, self._err())
+        self._pending[int(tag)] = dc
+        return st
+
+    def poll(self, cap=1024):
+        """List of dicts {tag, c, status, latency_ms, dc} for finished requests."""
+        tags = np.zeros(cap, dtype=np.uint64)
+        c = np.zeros(cap)
+        status = np.zeros(cap, dtype=np.int32)
+        lat = np.zeros(cap)
+        n = ctypes.c_int32(0)
+        st = L.lib().to_server_poll(self.handle, ctypes.c_void_p(tags.ctypes.data),
+                                    ctypes.c_void_p(c.ctypes.data), ctypes.c_void_p(status.ctypes.data),
+                                    ctypes.c_void_p(lat.ctypes.data), cap, ctypes.byref(n))
+        out = []
+        for i in range(n.value):
+            t = int(tags[i])
+            out.append({"tag": t, "c": float(c[i]), "status": int(status[i]),
+                        "latency_ms": float(lat[i]), "dc": self._pending.pop(t, None)})
+        if st != L.TO_OK and not out:
+            raise TopoError(st, self._err())
+        return out
+
+    def wait_idle(self, timeout_ms=600000.0):
+        return L.lib().to_server_wait_idle(self.handle, float(timeout_ms))
+
+    def stats(self):
+        live, queued = ctypes.c_int32(0), ctypes.c_int32(0)
+        ticks, free = ctypes.c_int64(0), ctypes.c_size_t(0)
+        _check(L.lib().to_server_stats(self.handle, ctypes.byref(live), ctypes.byref(queued),
+                                       ctypes.byref(ticks), ctypes.byref(free)))
+        return {"live": live.value, "queued": queued.value, "ticks": ticks.value,
+                "free_bytes": free.value}
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            L.lib().to_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -359,6 +359,7 @@ __global__ __launch_bounds__(MV_THREADS) void k_cg_matvec(const CgDesc<T> *descs
   __shared__ T ex[6][MV_THREADS];
   __shared__ double red[MV_THREADS / 64];
   const int2 bm = blockmap[blockIdx.x];
+  if (bm.x < 0) return;  // padding entry
   const CgDesc<T> &d = descs[bm.x];
   if (d.flags[F_DONE]) return;
   const int lb = bm.y;
@@ -406,6 +407,7 @@ __global__ __launch_bounds__(256) void k_cg_update(const CgDesc<T> *descs, const
                                                    int parity) {
   __shared__ double red[4];
   const int2 bm = blockmap[blockIdx.x];
+  if (bm.x < 0) return;  // padding entry
   const CgDesc<T> &d = descs[bm.x];
   if (d.flags[F_DONE]) return;
   const double pq = block_fixed_sum(d.cgp + CGP_PQ, d.nb_mv, red);
