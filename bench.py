@@ -12,9 +12,11 @@ HBM: state solve from a zero start (float32 inner Jacobi-PCG + float64 outer
 refinement), compliance and sensitivity, density filter (rmin 1.5) and
 sensitivity filter (R = 2), density -> SDF with the ersatz volume fraction.
 The plain float64 solve is timed the same way.  Both paths stop at the
-loosest outer residual that brings compliance and sensitivities within 1e-6
-of a tight float64 reference on calibration seeds (11, 12), chosen before
-timing.
+loosest outer residual that brings compliance and sensitivities within
+0.5e-6 of a tight float64 reference on calibration seeds (11, 12, 13),
+tightened by a further factor of 100 (the error/residual ratio varies a lot
+between designs), chosen before timing; the achieved errors on the timed
+design are reported.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -36,6 +38,8 @@ DIMS = (96, 48, 48)
 LARGE = (256, 128, 128)
 RTOL_LADDER = [1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 3e-6, 1e-6, 3e-7, 1e-7, 3e-8, 1e-8]
 TARGET = 1e-6
+CAL_MARGIN = 0.5          # calibrate to half the target: residuals are a loose proxy
+CAL_SAFETY = 1e-2         # and use a tolerance two decades below the calibrated rung
 HBM_PEAK_GBS = 8000.0
 
 
@@ -51,6 +55,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true", help="skip the 256x128x128 product timing")
     ap.add_argument("--cpu-iters", type=int, default=100)
+    ap.add_argument("--no-serving", action="store_true", help="skip the request-stream benchmark")
+    ap.add_argument("--requests", type=int, default=128)
     ap.add_argument("--probe", choices=["copy", "cg", "product"], default=None,
                     help="short runs for hardware-counter passes: a device copy of known size, "
                          "one workload solve, or products on 256x128x128")
@@ -121,6 +127,66 @@ def rel2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+class Calibrator:
+    """Chooses, per request class (grid, boundary condition) and precision
+    path, the loosest outer residual tolerance on RTOL_LADDER whose compliance
+    and sensitivity are within TARGET of a float64 reference solved to 1e-11
+    (with a 2x margin: CAL_MARGIN), on three calibration seeds per class that
+    are never timed."""
+
+    def __init__(self, A, inputs, dev):
+        self.A, self.inputs, self.dev = A, inputs, dev
+        self.refs, self.cache, self.ctx = {}, {}, {}
+
+    def field(self, dims, seed):
+        import torch
+        return torch.from_numpy(self.inputs.random_field(*dims, seed=seed, ell=min(6.0, dims[2] / 4),
+                                                         kappa=2.0)).to(self.dev)
+
+    def reference(self, dims, bc, seed):
+        key = (dims, bc, seed)
+        if key not in self.refs:
+            A = self.A
+            ck = (dims, bc, "ref")
+            if ck not in self.ctx:
+                self.ctx[ck] = A.to_create(A.Problem(*dims, bc=bc, precision=A.PREC_FP64, rtol=1e-11,
+                                                     max_iters=10 ** 6))
+            x = self.field(dims, seed)
+            u, info, st = A.to_solve(self.ctx[ck], x, raise_on_error=False)
+            assert info["rel_res"] <= 1e-10, info
+            c, dc = A.to_compliance_sensitivity(self.ctx[ck], x, u)
+            self.refs[key] = (u.cpu().numpy(), c, dc.cpu().numpy())
+        return self.refs[key]
+
+    def rtol(self, dims, bc, prec, seeds=None):
+        key = (dims, bc, prec)
+        if key in self.cache:
+            return self.cache[key]
+        A = self.A
+        seeds = seeds or tuple(2000 + 7 * dims[0] + 3 * bc + i for i in range(3))
+        chosen = RTOL_LADDER[-1]
+        for rt in RTOL_LADDER:
+            ctx = A.to_create(A.Problem(*dims, bc=bc, precision=prec, rtol=rt, max_iters=10 ** 6))
+            ok = True
+            for sd in seeds:
+                x = self.field(dims, sd)
+                u, info, _ = A.to_solve(ctx, x)
+                c, dc = A.to_compliance_sensitivity(ctx, x, u)
+                _, cr, dcr = self.reference(dims, bc, sd)
+                lim = CAL_MARGIN * TARGET
+                ok &= abs(c - cr) / abs(cr) <= lim and rel2(dc.cpu().numpy(), dcr) <= lim
+            ctx.close()
+            if ok:
+                chosen = rt
+                break
+        # the error/residual ratio varies by orders of magnitude between designs
+        # of one class; the safety factor covers designs the seeds do not
+        chosen = max(chosen * CAL_SAFETY, 1e-9)
+        log("calibrated %s bc=%d prec=%d: rtol %.0e" % ("x".join(map(str, dims)), bc, prec, chosen))
+        self.cache[key] = chosen
+        return chosen
+
+
 def main():
     args = parse()
     if args.probe:
@@ -148,41 +214,17 @@ def main():
                                                     kappa=2.0)).to(dev)
 
     # ---------------------------------------------------------- calibration
-    ref_ctx = A.to_create(problem(A.PREC_FP64, 1e-11))
-
-    def reference(x):
-        u, info, st = A.to_solve(ref_ctx, x, raise_on_error=False)
-        assert info["rel_res"] <= 1e-10, info
-        c, dc = A.to_compliance_sensitivity(ref_ctx, x, u)
-        return u.cpu().numpy(), c, dc.cpu().numpy(), info
-
-    def calibrate(prec, seeds):
-        refs = {s: reference(field(s)) for s in seeds}
-        for rtol in RTOL_LADDER:
-            ctx = A.to_create(problem(prec, rtol))
-            ok = True
-            for s in seeds:
-                x = field(s)
-                u, info, _ = A.to_solve(ctx, x)
-                c, dc = A.to_compliance_sensitivity(ctx, x, u)
-                _, cr, dcr, _ = refs[s]
-                ec, ed = abs(c - cr) / abs(cr), rel2(dc.cpu().numpy(), dcr)
-                ok &= ec <= TARGET and ed <= TARGET
-            ctx.close()
-            log("calibrate prec=%d rtol=%.0e ok=%s" % (prec, rtol, ok))
-            if ok:
-                return rtol
-        return RTOL_LADDER[-1]
-
+    cal = Calibrator(A, inputs, dev)
     t_cal = time.perf_counter()
-    rtol_mixed = calibrate(A.PREC_FP32_REFINE, (11, 12))
-    rtol_fp64 = calibrate(A.PREC_FP64, (11, 12))
+    rtol_mixed = cal.rtol(DIMS, A.BC_CANTILEVER, A.PREC_FP32_REFINE, seeds=(11, 12, 13))
+    rtol_fp64 = cal.rtol(DIMS, A.BC_CANTILEVER, A.PREC_FP64, seeds=(11, 12, 13))
     log("calibration %.1fs: rtol mixed %.0e fp64 %.0e" % (time.perf_counter() - t_cal, rtol_mixed,
                                                            rtol_fp64))
+    reference = cal.reference
 
     # ---------------------------------------------------------- timed steps
     x = field(1)
-    uref, cref, dcref, info_ref = reference(x)
+    uref, cref, dcref = reference(DIMS, A.BC_CANTILEVER, 1)
     prob_m = problem(A.PREC_FP32_REFINE, rtol_mixed)
     prob_d = problem(A.PREC_FP64, rtol_fp64)
     ctx_m = A.to_create(prob_m)
@@ -315,10 +357,121 @@ def main():
         "products": products, "errors": errors, "triangles": ntri, "roofline": roofline,
     }
 
+    # ---------------------------------------------------------- serving
+    if not args.no_serving:
+        out["serving"] = serving(args.requests, cal)
+
     # ---------------------------------------------------------- CPU oracle
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x.cpu().numpy(), res_d["iters"][-1], ntri, args.cpu_iters)
     print(json.dumps(out), flush=True)
+
+
+SERVE_GRIDS = [(32, 16, 16), (64, 32, 32), (96, 48, 48), (128, 64, 64)]
+
+
+def serving(nreq, cal):
+    """Request stream: grids uniform over SERVE_GRIDS, cantilever or MBB by a
+    coin flip, random-field densities (l = min(6, nelz/4), kappa 2, seed
+    1000 + k).  A closed-loop run (all requests submitted at once) gives the
+    capacity; the timed run submits at Poisson arrival times (seed 4242) at
+    0.75x that capacity.  The same requests are then solved one by one with
+    the plain float64 path (to_solve + to_compliance_sensitivity).  Each
+    path uses the tolerance calibrated for the request's class."""
+    import torch
+    from paper_2605_04735_amd import api as A
+    from paper_2605_04735_amd import inputs
+    rng = np.random.default_rng(4242)
+    reqs = []
+    for k in range(nreq):
+        dims = SERVE_GRIDS[rng.integers(len(SERVE_GRIDS))]
+        bc = A.BC_CANTILEVER if rng.uniform() < 0.5 else A.BC_MBB
+        x = inputs.random_field(*dims, seed=1000 + k, ell=min(6.0, dims[2] / 4), kappa=2.0)
+        reqs.append((k, dims, bc, x))
+    tol_m = {(d, b): cal.rtol(d, b, A.PREC_FP32_REFINE) for d in SERVE_GRIDS for b in (0, 1)}
+    tol_d = {(d, b): cal.rtol(d, b, A.PREC_FP64) for d in SERVE_GRIDS for b in (0, 1)}
+    budget = 8 << 30
+
+    def run(arrivals):
+        srv = A.Server(budget, 64)
+        res = {}
+        t0 = time.perf_counter()
+        try:
+            for (k, dims, bc, x), ta in zip(reqs, arrivals):
+                while time.perf_counter() - t0 < ta:
+                    for r in srv.poll():
+                        res[r["tag"]] = r
+                    time.sleep(0.0002)
+                srv.submit(A.Problem(*dims, bc=bc, precision=A.PREC_FP32_REFINE,
+                                     rtol=tol_m[(dims, bc)], max_iters=500000), x, tag=k)
+            assert srv.wait_idle(600000.0) == A.L.TO_OK
+            for r in srv.poll():
+                res[r["tag"]] = r
+            t1 = time.perf_counter()
+        finally:
+            srv.close()
+        return res, t1 - t0
+
+    closed, t_closed = run([0.0] * nreq)
+    capacity = nreq / t_closed
+    lam = 0.75 * capacity
+    gaps = np.random.default_rng(4242).exponential(1.0 / lam, nreq)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    served, t_served = run(list(arrivals))
+    lat = np.array([served[k]["latency_ms"] for k in range(nreq)])
+    ok = all(served[k]["status"] == A.L.TO_OK for k in range(nreq))
+    log("serving: capacity %.1f solves/s, lambda %.1f/s, p50 %.1f ms p99 %.1f ms"
+        % (capacity, lam, np.percentile(lat, 50), np.percentile(lat, 99)))
+    # plain float64, one request at a time, same requests
+    dev = torch.device("cuda:0")
+    ctxs = {}
+    t0 = time.perf_counter()
+    ref = {}
+    for k, dims, bc, x in reqs:
+        key = (dims, bc)
+        if key not in ctxs:
+            ctxs[key] = A.to_create(A.Problem(*dims, bc=bc, precision=A.PREC_FP64,
+                                              rtol=tol_d[key], max_iters=500000))
+        xg = torch.from_numpy(x).to(dev)
+        u, _, _ = A.to_solve(ctxs[key], xg)
+        c, dc = A.to_compliance_sensitivity(ctxs[key], xg, u)
+        ref[k] = (c, dc)
+    torch.cuda.synchronize()
+    t_fp64 = time.perf_counter() - t0
+    # errors of a sample of served and float64 results against tight references
+    errs = {"served_c": 0.0, "served_dc": 0.0, "fp64_c": 0.0, "fp64_dc": 0.0}
+    for k, dims, bc, x in reqs[:32]:
+        seed = 1000 + k
+        _, cr, dcr = tight_reference(cal, dims, bc, x)
+        errs["served_c"] = max(errs["served_c"], abs(served[k]["c"] - cr) / abs(cr))
+        errs["served_dc"] = max(errs["served_dc"], rel2(served[k]["dc"], dcr))
+        errs["fp64_c"] = max(errs["fp64_c"], abs(ref[k][0] - cr) / abs(cr))
+        errs["fp64_dc"] = max(errs["fp64_dc"], rel2(ref[k][1].cpu().numpy(), dcr))
+    sps = nreq / t_served
+    log("serving: %.1f solves/s served vs %.1f solves/s plain fp64" % (sps, nreq / t_fp64))
+    return {"requests": nreq, "grids": ["%dx%dx%d" % g for g in SERVE_GRIDS],
+            "all_ok": ok, "capacity_closed_loop_solves_per_s": round(capacity, 2),
+            "lambda_per_s": round(lam, 2), "solves_per_s": round(sps, 2),
+            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                           "max": float(lat.max())},
+            "fp64_sequential_solves_per_s": round(nreq / t_fp64, 2),
+            "speedup_vs_fp64_sequential": round(sps * t_fp64 / nreq, 3),
+            "max_rel_err_vs_tight_fp64_first32": errs,
+            "rtol_served": {"%dx%dx%d/%s" % (*d, "mbb" if b else "cant"): v for (d, b), v in tol_m.items()},
+            "rtol_fp64": {"%dx%dx%d/%s" % (*d, "mbb" if b else "cant"): v for (d, b), v in tol_d.items()}}
+
+
+def tight_reference(cal, dims, bc, x):
+    import torch
+    A = cal.A
+    ck = (dims, bc, "ref")
+    if ck not in cal.ctx:
+        cal.ctx[ck] = A.to_create(A.Problem(*dims, bc=bc, precision=A.PREC_FP64, rtol=1e-11,
+                                            max_iters=10 ** 6))
+    xg = torch.from_numpy(x).to(cal.dev)
+    u, info, _ = A.to_solve(cal.ctx[ck], xg, raise_on_error=False)
+    c, dc = A.to_compliance_sensitivity(cal.ctx[ck], xg, u)
+    return None, c, dc.cpu().numpy()
 
 
 def cpu_baseline(x, n_iters, ntri, cpu_iters):
