@@ -61,20 +61,20 @@ __device__ __forceinline__ void iwht8(T v[8]) {
   }
 }
 
-// y[a][c] = E * (k0 u)[3a+c]; u, y: [3][8] component-major.
+// Per-monomial stresses D from the transform coefficients C of the three
+// displacement components (C[c][0], the constant monomial, is never used):
+// D = d(E u^T k0 u / 2)/dC with the h/32 scaling folded into the
+// coefficients.  D[c][0] = 0.
 template <typename T>
-__device__ __forceinline__ void hex8_apply(T u[3][8], T E, const Coef<T> &k) {
+__device__ __forceinline__ void modal_stress(const T (&C)[3][8], T E, const Coef<T> &k,
+                                             T (&D)[3][8]) {
   const T L2 = E * k.L2, M4 = E * k.M4, M2 = E * k.M2;
   const T L2_3 = E * k.L2_3, M2_3 = E * k.M2_3, B9 = E * k.B9;
-  wht8(u[0]);
-  wht8(u[1]);
-  wht8(u[2]);
-  T(&cx)[8] = u[0];
-  T(&cy)[8] = u[1];
-  T(&cz)[8] = u[2];
+  const T(&cx)[8] = C[0];
+  const T(&cy)[8] = C[1];
+  const T(&cz)[8] = C[2];
   // monomial index m = mx + 2 my + 4 mz: 1 xi, 2 eta, 3 xi.eta, 4 zeta,
   // 5 xi.zeta, 6 eta.zeta, 7 xi.eta.zeta
-  T D[3][8];
   // constant gradient
   const T t0 = L2 * (cx[1] + cy[2] + cz[4]);
   D[0][1] = t0 + M4 * cx[1];
@@ -107,6 +107,16 @@ __device__ __forceinline__ void hex8_apply(T u[3][8], T E, const Coef<T> &k) {
   D[0][0] = 0;
   D[1][0] = 0;
   D[2][0] = 0;
+}
+
+// u[c][a] <- E (k0 u)[3a + c] for one element; u: [3][8] component-major.
+template <typename T>
+__device__ __forceinline__ void hex8_apply(T (&u)[3][8], T E, const Coef<T> &k) {
+  wht8(u[0]);
+  wht8(u[1]);
+  wht8(u[2]);
+  T D[3][8];
+  modal_stress(u, E, k, D);
   iwht8(D[0]);
   iwht8(D[1]);
   iwht8(D[2]);
@@ -114,6 +124,22 @@ __device__ __forceinline__ void hex8_apply(T u[3][8], T E, const Coef<T> &k) {
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int a = 0; a < 8; ++a) u[c][a] = D[c][a];
+}
+
+// Forward transform of one element face (4 corners (ax, ay) of a node plane
+// in LDS): F[m], m = mx + 2 my, the x and y butterflies of the 8-point
+// transform.
+template <typename T>
+__device__ __forceinline__ void face_forward(const T (*P)[TP * TP], int idx, T (&F)[3][4]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const T v00 = P[c][idx], v10 = P[c][idx + 1], v01 = P[c][idx + TP], v11 = P[c][idx + TP + 1];
+    const T s0 = v10 + v00, d0 = v10 - v00, s1 = v11 + v01, d1 = v11 - v01;
+    F[c][0] = s1 + s0;
+    F[c][1] = d1 + d0;
+    F[c][2] = s1 - s0;
+    F[c][3] = d1 - d0;
+  }
 }
 
 __device__ __forceinline__ double block_sum_d(double v, double *sh) {
@@ -145,17 +171,202 @@ __device__ __forceinline__ double from_next_lane(double v) {
 // node planes [bz kz, bz kz + kz).  Returns the block's partial sum (CG:
 // p^T q, RESID: ||r||^2) in thread 0.
 //
-// Per element layer L the block holds node planes L and L+1 in LDS; plane
-// L+2 is already being fetched into registers while layer L is computed.
-// Element outputs are combined without an LDS round trip of all 24 values:
-// along x by a DPP lane shift (node i gets element i-1's ax=1 corner and
-// element i's ax=0 corner from the next lane), along y through a 6-value LDS
-// exchange with the next row of the tile, along z through a register carry.
-// The summation order is fixed, so the result is deterministic.
-template <typename T, int MODE>
-__device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int by, int bz, T beta,
-                                               T (*pl)[3][TP * TP], T (*ex)[MV_THREADS],
-                                               double *red) {
+// Each lane owns one element column of the tile and carries it up the z
+// layers in transform space: the forward transform of the element's bottom
+// face is the top face of the layer below (kept in registers), so per layer a
+// lane reads only the 4 corners of node plane L+1 from LDS; the inverse
+// transform's contributions to a node plane are accumulated as face
+// transforms (top face of layer L-1 plus bottom face of layer L) and turned
+// into corner values once per plane.  The owned node's value then combines
+// the corners of the 4 elements around it: along x by a DPP lane shift (no
+// LDS), along y through a 3-value LDS exchange with the next tile row.  Node
+// plane L+2 is fetched into registers while layer L computes.  The
+// summation order is fixed: the result is deterministic.
+template <typename T, int MODE, typename BetaFn>
+__device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int by, int bz,
+                                               BetaFn &&get_beta, T (*pl)[3][TP * TP],
+                                               T (*ex)[MV_THREADS], double *red) {
+  const int tid = threadIdx.x;
+  const int NX = a.nelx + 1, NY = a.nely + 1, NZ = a.nelz + 1;
+  const int i0 = bx * TN, j0 = by * TN;
+  const int k0 = bz * a.kz;
+  const int k1 = min(k0 + a.kz, NZ);
+
+  const int ei = tid % TE, ej = tid / TE;
+  const int gi = i0 - 1 + ei, gj = j0 - 1 + ej;
+  const bool e_xy = gi >= 0 && gi < a.nelx && gj >= 0 && gj < a.nely;
+  // the node owned by this lane: (i0 + ei, j0 + ej), interior of the tile
+  const int gni = i0 + ei, gnj = j0 + ej;
+  const bool own = ei < TN && ej < TN && gni < NX && gnj < NY;
+  const unsigned plane = (unsigned)NX * (unsigned)NY;
+  const unsigned eplane = (unsigned)a.nelx * (unsigned)a.nely;
+  const unsigned ebase = e_xy ? (unsigned)gi + (unsigned)a.nelx * (unsigned)gj : 0u;
+  const unsigned nbase = (unsigned)gni + (unsigned)NX * (unsigned)gnj;
+
+  // register staging of one node plane (17 x 17 nodes, two slots per lane)
+  T rin[2][3], rpo[2][3];
+  unsigned rm[2], rbase[2];
+  bool rv[2], rown[2];
+#pragma unroll
+  for (int sl = 0; sl < 2; ++sl) {
+    const int idx = tid + sl * MV_THREADS;
+    const int li = idx % TP, lj = idx / TP;
+    const int gx = i0 - 1 + li, gy = j0 - 1 + lj;
+    rv[sl] = idx < TP * TP && gx >= 0 && gx < NX && gy >= 0 && gy < NY;
+    rown[sl] = li >= 1 && li <= TN && lj >= 1 && lj <= TN;
+    rbase[sl] = rv[sl] ? (unsigned)gx + (unsigned)NX * (unsigned)gy : 0u;
+  }
+  auto fetch = [&](int kp) {
+    const bool inz = kp >= 0 && kp < NZ;
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      rm[sl] = 7u;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        rin[sl][c] = 0;
+        rpo[sl][c] = 0;
+      }
+      if (rv[sl] && inz) {
+        const unsigned n = rbase[sl] + plane * (unsigned)kp;
+        rm[sl] = a.mask[n];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          rin[sl][c] = a.in[3u * n + c];
+          if (MODE == MV_CG) rpo[sl][c] = a.pold[3u * n + c];
+        }
+      }
+    }
+  };
+  T beta = 0;
+  auto stage = [&](int kp) {
+    T(*dst)[TP * TP] = pl[kp & 1];
+    const bool wr = MODE == MV_CG && kp >= k0 && kp < k1;
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      const int idx = tid + sl * MV_THREADS;
+      if (idx >= TP * TP) continue;
+      T v[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const bool fx = (rm[sl] >> c) & 1u;
+        v[c] = fx ? T(0) : rin[sl][c];
+        if (MODE == MV_CG) v[c] = fx ? T(0) : v[c] + beta * rpo[sl][c];
+        dst[c][idx] = v[c];
+      }
+      if (wr && rv[sl] && rown[sl]) {
+        const unsigned n = rbase[sl] + plane * (unsigned)kp;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a.pout[3u * n + c] = v[c];
+      }
+    }
+  };
+  auto modulus = [&](int L) -> T {
+    return (e_xy && L >= 0 && L < a.nelz) ? a.E[ebase + eplane * (unsigned)L] : T(0);
+  };
+
+  const int fidx = ei + TP * ej;  // corner (0,0) of this lane's element face in a plane
+  T F0[3][4];                     // forward face transform, plane L
+  T Gc[3][4];                     // accumulated inverse face transform, plane L
+  double acc = 0.0;
+  fetch(k0 - 1);
+  // the scalars of the step (CG: the previous reduction) while the first
+  // plane is in flight; false: nothing to do for this design
+  if (!get_beta(beta)) return 0.0;
+  stage(k0 - 1);
+  fetch(k0);
+  T Ecur = modulus(k0 - 1);
+  __syncthreads();
+  face_forward(pl[(k0 - 1) & 1], fidx, F0);
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) Gc[c][m] = 0;
+  for (int L = k0 - 1; L < k1; ++L) {
+    stage(L + 1);
+    if (L + 2 <= k1) fetch(L + 2);
+    const T Enext = modulus(L + 1);
+    __syncthreads();
+    T pn[3] = {0, 0, 0};
+    if (MODE == MV_CG && own) {
+      const int idx = (ei + 1) + TP * (ej + 1);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) pn[c] = pl[L & 1][c][idx];
+    }
+    T F1[3][4];
+    face_forward(pl[(L + 1) & 1], fidx, F1);
+    T C[3][8], D[3][8];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        C[c][m] = F1[c][m] + F0[c][m];
+        C[c][m + 4] = F1[c][m] - F0[c][m];
+        F0[c][m] = F1[c][m];
+      }
+    modal_stress(C, Ecur, a.k, D);
+    // inverse z butterfly: bottom (plane L) and top (plane L+1) face parts;
+    // plane L is now complete in transform space
+    T A[3][4];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        A[c][m] = Gc[c][m] + (D[c][m] - D[c][m + 4]);
+        Gc[c][m] = D[c][m] + D[c][m + 4];
+      }
+    // inverse x and y butterflies -> corner values y(ax, ay); then x combine
+    T xc[3][2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T e00 = A[c][0] - A[c][1], e10 = A[c][0] + A[c][1];   // my = 0
+      const T e01 = A[c][2] - A[c][3], e11 = A[c][2] + A[c][3];   // my = 1
+      const T y00 = e00 - e01, y01 = e00 + e01;                   // ax = 0
+      const T y10 = e10 - e11, y11 = e10 + e11;                   // ax = 1
+      xc[c][0] = y10 + from_next_lane(y00);
+      xc[c][1] = y11 + from_next_lane(y01);
+      ex[c][tid] = xc[c][0];
+    }
+    __syncthreads();
+    if (own && L >= k0) {
+      const unsigned n = nbase + plane * (unsigned)L;
+      T val[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) val[c] = xc[c][1] + ex[c][tid + TE];
+      const unsigned m = a.mask[n];
+      if (MODE == MV_APPLY) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a.out[3u * n + c] = ((m >> c) & 1u) ? a.in[3u * n + c] : val[c];
+      } else if (MODE == MV_CG) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const T q = ((m >> c) & 1u) ? T(0) : val[c];
+          a.out[3u * n + c] = q;
+          acc += (double)pn[c] * (double)q;
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const double r = ((m >> c) & 1u) ? 0.0 : a.f[3u * n + c] - (double)val[c];
+          a.out[3u * n + c] = (T)r;
+          acc += r * r;
+        }
+      }
+    }
+    Ecur = Enext;
+  }
+  if (MODE != MV_APPLY) return block_sum_d(acc, red);
+  return 0.0;
+}
+
+// Variant of the product block for the float64 inner CG: the element's 8
+// corners are read from both staged planes and transformed in full, and the
+// node sums carry along z in node space.  It needs far fewer registers than
+// the transform-space carry (which, with the fused direction update, pushes
+// float64 to two waves per SIMD or to spills) and measured faster there.
+template <typename T, int MODE, typename BetaFn>
+__device__ __forceinline__ double matvec_block_nodecarry(const MvArgs<T> &a, int bx, int by, int bz,
+                                                         BetaFn &&get_beta, T (*pl)[3][TP * TP],
+                                                         T (*ex)[MV_THREADS], double *red) {
   const int tid = threadIdx.x;
   const int NX = a.nelx + 1, NY = a.nely + 1, NZ = a.nelz + 1;
   const int i0 = bx * TN, j0 = by * TN;
@@ -198,6 +409,7 @@ __device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int b
       }
     }
   };
+  T beta = 0;
   auto stage = [&](int kp) {
     T(*dst)[TP * TP] = pl[kp & 1];
 #pragma unroll
@@ -231,6 +443,7 @@ __device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int b
   T carry[3] = {0, 0, 0};
   double acc = 0.0;
   fetch(k0 - 1);
+  if (!get_beta(beta)) return 0.0;
   stage(k0 - 1);
   fetch(k0);
   T Ecur = modulus(k0 - 1);
@@ -308,13 +521,14 @@ __device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int b
 }
 
 template <typename T, int MODE>
-__global__ __launch_bounds__(MV_THREADS) void k_matvec(const MvArgs<T> a, int tx, int ty) {
+__global__ __launch_bounds__(MV_THREADS) __attribute__((amdgpu_waves_per_eu(3)))
+void k_matvec(const MvArgs<T> a, int tx, int ty) {
   __shared__ T pl[2][3][TP * TP];
-  __shared__ T ex[6][MV_THREADS];
+  __shared__ T ex[3][MV_THREADS];
   __shared__ double red[MV_THREADS / 64];
   const int lb = xcd_local(blockIdx.x, gridDim.x);
-  const double s = matvec_block<T, MODE>(a, lb % tx, (lb / tx) % ty, lb / (tx * ty), T(0), pl, ex,
-                                         red);
+  const double s = matvec_block<T, MODE>(
+      a, lb % tx, (lb / tx) % ty, lb / (tx * ty), [](T &b) { b = T(0); return true; }, pl, ex, red);
   if (MODE != MV_APPLY && threadIdx.x == 0) a.part[lb] = s;
 }
 
@@ -347,6 +561,36 @@ __device__ double block_fixed_sum(const double *v, int n, double *sh) {
   return r;
 }
 
+// Two fixed-order sums (same length) with one round of loads.
+__device__ void block_fixed_sum2(const double *u, const double *v, int n, double *sh, double &su,
+                                 double &sv) {
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    a += u[i];
+    b += v[i];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_down(a, o, 64);
+    b += __shfl_down(b, o, 64);
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    sh[w] = a;
+    sh[w + 4] = b;
+  }
+  __syncthreads();
+  su = 0.0;
+  sv = 0.0;
+  const int nw = (blockDim.x + 63) >> 6;
+  for (int i = 0; i < nw; ++i) {
+    su += sh[i];
+    sv += sh[i + 4];
+  }
+  __syncthreads();
+}
+
 // Batched inner-CG product over a table of designs: blockmap[b] = (design,
 // local block).  Every block first completes the reduction of the previous
 // update (r^T z and ||r||^2, partial set parity^1): converged designs stop
@@ -357,29 +601,12 @@ __global__ __launch_bounds__(MV_THREADS) void k_cg_matvec(const CgDesc<T> *descs
                                                           const int2 *blockmap, int parity) {
   __shared__ T pl[2][3][TP * TP];
   __shared__ T ex[6][MV_THREADS];
-  __shared__ double red[MV_THREADS / 64];
+  __shared__ double red[8];
   const int2 bm = blockmap[blockIdx.x];
   if (bm.x < 0) return;  // padding entry
   const CgDesc<T> &d = descs[bm.x];
   if (d.flags[F_DONE]) return;
   const int lb = bm.y;
-  const double rz = block_fixed_sum(d.cgp + CGP_RZ + (parity ^ 1) * MAXB, d.nb_up, red);
-  const double rr = block_fixed_sum(d.cgp + CGP_RR + (parity ^ 1) * MAXB, d.nb_up, red);
-  const double rz_old = d.scal[S_RZ0 + parity];
-  const int iters = d.flags[F_ITERS];
-  const bool bad = !isfinite(rz) || !isfinite(rr);
-  if (bad || rr <= d.scal[S_TOL2] || iters >= d.flags[F_CAP]) {
-    if (lb == 0 && threadIdx.x == 0) {
-      if (bad) d.flags[F_STATUS] = 2;
-      d.scal[S_RR] = rr;
-      d.flags[F_DONE] = 1;
-    }
-    return;
-  }
-  if (lb == 0 && threadIdx.x == 0) {
-    d.scal[S_RZ0 + (parity ^ 1)] = rz;
-    d.scal[S_RR] = rr;
-  }
   MvArgs<T> a;
   a.nelx = d.nelx;
   a.nely = d.nely;
@@ -393,8 +620,33 @@ __global__ __launch_bounds__(MV_THREADS) void k_cg_matvec(const CgDesc<T> *descs
   a.mask = d.mask;
   a.k = d.k;
   const int bx = lb % d.tx, by = (lb / d.tx) % d.ty, bz = lb / (d.tx * d.ty);
-  const T beta = (T)(rz / rz_old);
-  const double s = matvec_block<T, MV_CG>(a, bx, by, bz, beta, pl, ex, red);
+  auto get_beta = [&](T &beta) -> bool {
+    double rz, rr;
+    block_fixed_sum2(d.cgp + CGP_RZ + (parity ^ 1) * MAXB, d.cgp + CGP_RR + (parity ^ 1) * MAXB,
+                     d.nb_up, red, rz, rr);
+    const double rz_old = d.scal[S_RZ0 + parity];
+    const int iters = d.flags[F_ITERS];
+    const bool bad = !isfinite(rz) || !isfinite(rr);
+    if (bad || rr <= d.scal[S_TOL2] || iters >= d.flags[F_CAP]) {
+      if (lb == 0 && threadIdx.x == 0) {
+        if (bad) d.flags[F_STATUS] = 2;
+        d.scal[S_RR] = rr;
+        d.flags[F_DONE] = 1;
+      }
+      return false;
+    }
+    if (lb == 0 && threadIdx.x == 0) {
+      d.scal[S_RZ0 + (parity ^ 1)] = rz;
+      d.scal[S_RR] = rr;
+    }
+    beta = (T)(rz / rz_old);
+    return true;
+  };
+  double s;
+  if constexpr (sizeof(T) == 8)
+    s = matvec_block_nodecarry<T, MV_CG>(a, bx, by, bz, get_beta, pl, ex, red);
+  else
+    s = matvec_block<T, MV_CG>(a, bx, by, bz, get_beta, pl, ex, red);
   if (threadIdx.x == 0) d.cgp[CGP_PQ + lb] = s;
 }
 
@@ -478,8 +730,8 @@ int matvec_kz(const Grid &g) {
       return v;
     }
   }
-  // about 8 blocks per CU while keeping the z recompute (kz + 1)/kz small
-  int chunks = (2048 + tiles - 1) / tiles;
+  // about 12 blocks per CU while keeping the z recompute (kz + 1)/kz small
+  int chunks = (3072 + tiles - 1) / tiles;
   int kz = (NZ + chunks - 1) / chunks;
   if (kz < 2) kz = 2;
   if (kz > 32) kz = 32;
