@@ -552,7 +552,10 @@ to_status to_solve(to_ctx *c, const double *d_x, const double *d_u0, double *d_u
       if (st != TO_OK) return st;
       total_inner += it;
       ++outer;
-      if (status == 1) { result = TO_E_SINGULAR; msg = "CG breakdown: p^T K p <= 0"; }
+      // A breakdown after some progress ends the inner solve like convergence
+      // (the float64 residual decides what happens next); without progress
+      // the system is singular or indefinite.
+      if (status == 1 && it == 0) { result = TO_E_SINGULAR; msg = "CG breakdown: p^T K p <= 0"; }
       if (status == 2) { result = TO_E_NONFINITE; msg = "non-finite value in CG"; }
       if (result != TO_OK) {
         st = residual64(c, d_u);

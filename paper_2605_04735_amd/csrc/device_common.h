@@ -1,0 +1,209 @@
+// Device helpers shared by the product kernels: the factored hex8 element
+// apply, lane shifts and fixed-order block reductions.
+#pragma once
+
+#include "common.h"
+
+namespace topo {
+
+template <typename T>
+__device__ __forceinline__ void wht8(T v[8]) {
+  // v[a] -> sum_a' prod_d (m_d ? s_d(a') : 1) v[a'], index bits d = 0,1,2
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      if (!((a >> d) & 1)) {
+        const int b = a | (1 << d);
+        const T lo = v[a], hi = v[b];
+        v[a] = hi + lo;
+        v[b] = hi - lo;
+      }
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void iwht8(T v[8]) {
+  // transpose of wht8 (the matrix is symmetric; butterflies in the same order)
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      if (!((a >> d) & 1)) {
+        const int b = a | (1 << d);
+        const T lo = v[a], hi = v[b];
+        v[a] = lo - hi;
+        v[b] = lo + hi;
+      }
+    }
+  }
+}
+
+// Per-monomial stresses D from the transform coefficients C of the three
+// displacement components (C[c][0], the constant monomial, is never used):
+// D = d(E u^T k0 u / 2)/dC with the h/32 scaling folded into the
+// coefficients.  D[c][0] = 0.
+template <typename T>
+__device__ __forceinline__ void modal_stress(const T (&C)[3][8], T E, const Coef<T> &k,
+                                             T (&D)[3][8]) {
+  const T L2 = E * k.L2, M4 = E * k.M4, M2 = E * k.M2;
+  const T L2_3 = E * k.L2_3, M2_3 = E * k.M2_3, B9 = E * k.B9;
+  const T(&cx)[8] = C[0];
+  const T(&cy)[8] = C[1];
+  const T(&cz)[8] = C[2];
+  // monomial index m = mx + 2 my + 4 mz: 1 xi, 2 eta, 3 xi.eta, 4 zeta,
+  // 5 xi.zeta, 6 eta.zeta, 7 xi.eta.zeta
+  // constant gradient
+  const T t0 = L2 * (cx[1] + cy[2] + cz[4]);
+  D[0][1] = t0 + M4 * cx[1];
+  D[1][2] = t0 + M4 * cy[2];
+  D[2][4] = t0 + M4 * cz[4];
+  const T sxy = M2 * (cy[1] + cx[2]);
+  const T sxz = M2 * (cz[1] + cx[4]);
+  const T syz = M2 * (cz[2] + cy[4]);
+  D[1][1] = sxy; D[0][2] = sxy;
+  D[2][1] = sxz; D[0][4] = sxz;
+  D[2][2] = syz; D[1][4] = syz;
+  // linear groups
+  const T txi = L2_3 * (cy[3] + cz[5]);
+  const T teta = L2_3 * (cx[3] + cz[6]);
+  const T tzeta = L2_3 * (cx[5] + cy[6]);
+  D[0][3] = teta + M2 * cx[3];
+  D[1][3] = txi + M2 * cy[3];
+  D[1][6] = tzeta + M2 * cy[6];
+  D[2][6] = teta + M2 * cz[6];
+  D[0][5] = tzeta + M2 * cx[5];
+  D[2][5] = txi + M2 * cz[5];
+  const T S = cz[3] + cy[5] + cx[6];
+  D[2][3] = M2_3 * (S + cz[3]);
+  D[0][6] = M2_3 * (S + cx[6]);
+  D[1][5] = M2_3 * (S + cy[5]);
+  // bilinear groups
+  D[0][7] = B9 * cx[7];
+  D[1][7] = B9 * cy[7];
+  D[2][7] = B9 * cz[7];
+  D[0][0] = 0;
+  D[1][0] = 0;
+  D[2][0] = 0;
+}
+
+// u[c][a] <- E (k0 u)[3a + c] for one element; u: [3][8] component-major.
+template <typename T>
+__device__ __forceinline__ void hex8_apply(T (&u)[3][8], T E, const Coef<T> &k) {
+  wht8(u[0]);
+  wht8(u[1]);
+  wht8(u[2]);
+  T D[3][8];
+  modal_stress(u, E, k, D);
+  iwht8(D[0]);
+  iwht8(D[1]);
+  iwht8(D[2]);
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int a = 0; a < 8; ++a) u[c][a] = D[c][a];
+}
+
+// Forward transform of one element face (4 corners (ax, ay) of a node plane
+// in LDS): F[m], m = mx + 2 my, the x and y butterflies of the 8-point
+// transform.
+template <typename T>
+__device__ __forceinline__ void face_forward(const T (*P)[TP * TP], int idx, T (&F)[3][4]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const T v00 = P[c][idx], v10 = P[c][idx + 1], v01 = P[c][idx + TP], v11 = P[c][idx + TP + 1];
+    const T s0 = v10 + v00, d0 = v10 - v00, s1 = v11 + v01, d1 = v11 - v01;
+    F[c][0] = s1 + s0;
+    F[c][1] = d1 + d0;
+    F[c][2] = s1 - s0;
+    F[c][3] = d1 - d0;
+  }
+}
+
+__device__ __forceinline__ double block_sum_d(double v, double *sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 0; i < nw; ++i) r += sh[i];
+  }
+  return r;
+}
+
+// Value of lane + 1 within each row of 16 lanes (0 for the last lane of a
+// row): the DPP row shift, no LDS traffic.
+__device__ __forceinline__ float from_next_lane(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x101, 0xF, 0xF, true));
+}
+__device__ __forceinline__ double from_next_lane(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x101, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x101, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+
+// Fixed-order sum of n block partials written by the previous kernel, done
+// by every block that needs it: the loads are independent batches per thread
+// (latency overlapped), followed by a fixed shuffle/wave tree, so each block
+// gets the bit-identical value and no block waits for another.
+__device__ inline double block_fixed_sum(const double *v, int n, double *sh) {
+  constexpr int K = 4;
+  double s = 0.0;
+  for (int base = 0; base < n; base += K * (int)blockDim.x) {
+    double t[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = base + k * (int)blockDim.x + (int)threadIdx.x;
+      t[k] = (i < n) ? v[i] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) s += t[k];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = s;
+  __syncthreads();
+  double r = 0.0;
+  const int nw = (blockDim.x + 63) >> 6;
+  for (int i = 0; i < nw; ++i) r += sh[i];
+  return r;
+}
+
+// Two fixed-order sums (same length) with one round of loads.
+__device__ inline void block_fixed_sum2(const double *u, const double *v, int n, double *sh, double &su,
+                                 double &sv) {
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    a += u[i];
+    b += v[i];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_down(a, o, 64);
+    b += __shfl_down(b, o, 64);
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    sh[w] = a;
+    sh[w + 4] = b;
+  }
+  __syncthreads();
+  su = 0.0;
+  sv = 0.0;
+  const int nw = (blockDim.x + 63) >> 6;
+  for (int i = 0; i < nw; ++i) {
+    su += sh[i];
+    sv += sh[i + 4];
+  }
+  __syncthreads();
+}
+
+
+}  // namespace topo

@@ -119,6 +119,7 @@ struct Slot {
   size_t stage_cap = 0;
   double fnorm = -1.0;
   int outer = 0, inner_total = 0;
+  double hist[4] = {0, 0, 0, 0}, best = 0.0;  // float64 residual history (stagnation)
   int32_t fail = TO_OK;
 };
 
@@ -461,7 +462,7 @@ void server_loop(to_server *s) {
         if (!fl[F_DONE]) continue;
         sl.inner_total += fl[F_ITERS];
         sl.outer++;
-        if (fl[F_STATUS] == 1) sl.fail = TO_E_SINGULAR;
+        if (fl[F_STATUS] == 1 && fl[F_ITERS] == 0) sl.fail = TO_E_SINGULAR;
         if (fl[F_STATUS] == 2) sl.fail = TO_E_NONFINITE;
         check(s, launch_axpy_out<float>(sl.g, sl.u, sl.v[0], sl.scal, s->stream));
         launch_resid(s, sl);
@@ -484,6 +485,17 @@ void server_loop(to_server *s) {
       if (!finish && (sl.inner_total >= p.max_iters || sl.outer >= 200)) {
         sl.fail = TO_E_NOCONV;
         finish = true;
+      }
+      // attainable accuracy: four refinement passes that have not halved the
+      // float64 residual end the request (same rule as the one-design solve)
+      if (!finish) {
+        if (sl.outer == 0) sl.best = rel;
+        sl.hist[sl.outer % 4] = rel;
+        if (sl.outer >= 4 && rel > 0.5 * sl.hist[(sl.outer + 1) % 4] && rel > 0.5 * sl.best) {
+          sl.fail = TO_E_NOCONV;
+          finish = true;
+        }
+        sl.best = std::min(sl.best, rel);
       }
       if (finish) {
         int nb = 0;
