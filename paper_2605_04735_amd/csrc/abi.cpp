@@ -241,14 +241,19 @@ void prof_collect(to_ctx *c) {
   c->ev_used = 0;
 }
 
-hipError_t prof_mark(to_ctx *c) {
-  if (c->ev_used == c->ev.size()) {
+// Hands out the next start/stop event pair (created on first use).  The pair
+// is attached to one product dispatch, so the elapsed time is that kernel's
+// execution alone, without the latency of separate event packets.
+hipError_t prof_pair(to_ctx *c, hipEvent_t *start, hipEvent_t *stop) {
+  while (c->ev_used + 2 > c->ev.size()) {
     hipEvent_t e;
     hipError_t r = hipEventCreate(&e);
     if (r != hipSuccess) return r;
     c->ev.push_back(e);
   }
-  return hipEventRecord(c->ev[c->ev_used++], c->stream);
+  *start = c->ev[c->ev_used++];
+  *stop = c->ev[c->ev_used++];
+  return hipSuccess;
 }
 
 to_status prepare_moduli(to_ctx *c, const double *d_x, bool check) {
@@ -312,10 +317,11 @@ to_status inner_pcg(to_ctx *c, T *const v[6], const T *dinv, double eta, int cap
   for (;;) {
     const int n = std::min(c->chunk, cap - launched);
     for (int it = 0; it < n; ++it) {
-      const bool mark = c->prof && ((launched + it) % c->prof_every == 0);
-      if (mark) HIPCHK(prof_mark(c));
-      HIPCHK(launch_cg_matvec<T>(desc, c->bmap_mv, c->nb_mv, c->parity, c->stream));
-      if (mark) HIPCHK(prof_mark(c));
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      // sampled away from the first launch after a host synchronisation
+      if (c->prof && (launched + it) % c->prof_every == c->prof_every / 2)
+        HIPCHK(prof_pair(c, &e0, &e1));
+      HIPCHK(launch_cg_matvec<T>(desc, c->bmap_mv, c->nb_mv, c->parity, c->stream, e0, e1));
       HIPCHK(launch_cg_update<T>(desc, c->bmap_up, c->nb_up, c->parity, c->stream));
       c->parity ^= 1;
     }

@@ -143,7 +143,7 @@ hipError_t launch_cg_init(const Grid &g, const double *b, const double *scal, T 
 // and convergence test).  blockmaps: (design, local block) per block.
 template <typename T>
 hipError_t launch_cg_matvec(const CgDesc<T> *descs, const int2 *bmap_mv, int nb_mv, int parity,
-                            hipStream_t s);
+                            hipStream_t s, hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 template <typename T>
 hipError_t launch_cg_update(const CgDesc<T> *descs, const int2 *bmap_up, int nb_up, int parity,
                             hipStream_t s);

@@ -23,6 +23,8 @@
 // contributions of layer L-1 (kept in registers) and layer L.  No atomics: the
 // result is deterministic.  Each element is computed by one block only in z
 // and by up to four blocks in x/y (halo), 256/225 ~ 1.14x element work.
+#include <hip/hip_ext.h>
+
 #include "common.h"
 #include "device_common.h"
 
@@ -559,8 +561,12 @@ hipError_t launch_matvec(const MvArgs<T> &a, int *nblocks, hipStream_t s) {
 
 template <typename T>
 hipError_t launch_cg_matvec(const CgDesc<T> *descs, const int2 *bmap_mv, int nb_mv, int parity,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_matvec<T>, dim3(nb_mv), dim3(MV_THREADS), 0, s, descs, bmap_mv, parity);
+                            hipStream_t s, hipEvent_t start, hipEvent_t stop) {
+  if (start && stop)  // timestamps taken by the dispatch itself
+    hipExtLaunchKernelGGL(k_cg_matvec<T>, dim3(nb_mv), dim3(MV_THREADS), 0, s, start, stop, 0,
+                          descs, bmap_mv, parity);
+  else
+    hipLaunchKernelGGL(k_cg_matvec<T>, dim3(nb_mv), dim3(MV_THREADS), 0, s, descs, bmap_mv, parity);
   return hipGetLastError();
 }
 
@@ -575,9 +581,9 @@ template hipError_t launch_matvec<double, MV_APPLY>(const MvArgs<double> &, int 
 template hipError_t launch_matvec<double, MV_RESID>(const MvArgs<double> &, int *, hipStream_t);
 template hipError_t launch_matvec<float, MV_APPLY>(const MvArgs<float> &, int *, hipStream_t);
 template hipError_t launch_cg_matvec<double>(const CgDesc<double> *, const int2 *, int, int,
-                                             hipStream_t);
+                                             hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_cg_matvec<float>(const CgDesc<float> *, const int2 *, int, int,
-                                            hipStream_t);
+                                            hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_cg_update<double>(const CgDesc<double> *, const int2 *, int, int,
                                              hipStream_t);
 template hipError_t launch_cg_update<float>(const CgDesc<float> *, const int2 *, int, int,

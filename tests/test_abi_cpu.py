@@ -54,7 +54,9 @@ def test_struct_layout_matches_header(tmp_path):
     """ctypes field offsets equal the C compiler's for include/to.h."""
     fields = [f for f, _ in L.ToProblem._fields_]
     src = tmp_path / "lay.c"
+    ifields = [f for f, _ in L.ToSolveInfo._fields_]
     body = "".join('printf("%%zu ", offsetof(to_problem, %s));' % f for f in fields)
+    body += "".join('printf("%%zu ", offsetof(to_solve_info, %s));' % f for f in ifields)
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "to.h"\n'
                    'int main(void){ %s printf("%%zu %%zu\\n", sizeof(to_problem), '
                    'sizeof(to_solve_info)); return 0; }' % body)
@@ -62,7 +64,8 @@ def test_struct_layout_matches_header(tmp_path):
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
                                            check=True).stdout.split()]
-    assert vals[:-2] == [getattr(L.ToProblem, f).offset for f in fields]
+    assert vals[:len(fields)] == [getattr(L.ToProblem, f).offset for f in fields]
+    assert vals[len(fields):-2] == [getattr(L.ToSolveInfo, f).offset for f in ifields]
     assert vals[-2] == ctypes.sizeof(L.ToProblem)
     assert vals[-1] == ctypes.sizeof(L.ToSolveInfo)
 
