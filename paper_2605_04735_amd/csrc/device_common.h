@@ -146,6 +146,69 @@ __device__ __forceinline__ double from_next_lane(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// ---- raw buffer access.  A buffer resource spans `bytes` bytes from p; a
+// lane whose offset lies past the end loads 0 and its store is dropped, so
+// lanes outside the grid take the offset OOB instead of a branch.  Offsets are
+// 32-bit: voffset per lane, soffset uniform (an SGPR: the z plane).
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr unsigned OOB = 0x80000000u;
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void *p, unsigned bytes) {
+  // word 3 0x00020000: 32-bit raw data, range checked against `bytes`
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ void bload3(rsrc_t r, unsigned vo, unsigned so, float (&v)[3]) {
+  const auto w = __builtin_amdgcn_raw_buffer_load_b96(r, (int)vo, (int)so, 0);
+  v[0] = __uint_as_float(w[0]);
+  v[1] = __uint_as_float(w[1]);
+  v[2] = __uint_as_float(w[2]);
+}
+__device__ __forceinline__ void bload3(rsrc_t r, unsigned vo, unsigned so, double (&v)[3]) {
+  const auto a = __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, 0);
+  const auto b = __builtin_amdgcn_raw_buffer_load_b64(r, (int)(vo + 16u), (int)so, 0);
+  v[0] = __hiloint2double((int)a[1], (int)a[0]);
+  v[1] = __hiloint2double((int)a[3], (int)a[2]);
+  v[2] = __hiloint2double((int)b[1], (int)b[0]);
+}
+__device__ __forceinline__ void bstore3(rsrc_t r, unsigned vo, unsigned so, const float (&v)[3]) {
+  typedef unsigned u3 __attribute__((ext_vector_type(3)));
+  u3 w;
+  w[0] = __float_as_uint(v[0]);
+  w[1] = __float_as_uint(v[1]);
+  w[2] = __float_as_uint(v[2]);
+  __builtin_amdgcn_raw_buffer_store_b96(w, r, (int)vo, (int)so, 0);
+}
+__device__ __forceinline__ void bstore3(rsrc_t r, unsigned vo, unsigned so, const double (&v)[3]) {
+  typedef unsigned u4 __attribute__((ext_vector_type(4)));
+  typedef unsigned u2 __attribute__((ext_vector_type(2)));
+  u4 a;
+  a[0] = (unsigned)__double2loint(v[0]);
+  a[1] = (unsigned)__double2hiint(v[0]);
+  a[2] = (unsigned)__double2loint(v[1]);
+  a[3] = (unsigned)__double2hiint(v[1]);
+  u2 b;
+  b[0] = (unsigned)__double2loint(v[2]);
+  b[1] = (unsigned)__double2hiint(v[2]);
+  __builtin_amdgcn_raw_buffer_store_b128(a, r, (int)vo, (int)so, 0);
+  __builtin_amdgcn_raw_buffer_store_b64(b, r, (int)(vo + 16u), (int)so, 0);
+}
+__device__ __forceinline__ float bload1f(rsrc_t r, unsigned vo, unsigned so) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0));
+}
+__device__ __forceinline__ double bload1d(rsrc_t r, unsigned vo, unsigned so) {
+  const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0);
+  return __hiloint2double((int)w[1], (int)w[0]);
+}
+template <typename T>
+__device__ __forceinline__ T bload1(rsrc_t r, unsigned vo, unsigned so) {
+  if constexpr (sizeof(T) == 4) return bload1f(r, vo, so);
+  else return bload1d(r, vo, so);
+}
+__device__ __forceinline__ unsigned bload_u8(rsrc_t r, unsigned vo, unsigned so) {
+  return (unsigned)__builtin_amdgcn_raw_buffer_load_b8(r, (int)vo, (int)so, 0);
+}
+
 // Fixed-order sum of n block partials written by the previous kernel, done
 // by every block that needs it: the loads are independent batches per thread
 // (latency overlapped), followed by a fixed shuffle/wave tree, so each block
@@ -175,13 +238,25 @@ __device__ inline double block_fixed_sum(const double *v, int n, double *sh) {
   return r;
 }
 
-// Two fixed-order sums (same length) with one round of loads.
-__device__ inline void block_fixed_sum2(const double *u, const double *v, int n, double *sh, double &su,
-                                 double &sv) {
+// Two fixed-order sums (same length): loads in independent batches of
+// K per thread (one round trip for n <= K blockDim.x), then the fixed tree.
+__device__ inline void block_fixed_sum2(const double *u, const double *v, int n, double *sh,
+                                        double &su, double &sv) {
+  constexpr int K = 4;
   double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    a += u[i];
-    b += v[i];
+  for (int base = 0; base < n; base += K * (int)blockDim.x) {
+    double ta[K], tb[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = base + k * (int)blockDim.x + (int)threadIdx.x;
+      ta[k] = (i < n) ? u[i] : 0.0;
+      tb[k] = (i < n) ? v[i] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      a += ta[k];
+      b += tb[k];
+    }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -204,6 +279,5 @@ __device__ inline void block_fixed_sum2(const double *u, const double *v, int n,
   }
   __syncthreads();
 }
-
 
 }  // namespace topo

@@ -49,11 +49,27 @@ template <typename T, int MODE, typename BetaFn>
 __device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int by, int bz,
                                                BetaFn &&get_beta, T (*pl)[3][TP * TP],
                                                T (*ex)[MV_THREADS], double *red) {
+  // CG inputs (z, p) are zero on fixed DOFs by construction and q there is
+  // never used (the update masks r), so only APPLY and RESID read the mask.
+  constexpr bool CG = MODE == MV_CG;
+  constexpr bool MASKED = !CG;
+  constexpr unsigned S = sizeof(T);
   const int tid = threadIdx.x;
   const int NX = a.nelx + 1, NY = a.nely + 1, NZ = a.nelz + 1;
   const int i0 = bx * TN, j0 = by * TN;
   const int k0 = bz * a.kz;
   const int k1 = min(k0 + a.kz, NZ);
+  const unsigned plane = (unsigned)NX * (unsigned)NY;
+  const unsigned eplane = (unsigned)a.nelx * (unsigned)a.nely;
+  const unsigned nn = plane * (unsigned)NZ;
+  const rsrc_t rIn = make_rsrc(a.in, 3u * nn * S);
+  const rsrc_t rOut = make_rsrc(a.out, 3u * nn * S);
+  const rsrc_t rE = make_rsrc(a.E, eplane * (unsigned)a.nelz * S);
+  // (resources a mode does not use span 0 bytes and are never accessed)
+  const rsrc_t rPo = make_rsrc(a.pold, CG ? 3u * nn * S : 0u);
+  const rsrc_t rPn = make_rsrc(a.pout, CG ? 3u * nn * S : 0u);
+  const rsrc_t rM = make_rsrc(a.mask, MASKED ? nn : 0u);
+  const rsrc_t rF = make_rsrc(a.f, MODE == MV_RESID ? 3u * nn * 8u : 0u);
 
   const int ei = tid % TE, ej = tid / TE;
   const int gi = i0 - 1 + ei, gj = j0 - 1 + ej;
@@ -61,49 +77,58 @@ __device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int b
   // the node owned by this lane: (i0 + ei, j0 + ej), interior of the tile
   const int gni = i0 + ei, gnj = j0 + ej;
   const bool own = ei < TN && ej < TN && gni < NX && gnj < NY;
-  const unsigned plane = (unsigned)NX * (unsigned)NY;
-  const unsigned eplane = (unsigned)a.nelx * (unsigned)a.nely;
-  const unsigned ebase = e_xy ? (unsigned)gi + (unsigned)a.nelx * (unsigned)gj : 0u;
-  const unsigned nbase = (unsigned)gni + (unsigned)NX * (unsigned)gnj;
+  const unsigned nown = (unsigned)gni + (unsigned)NX * (unsigned)gnj;
+  const unsigned voE = e_xy ? ((unsigned)gi + (unsigned)a.nelx * (unsigned)gj) * S : OOB;
+  const unsigned voOwn = own ? 3u * S * nown : OOB;
 
-  // register staging of one node plane (17 x 17 nodes, two slots per lane)
-  T rin[2][3], rpo[2][3];
-  unsigned rm[2], rbase[2];
-  bool rv[2], rown[2];
+  // per lane, two slots of the 17 x 17 node plane; their buffer offsets
+  unsigned voN[2], voM[2], voP[2];
 #pragma unroll
   for (int sl = 0; sl < 2; ++sl) {
     const int idx = tid + sl * MV_THREADS;
     const int li = idx % TP, lj = idx / TP;
     const int gx = i0 - 1 + li, gy = j0 - 1 + lj;
-    rv[sl] = idx < TP * TP && gx >= 0 && gx < NX && gy >= 0 && gy < NY;
-    rown[sl] = li >= 1 && li <= TN && lj >= 1 && lj <= TN;
-    rbase[sl] = rv[sl] ? (unsigned)gx + (unsigned)NX * (unsigned)gy : 0u;
+    const bool v = idx < TP * TP && gx >= 0 && gx < NX && gy >= 0 && gy < NY;
+    const bool mine = li >= 1 && li <= TN && lj >= 1 && lj <= TN;
+    const unsigned n = (unsigned)gx + (unsigned)NX * (unsigned)gy;
+    voN[sl] = v ? 3u * S * n : OOB;
+    voM[sl] = v ? n : OOB;
+    voP[sl] = v && mine ? 3u * S * n : OOB;
   }
-  auto fetch = [&](int kp) {
-    const bool inz = kp >= 0 && kp < NZ;
+
+  // register ring: two node planes (and the moduli of the element layer on
+  // top of each) in flight while a layer computes
+  struct Plane {
+    T in[2][3], po[2][3];
+    unsigned m[2];
+    T e;
+  };
+  auto fetch = [&](Plane &R, int kp) {
+    if (kp < 0 || kp >= NZ) {  // uniform
+#pragma unroll
+      for (int sl = 0; sl < 2; ++sl) {
+        R.m[sl] = 7u;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) R.in[sl][c] = R.po[sl][c] = T(0);
+      }
+      R.e = T(0);
+      return;
+    }
+    const unsigned so = (unsigned)kp * plane * 3u * S;
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
-      rm[sl] = 7u;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        rin[sl][c] = 0;
-        rpo[sl][c] = 0;
-      }
-      if (rv[sl] && inz) {
-        const unsigned n = rbase[sl] + plane * (unsigned)kp;
-        rm[sl] = a.mask[n];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          rin[sl][c] = a.in[3u * n + c];
-          if (MODE == MV_CG) rpo[sl][c] = a.pold[3u * n + c];
-        }
-      }
+      bload3(rIn, voN[sl], so, R.in[sl]);
+      if constexpr (CG) bload3(rPo, voN[sl], so, R.po[sl]);
+      if constexpr (MASKED) R.m[sl] = bload_u8(rM, voM[sl], (unsigned)kp * plane);
     }
+    R.e = kp < a.nelz ? bload1<T>(rE, voE, (unsigned)kp * eplane * S) : T(0);
   };
   T beta = 0;
-  auto stage = [&](int kp) {
+  // plane kp into LDS (CG: p = z + beta p_old, and p written out for the
+  // nodes this block owns); returns the moduli of element layer kp
+  auto stage = [&](Plane &R, int kp) -> T {
     T(*dst)[TP * TP] = pl[kp & 1];
-    const bool wr = MODE == MV_CG && kp >= k0 && kp < k1;
+    const bool wr = CG && kp >= k0 && kp < k1;
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
       const int idx = tid + sl * MV_THREADS;
@@ -111,62 +136,37 @@ __device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int b
       T v[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const bool fx = (rm[sl] >> c) & 1u;
-        v[c] = fx ? T(0) : rin[sl][c];
-        if (MODE == MV_CG) v[c] = fx ? T(0) : v[c] + beta * rpo[sl][c];
+        if constexpr (CG) v[c] = R.in[sl][c] + beta * R.po[sl][c];
+        else v[c] = ((R.m[sl] >> c) & 1u) ? T(0) : R.in[sl][c];
         dst[c][idx] = v[c];
       }
-      if (wr && rv[sl] && rown[sl]) {
-        const unsigned n = rbase[sl] + plane * (unsigned)kp;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) a.pout[3u * n + c] = v[c];
-      }
+      if (wr) bstore3(rPn, voP[sl], (unsigned)kp * plane * 3u * S, v);
     }
-  };
-  auto modulus = [&](int L) -> T {
-    return (e_xy && L >= 0 && L < a.nelz) ? a.E[ebase + eplane * (unsigned)L] : T(0);
+    return R.e;
   };
 
   const int fidx = ei + TP * ej;  // corner (0,0) of this lane's element face in a plane
-  T F0[3][4];                     // forward face transform, plane L
-  T Gc[3][4];                     // accumulated inverse face transform, plane L
   double acc = 0.0;
-  fetch(k0 - 1);
-  // the scalars of the step (CG: the previous reduction) while the first
-  // plane is in flight; false: nothing to do for this design
-  if (!get_beta(beta)) return 0.0;
-  stage(k0 - 1);
-  fetch(k0);
-  T Ecur = modulus(k0 - 1);
-  __syncthreads();
-  face_forward(pl[(k0 - 1) & 1], fidx, F0);
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int m = 0; m < 4; ++m) Gc[c][m] = 0;
-  for (int L = k0 - 1; L < k1; ++L) {
-    stage(L + 1);
-    if (L + 2 <= k1) fetch(L + 2);
-    const T Enext = modulus(L + 1);
-    __syncthreads();
+  T acc_t = 0;  // CG: this lane's p^T q terms (at most 3 kz), in the product's precision
+  // one element layer L: faces Fb (plane L, transformed) -> Ft (plane L+1),
+  // inverse-transform carry Gb (plane L so far) -> Gt (plane L+1 so far)
+  auto layer = [&](int L, T E, T (&Fb)[3][4], T (&Ft)[3][4], T (&Gb)[3][4], T (&Gt)[3][4]) {
     T pn[3] = {0, 0, 0};
-    if (MODE == MV_CG && own) {
+    if (CG && own) {
       const int idx = (ei + 1) + TP * (ej + 1);
 #pragma unroll
       for (int c = 0; c < 3; ++c) pn[c] = pl[L & 1][c][idx];
     }
-    T F1[3][4];
-    face_forward(pl[(L + 1) & 1], fidx, F1);
+    face_forward(pl[(L + 1) & 1], fidx, Ft);
     T C[3][8], D[3][8];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        C[c][m] = F1[c][m] + F0[c][m];
-        C[c][m + 4] = F1[c][m] - F0[c][m];
-        F0[c][m] = F1[c][m];
+        C[c][m] = Ft[c][m] + Fb[c][m];
+        C[c][m + 4] = Ft[c][m] - Fb[c][m];
       }
-    modal_stress(C, Ecur, a.k, D);
+    modal_stress(C, E, a.k, D);
     // inverse z butterfly: bottom (plane L) and top (plane L+1) face parts;
     // plane L is now complete in transform space
     T A[3][4];
@@ -174,49 +174,91 @@ __device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int b
     for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        A[c][m] = Gc[c][m] + (D[c][m] - D[c][m + 4]);
-        Gc[c][m] = D[c][m] + D[c][m + 4];
+        A[c][m] = Gb[c][m] + (D[c][m] - D[c][m + 4]);
+        Gt[c][m] = D[c][m] + D[c][m + 4];
       }
     // inverse x and y butterflies -> corner values y(ax, ay); then x combine
     T xc[3][2];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const T e00 = A[c][0] - A[c][1], e10 = A[c][0] + A[c][1];   // my = 0
-      const T e01 = A[c][2] - A[c][3], e11 = A[c][2] + A[c][3];   // my = 1
-      const T y00 = e00 - e01, y01 = e00 + e01;                   // ax = 0
-      const T y10 = e10 - e11, y11 = e10 + e11;                   // ax = 1
+      const T e00 = A[c][0] - A[c][1], e10 = A[c][0] + A[c][1];  // my = 0
+      const T e01 = A[c][2] - A[c][3], e11 = A[c][2] + A[c][3];  // my = 1
+      const T y00 = e00 - e01, y01 = e00 + e01;                  // ax = 0
+      const T y10 = e10 - e11, y11 = e10 + e11;                  // ax = 1
       xc[c][0] = y10 + from_next_lane(y00);
       xc[c][1] = y11 + from_next_lane(y01);
       ex[c][tid] = xc[c][0];
     }
     __syncthreads();
     if (own && L >= k0) {
-      const unsigned n = nbase + plane * (unsigned)L;
+      const unsigned so = (unsigned)L * plane * 3u * S;
       T val[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) val[c] = xc[c][1] + ex[c][tid + TE];
-      const unsigned m = a.mask[n];
-      if (MODE == MV_APPLY) {
+      if constexpr (MODE == MV_CG) {
+        bstore3(rOut, voOwn, so, val);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) a.out[3u * n + c] = ((m >> c) & 1u) ? a.in[3u * n + c] : val[c];
-      } else if (MODE == MV_CG) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const T q = ((m >> c) & 1u) ? T(0) : val[c];
-          a.out[3u * n + c] = q;
-          acc += (double)pn[c] * (double)q;
-        }
+        for (int c = 0; c < 3; ++c) acc_t += pn[c] * val[c];
       } else {
+        const unsigned m = bload_u8(rM, nown, (unsigned)L * plane);
+        if constexpr (MODE == MV_APPLY) {
+          T u[3];
+          bload3(rIn, voOwn, so, u);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const double r = ((m >> c) & 1u) ? 0.0 : a.f[3u * n + c] - (double)val[c];
-          a.out[3u * n + c] = (T)r;
-          acc += r * r;
+          for (int c = 0; c < 3; ++c) val[c] = ((m >> c) & 1u) ? u[c] : val[c];
+          bstore3(rOut, voOwn, so, val);
+        } else {
+          double f[3];
+          bload3(rF, 3u * 8u * nown, (unsigned)L * plane * 24u, f);
+          T r[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const double rd = ((m >> c) & 1u) ? 0.0 : f[c] - (double)val[c];
+            r[c] = (T)rd;
+            acc += rd * rd;
+          }
+          bstore3(rOut, voOwn, so, r);
         }
       }
     }
-    Ecur = Enext;
+  };
+
+  Plane R0, R1;
+  fetch(R0, k0 - 1);
+  fetch(R1, k0);
+  // the scalars of the step (CG: the previous reduction) while the first
+  // planes are in flight; false: nothing to do for this design
+  if (!get_beta(beta)) return 0.0;
+  T E = stage(R0, k0 - 1);
+  if (k0 + 1 <= k1) fetch(R0, k0 + 1);
+  __syncthreads();
+  T Fa[3][4], Fb[3][4], Ga[3][4], Gb[3][4];
+  face_forward(pl[(k0 - 1) & 1], fidx, Fa);
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) Ga[c][m] = 0;
+  // layer L stages plane L + 1 from the ring and refills its set with plane
+  // L + 3; unrolled by two so that ring sets and carries alternate statically
+  for (int L = k0 - 1;;) {
+    {
+      const T En = stage(R1, L + 1);
+      if (L + 3 <= k1) fetch(R1, L + 3);
+      __syncthreads();
+      layer(L, E, Fa, Fb, Ga, Gb);
+      E = En;
+    }
+    if (++L >= k1) break;
+    {
+      const T En = stage(R0, L + 1);
+      if (L + 3 <= k1) fetch(R0, L + 3);
+      __syncthreads();
+      layer(L, E, Fb, Fa, Gb, Ga);
+      E = En;
+    }
+    if (++L >= k1) break;
   }
+  if constexpr (MODE == MV_CG) acc = (double)acc_t;
   if (MODE != MV_APPLY) return block_sum_d(acc, red);
   return 0.0;
 }
@@ -409,7 +451,6 @@ __global__ __launch_bounds__(MV_THREADS) void k_cg_matvec(const CgDesc<T> *descs
   const int2 bm = blockmap[blockIdx.x];
   if (bm.x < 0) return;  // padding entry
   const CgDesc<T> &d = descs[bm.x];
-  if (d.flags[F_DONE]) return;
   const int lb = bm.y;
   MvArgs<T> a;
   a.nelx = d.nelx;
@@ -424,7 +465,11 @@ __global__ __launch_bounds__(MV_THREADS) void k_cg_matvec(const CgDesc<T> *descs
   a.mask = d.mask;
   a.k = d.k;
   const int bx = lb % d.tx, by = (lb / d.tx) % d.ty, bz = lb / (d.tx * d.ty);
+  bool run = false;
   auto get_beta = [&](T &beta) -> bool {
+    // checked once the first planes are in flight: a finished design only
+    // costs this block its loads
+    if (d.flags[F_DONE]) return false;
     double rz, rr;
     block_fixed_sum2(d.cgp + CGP_RZ + (parity ^ 1) * MAXB, d.cgp + CGP_RR + (parity ^ 1) * MAXB,
                      d.nb_up, red, rz, rr);
@@ -444,6 +489,7 @@ __global__ __launch_bounds__(MV_THREADS) void k_cg_matvec(const CgDesc<T> *descs
       d.scal[S_RR] = rr;
     }
     beta = (T)(rz / rz_old);
+    run = true;
     return true;
   };
   double s;
@@ -451,13 +497,14 @@ __global__ __launch_bounds__(MV_THREADS) void k_cg_matvec(const CgDesc<T> *descs
     s = matvec_block_nodecarry<T, MV_CG>(a, bx, by, bz, get_beta, pl, ex, red);
   else
     s = matvec_block<T, MV_CG>(a, bx, by, bz, get_beta, pl, ex, red);
-  if (threadIdx.x == 0) d.cgp[CGP_PQ + lb] = s;
+  if (run && threadIdx.x == 0) d.cgp[CGP_PQ + lb] = s;
 }
 
 // Batched CG vector update: every block completes the p^T q reduction of the
-// product, alpha = (r^T z) / (p^T q), then x += alpha p; r -= alpha q;
-// z = D r (fixed DOFs 0) and the block's r^T z and ||r||^2 partials go to set
-// `parity` for the next product.
+// product, alpha = (r^T z) / (p^T q), then x += alpha p; r -= alpha q (fixed
+// DOFs 0); z = D r, and the block's r^T z and ||r||^2 partials go to set
+// `parity` for the next product.  A thread's first two nodes are loaded before
+// the reduction, so their latency overlaps it.
 template <typename T>
 __global__ __launch_bounds__(256) void k_cg_update(const CgDesc<T> *descs, const int2 *blockmap,
                                                    int parity) {
@@ -465,6 +512,31 @@ __global__ __launch_bounds__(256) void k_cg_update(const CgDesc<T> *descs, const
   const int2 bm = blockmap[blockIdx.x];
   if (bm.x < 0) return;  // padding entry
   const CgDesc<T> &d = descs[bm.x];
+  constexpr unsigned S = sizeof(T);
+  const unsigned nn = (unsigned)d.nn;
+  const rsrc_t rX = make_rsrc(d.x, 3u * nn * S), rR = make_rsrc(d.r, 3u * nn * S);
+  const rsrc_t rZ = make_rsrc(d.z, 3u * nn * S), rQ = make_rsrc(d.q, 3u * nn * S);
+  const rsrc_t rP = make_rsrc(d.p[parity ^ 1], 3u * nn * S);
+  const rsrc_t rD = make_rsrc(d.dinv, nn * S), rM = make_rsrc(d.mask, nn);
+  const unsigned stride = (unsigned)d.nb_up * 256u;
+  struct Node {
+    T x[3], p[3], r[3], q[3], di;
+    unsigned m, vo;
+  };
+  auto load = [&](Node &v, unsigned n) {
+    const bool in = n < nn;
+    v.vo = in ? 3u * S * n : OOB;
+    bload3(rX, v.vo, 0, v.x);
+    bload3(rP, v.vo, 0, v.p);
+    bload3(rR, v.vo, 0, v.r);
+    bload3(rQ, v.vo, 0, v.q);
+    v.di = bload1<T>(rD, in ? S * n : OOB, 0);
+    v.m = bload_u8(rM, in ? n : OOB, 0);
+  };
+  const unsigned n0 = (unsigned)bm.y * 256u + threadIdx.x;
+  Node A, B;
+  load(A, n0);
+  load(B, n0 + stride);
   if (d.flags[F_DONE]) return;
   const double pq = block_fixed_sum(d.cgp + CGP_PQ, d.nb_mv, red);
   if (!(pq > 0.0) || !isfinite(pq)) {
@@ -477,38 +549,28 @@ __global__ __launch_bounds__(256) void k_cg_update(const CgDesc<T> *descs, const
   }
   const double rz = d.scal[S_RZ0 + (parity ^ 1)];
   const T alpha = (T)(rz / pq);
-  const T *__restrict__ p = d.p[parity ^ 1];
-  T *__restrict__ x = d.x;
-  T *__restrict__ r = d.r;
-  T *__restrict__ z = d.z;
-  const T *__restrict__ q = d.q;
-  const T *__restrict__ dinv = d.dinv;
-  const uint8_t *__restrict__ mask = d.mask;
-  const size_t nn = (size_t)d.nn;
-  const size_t stride = (size_t)d.nb_up * 256;
   double rzs = 0.0, rrs = 0.0;
-  for (size_t n = (size_t)bm.y * 256 + threadIdx.x; n < nn; n += stride) {
-    const unsigned m = mask[n];
-    const T di = dinv[n];
-    T xv[3], pv[3], rv[3], qv[3];
+  auto update = [&](const Node &v) {
+    T xn[3], rn[3], zn[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      xv[c] = x[3 * n + c];
-      pv[c] = p[3 * n + c];
-      rv[c] = r[3 * n + c];
-      qv[c] = q[3 * n + c];
+      xn[c] = v.x[c] + alpha * v.p[c];
+      rn[c] = ((v.m >> c) & 1u) ? T(0) : v.r[c] - alpha * v.q[c];
+      zn[c] = v.di * rn[c];
+      rzs += (double)rn[c] * (double)zn[c];
+      rrs += (double)rn[c] * (double)rn[c];
     }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const T xn = xv[c] + alpha * pv[c];
-      const T rn = ((m >> c) & 1u) ? T(0) : rv[c] - alpha * qv[c];
-      const T zn = di * rn;
-      x[3 * n + c] = xn;
-      r[3 * n + c] = rn;
-      z[3 * n + c] = zn;
-      rzs += (double)rn * (double)zn;
-      rrs += (double)rn * (double)rn;
-    }
+    bstore3(rX, v.vo, 0, xn);
+    bstore3(rR, v.vo, 0, rn);
+    bstore3(rZ, v.vo, 0, zn);
+  };
+  update(A);
+  update(B);
+  for (unsigned n = n0 + 2u * stride; n < nn; n += 2u * stride) {
+    load(A, n);
+    load(B, n + stride);
+    update(A);
+    update(B);
   }
   const double s1 = block_sum_d(rzs, red);
   __syncthreads();

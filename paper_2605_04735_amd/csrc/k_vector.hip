@@ -165,7 +165,7 @@ int update_blocks(size_t nn) {
   if (const char *e = getenv("TOPO_UPB")) cap = (size_t)atoi(e);
   if (cap < 1) cap = 1;
   if (cap > (size_t)MAXB) cap = MAXB;
-  size_t b = (nn + 1023) / 1024;
+  size_t b = (nn + 511) / 512;  // two nodes per thread: both loaded before the p^T q sum
   if (b < 64) b = 64;
   if (b > cap) b = cap;
   if (b > (nn + 255) / 256) b = (nn + 255) / 256;
