@@ -59,8 +59,8 @@ struct to_ctx {
   int *cnt = nullptr, *toff = nullptr, *bsums = nullptr;
 
   // batched inner-CG tables for this single design
-  void *desc = nullptr;          // CgDesc<T> (T by precision)
-  int2 *bmap_mv = nullptr, *bmap_up = nullptr;
+  CgDesc<float> hd32{};          // CG descriptors, passed by value to the CG kernels
+  CgDesc<double> hd64{};
   double *cgp = nullptr;         // block partials of the batched CG kernels
   int nb_mv = 0, nb_up = 0;
   int parity = 0;
@@ -163,8 +163,6 @@ size_t carve(to_ctx *c, const Grid &g, int precision, char *base) {
   const size_t oCnt = L.take<int>(g.nel), oToff = L.take<int>(g.nel);
   const size_t oBs = L.take<int>(g.nel / 1024 + 4);
   const int nbm = matvec_blocks(g, matvec_kz(g)), nbu = update_blocks(g.nn);
-  const size_t oDesc = L.take<char>(std::max(sizeof(CgDesc<double>), sizeof(CgDesc<float>)));
-  const size_t oBm = L.take<int2>(nbm), oBu = L.take<int2>(nbu);
   const size_t oCgp = L.take<double>(CGP_SIZE);
   const size_t total = (L.off + 255) & ~size_t(255);
   if (base) {
@@ -189,9 +187,6 @@ size_t carve(to_ctx *c, const Grid &g, int precision, char *base) {
     c->cnt = (int *)(base + oCnt);
     c->toff = (int *)(base + oToff);
     c->bsums = (int *)(base + oBs);
-    c->desc = (void *)(base + oDesc);
-    c->bmap_mv = (int2 *)(base + oBm);
-    c->bmap_up = (int2 *)(base + oBu);
     c->cgp = (double *)(base + oCgp);
     c->nb_mv = nbm;
     c->nb_up = nbu;
@@ -310,7 +305,9 @@ to_status inner_pcg(to_ctx *c, T *const v[6], const T *dinv, double eta, int cap
   HIPCHK(launch_cg_init<T>(g, c->r64, c->scal, v[0], v[1], v[2], v[3], v[4], dinv, c->mask, c->cgp,
                            slot, c->nb_up, c->stream));
   HIPCHK(launch_finish_init(c->cgp, c->nb_up, slot, eta * eta, cap, c->scal, c->flags, c->stream));
-  const CgDesc<T> *desc = (const CgDesc<T> *)c->desc;
+  const CgDesc<T> *hd;
+  if constexpr (sizeof(T) == 4) hd = &c->hd32;
+  else hd = &c->hd64;
   int launched = 0;
   *iters = 0;
   *status = 0;
@@ -321,8 +318,8 @@ to_status inner_pcg(to_ctx *c, T *const v[6], const T *dinv, double eta, int cap
       // sampled away from the first launch after a host synchronisation
       if (c->prof && (launched + it) % c->prof_every == c->prof_every / 2)
         HIPCHK(prof_pair(c, &e0, &e1));
-      HIPCHK(launch_cg_matvec<T>(desc, c->bmap_mv, c->nb_mv, c->parity, c->stream, e0, e1));
-      HIPCHK(launch_cg_update<T>(desc, c->bmap_up, c->nb_up, c->parity, c->stream));
+      HIPCHK(launch_cg_matvec1<T>(*hd, c->parity, c->stream, e0, e1));
+      HIPCHK(launch_cg_update1<T>(*hd, c->parity, c->stream));
       c->parity ^= 1;
     }
     launched += n;
@@ -426,24 +423,9 @@ to_status to_create(const to_problem *prob, void *d_workspace, size_t bytes, voi
   }
   c->kz = matvec_kz(c->g);
   hipStream_t s = c->stream;
-  {
-    // single-design tables of the batched CG kernels
-    std::vector<int2> bm(c->nb_mv), bu(c->nb_up);
-    for (int b = 0; b < c->nb_mv; ++b) bm[b] = make_int2(0, xcd_local(b, c->nb_mv));
-    for (int b = 0; b < c->nb_up; ++b) bu[b] = make_int2(0, b);
-    bool ok = hipMemcpy(c->bmap_mv, bm.data(), bm.size() * sizeof(int2), hipMemcpyHostToDevice) ==
-                  hipSuccess &&
-              hipMemcpy(c->bmap_up, bu.data(), bu.size() * sizeof(int2), hipMemcpyHostToDevice) ==
-                  hipSuccess;
-    if (prob->precision == TO_PREC_FP64) {
-      const CgDesc<double> d = make_desc<double>(c, c->v64, c->E64, c->dinv64, c->k64);
-      ok = ok && hipMemcpy(c->desc, &d, sizeof(d), hipMemcpyHostToDevice) == hipSuccess;
-    } else {
-      const CgDesc<float> d = make_desc<float>(c, c->v32, c->E32, c->dinv32, c->k32);
-      ok = ok && hipMemcpy(c->desc, &d, sizeof(d), hipMemcpyHostToDevice) == hipSuccess;
-    }
-    if (!ok) return bail(TO_E_HIP, "uploading the CG tables failed");
-  }
+  // descriptors of the CG kernels (passed by value at each launch)
+  if (prob->precision == TO_PREC_FP64) c->hd64 = make_desc<double>(c, c->v64, c->E64, c->dinv64, c->k64);
+  else c->hd32 = make_desc<float>(c, c->v32, c->E32, c->dinv32, c->k32);
   if (prob->bc == TO_BC_CUSTOM) {
     // host arrays -> device: the per-DOF mask goes through the triangle
     // scratch (int array of nel >= ... may be small), so use a temporary

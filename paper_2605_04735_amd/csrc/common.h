@@ -141,6 +141,12 @@ hipError_t launch_cg_init(const Grid &g, const double *b, const double *scal, T 
 // One CG iteration for every design of a batch is the product kernel (with
 // its last-block step length) followed by the update kernel (last-block beta
 // and convergence test).  blockmaps: (design, local block) per block.
+// One design, descriptor by value (the single-solve path).
+template <typename T>
+hipError_t launch_cg_matvec1(const CgDesc<T> &d, int parity, hipStream_t s,
+                             hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
+template <typename T>
+hipError_t launch_cg_update1(const CgDesc<T> &d, int parity, hipStream_t s);
 template <typename T>
 hipError_t launch_cg_matvec(const CgDesc<T> *descs, const int2 *bmap_mv, int nb_mv, int parity,
                             hipStream_t s, hipEvent_t start = nullptr, hipEvent_t stop = nullptr);

@@ -437,21 +437,16 @@ void k_matvec(const MvArgs<T> a, int tx, int ty) {
   if (MODE != MV_APPLY && threadIdx.x == 0) a.part[lb] = s;
 }
 
-// Batched inner-CG product over a table of designs: blockmap[b] = (design,
-// local block).  Every block first completes the reduction of the previous
-// update (r^T z and ||r||^2, partial set parity^1): converged designs stop
-// here; otherwise beta = (r^T z)_new / (r^T z)_old, p = z + beta p_old,
-// q = K p, and the block's p^T q partial is written for the update kernel.
+// Inner-CG product, local block lb of design d.  Every block first completes
+// the reduction of the previous update (r^T z and ||r||^2, partial set
+// parity^1): converged designs stop here; otherwise beta = (r^T z)_new /
+// (r^T z)_old, p = z + beta p_old, q = K p, and the block's p^T q partial is
+// written for the update kernel.
 template <typename T>
-__global__ __launch_bounds__(MV_THREADS) void k_cg_matvec(const CgDesc<T> *descs,
-                                                          const int2 *blockmap, int parity) {
+__device__ __forceinline__ void cg_matvec_block(const CgDesc<T> &d, int lb, int parity) {
   __shared__ T pl[2][3][TP * TP];
   __shared__ T ex[6][MV_THREADS];
   __shared__ double red[8];
-  const int2 bm = blockmap[blockIdx.x];
-  if (bm.x < 0) return;  // padding entry
-  const CgDesc<T> &d = descs[bm.x];
-  const int lb = bm.y;
   MvArgs<T> a;
   a.nelx = d.nelx;
   a.nely = d.nely;
@@ -500,18 +495,30 @@ __global__ __launch_bounds__(MV_THREADS) void k_cg_matvec(const CgDesc<T> *descs
   if (run && threadIdx.x == 0) d.cgp[CGP_PQ + lb] = s;
 }
 
+// Batched form over a table of designs: blockmap[b] = (design, local block).
+template <typename T>
+__global__ __launch_bounds__(MV_THREADS) void k_cg_matvec(const CgDesc<T> *descs,
+                                                          const int2 *blockmap, int parity) {
+  const int2 bm = blockmap[blockIdx.x];
+  if (bm.x < 0) return;  // padding entry
+  cg_matvec_block<T>(descs[bm.x], bm.y, parity);
+}
+
+// One design, its descriptor passed by value (kernel arguments: no dependent
+// table loads before the block can start its own).
+template <typename T>
+__global__ __launch_bounds__(MV_THREADS) void k_cg_matvec1(const CgDesc<T> d, int parity) {
+  cg_matvec_block<T>(d, xcd_local(blockIdx.x, gridDim.x), parity);
+}
+
 // Batched CG vector update: every block completes the p^T q reduction of the
 // product, alpha = (r^T z) / (p^T q), then x += alpha p; r -= alpha q (fixed
 // DOFs 0); z = D r, and the block's r^T z and ||r||^2 partials go to set
 // `parity` for the next product.  A thread's first two nodes are loaded before
 // the reduction, so their latency overlaps it.
 template <typename T>
-__global__ __launch_bounds__(256) void k_cg_update(const CgDesc<T> *descs, const int2 *blockmap,
-                                                   int parity) {
+__device__ __forceinline__ void cg_update_block(const CgDesc<T> &d, int lb, int parity) {
   __shared__ double red[4];
-  const int2 bm = blockmap[blockIdx.x];
-  if (bm.x < 0) return;  // padding entry
-  const CgDesc<T> &d = descs[bm.x];
   constexpr unsigned S = sizeof(T);
   const unsigned nn = (unsigned)d.nn;
   const rsrc_t rX = make_rsrc(d.x, 3u * nn * S), rR = make_rsrc(d.r, 3u * nn * S);
@@ -533,14 +540,14 @@ __global__ __launch_bounds__(256) void k_cg_update(const CgDesc<T> *descs, const
     v.di = bload1<T>(rD, in ? S * n : OOB, 0);
     v.m = bload_u8(rM, in ? n : OOB, 0);
   };
-  const unsigned n0 = (unsigned)bm.y * 256u + threadIdx.x;
+  const unsigned n0 = (unsigned)lb * 256u + threadIdx.x;
   Node A, B;
   load(A, n0);
   load(B, n0 + stride);
   if (d.flags[F_DONE]) return;
   const double pq = block_fixed_sum(d.cgp + CGP_PQ, d.nb_mv, red);
   if (!(pq > 0.0) || !isfinite(pq)) {
-    if (bm.y == 0 && threadIdx.x == 0) {
+    if (lb == 0 && threadIdx.x == 0) {
       d.scal[S_PQ] = pq;
       d.flags[F_STATUS] = isfinite(pq) ? 1 : 2;
       d.flags[F_DONE] = 1;
@@ -576,14 +583,27 @@ __global__ __launch_bounds__(256) void k_cg_update(const CgDesc<T> *descs, const
   __syncthreads();
   const double s2 = block_sum_d(rrs, red);
   if (threadIdx.x == 0) {
-    d.cgp[CGP_RZ + parity * MAXB + bm.y] = s1;
-    d.cgp[CGP_RR + parity * MAXB + bm.y] = s2;
-    if (bm.y == 0) {
+    d.cgp[CGP_RZ + parity * MAXB + lb] = s1;
+    d.cgp[CGP_RR + parity * MAXB + lb] = s2;
+    if (lb == 0) {
       d.scal[S_PQ] = pq;
       d.scal[S_ALPHA] = rz / pq;
       d.flags[F_ITERS] = d.flags[F_ITERS] + 1;
     }
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_update(const CgDesc<T> *descs, const int2 *blockmap,
+                                                   int parity) {
+  const int2 bm = blockmap[blockIdx.x];
+  if (bm.x < 0) return;  // padding entry
+  cg_update_block<T>(descs[bm.x], bm.y, parity);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_update1(const CgDesc<T> d, int parity) {
+  cg_update_block<T>(d, blockIdx.x, parity);
 }
 
 int matvec_kz(const Grid &g) {
@@ -642,6 +662,29 @@ hipError_t launch_cg_update(const CgDesc<T> *descs, const int2 *bmap_up, int nb_
 template hipError_t launch_matvec<double, MV_APPLY>(const MvArgs<double> &, int *, hipStream_t);
 template hipError_t launch_matvec<double, MV_RESID>(const MvArgs<double> &, int *, hipStream_t);
 template hipError_t launch_matvec<float, MV_APPLY>(const MvArgs<float> &, int *, hipStream_t);
+template <typename T>
+hipError_t launch_cg_matvec1(const CgDesc<T> &d, int parity, hipStream_t s, hipEvent_t start,
+                             hipEvent_t stop) {
+  if (start && stop)
+    hipExtLaunchKernelGGL(k_cg_matvec1<T>, dim3(d.nb_mv), dim3(MV_THREADS), 0, s, start, stop, 0, d,
+                          parity);
+  else
+    hipLaunchKernelGGL(k_cg_matvec1<T>, dim3(d.nb_mv), dim3(MV_THREADS), 0, s, d, parity);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cg_update1(const CgDesc<T> &d, int parity, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_update1<T>, dim3(d.nb_up), dim3(256), 0, s, d, parity);
+  return hipGetLastError();
+}
+
+template hipError_t launch_cg_matvec1<double>(const CgDesc<double> &, int, hipStream_t, hipEvent_t,
+                                              hipEvent_t);
+template hipError_t launch_cg_matvec1<float>(const CgDesc<float> &, int, hipStream_t, hipEvent_t,
+                                             hipEvent_t);
+template hipError_t launch_cg_update1<double>(const CgDesc<double> &, int, hipStream_t);
+template hipError_t launch_cg_update1<float>(const CgDesc<float> &, int, hipStream_t);
 template hipError_t launch_cg_matvec<double>(const CgDesc<double> *, const int2 *, int, int,
                                              hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_cg_matvec<float>(const CgDesc<float> *, const int2 *, int, int,
