@@ -135,6 +135,32 @@ __device__ __forceinline__ double block_sum_d(double v, double *sh) {
   return r;
 }
 
+// Two block sums in one pass (thread 0 holds both); sh: 8 doubles.
+__device__ __forceinline__ void block_sum_d2(double a, double b, double *sh, double &sa,
+                                             double &sb) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_down(a, o, 64);
+    b += __shfl_down(b, o, 64);
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    sh[w] = a;
+    sh[w + 4] = b;
+  }
+  __syncthreads();
+  sa = 0.0;
+  sb = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 0; i < nw; ++i) {
+      sa += sh[i];
+      sb += sh[i + 4];
+    }
+  }
+}
+
 // Value of lane + 1 within each row of 16 lanes (0 for the last lane of a
 // row): the DPP row shift, no LDS traffic.
 __device__ __forceinline__ float from_next_lane(float v) {
@@ -210,75 +236,55 @@ __device__ __forceinline__ unsigned bload_u8(rsrc_t r, unsigned vo, unsigned so)
   return (unsigned)__builtin_amdgcn_raw_buffer_load_b8(r, (int)vo, (int)so, 0);
 }
 
-// Fixed-order sum of n block partials written by the previous kernel, done
-// by every block that needs it: the loads are independent batches per thread
-// (latency overlapped), followed by a fixed shuffle/wave tree, so each block
-// gets the bit-identical value and no block waits for another.
-__device__ inline double block_fixed_sum(const double *v, int n, double *sh) {
-  constexpr int K = 4;
-  double s = 0.0;
-  for (int base = 0; base < n; base += K * (int)blockDim.x) {
-    double t[K];
+// Fixed-order sums of n block partials (NV arrays of the same length), split
+// in two: load() issues this thread's first PK partials of each array (all of
+// them when n <= PK blockDim.x) so that their round trip can start before
+// other loads, sum() adds them in a fixed order (further batches if n is
+// larger), then a fixed shuffle/wave tree.  Every block gets the
+// bit-identical values.  sh: 8 doubles.
+template <int PK, int NV>
+struct Partials {
+  double t[NV][PK];
+  __device__ __forceinline__ void load(const double *const (&v)[NV], int n) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int i = base + k * (int)blockDim.x + (int)threadIdx.x;
-      t[k] = (i < n) ? v[i] : 0.0;
-    }
+    for (int k = 0; k < PK; ++k) {
+      const int i = k * (int)blockDim.x + (int)threadIdx.x;
 #pragma unroll
-    for (int k = 0; k < K; ++k) s += t[k];
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) sh[w] = s;
-  __syncthreads();
-  double r = 0.0;
-  const int nw = (blockDim.x + 63) >> 6;
-  for (int i = 0; i < nw; ++i) r += sh[i];
-  return r;
-}
-
-// Two fixed-order sums (same length): loads in independent batches of
-// K per thread (one round trip for n <= K blockDim.x), then the fixed tree.
-__device__ inline void block_fixed_sum2(const double *u, const double *v, int n, double *sh,
-                                        double &su, double &sv) {
-  constexpr int K = 4;
-  double a = 0.0, b = 0.0;
-  for (int base = 0; base < n; base += K * (int)blockDim.x) {
-    double ta[K], tb[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int i = base + k * (int)blockDim.x + (int)threadIdx.x;
-      ta[k] = (i < n) ? u[i] : 0.0;
-      tb[k] = (i < n) ? v[i] : 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      a += ta[k];
-      b += tb[k];
+      for (int a = 0; a < NV; ++a) t[a][k] = (i < n) ? v[a][i] : 0.0;
     }
   }
+  __device__ __forceinline__ void sum(const double *const (&v)[NV], int n, double *sh,
+                                      double (&out)[NV]) {
+    double s[NV];
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    a += __shfl_down(a, o, 64);
-    b += __shfl_down(b, o, 64);
+    for (int a = 0; a < NV; ++a) {
+      s[a] = 0.0;
+#pragma unroll
+      for (int k = 0; k < PK; ++k) s[a] += t[a][k];
+    }
+    for (int base = PK * (int)blockDim.x; base < n; base += (int)blockDim.x) {
+      const int i = base + (int)threadIdx.x;
+#pragma unroll
+      for (int a = 0; a < NV; ++a) s[a] += (i < n) ? v[a][i] : 0.0;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+      for (int a = 0; a < NV; ++a) s[a] += __shfl_down(s[a], o, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+      for (int a = 0; a < NV; ++a) sh[w + 4 * a] = s[a];
+    __syncthreads();
+    const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int a = 0; a < NV; ++a) {
+      out[a] = 0.0;
+      for (int i = 0; i < nw; ++i) out[a] += sh[i + 4 * a];
+    }
+    __syncthreads();
   }
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) {
-    sh[w] = a;
-    sh[w + 4] = b;
-  }
-  __syncthreads();
-  su = 0.0;
-  sv = 0.0;
-  const int nw = (blockDim.x + 63) >> 6;
-  for (int i = 0; i < nw; ++i) {
-    su += sh[i];
-    sv += sh[i + 4];
-  }
-  __syncthreads();
-}
+};
 
 }  // namespace topo

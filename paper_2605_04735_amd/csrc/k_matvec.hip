@@ -45,10 +45,11 @@ namespace topo {
 // LDS), along y through a 3-value LDS exchange with the next tile row.  Node
 // plane L+2 is fetched into registers while layer L computes.  The
 // summation order is fixed: the result is deterministic.
-template <typename T, int MODE, typename BetaFn>
+template <typename T, int MODE, typename PreFn, typename BetaFn>
 __device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int by, int bz,
-                                               BetaFn &&get_beta, T (*pl)[3][TP * TP],
-                                               T (*ex)[MV_THREADS], double *red) {
+                                               PreFn &&pre, BetaFn &&get_beta,
+                                               T (*pl)[3][TP * TP], T (*ex)[MV_THREADS],
+                                               double *red) {
   // CG inputs (z, p) are zero on fixed DOFs by construction and q there is
   // never used (the update masks r), so only APPLY and RESID read the mask.
   constexpr bool CG = MODE == MV_CG;
@@ -224,10 +225,11 @@ __device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int b
   };
 
   Plane R0, R1;
+  pre();  // loads of the step's scalars (CG: the previous reduction) first
   fetch(R0, k0 - 1);
   fetch(R1, k0);
-  // the scalars of the step (CG: the previous reduction) while the first
-  // planes are in flight; false: nothing to do for this design
+  // the scalars complete while the first planes are in flight; false:
+  // nothing to do for this design
   if (!get_beta(beta)) return 0.0;
   T E = stage(R0, k0 - 1);
   if (k0 + 1 <= k1) fetch(R0, k0 + 1);
@@ -268,10 +270,11 @@ __device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int b
 // node sums carry along z in node space.  It needs far fewer registers than
 // the transform-space carry (which, with the fused direction update, pushes
 // float64 to two waves per SIMD or to spills) and measured faster there.
-template <typename T, int MODE, typename BetaFn>
+template <typename T, int MODE, typename PreFn, typename BetaFn>
 __device__ __forceinline__ double matvec_block_nodecarry(const MvArgs<T> &a, int bx, int by, int bz,
-                                                         BetaFn &&get_beta, T (*pl)[3][TP * TP],
-                                                         T (*ex)[MV_THREADS], double *red) {
+                                                         PreFn &&pre, BetaFn &&get_beta,
+                                                         T (*pl)[3][TP * TP], T (*ex)[MV_THREADS],
+                                                         double *red) {
   const int tid = threadIdx.x;
   const int NX = a.nelx + 1, NY = a.nely + 1, NZ = a.nelz + 1;
   const int i0 = bx * TN, j0 = by * TN;
@@ -347,6 +350,7 @@ __device__ __forceinline__ double matvec_block_nodecarry(const MvArgs<T> &a, int
 
   T carry[3] = {0, 0, 0};
   double acc = 0.0;
+  pre();
   fetch(k0 - 1);
   if (!get_beta(beta)) return 0.0;
   stage(k0 - 1);
@@ -433,7 +437,8 @@ void k_matvec(const MvArgs<T> a, int tx, int ty) {
   __shared__ double red[MV_THREADS / 64];
   const int lb = xcd_local(blockIdx.x, gridDim.x);
   const double s = matvec_block<T, MODE>(
-      a, lb % tx, (lb / tx) % ty, lb / (tx * ty), [](T &b) { b = T(0); return true; }, pl, ex, red);
+      a, lb % tx, (lb / tx) % ty, lb / (tx * ty), [] {}, [](T &b) { b = T(0); return true; }, pl,
+      ex, red);
   if (MODE != MV_APPLY && threadIdx.x == 0) a.part[lb] = s;
 }
 
@@ -461,17 +466,29 @@ __device__ __forceinline__ void cg_matvec_block(const CgDesc<T> &d, int lb, int 
   a.k = d.k;
   const int bx = lb % d.tx, by = (lb / d.tx) % d.ty, bz = lb / (d.tx * d.ty);
   bool run = false;
+  // the r^T z and ||r||^2 partials are loaded before the first planes, the
+  // flags and scalars in the same round trip; a finished design only costs
+  // this block its loads
+  const double *const parts[2] = {d.cgp + CGP_RZ + (parity ^ 1) * MAXB,
+                                  d.cgp + CGP_RR + (parity ^ 1) * MAXB};
+  Partials<2, 2> P;
+  int done = 0, iters = 0, cap = 0;
+  double rz_old = 0.0, tol2 = 0.0;
+  auto pre = [&] {
+    P.load(parts, d.nb_up);
+    done = d.flags[F_DONE];
+    iters = d.flags[F_ITERS];
+    cap = d.flags[F_CAP];
+    rz_old = d.scal[S_RZ0 + parity];
+    tol2 = d.scal[S_TOL2];
+  };
   auto get_beta = [&](T &beta) -> bool {
-    // checked once the first planes are in flight: a finished design only
-    // costs this block its loads
-    if (d.flags[F_DONE]) return false;
-    double rz, rr;
-    block_fixed_sum2(d.cgp + CGP_RZ + (parity ^ 1) * MAXB, d.cgp + CGP_RR + (parity ^ 1) * MAXB,
-                     d.nb_up, red, rz, rr);
-    const double rz_old = d.scal[S_RZ0 + parity];
-    const int iters = d.flags[F_ITERS];
+    double sums[2];
+    P.sum(parts, d.nb_up, red, sums);
+    const double rz = sums[0], rr = sums[1];
+    if (done) return false;
     const bool bad = !isfinite(rz) || !isfinite(rr);
-    if (bad || rr <= d.scal[S_TOL2] || iters >= d.flags[F_CAP]) {
+    if (bad || rr <= tol2 || iters >= cap) {
       if (lb == 0 && threadIdx.x == 0) {
         if (bad) d.flags[F_STATUS] = 2;
         d.scal[S_RR] = rr;
@@ -489,9 +506,9 @@ __device__ __forceinline__ void cg_matvec_block(const CgDesc<T> &d, int lb, int 
   };
   double s;
   if constexpr (sizeof(T) == 8)
-    s = matvec_block_nodecarry<T, MV_CG>(a, bx, by, bz, get_beta, pl, ex, red);
+    s = matvec_block_nodecarry<T, MV_CG>(a, bx, by, bz, pre, get_beta, pl, ex, red);
   else
-    s = matvec_block<T, MV_CG>(a, bx, by, bz, get_beta, pl, ex, red);
+    s = matvec_block<T, MV_CG>(a, bx, by, bz, pre, get_beta, pl, ex, red);
   if (run && threadIdx.x == 0) d.cgp[CGP_PQ + lb] = s;
 }
 
@@ -518,7 +535,7 @@ __global__ __launch_bounds__(MV_THREADS) void k_cg_matvec1(const CgDesc<T> d, in
 // the reduction, so their latency overlaps it.
 template <typename T>
 __device__ __forceinline__ void cg_update_block(const CgDesc<T> &d, int lb, int parity) {
-  __shared__ double red[4];
+  __shared__ double red[8];
   constexpr unsigned S = sizeof(T);
   const unsigned nn = (unsigned)d.nn;
   const rsrc_t rX = make_rsrc(d.x, 3u * nn * S), rR = make_rsrc(d.r, 3u * nn * S);
@@ -541,11 +558,18 @@ __device__ __forceinline__ void cg_update_block(const CgDesc<T> &d, int lb, int 
     v.m = bload_u8(rM, in ? n : OOB, 0);
   };
   const unsigned n0 = (unsigned)lb * 256u + threadIdx.x;
+  const double *const parts[1] = {d.cgp + CGP_PQ};
+  Partials<4, 1> P;
+  P.load(parts, d.nb_mv);
+  const int done = d.flags[F_DONE];
+  const double rz = d.scal[S_RZ0 + (parity ^ 1)];
   Node A, B;
   load(A, n0);
   load(B, n0 + stride);
-  if (d.flags[F_DONE]) return;
-  const double pq = block_fixed_sum(d.cgp + CGP_PQ, d.nb_mv, red);
+  double pqs[1];
+  P.sum(parts, d.nb_mv, red, pqs);
+  const double pq = pqs[0];
+  if (done) return;
   if (!(pq > 0.0) || !isfinite(pq)) {
     if (lb == 0 && threadIdx.x == 0) {
       d.scal[S_PQ] = pq;
@@ -554,7 +578,6 @@ __device__ __forceinline__ void cg_update_block(const CgDesc<T> &d, int lb, int 
     }
     return;
   }
-  const double rz = d.scal[S_RZ0 + (parity ^ 1)];
   const T alpha = (T)(rz / pq);
   double rzs = 0.0, rrs = 0.0;
   auto update = [&](const Node &v) {
@@ -579,9 +602,8 @@ __device__ __forceinline__ void cg_update_block(const CgDesc<T> &d, int lb, int 
     update(A);
     update(B);
   }
-  const double s1 = block_sum_d(rzs, red);
-  __syncthreads();
-  const double s2 = block_sum_d(rrs, red);
+  double s1, s2;
+  block_sum_d2(rzs, rrs, red, s1, s2);
   if (threadIdx.x == 0) {
     d.cgp[CGP_RZ + parity * MAXB + lb] = s1;
     d.cgp[CGP_RR + parity * MAXB + lb] = s2;
