@@ -319,6 +319,12 @@ def main():
     for k, v in products.items():
         log("product %s: %s" % (k, v))
 
+    # ---------------------------------------------------------- workloads
+    workloads = {}
+    if not args.no_large:
+        workloads["mbb_sdf_ersatz_192x64x32"] = workload_mbb_sdf(A, inputs, dev)
+        workloads["cantilever_256x128x128"] = workload_large(A, inputs, dev)
+
     # ---------------------------------------------------------- roofline
     # dominant kernel: the fused inner-CG product (p = z + beta p_old, q = K p,
     # p^T q) in float32; algorithmic bytes per launch: read z and p_old
@@ -364,6 +370,7 @@ def main():
         "cg_iters_per_s": {"fp32_refine": res_m["iters"][-1] * sps_m,
                            "fp64": res_d["iters"][-1] * sps_d},
         "products": products, "errors": errors, "triangles": ntri, "roofline": roofline,
+        "workloads": workloads,
     }
 
     # ---------------------------------------------------------- serving
@@ -374,6 +381,88 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x.cpu().numpy(), res_d["iters"][-1], ntri, args.cpu_iters)
     print(json.dumps(out), flush=True)
+
+
+def _timed_solve(A, ctx, x, u=None):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u, info, st = A.to_solve(ctx, x, u=u, raise_on_error=False)
+    c, dc = A.to_compliance_sensitivity(ctx, x, u)
+    torch.cuda.synchronize()
+    return u, c, dc, info, st, (time.perf_counter() - t0) * 1e3
+
+
+def workload_mbb_sdf(A, inputs, dev):
+    """MBB half-beam 192x64x32: SIMP-like densities (l = 6, kappa = 8, seed 2,
+    shifted so that 40% of the elements exceed 0.5) -> density->SDF at 0.5 ->
+    per-element volume fraction -> ersatz moduli E = max(vf, 1e-3) (penal 1,
+    Emin 0) -> compliance and sensitivity, float32-inner/float64-refined and
+    float64, both to rtol 1e-8, against a float64 solve to 1e-11."""
+    import torch
+    dims = (192, 64, 32)
+    x = torch.from_numpy(inputs.random_field(*dims, seed=2, ell=6.0, kappa=8.0,
+                                             solid_fraction=0.4)).to(dev)
+    geo = A.to_create(A.Problem(*dims, bc=A.BC_MBB))
+    A.to_density_to_sdf(geo, x, 0.5)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    phi, _, vf = A.to_density_to_sdf(geo, x, 0.5)
+    torch.cuda.synchronize()
+    t_sdf = (time.perf_counter() - t0) * 1e3
+    ntri = A.last_triangle_count(geo)
+    xe = torch.clamp(vf, min=1e-3)
+    out = {"sdf_ms": round(t_sdf, 3), "triangles": ntri,
+           "solid_fraction_vf": float(vf.mean().item())}
+    res = {}
+    for name, prec, rtol in (("reference", A.PREC_FP64, 1e-11), ("fp32_refine", A.PREC_FP32_REFINE, 1e-8),
+                             ("fp64", A.PREC_FP64, 1e-8)):
+        ctx = A.to_create(A.Problem(*dims, bc=A.BC_MBB, penal=1.0, Emin=0.0, precision=prec,
+                                    rtol=rtol, max_iters=10 ** 6))
+        _timed_solve(A, ctx, xe)  # warm
+        u, c, dc, info, st, ms = _timed_solve(A, ctx, xe)
+        res[name] = (u.cpu().numpy(), c, dc.cpu().numpy())
+        out[name] = {"ms": round(ms, 2), "status": A.L.STATUS_NAMES.get(st, st),
+                     "inner_iters": info["inner_iters"], "rel_res": info["rel_res"]}
+        ctx.close()
+    ur, cr, dcr = res["reference"]
+    for name in ("fp32_refine", "fp64"):
+        u, c, dc = res[name]
+        out[name]["err"] = {"u": rel2(u, ur), "c": abs(c - cr) / abs(cr), "dc": rel2(dc, dcr)}
+    log("mbb+sdf 192x64x32: sdf %.1f ms (%d triangles); fp32+refine %s; fp64 %s"
+        % (t_sdf, ntri, out["fp32_refine"], out["fp64"]))
+    return out
+
+
+def workload_large(A, inputs, dev):
+    """Cantilever 256x128x128 (12.8M DOF), random-field densities (l = 6,
+    kappa = 2, seed 3): float64, float32-inner/float64-refined, and the same
+    with the inner z stored in bfloat16, each to rtol 1e-8 with compliance and
+    sensitivity; errors of the mixed paths against the float64 one."""
+    import torch
+    dims = LARGE
+    x = torch.from_numpy(inputs.random_field(*dims, seed=3, ell=6.0, kappa=2.0)).to(dev)
+    out, res = {}, {}
+    for name, prec in (("fp64", A.PREC_FP64), ("fp32_refine", A.PREC_FP32_REFINE),
+                       ("fp32_refine_bf16", A.PREC_FP32_REFINE_BF16)):
+        ctx = A.to_create(A.Problem(*dims, precision=prec, rtol=1e-8, max_iters=10 ** 6))
+        u, c, dc, info, st, ms = _timed_solve(A, ctx, x)
+        res[name] = (u.cpu().numpy(), c, dc.cpu().numpy())
+        out[name] = {"ms": round(ms, 1), "status": A.L.STATUS_NAMES.get(st, st),
+                     "inner_iters": info["inner_iters"], "outer_iters": info["outer_iters"],
+                     "rel_res": info["rel_res"],
+                     "cg_iters_per_s": round(info["inner_iters"] / (ms * 1e-3), 1)}
+        ctx.close()
+        del u, dc
+        torch.cuda.empty_cache()
+    ud, cd, dcd = res["fp64"]
+    for name in ("fp32_refine", "fp32_refine_bf16"):
+        um, cm, dcm = res[name]
+        out[name]["err_vs_fp64"] = {"u": rel2(um, ud), "c": abs(cm - cd) / abs(cd),
+                                    "dc": rel2(dcm, dcd)}
+    log("cantilever 256x128x128: fp64 %s; fp32+refine %s; bf16 z %s"
+        % (out["fp64"], out["fp32_refine"], out["fp32_refine_bf16"]))
+    return out
 
 
 SERVE_GRIDS = [(32, 16, 16), (64, 32, 32), (96, 48, 48), (128, 64, 64)]

@@ -51,9 +51,12 @@ typedef enum { TO_BC_CANTILEVER = 0, TO_BC_MBB = 1, TO_BC_CUSTOM = 2 } to_bc;
 /* Arithmetic of the state solve.  FP64: Jacobi-PCG in float64 throughout.
  * FP32_REFINE: inner Jacobi-PCG with float32 vectors and float32 element
  * arithmetic, outer iterative refinement whose residual f - K u, norms and
- * solution update are float64.  FP32_REFINE_BF16: as FP32_REFINE with the CG
- * search direction stored in bfloat16 (the same rounded direction is used in
- * the product and in the solution update). */
+ * solution update are float64.  FP32_REFINE_BF16: as FP32_REFINE with the
+ * inner CG's preconditioned residual z stored in bfloat16 (search directions,
+ * residual and iterate stay float32; float32 arithmetic and accumulation):
+ * flexible CG, whose direction update keeps consecutive directions
+ * K-conjugate under the rounding.  Fewer bytes per iteration, more
+ * iterations; the float64 refinement sets the final accuracy. */
 typedef enum { TO_PREC_FP64 = 0, TO_PREC_FP32_REFINE = 1, TO_PREC_FP32_REFINE_BF16 = 2 } to_prec;
 
 typedef enum { TO_FILTER_DENS = 0, TO_FILTER_DENS_T = 1, TO_FILTER_SENS = 2 } to_filter_mode;

@@ -123,9 +123,6 @@ bool validate_problem(const to_problem *p, std::string *why) {
   }
   if (p->bc != TO_BC_CUSTOM && !std::isfinite(p->load_total)) { *why = "bad load_total"; return false; }
   if (p->precision < 0 || p->precision > 2) { *why = "unknown precision"; return false; }
-  if (p->precision == TO_PREC_FP32_REFINE_BF16) {
-    *why = "bfloat16 direction storage is not available in this build"; return false;
-  }
   if (!(p->rtol > 0) || !(p->rtol < 1)) { *why = "need 0 < rtol < 1"; return false; }
   if (p->max_iters < 1) { *why = "max_iters must be >= 1"; return false; }
   return true;
@@ -276,6 +273,7 @@ CgDesc<T> make_desc(to_ctx *c, T *const v[6], const T *E, const T *dinv, const C
   d.ty = (g.nely + 1 + TN - 1) / TN;
   d.nb_mv = c->nb_mv;
   d.nb_up = c->nb_up;
+  d.zbf16 = sizeof(T) == 4 && c->p.precision == TO_PREC_FP32_REFINE_BF16;
   d.nn = (long long)g.nn;
   d.k = k;
   d.E = E;
@@ -302,8 +300,9 @@ to_status inner_pcg(to_ctx *c, T *const v[6], const T *dinv, double eta, int cap
   const Grid &g = c->g;
   // the first product runs with parity c->parity and reads partial set parity ^ 1
   const int slot = c->parity ^ 1;
+  const int zbf = sizeof(T) == 4 && c->p.precision == TO_PREC_FP32_REFINE_BF16;
   HIPCHK(launch_cg_init<T>(g, c->r64, c->scal, v[0], v[1], v[2], v[3], v[4], dinv, c->mask, c->cgp,
-                           slot, c->nb_up, c->stream));
+                           slot, c->nb_up, c->stream, zbf));
   HIPCHK(launch_finish_init(c->cgp, c->nb_up, slot, eta * eta, cap, c->scal, c->flags, c->stream));
   const CgDesc<T> *hd;
   if constexpr (sizeof(T) == 4) hd = &c->hd32;
@@ -362,6 +361,7 @@ to_status residual64(to_ctx *c, const double *u) {
   HIPCHK(launch_set_scale(c->scal, c->stream));
   return TO_OK;
 }
+
 
 }  // namespace
 

@@ -24,6 +24,7 @@ enum Scal {
   S_TMP,
   S_RZ0,        // r^T z of the partial-sum set of parity 0 / 1 (batched CG)
   S_RZ1,
+  S_RP,         // bfloat16 directions: r^T p_old of the current iterate (see CGP_RP)
   S_COUNT = 16
 };
 enum Flag {
@@ -78,6 +79,7 @@ struct CgDesc {
   int nelx, nely, nelz, kz;
   int tx, ty;           // product tiles along x and y (blocks: tx * ty * tz)
   int nb_mv, nb_up;     // blocks of this design in the product / update kernels
+  int zbf16, pad_;      // float32 CG: z stored in bfloat16 (2 bytes per component)
   long long nn;
   Coef<T> k;
   const T *E;
@@ -96,7 +98,16 @@ struct CgDesc {
 constexpr int CGP_PQ = 0;
 constexpr int CGP_RZ = MAXB;          // + P * MAXB
 constexpr int CGP_RR = 3 * MAXB;      // + P * MAXB
-constexpr int CGP_SIZE = 5 * MAXB;
+// bfloat16 z only (flexible CG with one-step orthogonalisation), written with
+// r^T z (same parity): r_new^T p and z_new^T q partials.  Rounding z makes the
+// Jacobi preconditioner vary from one iteration to the next, so the identities
+// r_k^T p_(k-1) = 0 and beta = r^T z / (r^T z)_old no longer hold; the
+// direction update beta = -z_new^T q_old / p_old^T q_old keeps consecutive
+// directions K-conjugate, and the step length (r^T z + beta r^T p_old) /
+// p^T K p is the exact line search along p.
+constexpr int CGP_RP = 5 * MAXB;      // + P * MAXB
+constexpr int CGP_ZQ = 7 * MAXB;      // + P * MAXB
+constexpr int CGP_SIZE = 9 * MAXB;
 
 // Workgroups are dispatched to the 8 XCDs (each with its own L2) round-robin
 // by block index.  xcd_local maps block b of nb to a local tile index such
@@ -137,7 +148,7 @@ int vec_blocks(size_t nn);
 template <typename T>
 hipError_t launch_cg_init(const Grid &g, const double *b, const double *scal, T *x, T *r, T *z,
                           T *pA, T *pB, const T *dinv, const uint8_t *mask, double *cgp, int slot,
-                          int nb_up, hipStream_t s);
+                          int nb_up, hipStream_t s, int zbf = 0);  // zbf: z stored in bfloat16
 // One CG iteration for every design of a batch is the product kernel (with
 // its last-block step length) followed by the update kernel (last-block beta
 // and convergence test).  blockmaps: (design, local block) per block.

@@ -232,6 +232,25 @@ __device__ __forceinline__ T bload1(rsrc_t r, unsigned vo, unsigned so) {
   if constexpr (sizeof(T) == 4) return bload1f(r, vo, so);
   else return bload1d(r, vo, so);
 }
+// bfloat16 storage of float32 vectors (3 components of 2 bytes per node):
+// round to nearest even once, keep the rounded value in float32.
+__device__ __forceinline__ float bf16_round(float v) {
+  const __bf16 b = (__bf16)v;
+  return __uint_as_float((unsigned)__builtin_bit_cast(unsigned short, b) << 16);
+}
+__device__ __forceinline__ void bload3_bf16(rsrc_t r, unsigned vo, unsigned so, float (&v)[3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    v[c] = __uint_as_float(
+        (unsigned)__builtin_amdgcn_raw_buffer_load_b16(r, (int)(vo + 2u * c), (int)so, 0) << 16);
+}
+// v holds bfloat16-rounded values: the upper halves are exact
+__device__ __forceinline__ void bstore3_bf16(rsrc_t r, unsigned vo, unsigned so, const float (&v)[3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    __builtin_amdgcn_raw_buffer_store_b16((unsigned short)(__float_as_uint(v[c]) >> 16), r,
+                                          (int)(vo + 2u * c), (int)so, 2);
+}
 __device__ __forceinline__ unsigned bload_u8(rsrc_t r, unsigned vo, unsigned so) {
   return (unsigned)__builtin_amdgcn_raw_buffer_load_b8(r, (int)vo, (int)so, 0);
 }
@@ -241,7 +260,7 @@ __device__ __forceinline__ unsigned bload_u8(rsrc_t r, unsigned vo, unsigned so)
 // them when n <= PK blockDim.x) so that their round trip can start before
 // other loads, sum() adds them in a fixed order (further batches if n is
 // larger), then a fixed shuffle/wave tree.  Every block gets the
-// bit-identical values.  sh: 8 doubles.
+// bit-identical values.  sh: 4 NV doubles.
 template <int PK, int NV>
 struct Partials {
   double t[NV][PK];

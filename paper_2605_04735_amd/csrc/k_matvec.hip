@@ -45,14 +45,18 @@ namespace topo {
 // LDS), along y through a 3-value LDS exchange with the next tile row.  Node
 // plane L+2 is fetched into registers while layer L computes.  The
 // summation order is fixed: the result is deterministic.
-template <typename T, int MODE, typename PreFn, typename BetaFn>
+template <typename T, int MODE, bool ZBF = false, typename PreFn, typename BetaFn>
 __device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int by, int bz,
                                                PreFn &&pre, BetaFn &&get_beta,
                                                T (*pl)[3][TP * TP], T (*ex)[MV_THREADS],
                                                double *red) {
   // CG inputs (z, p) are zero on fixed DOFs by construction and q there is
   // never used (the update masks r), so only APPLY and RESID read the mask.
+  // ZBF: the preconditioned residual z arrives in bfloat16 (float32 arithmetic,
+  // float32 directions).
   constexpr bool CG = MODE == MV_CG;
+  static_assert(!ZBF || (CG && sizeof(T) == 4), "bfloat16 z: float32 CG only");
+  constexpr unsigned SZ = ZBF ? 2u : sizeof(T);  // bytes per component of the input vector
   constexpr bool MASKED = !CG;
   constexpr unsigned S = sizeof(T);
   const int tid = threadIdx.x;
@@ -63,7 +67,7 @@ __device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int b
   const unsigned plane = (unsigned)NX * (unsigned)NY;
   const unsigned eplane = (unsigned)a.nelx * (unsigned)a.nely;
   const unsigned nn = plane * (unsigned)NZ;
-  const rsrc_t rIn = make_rsrc(a.in, 3u * nn * S);
+  const rsrc_t rIn = make_rsrc(a.in, 3u * nn * SZ);
   const rsrc_t rOut = make_rsrc(a.out, 3u * nn * S);
   const rsrc_t rE = make_rsrc(a.E, eplane * (unsigned)a.nelz * S);
   // (resources a mode does not use span 0 bytes and are never accessed)
@@ -83,7 +87,7 @@ __device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int b
   const unsigned voOwn = own ? 3u * S * nown : OOB;
 
   // per lane, two slots of the 17 x 17 node plane; their buffer offsets
-  unsigned voN[2], voM[2], voP[2];
+  unsigned voN[2], voM[2], voP[2], voZ[2];  // voZ: the input vector (SZ bytes per component)
 #pragma unroll
   for (int sl = 0; sl < 2; ++sl) {
     const int idx = tid + sl * MV_THREADS;
@@ -94,6 +98,7 @@ __device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int b
     const unsigned n = (unsigned)gx + (unsigned)NX * (unsigned)gy;
     voN[sl] = v ? 3u * S * n : OOB;
     voM[sl] = v ? n : OOB;
+    voZ[sl] = v ? 3u * SZ * n : OOB;
     voP[sl] = v && mine ? 3u * S * n : OOB;
   }
 
@@ -116,9 +121,11 @@ __device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int b
       return;
     }
     const unsigned so = (unsigned)kp * plane * 3u * S;
+    const unsigned sz = (unsigned)kp * plane * 3u * SZ;
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
-      bload3(rIn, voN[sl], so, R.in[sl]);
+      if constexpr (ZBF) bload3_bf16(rIn, voZ[sl], sz, R.in[sl]);
+      else bload3(rIn, voZ[sl], sz, R.in[sl]);
       if constexpr (CG) bload3(rPo, voN[sl], so, R.po[sl]);
       if constexpr (MASKED) R.m[sl] = bload_u8(rM, voM[sl], (unsigned)kp * plane);
     }
@@ -447,11 +454,11 @@ void k_matvec(const MvArgs<T> a, int tx, int ty) {
 // parity^1): converged designs stop here; otherwise beta = (r^T z)_new /
 // (r^T z)_old, p = z + beta p_old, q = K p, and the block's p^T q partial is
 // written for the update kernel.
-template <typename T>
+template <typename T, bool ZBF = false>
 __device__ __forceinline__ void cg_matvec_block(const CgDesc<T> &d, int lb, int parity) {
   __shared__ T pl[2][3][TP * TP];
   __shared__ T ex[6][MV_THREADS];
-  __shared__ double red[8];
+  __shared__ double red[16];
   MvArgs<T> a;
   a.nelx = d.nelx;
   a.nely = d.nely;
@@ -469,11 +476,17 @@ __device__ __forceinline__ void cg_matvec_block(const CgDesc<T> &d, int lb, int 
   // the r^T z and ||r||^2 partials are loaded before the first planes, the
   // flags and scalars in the same round trip; a finished design only costs
   // this block its loads
-  const double *const parts[2] = {d.cgp + CGP_RZ + (parity ^ 1) * MAXB,
-                                  d.cgp + CGP_RR + (parity ^ 1) * MAXB};
-  Partials<2, 2> P;
+  constexpr int NP = ZBF ? 4 : 2;  // bfloat16 z: also r^T p_old, z^T q_old
+  const double *parts[NP];
+  parts[0] = d.cgp + CGP_RZ + (parity ^ 1) * MAXB;
+  parts[1] = d.cgp + CGP_RR + (parity ^ 1) * MAXB;
+  if constexpr (ZBF) {
+    parts[2] = d.cgp + CGP_RP + (parity ^ 1) * MAXB;
+    parts[3] = d.cgp + CGP_ZQ + (parity ^ 1) * MAXB;
+  }
+  Partials<2, NP> P;
   int done = 0, iters = 0, cap = 0;
-  double rz_old = 0.0, tol2 = 0.0;
+  double rz_old = 0.0, tol2 = 0.0, pq_old = 0.0;
   auto pre = [&] {
     P.load(parts, d.nb_up);
     done = d.flags[F_DONE];
@@ -481,9 +494,10 @@ __device__ __forceinline__ void cg_matvec_block(const CgDesc<T> &d, int lb, int 
     cap = d.flags[F_CAP];
     rz_old = d.scal[S_RZ0 + parity];
     tol2 = d.scal[S_TOL2];
+    if constexpr (ZBF) pq_old = d.scal[S_PQ];
   };
   auto get_beta = [&](T &beta) -> bool {
-    double sums[2];
+    double sums[NP];
     P.sum(parts, d.nb_up, red, sums);
     const double rz = sums[0], rr = sums[1];
     if (done) return false;
@@ -496,11 +510,17 @@ __device__ __forceinline__ void cg_matvec_block(const CgDesc<T> &d, int lb, int 
       }
       return false;
     }
+    double b = rz / rz_old;
+    if constexpr (ZBF) b = iters == 0 ? 0.0 : -sums[3] / pq_old;
     if (lb == 0 && threadIdx.x == 0) {
       d.scal[S_RZ0 + (parity ^ 1)] = rz;
       d.scal[S_RR] = rr;
+      if constexpr (ZBF) {
+        d.scal[S_BETA] = b;
+        d.scal[S_RP] = sums[2];
+      }
     }
-    beta = (T)(rz / rz_old);
+    beta = (T)b;
     run = true;
     return true;
   };
@@ -508,7 +528,7 @@ __device__ __forceinline__ void cg_matvec_block(const CgDesc<T> &d, int lb, int 
   if constexpr (sizeof(T) == 8)
     s = matvec_block_nodecarry<T, MV_CG>(a, bx, by, bz, pre, get_beta, pl, ex, red);
   else
-    s = matvec_block<T, MV_CG>(a, bx, by, bz, pre, get_beta, pl, ex, red);
+    s = matvec_block<T, MV_CG, ZBF>(a, bx, by, bz, pre, get_beta, pl, ex, red);
   if (run && threadIdx.x == 0) d.cgp[CGP_PQ + lb] = s;
 }
 
@@ -523,9 +543,9 @@ __global__ __launch_bounds__(MV_THREADS) void k_cg_matvec(const CgDesc<T> *descs
 
 // One design, its descriptor passed by value (kernel arguments: no dependent
 // table loads before the block can start its own).
-template <typename T>
+template <typename T, bool ZBF>
 __global__ __launch_bounds__(MV_THREADS) void k_cg_matvec1(const CgDesc<T> d, int parity) {
-  cg_matvec_block<T>(d, xcd_local(blockIdx.x, gridDim.x), parity);
+  cg_matvec_block<T, ZBF>(d, xcd_local(blockIdx.x, gridDim.x), parity);
 }
 
 // Batched CG vector update: every block completes the p^T q reduction of the
@@ -533,23 +553,25 @@ __global__ __launch_bounds__(MV_THREADS) void k_cg_matvec1(const CgDesc<T> d, in
 // DOFs 0); z = D r, and the block's r^T z and ||r||^2 partials go to set
 // `parity` for the next product.  A thread's first two nodes are loaded before
 // the reduction, so their latency overlaps it.
-template <typename T>
+template <typename T, bool ZBF = false>
 __device__ __forceinline__ void cg_update_block(const CgDesc<T> &d, int lb, int parity) {
   __shared__ double red[8];
   constexpr unsigned S = sizeof(T);
+  constexpr unsigned SZ = ZBF ? 2u : sizeof(T);  // stored z component
   const unsigned nn = (unsigned)d.nn;
   const rsrc_t rX = make_rsrc(d.x, 3u * nn * S), rR = make_rsrc(d.r, 3u * nn * S);
-  const rsrc_t rZ = make_rsrc(d.z, 3u * nn * S), rQ = make_rsrc(d.q, 3u * nn * S);
+  const rsrc_t rZ = make_rsrc(d.z, 3u * nn * SZ), rQ = make_rsrc(d.q, 3u * nn * S);
   const rsrc_t rP = make_rsrc(d.p[parity ^ 1], 3u * nn * S);
   const rsrc_t rD = make_rsrc(d.dinv, nn * S), rM = make_rsrc(d.mask, nn);
   const unsigned stride = (unsigned)d.nb_up * 256u;
   struct Node {
     T x[3], p[3], r[3], q[3], di;
-    unsigned m, vo;
+    unsigned m, vo, vz;  // vz: offset of the node's z (SZ bytes per component)
   };
   auto load = [&](Node &v, unsigned n) {
     const bool in = n < nn;
     v.vo = in ? 3u * S * n : OOB;
+    v.vz = in ? 3u * SZ * n : OOB;
     bload3(rX, v.vo, 0, v.x);
     bload3(rP, v.vo, 0, v.p);
     bload3(rR, v.vo, 0, v.r);
@@ -562,7 +584,10 @@ __device__ __forceinline__ void cg_update_block(const CgDesc<T> &d, int lb, int 
   Partials<4, 1> P;
   P.load(parts, d.nb_mv);
   const int done = d.flags[F_DONE];
-  const double rz = d.scal[S_RZ0 + (parity ^ 1)];
+  double rz = d.scal[S_RZ0 + (parity ^ 1)];
+  // bfloat16 z (a preconditioner that varies with the rounding): the exact
+  // line search along p, r^T p = r^T z + beta r^T p_old
+  if constexpr (ZBF) rz += d.scal[S_BETA] * d.scal[S_RP];
   Node A, B;
   load(A, n0);
   load(B, n0 + stride);
@@ -579,7 +604,7 @@ __device__ __forceinline__ void cg_update_block(const CgDesc<T> &d, int lb, int 
     return;
   }
   const T alpha = (T)(rz / pq);
-  double rzs = 0.0, rrs = 0.0;
+  double rzs = 0.0, rrs = 0.0, rps = 0.0, zqs = 0.0;
   auto update = [&](const Node &v) {
     T xn[3], rn[3], zn[3];
 #pragma unroll
@@ -587,12 +612,18 @@ __device__ __forceinline__ void cg_update_block(const CgDesc<T> &d, int lb, int 
       xn[c] = v.x[c] + alpha * v.p[c];
       rn[c] = ((v.m >> c) & 1u) ? T(0) : v.r[c] - alpha * v.q[c];
       zn[c] = v.di * rn[c];
+      if constexpr (ZBF) zn[c] = bf16_round(zn[c]);  // the z the next product reads
       rzs += (double)rn[c] * (double)zn[c];
       rrs += (double)rn[c] * (double)rn[c];
+      if constexpr (ZBF) {
+        rps += (double)rn[c] * (double)v.p[c];
+        zqs += (double)zn[c] * (double)v.q[c];
+      }
     }
     bstore3(rX, v.vo, 0, xn);
     bstore3(rR, v.vo, 0, rn);
-    bstore3(rZ, v.vo, 0, zn);
+    if constexpr (ZBF) bstore3_bf16(rZ, v.vz, 0, zn);
+    else bstore3(rZ, v.vz, 0, zn);
   };
   update(A);
   update(B);
@@ -602,9 +633,19 @@ __device__ __forceinline__ void cg_update_block(const CgDesc<T> &d, int lb, int 
     update(A);
     update(B);
   }
-  double s1, s2;
-  block_sum_d2(rzs, rrs, red, s1, s2);
+  double s1, s2, s3 = 0.0, s4 = 0.0;
+  if constexpr (ZBF) {
+    block_sum_d2(rzs, rrs, red, s1, s2);
+    __syncthreads();
+    block_sum_d2(rps, zqs, red, s3, s4);
+  } else {
+    block_sum_d2(rzs, rrs, red, s1, s2);
+  }
   if (threadIdx.x == 0) {
+    if constexpr (ZBF) {
+      d.cgp[CGP_RP + parity * MAXB + lb] = s3;
+      d.cgp[CGP_ZQ + parity * MAXB + lb] = s4;
+    }
     d.cgp[CGP_RZ + parity * MAXB + lb] = s1;
     d.cgp[CGP_RR + parity * MAXB + lb] = s2;
     if (lb == 0) {
@@ -623,9 +664,9 @@ __global__ __launch_bounds__(256) void k_cg_update(const CgDesc<T> *descs, const
   cg_update_block<T>(descs[bm.x], bm.y, parity);
 }
 
-template <typename T>
+template <typename T, bool ZBF>
 __global__ __launch_bounds__(256) void k_cg_update1(const CgDesc<T> d, int parity) {
-  cg_update_block<T>(d, blockIdx.x, parity);
+  cg_update_block<T, ZBF>(d, blockIdx.x, parity);
 }
 
 int matvec_kz(const Grid &g) {
@@ -687,17 +728,33 @@ template hipError_t launch_matvec<float, MV_APPLY>(const MvArgs<float> &, int *,
 template <typename T>
 hipError_t launch_cg_matvec1(const CgDesc<T> &d, int parity, hipStream_t s, hipEvent_t start,
                              hipEvent_t stop) {
+  if constexpr (sizeof(T) == 4) {
+    if (d.zbf16) {
+      if (start && stop)
+        hipExtLaunchKernelGGL((k_cg_matvec1<T, true>), dim3(d.nb_mv), dim3(MV_THREADS), 0, s, start,
+                              stop, 0, d, parity);
+      else
+        hipLaunchKernelGGL((k_cg_matvec1<T, true>), dim3(d.nb_mv), dim3(MV_THREADS), 0, s, d, parity);
+      return hipGetLastError();
+    }
+  }
   if (start && stop)
-    hipExtLaunchKernelGGL(k_cg_matvec1<T>, dim3(d.nb_mv), dim3(MV_THREADS), 0, s, start, stop, 0, d,
-                          parity);
+    hipExtLaunchKernelGGL((k_cg_matvec1<T, false>), dim3(d.nb_mv), dim3(MV_THREADS), 0, s, start,
+                          stop, 0, d, parity);
   else
-    hipLaunchKernelGGL(k_cg_matvec1<T>, dim3(d.nb_mv), dim3(MV_THREADS), 0, s, d, parity);
+    hipLaunchKernelGGL((k_cg_matvec1<T, false>), dim3(d.nb_mv), dim3(MV_THREADS), 0, s, d, parity);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_cg_update1(const CgDesc<T> &d, int parity, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_update1<T>, dim3(d.nb_up), dim3(256), 0, s, d, parity);
+  if constexpr (sizeof(T) == 4) {
+    if (d.zbf16) {
+      hipLaunchKernelGGL((k_cg_update1<T, true>), dim3(d.nb_up), dim3(256), 0, s, d, parity);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((k_cg_update1<T, false>), dim3(d.nb_up), dim3(256), 0, s, d, parity);
   return hipGetLastError();
 }
 

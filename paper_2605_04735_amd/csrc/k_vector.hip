@@ -187,7 +187,9 @@ __global__ __launch_bounds__(256) void k_cg_init(size_t nn, const double *__rest
                                                  T *__restrict__ p, T *__restrict__ p2,
                                                  const T *__restrict__ dinv,
                                                  const uint8_t *__restrict__ mask,
-                                                 double *__restrict__ rzp, double *__restrict__ rrp) {
+                                                 double *__restrict__ rzp, double *__restrict__ rrp,
+                                                 double *__restrict__ rpp, double *__restrict__ zqp,
+                                                 int zbf) {
   __shared__ double sh[4];
   const double sc = scal[S_SCALE];
   double rz = 0.0, rr = 0.0;
@@ -199,10 +201,19 @@ __global__ __launch_bounds__(256) void k_cg_init(size_t nn, const double *__rest
     for (int c = 0; c < 3; ++c) {
       const size_t i = 3 * n + c;
       const T rv = ((m >> c) & 1u) ? T(0) : (T)(b[i] * sc);
-      const T zv = di * rv;
+      T zv = di * rv;
       x[i] = 0;
       r[i] = rv;
-      z[i] = zv;
+      bool zdone = false;
+      if constexpr (sizeof(T) == 4) {
+        if (zbf) {  // z in bfloat16 (the float32 buffer's first half), rounded once
+          const __bf16 zb = (__bf16)zv;
+          zv = (T)(float)zb;
+          ((unsigned short *)z)[i] = __builtin_bit_cast(unsigned short, zb);
+          zdone = true;
+        }
+      }
+      if (!zdone) z[i] = zv;
       p[i] = 0;
       p2[i] = 0;
       rz += (double)rv * (double)zv;
@@ -214,15 +225,18 @@ __global__ __launch_bounds__(256) void k_cg_init(size_t nn, const double *__rest
   if (threadIdx.x == 0) {
     rzp[blockIdx.x] = s1;
     rrp[blockIdx.x] = s2;
+    rpp[blockIdx.x] = 0.0;  // r^T p_old and z^T q_old with p_old = 0
+    zqp[blockIdx.x] = 0.0;
   }
 }
 
 template <typename T>
 hipError_t launch_cg_init(const Grid &g, const double *b, const double *scal, T *x, T *r, T *z,
                           T *pA, T *pB, const T *dinv, const uint8_t *mask, double *cgp, int slot,
-                          int nb_up, hipStream_t s) {
+                          int nb_up, hipStream_t s, int zbf) {
   hipLaunchKernelGGL(k_cg_init<T>, dim3(nb_up), dim3(256), 0, s, g.nn, b, scal, x, r, z, pA, pB,
-                     dinv, mask, cgp + CGP_RZ + slot * MAXB, cgp + CGP_RR + slot * MAXB);
+                     dinv, mask, cgp + CGP_RZ + slot * MAXB, cgp + CGP_RR + slot * MAXB,
+                     cgp + CGP_RP + slot * MAXB, cgp + CGP_ZQ + slot * MAXB, zbf);
   return hipGetLastError();
 }
 
@@ -361,10 +375,10 @@ hipError_t launch_set_scale(double *scal, hipStream_t s) {
 
 template hipError_t launch_cg_init<double>(const Grid &, const double *, const double *, double *,
                                            double *, double *, double *, double *, const double *,
-                                           const uint8_t *, double *, int, int, hipStream_t);
+                                           const uint8_t *, double *, int, int, hipStream_t, int);
 template hipError_t launch_cg_init<float>(const Grid &, const double *, const double *, float *,
                                           float *, float *, float *, float *, const float *,
-                                          const uint8_t *, double *, int, int, hipStream_t);
+                                          const uint8_t *, double *, int, int, hipStream_t, int);
 template hipError_t launch_axpy_out<double>(const Grid &, double *, const double *,
                                             const double *, hipStream_t);
 template hipError_t launch_axpy_out<float>(const Grid &, double *, const float *, const double *,

@@ -109,7 +109,7 @@ CASES = [("config0", (24, 12, 6), A.BC_CANTILEVER, "uniform"),
 
 
 @pytest.mark.parametrize("name,dims,bc,kind", CASES)
-@pytest.mark.parametrize("prec", [A.PREC_FP64, A.PREC_FP32_REFINE])
+@pytest.mark.parametrize("prec", [A.PREC_FP64, A.PREC_FP32_REFINE, A.PREC_FP32_REFINE_BF16])
 def test_solve_vs_oracle(name, dims, bc, kind, prec):
     nelx, nely, nelz = dims
     print("solve", name, prec, flush=True)
@@ -125,11 +125,11 @@ def test_solve_vs_oracle(name, dims, bc, kind, prec):
     assert info["rel_res"] <= rtol
     c, dc = A.to_compliance_sensitivity(ctx, xg, u)
     uref, cref, dcref = _oracle_solution(nelx, nely, nelz, x, prob)
-    # float64: u, c, dc <= 1e-8.  float32 inner + float64 refinement: c and dc
-    # <= 1e-6; u only to 1e-5, because with E_min = 1e-9 the displacement of
-    # near-void regions is barely determined by the residual (their stiffness
-    # is below float32 resolution next to solid elements) while it hardly
-    # enters c or dc.
+    # float64: u, c, dc <= 1e-8.  float32 inner + float64 refinement (CG
+    # directions stored in float32 or bfloat16): c and dc <= 1e-6; u only to
+    # 1e-5, because with E_min = 1e-9 the displacement of near-void regions is
+    # barely determined by the residual (their stiffness is below float32
+    # resolution next to solid elements) while it hardly enters c or dc.
     tol = 1e-8 if prec == A.PREC_FP64 else 1e-6
     tol_u = 1e-8 if prec == A.PREC_FP64 else 1e-5
     un = cpu(u)
