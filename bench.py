@@ -59,7 +59,7 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=100)
     ap.add_argument("--no-serving", action="store_true", help="skip the request-stream benchmark")
     ap.add_argument("--requests", type=int, default=128)
-    ap.add_argument("--probe", choices=["copy", "cg", "product"], default=None,
+    ap.add_argument("--probe", choices=["copy", "cg", "cg3", "product"], default=None,
                     help="short runs for hardware-counter passes: a device copy of known size, "
                          "one workload solve, or products on 256x128x128")
     return ap.parse_args()
@@ -83,9 +83,10 @@ def probe(kind):
         log("copy probe: 5 copies of %d bytes (read %d, write %d each)" % (COPY_BYTES, COPY_BYTES,
                                                                              COPY_BYTES))
         return
-    if kind == "cg":
-        x = torch.from_numpy(inputs.random_field(*DIMS, seed=1, ell=6.0, kappa=2.0)).to(dev)
-        ctx = A.to_create(A.Problem(*DIMS, precision=A.PREC_FP32_REFINE, rtol=1e-4))
+    if kind in ("cg", "cg3"):
+        dims, seed, rtol = (DIMS, 1, 1e-4) if kind == "cg" else (LARGE, 3, 1e-2)
+        x = torch.from_numpy(inputs.random_field(*dims, seed=seed, ell=6.0, kappa=2.0)).to(dev)
+        ctx = A.to_create(A.Problem(*dims, precision=A.PREC_FP32_REFINE, rtol=rtol))
         u, info, _ = A.to_solve(ctx, x)
         torch.cuda.synchronize()
         log("cg probe: %s" % info)
@@ -333,10 +334,10 @@ def main():
     bytes_launch = 48 * nn + 4 * nel
     achieved = bytes_launch / (mv_us * 1e-6) / 1e9
     traffic = measured_traffic("pmc_cg_matvec_f32_cantilever_96x48x48.txt",
-                               "void topo::k_cg_matvec<float>")
+                               "void topo::k_cg_matvec1<float, false>")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_cg_matvec<float>", "avg_us": round(mv_us, 3),
+                "kernel": "k_cg_matvec1<float, false>", "avg_us": round(mv_us, 3),
                 "bytes_per_launch": bytes_launch}
 
     # ---------------------------------------------------------- errors
@@ -398,7 +399,7 @@ def workload_mbb_sdf(A, inputs, dev):
     shifted so that 40% of the elements exceed 0.5) -> density->SDF at 0.5 ->
     per-element volume fraction -> ersatz moduli E = max(vf, 1e-3) (penal 1,
     Emin 0) -> compliance and sensitivity, float32-inner/float64-refined and
-    float64, both to rtol 1e-8, against a float64 solve to 1e-11."""
+    float64, both to rtol 1e-8, against a float64 solve to 1e-10."""
     import torch
     dims = (192, 64, 32)
     x = torch.from_numpy(inputs.random_field(*dims, seed=2, ell=6.0, kappa=8.0,
@@ -415,7 +416,7 @@ def workload_mbb_sdf(A, inputs, dev):
     out = {"sdf_ms": round(t_sdf, 3), "triangles": ntri,
            "solid_fraction_vf": float(vf.mean().item())}
     res = {}
-    for name, prec, rtol in (("reference", A.PREC_FP64, 1e-11), ("fp32_refine", A.PREC_FP32_REFINE, 1e-8),
+    for name, prec, rtol in (("reference", A.PREC_FP64, 1e-10), ("fp32_refine", A.PREC_FP32_REFINE, 1e-8),
                              ("fp64", A.PREC_FP64, 1e-8)):
         ctx = A.to_create(A.Problem(*dims, bc=A.BC_MBB, penal=1.0, Emin=0.0, precision=prec,
                                     rtol=rtol, max_iters=10 ** 6))

@@ -25,6 +25,8 @@
 // and by up to four blocks in x/y (halo), 256/225 ~ 1.14x element work.
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+
 #include "common.h"
 #include "device_common.h"
 
@@ -679,11 +681,16 @@ int matvec_kz(const Grid &g) {
       return v;
     }
   }
-  // about 12 blocks per CU while keeping the z recompute (kz + 1)/kz small
-  int chunks = (3072 + tiles - 1) / tiles;
+  // about 8 blocks per CU while keeping the z recompute (kz + 1)/kz small,
+  // with the node planes split into chunks of (nearly) equal size: a short
+  // last chunk leaves its blocks idle for most of the launch
+  int chunks = std::max(1, 2048 / tiles);
   int kz = (NZ + chunks - 1) / chunks;
   if (kz < 2) kz = 2;
   if (kz > 32) kz = 32;
+  chunks = (NZ + kz - 1) / kz;
+  kz = (NZ + chunks - 1) / chunks;
+  if (kz < 2) kz = 2;
   while (tiles * ((NZ + kz - 1) / kz) > MAXB) ++kz;  // partial sums must fit
   return kz;
 }
