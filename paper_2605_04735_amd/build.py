@@ -18,6 +18,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 SOURCES = ["abi.cpp", "k_matvec.hip", "k_vector.hip", "k_filter.hip", "k_sdf.hip", "serve.cpp"]
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # the first 8 argument dwords of each kernel arrive preloaded in SGPRs
+         "-mllvm", "-amdgpu-kernarg-preload-count=8",
          "-Wno-unused-command-line-argument", "-I", INCLUDE, "-I", CSRC]
 
 

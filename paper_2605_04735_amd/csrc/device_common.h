@@ -257,19 +257,21 @@ __device__ __forceinline__ unsigned bload_u8(rsrc_t r, unsigned vo, unsigned so)
 
 // Fixed-order sums of n block partials (NV arrays of the same length), split
 // in two: load() issues this thread's first PK partials of each array (all of
-// them when n <= PK blockDim.x) so that their round trip can start before
-// other loads, sum() adds them in a fixed order (further batches if n is
-// larger), then a fixed shuffle/wave tree.  Every block gets the
-// bit-identical values.  sh: 4 NV doubles.
-template <int PK, int NV>
+// them when n <= PK BS; past n a buffer load returns 0, so there is
+// no select) so that their round trip can start before other loads; sum()
+// adds them in a fixed order (further batches only if n is larger), then a
+// fixed shuffle/wave tree.  Every block gets the bit-identical values.
+// sh: 4 NV doubles.
+template <int PK, int NV, int BS = 256>  // BS: threads per block
 struct Partials {
   double t[NV][PK];
   __device__ __forceinline__ void load(const double *const (&v)[NV], int n) {
 #pragma unroll
-    for (int k = 0; k < PK; ++k) {
-      const int i = k * (int)blockDim.x + (int)threadIdx.x;
+    for (int a = 0; a < NV; ++a) {
+      const rsrc_t r = make_rsrc(v[a], (unsigned)n * 8u);
 #pragma unroll
-      for (int a = 0; a < NV; ++a) t[a][k] = (i < n) ? v[a][i] : 0.0;
+      for (int k = 0; k < PK; ++k)
+        t[a][k] = bload1d(r, 8u * (k * BS + threadIdx.x), 0);
     }
   }
   __device__ __forceinline__ void sum(const double *const (&v)[NV], int n, double *sh,
@@ -281,10 +283,12 @@ struct Partials {
 #pragma unroll
       for (int k = 0; k < PK; ++k) s[a] += t[a][k];
     }
-    for (int base = PK * (int)blockDim.x; base < n; base += (int)blockDim.x) {
-      const int i = base + (int)threadIdx.x;
+    if (n > PK * BS) {
+      for (int base = PK * BS; base < n; base += BS) {
+        const int i = base + (int)threadIdx.x;
 #pragma unroll
-      for (int a = 0; a < NV; ++a) s[a] += (i < n) ? v[a][i] : 0.0;
+        for (int a = 0; a < NV; ++a) s[a] += (i < n) ? v[a][i] : 0.0;
+      }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1)
@@ -296,7 +300,7 @@ struct Partials {
 #pragma unroll
       for (int a = 0; a < NV; ++a) sh[w + 4 * a] = s[a];
     __syncthreads();
-    const int nw = (blockDim.x + 63) >> 6;
+    constexpr int nw = BS / 64;
 #pragma unroll
     for (int a = 0; a < NV; ++a) {
       out[a] = 0.0;

@@ -457,10 +457,37 @@ void k_matvec(const MvArgs<T> a, int tx, int ty) {
 // (r^T z)_old, p = z + beta p_old, q = K p, and the block's p^T q partial is
 // written for the update kernel.
 template <typename T, bool ZBF = false>
-__device__ __forceinline__ void cg_matvec_block(const CgDesc<T> &d, int lb, int parity) {
+__device__ __forceinline__ void cg_matvec_block(const CgDesc<T> &d, double *scal, int *flags,
+                                                double *cgp, int nparts, int lb_in, int parity) {
   __shared__ T pl[2][3][TP * TP];
   __shared__ T ex[6][MV_THREADS];
   __shared__ double red[16];
+  bool run = false;
+  // the r^T z and ||r||^2 partials are loaded before the first planes, the
+  // flags and scalars in the same round trip; a finished design only costs
+  // this block its loads
+  constexpr int NP = ZBF ? 4 : 2;  // bfloat16 z: also r^T p_old, z^T q_old
+  const double *parts[NP];
+  parts[0] = cgp + CGP_RZ + (parity ^ 1) * MAXB;
+  parts[1] = cgp + CGP_RR + (parity ^ 1) * MAXB;
+  if constexpr (ZBF) {
+    parts[2] = cgp + CGP_RP + (parity ^ 1) * MAXB;
+    parts[3] = cgp + CGP_ZQ + (parity ^ 1) * MAXB;
+  }
+  Partials<2, NP> P;
+  int done = 0, iters = 0, cap = 0;
+  double rz_old = 0.0, tol2 = 0.0, pq_old = 0.0;
+  // first the loads that need nothing but the leading arguments
+  P.load(parts, nparts);
+  done = flags[F_DONE];
+  iters = flags[F_ITERS];
+  cap = flags[F_CAP];
+  rz_old = scal[S_RZ0 + parity];
+  tol2 = scal[S_TOL2];
+  if constexpr (ZBF) pq_old = scal[S_PQ];
+  __builtin_amdgcn_sched_barrier(0);  // keep those loads first
+  // then every descriptor field in one round trip (the empty asm makes the
+  // values needed at once, so their loads issue together)
   MvArgs<T> a;
   a.nelx = d.nelx;
   a.nely = d.nely;
@@ -468,58 +495,41 @@ __device__ __forceinline__ void cg_matvec_block(const CgDesc<T> &d, int lb, int 
   a.kz = d.kz;
   a.E = d.E;
   a.in = d.z;
-  a.pold = d.p[parity];
-  a.pout = d.p[parity ^ 1];
+  T *const p0 = d.p[0], *const p1 = d.p[1];
+  a.pold = parity ? p1 : p0;
+  a.pout = parity ? p0 : p1;
   a.out = d.q;
   a.mask = d.mask;
   a.k = d.k;
-  const int bx = lb % d.tx, by = (lb / d.tx) % d.ty, bz = lb / (d.tx * d.ty);
-  bool run = false;
-  // the r^T z and ||r||^2 partials are loaded before the first planes, the
-  // flags and scalars in the same round trip; a finished design only costs
-  // this block its loads
-  constexpr int NP = ZBF ? 4 : 2;  // bfloat16 z: also r^T p_old, z^T q_old
-  const double *parts[NP];
-  parts[0] = d.cgp + CGP_RZ + (parity ^ 1) * MAXB;
-  parts[1] = d.cgp + CGP_RR + (parity ^ 1) * MAXB;
-  if constexpr (ZBF) {
-    parts[2] = d.cgp + CGP_RP + (parity ^ 1) * MAXB;
-    parts[3] = d.cgp + CGP_ZQ + (parity ^ 1) * MAXB;
-  }
-  Partials<2, NP> P;
-  int done = 0, iters = 0, cap = 0;
-  double rz_old = 0.0, tol2 = 0.0, pq_old = 0.0;
-  auto pre = [&] {
-    P.load(parts, d.nb_up);
-    done = d.flags[F_DONE];
-    iters = d.flags[F_ITERS];
-    cap = d.flags[F_CAP];
-    rz_old = d.scal[S_RZ0 + parity];
-    tol2 = d.scal[S_TOL2];
-    if constexpr (ZBF) pq_old = d.scal[S_PQ];
-  };
+  const int tx = d.tx, ty = d.ty;
+  // local block: from the table (batched), or this block's XCD-contiguous tile
+  const int lb = lb_in >= 0 ? lb_in : xcd_local((int)blockIdx.x, d.nb_mv);
+  asm volatile("" ::"s"(a.nelx), "s"(a.nely), "s"(a.nelz), "s"(a.kz), "s"(tx), "s"(ty), "s"(a.E),
+               "s"(a.in), "s"(p0), "s"(p1), "s"(a.out), "s"(a.k.L2), "s"(a.k.M4), "s"(a.k.M2),
+               "s"(a.k.L2_3), "s"(a.k.M2_3), "s"(a.k.B9));
+  const int bx = lb % tx, by = (lb / tx) % ty, bz = lb / (tx * ty);
   auto get_beta = [&](T &beta) -> bool {
     double sums[NP];
-    P.sum(parts, d.nb_up, red, sums);
+    P.sum(parts, nparts, red, sums);
     const double rz = sums[0], rr = sums[1];
     if (done) return false;
     const bool bad = !isfinite(rz) || !isfinite(rr);
     if (bad || rr <= tol2 || iters >= cap) {
       if (lb == 0 && threadIdx.x == 0) {
-        if (bad) d.flags[F_STATUS] = 2;
-        d.scal[S_RR] = rr;
-        d.flags[F_DONE] = 1;
+        if (bad) flags[F_STATUS] = 2;
+        scal[S_RR] = rr;
+        flags[F_DONE] = 1;
       }
       return false;
     }
     double b = rz / rz_old;
     if constexpr (ZBF) b = iters == 0 ? 0.0 : -sums[3] / pq_old;
     if (lb == 0 && threadIdx.x == 0) {
-      d.scal[S_RZ0 + (parity ^ 1)] = rz;
-      d.scal[S_RR] = rr;
+      scal[S_RZ0 + (parity ^ 1)] = rz;
+      scal[S_RR] = rr;
       if constexpr (ZBF) {
-        d.scal[S_BETA] = b;
-        d.scal[S_RP] = sums[2];
+        scal[S_BETA] = b;
+        scal[S_RP] = sums[2];
       }
     }
     beta = (T)b;
@@ -528,10 +538,10 @@ __device__ __forceinline__ void cg_matvec_block(const CgDesc<T> &d, int lb, int 
   };
   double s;
   if constexpr (sizeof(T) == 8)
-    s = matvec_block_nodecarry<T, MV_CG>(a, bx, by, bz, pre, get_beta, pl, ex, red);
+    s = matvec_block_nodecarry<T, MV_CG>(a, bx, by, bz, [] {}, get_beta, pl, ex, red);
   else
-    s = matvec_block<T, MV_CG, ZBF>(a, bx, by, bz, pre, get_beta, pl, ex, red);
-  if (run && threadIdx.x == 0) d.cgp[CGP_PQ + lb] = s;
+    s = matvec_block<T, MV_CG, ZBF>(a, bx, by, bz, [] {}, get_beta, pl, ex, red);
+  if (run && threadIdx.x == 0) cgp[CGP_PQ + lb] = s;
 }
 
 // Batched form over a table of designs: blockmap[b] = (design, local block).
@@ -540,14 +550,19 @@ __global__ __launch_bounds__(MV_THREADS) void k_cg_matvec(const CgDesc<T> *descs
                                                           const int2 *blockmap, int parity) {
   const int2 bm = blockmap[blockIdx.x];
   if (bm.x < 0) return;  // padding entry
-  cg_matvec_block<T>(descs[bm.x], bm.y, parity);
+  const CgDesc<T> &d = descs[bm.x];
+  cg_matvec_block<T>(d, d.scal, d.flags, d.cgp, d.nb_up, bm.y, parity);
 }
 
-// One design, its descriptor passed by value (kernel arguments: no dependent
-// table loads before the block can start its own).
+// One design, its descriptor passed by value.  The scalars, flags, partial
+// sums, parity and partial count lead the arguments (8 dwords) so that they
+// arrive preloaded in SGPRs: the block's first loads (the previous reduction)
+// need no argument load before them.
 template <typename T, bool ZBF>
-__global__ __launch_bounds__(MV_THREADS) void k_cg_matvec1(const CgDesc<T> d, int parity) {
-  cg_matvec_block<T, ZBF>(d, xcd_local(blockIdx.x, gridDim.x), parity);
+__global__ __launch_bounds__(MV_THREADS) void k_cg_matvec1(double *scal, int *flags, double *cgp,
+                                                           int parity, int nparts,
+                                                           const CgDesc<T> d) {
+  cg_matvec_block<T, ZBF>(d, scal, flags, cgp, nparts, -1, parity);
 }
 
 // Batched CG vector update: every block completes the p^T q reduction of the
@@ -556,16 +571,35 @@ __global__ __launch_bounds__(MV_THREADS) void k_cg_matvec1(const CgDesc<T> d, in
 // `parity` for the next product.  A thread's first two nodes are loaded before
 // the reduction, so their latency overlaps it.
 template <typename T, bool ZBF = false>
-__device__ __forceinline__ void cg_update_block(const CgDesc<T> &d, int lb, int parity) {
+__device__ __forceinline__ void cg_update_block(const CgDesc<T> &d, double *scal, int *flags,
+                                                double *cgp, int nparts, int lb, int parity) {
   __shared__ double red[8];
   constexpr unsigned S = sizeof(T);
   constexpr unsigned SZ = ZBF ? 2u : sizeof(T);  // stored z component
+  // first the loads that need nothing but the leading arguments
+  const double *const parts[1] = {cgp + CGP_PQ};
+  Partials<4, 1> P;
+  P.load(parts, nparts);
+  const int done = flags[F_DONE];
+  double rz = scal[S_RZ0 + (parity ^ 1)];
+  // bfloat16 z (a preconditioner that varies with the rounding): the exact
+  // line search along p, r^T p = r^T z + beta r^T p_old
+  if constexpr (ZBF) rz += scal[S_BETA] * scal[S_RP];
+  __builtin_amdgcn_sched_barrier(0);  // keep those loads first
+  // then the descriptor fields in one round trip
   const unsigned nn = (unsigned)d.nn;
-  const rsrc_t rX = make_rsrc(d.x, 3u * nn * S), rR = make_rsrc(d.r, 3u * nn * S);
-  const rsrc_t rZ = make_rsrc(d.z, 3u * nn * SZ), rQ = make_rsrc(d.q, 3u * nn * S);
-  const rsrc_t rP = make_rsrc(d.p[parity ^ 1], 3u * nn * S);
-  const rsrc_t rD = make_rsrc(d.dinv, nn * S), rM = make_rsrc(d.mask, nn);
-  const unsigned stride = (unsigned)d.nb_up * 256u;
+  T *const x = d.x, *const r = d.r, *const z = d.z, *const q = d.q;
+  T *const p0 = d.p[0], *const p1 = d.p[1];
+  const T *const dinv = d.dinv;
+  const uint8_t *const mask = d.mask;
+  const int nb_up = d.nb_up;
+  asm volatile("" ::"s"(nn), "s"(x), "s"(r), "s"(z), "s"(q), "s"(p0), "s"(p1), "s"(dinv),
+               "s"(mask), "s"(nb_up));
+  const rsrc_t rX = make_rsrc(x, 3u * nn * S), rR = make_rsrc(r, 3u * nn * S);
+  const rsrc_t rZ = make_rsrc(z, 3u * nn * SZ), rQ = make_rsrc(q, 3u * nn * S);
+  const rsrc_t rP = make_rsrc(parity ? p0 : p1, 3u * nn * S);  // p[parity ^ 1]
+  const rsrc_t rD = make_rsrc(dinv, nn * S), rM = make_rsrc(mask, nn);
+  const unsigned stride = (unsigned)nb_up * 256u;
   struct Node {
     T x[3], p[3], r[3], q[3], di;
     unsigned m, vo, vz;  // vz: offset of the node's z (SZ bytes per component)
@@ -582,26 +616,18 @@ __device__ __forceinline__ void cg_update_block(const CgDesc<T> &d, int lb, int 
     v.m = bload_u8(rM, in ? n : OOB, 0);
   };
   const unsigned n0 = (unsigned)lb * 256u + threadIdx.x;
-  const double *const parts[1] = {d.cgp + CGP_PQ};
-  Partials<4, 1> P;
-  P.load(parts, d.nb_mv);
-  const int done = d.flags[F_DONE];
-  double rz = d.scal[S_RZ0 + (parity ^ 1)];
-  // bfloat16 z (a preconditioner that varies with the rounding): the exact
-  // line search along p, r^T p = r^T z + beta r^T p_old
-  if constexpr (ZBF) rz += d.scal[S_BETA] * d.scal[S_RP];
   Node A, B;
   load(A, n0);
   load(B, n0 + stride);
   double pqs[1];
-  P.sum(parts, d.nb_mv, red, pqs);
+  P.sum(parts, nparts, red, pqs);
   const double pq = pqs[0];
   if (done) return;
   if (!(pq > 0.0) || !isfinite(pq)) {
     if (lb == 0 && threadIdx.x == 0) {
-      d.scal[S_PQ] = pq;
-      d.flags[F_STATUS] = isfinite(pq) ? 1 : 2;
-      d.flags[F_DONE] = 1;
+      scal[S_PQ] = pq;
+      flags[F_STATUS] = isfinite(pq) ? 1 : 2;
+      flags[F_DONE] = 1;
     }
     return;
   }
@@ -645,15 +671,15 @@ __device__ __forceinline__ void cg_update_block(const CgDesc<T> &d, int lb, int 
   }
   if (threadIdx.x == 0) {
     if constexpr (ZBF) {
-      d.cgp[CGP_RP + parity * MAXB + lb] = s3;
-      d.cgp[CGP_ZQ + parity * MAXB + lb] = s4;
+      cgp[CGP_RP + parity * MAXB + lb] = s3;
+      cgp[CGP_ZQ + parity * MAXB + lb] = s4;
     }
-    d.cgp[CGP_RZ + parity * MAXB + lb] = s1;
-    d.cgp[CGP_RR + parity * MAXB + lb] = s2;
+    cgp[CGP_RZ + parity * MAXB + lb] = s1;
+    cgp[CGP_RR + parity * MAXB + lb] = s2;
     if (lb == 0) {
-      d.scal[S_PQ] = pq;
-      d.scal[S_ALPHA] = rz / pq;
-      d.flags[F_ITERS] = d.flags[F_ITERS] + 1;
+      scal[S_PQ] = pq;
+      scal[S_ALPHA] = rz / pq;
+      flags[F_ITERS] = flags[F_ITERS] + 1;
     }
   }
 }
@@ -663,12 +689,14 @@ __global__ __launch_bounds__(256) void k_cg_update(const CgDesc<T> *descs, const
                                                    int parity) {
   const int2 bm = blockmap[blockIdx.x];
   if (bm.x < 0) return;  // padding entry
-  cg_update_block<T>(descs[bm.x], bm.y, parity);
+  const CgDesc<T> &d = descs[bm.x];
+  cg_update_block<T>(d, d.scal, d.flags, d.cgp, d.nb_mv, bm.y, parity);
 }
 
 template <typename T, bool ZBF>
-__global__ __launch_bounds__(256) void k_cg_update1(const CgDesc<T> d, int parity) {
-  cg_update_block<T, ZBF>(d, blockIdx.x, parity);
+__global__ __launch_bounds__(256) void k_cg_update1(double *scal, int *flags, double *cgp,
+                                                    int parity, int nparts, const CgDesc<T> d) {
+  cg_update_block<T, ZBF>(d, scal, flags, cgp, nparts, blockIdx.x, parity);
 }
 
 int matvec_kz(const Grid &g) {
@@ -739,17 +767,19 @@ hipError_t launch_cg_matvec1(const CgDesc<T> &d, int parity, hipStream_t s, hipE
     if (d.zbf16) {
       if (start && stop)
         hipExtLaunchKernelGGL((k_cg_matvec1<T, true>), dim3(d.nb_mv), dim3(MV_THREADS), 0, s, start,
-                              stop, 0, d, parity);
+                              stop, 0, d.scal, d.flags, d.cgp, parity, d.nb_up, d);
       else
-        hipLaunchKernelGGL((k_cg_matvec1<T, true>), dim3(d.nb_mv), dim3(MV_THREADS), 0, s, d, parity);
+        hipLaunchKernelGGL((k_cg_matvec1<T, true>), dim3(d.nb_mv), dim3(MV_THREADS), 0, s, d.scal,
+                           d.flags, d.cgp, parity, d.nb_up, d);
       return hipGetLastError();
     }
   }
   if (start && stop)
     hipExtLaunchKernelGGL((k_cg_matvec1<T, false>), dim3(d.nb_mv), dim3(MV_THREADS), 0, s, start,
-                          stop, 0, d, parity);
+                          stop, 0, d.scal, d.flags, d.cgp, parity, d.nb_up, d);
   else
-    hipLaunchKernelGGL((k_cg_matvec1<T, false>), dim3(d.nb_mv), dim3(MV_THREADS), 0, s, d, parity);
+    hipLaunchKernelGGL((k_cg_matvec1<T, false>), dim3(d.nb_mv), dim3(MV_THREADS), 0, s, d.scal,
+                       d.flags, d.cgp, parity, d.nb_up, d);
   return hipGetLastError();
 }
 
@@ -757,11 +787,13 @@ template <typename T>
 hipError_t launch_cg_update1(const CgDesc<T> &d, int parity, hipStream_t s) {
   if constexpr (sizeof(T) == 4) {
     if (d.zbf16) {
-      hipLaunchKernelGGL((k_cg_update1<T, true>), dim3(d.nb_up), dim3(256), 0, s, d, parity);
+      hipLaunchKernelGGL((k_cg_update1<T, true>), dim3(d.nb_up), dim3(256), 0, s, d.scal, d.flags,
+                         d.cgp, parity, d.nb_mv, d);
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((k_cg_update1<T, false>), dim3(d.nb_up), dim3(256), 0, s, d, parity);
+  hipLaunchKernelGGL((k_cg_update1<T, false>), dim3(d.nb_up), dim3(256), 0, s, d.scal, d.flags,
+                     d.cgp, parity, d.nb_mv, d);
   return hipGetLastError();
 }
 
