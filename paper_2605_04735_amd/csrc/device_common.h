@@ -121,9 +121,30 @@ __device__ __forceinline__ void face_forward(const T (*P)[TP * TP], int idx, T (
   }
 }
 
+// Sum over the 64 lanes of a wave, in a fixed order, returned in every lane:
+// DPP row shifts 1, 2, 4, 8 leave each row's sum in its lane 15, the row
+// broadcasts 15 and 31 carry those into lane 63, which is then read out.
+// (A few cycles per step, against an LDS round trip per step for shuffles.)
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_take(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_sum_d(double v) {
+  v += dpp_take<0x111, 0xF>(v);  // row_shr:1
+  v += dpp_take<0x112, 0xF>(v);  // row_shr:2
+  v += dpp_take<0x114, 0xF>(v);  // row_shr:4
+  v += dpp_take<0x118, 0xF>(v);  // row_shr:8
+  v += dpp_take<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_take<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ double block_sum_d(double v, double *sh) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  v = wave_sum_d(v);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (lane == 0) sh[w] = v;
   __syncthreads();
@@ -138,11 +159,8 @@ __device__ __forceinline__ double block_sum_d(double v, double *sh) {
 // Two block sums in one pass (thread 0 holds both); sh: 8 doubles.
 __device__ __forceinline__ void block_sum_d2(double a, double b, double *sh, double &sa,
                                              double &sb) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    a += __shfl_down(a, o, 64);
-    b += __shfl_down(b, o, 64);
-  }
+  a = wave_sum_d(a);
+  b = wave_sum_d(b);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   __syncthreads();
   if (lane == 0) {
@@ -291,9 +309,7 @@ struct Partials {
       }
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-#pragma unroll
-      for (int a = 0; a < NV; ++a) s[a] += __shfl_down(s[a], o, 64);
+    for (int a = 0; a < NV; ++a) s[a] = wave_sum_d(s[a]);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     __syncthreads();
     if (lane == 0)

@@ -2,12 +2,12 @@
 // load vector) and the streaming kernels of Jacobi-preconditioned CG with
 // deterministic two-stage reductions.
 #include "common.h"
+#include "device_common.h"
 
 namespace topo {
 
 __device__ __forceinline__ double block_sum(double v, double *sh) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  v = wave_sum_d(v);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (lane == 0) sh[w] = v;
   __syncthreads();
