@@ -112,26 +112,24 @@ __device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int b
     T e;
   };
   auto fetch = [&](Plane &R, int kp) {
-    if (kp < 0 || kp >= NZ) {  // uniform
-#pragma unroll
-      for (int sl = 0; sl < 2; ++sl) {
-        R.m[sl] = 7u;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) R.in[sl][c] = R.po[sl][c] = T(0);
-      }
-      R.e = T(0);
-      return;
-    }
-    const unsigned so = (unsigned)kp * plane * 3u * S;
-    const unsigned sz = (unsigned)kp * plane * 3u * SZ;
+    // a plane outside the grid reads through empty resources (all zeros):
+    // no branch, so the waits on loads already in flight stay exact
+    const bool inz = kp >= 0 && kp < NZ;  // uniform
+    const unsigned kc = inz ? (unsigned)kp : 0u;
+    const unsigned so = kc * plane * 3u * S;
+    const unsigned sz = kc * plane * 3u * SZ;
+    const rsrc_t ri = make_rsrc(a.in, inz ? 3u * nn * SZ : 0u);
+    const rsrc_t rp = make_rsrc(a.pold, CG && inz ? 3u * nn * S : 0u);
+    const rsrc_t rm = make_rsrc(a.mask, MASKED && inz ? nn : 0u);
+    const rsrc_t re = make_rsrc(a.E, kp >= 0 && kp < a.nelz ? eplane * (unsigned)a.nelz * S : 0u);
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
-      if constexpr (ZBF) bload3_bf16(rIn, voZ[sl], sz, R.in[sl]);
-      else bload3(rIn, voZ[sl], sz, R.in[sl]);
-      if constexpr (CG) bload3(rPo, voN[sl], so, R.po[sl]);
-      if constexpr (MASKED) R.m[sl] = bload_u8(rM, voM[sl], (unsigned)kp * plane);
+      if constexpr (ZBF) bload3_bf16(ri, voZ[sl], sz, R.in[sl]);
+      else bload3(ri, voZ[sl], sz, R.in[sl]);
+      if constexpr (CG) bload3(rp, voN[sl], so, R.po[sl]);
+      if constexpr (MASKED) R.m[sl] = bload_u8(rm, voM[sl], kc * plane);
     }
-    R.e = kp < a.nelz ? bload1<T>(rE, voE, (unsigned)kp * eplane * S) : T(0);
+    R.e = bload1<T>(re, voE, kc * eplane * S);
   };
   T beta = 0;
   // plane kp into LDS (CG: p = z + beta p_old, and p written out for the
@@ -479,12 +477,15 @@ __device__ __forceinline__ void cg_matvec_block(const CgDesc<T> &d, double *scal
   double rz_old = 0.0, tol2 = 0.0, pq_old = 0.0;
   // first the loads that need nothing but the leading arguments
   P.load(parts, nparts);
-  done = flags[F_DONE];
-  iters = flags[F_ITERS];
-  cap = flags[F_CAP];
-  rz_old = scal[S_RZ0 + parity];
-  tol2 = scal[S_TOL2];
-  if constexpr (ZBF) pq_old = scal[S_PQ];
+  {  // buffer loads from the preloaded pointers, issued with the partials
+    const rsrc_t rf = make_rsrc(flags, F_COUNT * 4u), rs = make_rsrc(scal, S_COUNT * 8u);
+    done = (int)__builtin_amdgcn_raw_buffer_load_b32(rf, 4 * F_DONE, 0, 0);
+    iters = (int)__builtin_amdgcn_raw_buffer_load_b32(rf, 4 * F_ITERS, 0, 0);
+    cap = (int)__builtin_amdgcn_raw_buffer_load_b32(rf, 4 * F_CAP, 0, 0);
+    rz_old = bload1d(rs, 8u * (S_RZ0 + parity), 0);
+    tol2 = bload1d(rs, 8u * S_TOL2, 0);
+    if constexpr (ZBF) pq_old = bload1d(rs, 8u * S_PQ, 0);
+  }
   __builtin_amdgcn_sched_barrier(0);  // keep those loads first
   // then every descriptor field in one round trip (the empty asm makes the
   // values needed at once, so their loads issue together)
@@ -580,11 +581,12 @@ __device__ __forceinline__ void cg_update_block(const CgDesc<T> &d, double *scal
   const double *const parts[1] = {cgp + CGP_PQ};
   Partials<4, 1> P;
   P.load(parts, nparts);
-  const int done = flags[F_DONE];
-  double rz = scal[S_RZ0 + (parity ^ 1)];
+  const rsrc_t rf = make_rsrc(flags, F_COUNT * 4u), rs = make_rsrc(scal, S_COUNT * 8u);
+  const int done = (int)__builtin_amdgcn_raw_buffer_load_b32(rf, 4 * F_DONE, 0, 0);
+  double rz = bload1d(rs, 8u * (S_RZ0 + (parity ^ 1)), 0);
   // bfloat16 z (a preconditioner that varies with the rounding): the exact
   // line search along p, r^T p = r^T z + beta r^T p_old
-  if constexpr (ZBF) rz += scal[S_BETA] * scal[S_RP];
+  if constexpr (ZBF) rz += bload1d(rs, 8u * S_BETA, 0) * bload1d(rs, 8u * S_RP, 0);
   __builtin_amdgcn_sched_barrier(0);  // keep those loads first
   // then the descriptor fields in one round trip
   const unsigned nn = (unsigned)d.nn;
