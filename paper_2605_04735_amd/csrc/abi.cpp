@@ -89,6 +89,12 @@ struct to_ctx {
   double prof_ms = 0.0;
   long long prof_count = 0;
   int prof_every = 16;  // bracket one product launch in this many
+  // a chunk of CG iterations as one graph launch, per precision and starting
+  // parity (built on first use); with timing on, one chunk in four runs as
+  // separate launches so that product launches can be sampled
+  bool use_graph = true;
+  long long chunks = 0;
+  hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   std::string err;
 };
 
@@ -312,14 +318,21 @@ to_status inner_pcg(to_ctx *c, T *const v[6], const T *dinv, double eta, int cap
   *status = 0;
   for (;;) {
     const int n = std::min(c->chunk, cap - launched);
-    for (int it = 0; it < n; ++it) {
-      hipEvent_t e0 = nullptr, e1 = nullptr;
-      // sampled away from the first launch after a host synchronisation
-      if (c->prof && (launched + it) % c->prof_every == c->prof_every / 2)
-        HIPCHK(prof_pair(c, &e0, &e1));
-      HIPCHK(launch_cg_matvec1<T>(*hd, c->parity, c->stream, e0, e1));
-      HIPCHK(launch_cg_update1<T>(*hd, c->parity, c->stream));
-      c->parity ^= 1;
+    hipGraphExec_t &gx = c->graph[sizeof(T) == 8][c->parity];
+    const bool sample = c->prof && (c->chunks++ % 4 == 0);
+    if (c->use_graph && !sample && n == c->chunk && c->chunk % 2 == 0) {
+      if (!gx) HIPCHK(build_cg_graph<T>(*hd, c->parity, c->chunk, &gx));
+      HIPCHK(hipGraphLaunch(gx, c->stream));  // an even chunk keeps the parity
+    } else {
+      for (int it = 0; it < n; ++it) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        // sampled away from the first launch after a host synchronisation
+        if (c->prof && (launched + it) % c->prof_every == c->prof_every / 2)
+          HIPCHK(prof_pair(c, &e0, &e1));
+        HIPCHK(launch_cg_matvec1<T>(*hd, c->parity, c->stream, e0, e1));
+        HIPCHK(launch_cg_update1<T>(*hd, c->parity, c->stream));
+        c->parity ^= 1;
+      }
     }
     launched += n;
     to_status s = sync_read(c);
@@ -393,6 +406,7 @@ to_status to_create(const to_problem *prob, void *d_workspace, size_t bytes, voi
   if (const char *e = std::getenv("TOPO_CHUNK")) c->chunk = std::max(1, std::atoi(e));
   if (const char *e = std::getenv("TOPO_TRACE")) c->trace = std::atoi(e) != 0;
   if (const char *e = std::getenv("TOPO_PROF_EVERY")) c->prof_every = std::max(1, std::atoi(e));
+  if (const char *e = std::getenv("TOPO_GRAPH")) c->use_graph = std::atoi(e) != 0;
   auto bail = [&](to_status s, const std::string &m) {
     to_status r = fail(nullptr, s, m);
     to_destroy(c);
@@ -459,6 +473,9 @@ void to_destroy(to_ctx *c) {
   if (c->stream) hipStreamSynchronize(c->stream);
   else hipDeviceSynchronize();
   for (hipEvent_t e : c->ev) hipEventDestroy(e);
+  for (auto &row : c->graph)
+    for (hipGraphExec_t &g : row)
+      if (g) hipGraphExecDestroy(g);
   if (c->owns_ws && c->ws) hipFree(c->ws);
   if (c->tri) hipFree(c->tri);
   if (c->h_scal) hipHostFree(c->h_scal);

@@ -158,6 +158,9 @@ hipError_t launch_cg_matvec1(const CgDesc<T> &d, int parity, hipStream_t s,
                              hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 template <typename T>
 hipError_t launch_cg_update1(const CgDesc<T> &d, int parity, hipStream_t s);
+// `iters` CG iterations of one design as an instantiated graph (see k_matvec.hip)
+template <typename T>
+hipError_t build_cg_graph(const CgDesc<T> &d, int parity0, int iters, hipGraphExec_t *out);
 template <typename T>
 hipError_t launch_cg_matvec(const CgDesc<T> *descs, const int2 *bmap_mv, int nb_mv, int parity,
                             hipStream_t s, hipEvent_t start = nullptr, hipEvent_t stop = nullptr);

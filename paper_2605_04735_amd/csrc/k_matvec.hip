@@ -799,6 +799,49 @@ hipError_t launch_cg_update1(const CgDesc<T> &d, int parity, hipStream_t s) {
   return hipGetLastError();
 }
 
+// A graph of `iters` CG iterations (product then update, alternating parity
+// from parity0) for one design: the same launches as launch_cg_matvec1 /
+// launch_cg_update1, built as explicit kernel nodes in a chain.
+template <typename T>
+hipError_t build_cg_graph(const CgDesc<T> &d, int parity0, int iters, hipGraphExec_t *out) {
+  *out = nullptr;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipGraphCreate(&g, 0);
+  if (e != hipSuccess) return e;
+  void *fmv = (void *)k_cg_matvec1<T, false>, *fup = (void *)k_cg_update1<T, false>;
+  if constexpr (sizeof(T) == 4) {
+    if (d.zbf16) {
+      fmv = (void *)k_cg_matvec1<T, true>;
+      fup = (void *)k_cg_update1<T, true>;
+    }
+  }
+  hipGraphNode_t prev = nullptr;
+  for (int i = 0; i < 2 * iters && e == hipSuccess; ++i) {
+    int parity = parity0 ^ ((i >> 1) & 1);
+    const bool mv = (i & 1) == 0;
+    int nparts = mv ? d.nb_up : d.nb_mv;
+    double *scal = d.scal, *cgp = d.cgp;
+    int *flags = d.flags;
+    CgDesc<T> dd = d;
+    void *args[] = {&scal, &flags, &cgp, &parity, &nparts, &dd};
+    hipKernelNodeParams kp{};
+    kp.func = mv ? fmv : fup;
+    kp.gridDim = dim3(mv ? d.nb_mv : d.nb_up);
+    kp.blockDim = dim3(mv ? MV_THREADS : 256);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    hipGraphNode_t node = nullptr;
+    e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+    prev = node;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  return e;
+}
+template hipError_t build_cg_graph<double>(const CgDesc<double> &, int, int, hipGraphExec_t *);
+template hipError_t build_cg_graph<float>(const CgDesc<float> &, int, int, hipGraphExec_t *);
+
 template hipError_t launch_cg_matvec1<double>(const CgDesc<double> &, int, hipStream_t, hipEvent_t,
                                               hipEvent_t);
 template hipError_t launch_cg_matvec1<float>(const CgDesc<float> &, int, hipStream_t, hipEvent_t,

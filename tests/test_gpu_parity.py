@@ -155,6 +155,28 @@ def test_warm_start_and_determinism():
     assert i3["inner_iters"] == 0 and torch.equal(u3, u1)
 
 
+@pytest.mark.parametrize("prec", [A.PREC_FP64, A.PREC_FP32_REFINE, A.PREC_FP32_REFINE_BF16])
+def test_graph_chunks_equal_separate_launches(prec, monkeypatch):
+    """CG chunks replayed as one graph launch give bit-for-bit the result of
+    separate launches, over repeated replays with other work in between."""
+    nelx, nely, nelz = 40, 33, 19
+    x = inputs.random_field(nelx, nely, nelz, seed=6, ell=4.0)
+    xg = gpu(x)
+    print("graph vs launches, precision", prec, flush=True)
+    monkeypatch.setenv("TOPO_GRAPH", "0")
+    eager = A.to_create(A.Problem(nelx, nely, nelz, precision=prec, rtol=1e-8))
+    monkeypatch.setenv("TOPO_GRAPH", "1")
+    graph = A.to_create(A.Problem(nelx, nely, nelz, precision=prec, rtol=1e-8))
+    ue, ie, _ = A.to_solve(eager, xg)
+    assert ie["inner_iters"] > 2 * 32  # several full chunks
+    for rep in range(3):
+        ug, ig, _ = A.to_solve(graph, xg)
+        torch.cuda.synchronize()
+        assert ig["inner_iters"] == ie["inner_iters"], rep
+        assert torch.equal(ug, ue), rep
+        A.to_filter(graph, 1.5, A.FILTER_DENS, xg)  # other work on the stream between replays
+
+
 def test_sensitivity_kernel_on_oracle_u():
     nelx, nely, nelz = 23, 14, 9
     x = inputs.random_field(nelx, nely, nelz, seed=4, ell=2.0)
