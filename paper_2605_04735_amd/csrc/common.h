@@ -92,6 +92,17 @@ struct CgDesc {
   int *flags;           // [F_COUNT]
 };
 
+// One block of a batched CG launch: its design (-1: padding, no work), its
+// local block, and the design's partial-sum array, scalars, flags and the
+// number of partials the kernel reads, so that one load gives a block
+// everything its first loads need.
+struct BlockEntry {
+  double *cgp;
+  double *scal;
+  int *flags;
+  int design, lb, nparts, pad_;
+};
+
 // Layout of CgDesc::cgp.  The product kernel of parity P reads the r^T z and
 // ||r||^2 partials of set P^1 and writes the p^T q partials; the update
 // kernel of parity P reads those and writes set P.
@@ -162,10 +173,10 @@ hipError_t launch_cg_update1(const CgDesc<T> &d, int parity, hipStream_t s);
 template <typename T>
 hipError_t build_cg_graph(const CgDesc<T> &d, int parity0, int iters, hipGraphExec_t *out);
 template <typename T>
-hipError_t launch_cg_matvec(const CgDesc<T> *descs, const int2 *bmap_mv, int nb_mv, int parity,
+hipError_t launch_cg_matvec(const CgDesc<T> *descs, const BlockEntry *bmap_mv, int nb_mv, int parity,
                             hipStream_t s, hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 template <typename T>
-hipError_t launch_cg_update(const CgDesc<T> *descs, const int2 *bmap_up, int nb_up, int parity,
+hipError_t launch_cg_update(const CgDesc<T> *descs, const BlockEntry *bmap_up, int nb_up, int parity,
                             hipStream_t s);
 int update_blocks(size_t nn);
 template <typename T>

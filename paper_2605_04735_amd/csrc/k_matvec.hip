@@ -548,11 +548,10 @@ __device__ __forceinline__ void cg_matvec_block(const CgDesc<T> &d, double *scal
 // Batched form over a table of designs: blockmap[b] = (design, local block).
 template <typename T>
 __global__ __launch_bounds__(MV_THREADS) void k_cg_matvec(const CgDesc<T> *descs,
-                                                          const int2 *blockmap, int parity) {
-  const int2 bm = blockmap[blockIdx.x];
-  if (bm.x < 0) return;  // padding entry
-  const CgDesc<T> &d = descs[bm.x];
-  cg_matvec_block<T>(d, d.scal, d.flags, d.cgp, d.nb_up, bm.y, parity);
+                                                          const BlockEntry *blockmap, int parity) {
+  const BlockEntry be = blockmap[blockIdx.x];
+  if (be.design < 0) return;  // padding entry
+  cg_matvec_block<T>(descs[be.design], be.scal, be.flags, be.cgp, be.nparts, be.lb, parity);
 }
 
 // One design, its descriptor passed by value.  The scalars, flags, partial
@@ -687,12 +686,11 @@ __device__ __forceinline__ void cg_update_block(const CgDesc<T> &d, double *scal
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_cg_update(const CgDesc<T> *descs, const int2 *blockmap,
-                                                   int parity) {
-  const int2 bm = blockmap[blockIdx.x];
-  if (bm.x < 0) return;  // padding entry
-  const CgDesc<T> &d = descs[bm.x];
-  cg_update_block<T>(d, d.scal, d.flags, d.cgp, d.nb_mv, bm.y, parity);
+__global__ __launch_bounds__(256) void k_cg_update(const CgDesc<T> *descs,
+                                                   const BlockEntry *blockmap, int parity) {
+  const BlockEntry be = blockmap[blockIdx.x];
+  if (be.design < 0) return;  // padding entry
+  cg_update_block<T>(descs[be.design], be.scal, be.flags, be.cgp, be.nparts, be.lb, parity);
 }
 
 template <typename T, bool ZBF>
@@ -742,7 +740,7 @@ hipError_t launch_matvec(const MvArgs<T> &a, int *nblocks, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_cg_matvec(const CgDesc<T> *descs, const int2 *bmap_mv, int nb_mv, int parity,
+hipError_t launch_cg_matvec(const CgDesc<T> *descs, const BlockEntry *bmap_mv, int nb_mv, int parity,
                             hipStream_t s, hipEvent_t start, hipEvent_t stop) {
   if (start && stop)  // timestamps taken by the dispatch itself
     hipExtLaunchKernelGGL(k_cg_matvec<T>, dim3(nb_mv), dim3(MV_THREADS), 0, s, start, stop, 0,
@@ -753,7 +751,7 @@ hipError_t launch_cg_matvec(const CgDesc<T> *descs, const int2 *bmap_mv, int nb_
 }
 
 template <typename T>
-hipError_t launch_cg_update(const CgDesc<T> *descs, const int2 *bmap_up, int nb_up, int parity,
+hipError_t launch_cg_update(const CgDesc<T> *descs, const BlockEntry *bmap_up, int nb_up, int parity,
                             hipStream_t s) {
   hipLaunchKernelGGL(k_cg_update<T>, dim3(nb_up), dim3(256), 0, s, descs, bmap_up, parity);
   return hipGetLastError();
@@ -848,13 +846,13 @@ template hipError_t launch_cg_matvec1<float>(const CgDesc<float> &, int, hipStre
                                              hipEvent_t);
 template hipError_t launch_cg_update1<double>(const CgDesc<double> &, int, hipStream_t);
 template hipError_t launch_cg_update1<float>(const CgDesc<float> &, int, hipStream_t);
-template hipError_t launch_cg_matvec<double>(const CgDesc<double> *, const int2 *, int, int,
+template hipError_t launch_cg_matvec<double>(const CgDesc<double> *, const BlockEntry *, int, int,
                                              hipStream_t, hipEvent_t, hipEvent_t);
-template hipError_t launch_cg_matvec<float>(const CgDesc<float> *, const int2 *, int, int,
+template hipError_t launch_cg_matvec<float>(const CgDesc<float> *, const BlockEntry *, int, int,
                                             hipStream_t, hipEvent_t, hipEvent_t);
-template hipError_t launch_cg_update<double>(const CgDesc<double> *, const int2 *, int, int,
+template hipError_t launch_cg_update<double>(const CgDesc<double> *, const BlockEntry *, int, int,
                                              hipStream_t);
-template hipError_t launch_cg_update<float>(const CgDesc<float> *, const int2 *, int, int,
+template hipError_t launch_cg_update<float>(const CgDesc<float> *, const BlockEntry *, int, int,
                                             hipStream_t);
 
 // ---------------------------------------------------------------- energies

@@ -201,7 +201,7 @@ struct to_server {
   int *d_flags = nullptr, *h_flags = nullptr;
   // batch tables
   CgDesc<float> *d_desc = nullptr, *h_desc = nullptr;
-  int2 *d_bmv = nullptr, *d_bup = nullptr, *h_bmv = nullptr, *h_bup = nullptr;
+  BlockEntry *d_bmv = nullptr, *d_bup = nullptr, *h_bmv = nullptr, *h_bup = nullptr;
   size_t bmap_cap = 0;
   int nb_mv = 0, nb_up = 0;
   bool batch_dirty = true;
@@ -352,20 +352,24 @@ CgDesc<float> make_desc(const Slot &sl) {
 }
 
 // Rebuilds the batch tables for the slots in INNER state: descriptors, and
-// per kernel a block -> (design, local block) map.  Each design's blocks are
-// padded to a multiple of 8 so that its tile ranges stay XCD-contiguous;
-// padding entries name design -1 (no work).
+// per kernel a block -> (design, local block, design's partials, scalars,
+// flags, partial count) map.  Each design's blocks are padded to a multiple
+// of 8 so that its tile ranges stay XCD-contiguous; padding entries name
+// design -1 (no work).
 bool rebuild_batch(to_server *s) {
   int nd = 0;
-  std::vector<int2> bmv, bup;
+  std::vector<BlockEntry> bmv, bup;
   for (size_t i = 0; i < s->slots.size(); ++i) {
     Slot &sl = s->slots[i];
     if (sl.state != INNER) continue;
     s->h_desc[nd] = make_desc(sl);
     const int pad_mv = (sl.nb_mv + NXCD - 1) / NXCD * NXCD;
     for (int b = 0; b < pad_mv; ++b)
-      bmv.push_back(b < sl.nb_mv ? make_int2(nd, xcd_local(b, sl.nb_mv)) : make_int2(-1, 0));
-    for (int b = 0; b < sl.nb_up; ++b) bup.push_back(make_int2(nd, b));
+      bmv.push_back(b < sl.nb_mv
+                        ? BlockEntry{sl.cgp, sl.scal, sl.flags, nd, xcd_local(b, sl.nb_mv), sl.nb_up, 0}
+                        : BlockEntry{sl.cgp, sl.scal, sl.flags, -1, 0, 0, 0});
+    for (int b = 0; b < sl.nb_up; ++b)
+      bup.push_back(BlockEntry{sl.cgp, sl.scal, sl.flags, nd, b, sl.nb_mv, 0});
     ++nd;
   }
   s->nb_mv = (int)bmv.size();
@@ -378,9 +382,9 @@ bool rebuild_batch(to_server *s) {
   if (nd) {
     ok = check(s, hipMemcpyAsync(s->d_desc, s->h_desc, nd * sizeof(CgDesc<float>),
                                  hipMemcpyHostToDevice, st)) &&
-         check(s, hipMemcpyAsync(s->d_bmv, s->h_bmv, s->nb_mv * sizeof(int2),
+         check(s, hipMemcpyAsync(s->d_bmv, s->h_bmv, s->nb_mv * sizeof(BlockEntry),
                                  hipMemcpyHostToDevice, st)) &&
-         check(s, hipMemcpyAsync(s->d_bup, s->h_bup, s->nb_up * sizeof(int2),
+         check(s, hipMemcpyAsync(s->d_bup, s->h_bup, s->nb_up * sizeof(BlockEntry),
                                  hipMemcpyHostToDevice, st));
   }
   s->batch_dirty = false;
@@ -553,17 +557,17 @@ to_status to_server_create(size_t hbm_budget_bytes, int32_t max_slots, void *str
                 hipSuccess &&
             hipMalloc((void **)&s->d_flags, (size_t)max_slots * F_COUNT * sizeof(int)) == hipSuccess &&
             hipMalloc((void **)&s->d_desc, (size_t)max_slots * sizeof(CgDesc<float>)) == hipSuccess &&
-            hipMalloc((void **)&s->d_bmv, s->bmap_cap * sizeof(int2)) == hipSuccess &&
-            hipMalloc((void **)&s->d_bup, s->bmap_cap * sizeof(int2)) == hipSuccess &&
+            hipMalloc((void **)&s->d_bmv, s->bmap_cap * sizeof(BlockEntry)) == hipSuccess &&
+            hipMalloc((void **)&s->d_bup, s->bmap_cap * sizeof(BlockEntry)) == hipSuccess &&
             hipHostMalloc((void **)&s->h_scal, (size_t)max_slots * S_COUNT * sizeof(double),
                           hipHostMallocDefault) == hipSuccess &&
             hipHostMalloc((void **)&s->h_flags, (size_t)max_slots * F_COUNT * sizeof(int),
                           hipHostMallocDefault) == hipSuccess &&
             hipHostMalloc((void **)&s->h_desc, (size_t)max_slots * sizeof(CgDesc<float>),
                           hipHostMallocDefault) == hipSuccess &&
-            hipHostMalloc((void **)&s->h_bmv, s->bmap_cap * sizeof(int2), hipHostMallocDefault) ==
+            hipHostMalloc((void **)&s->h_bmv, s->bmap_cap * sizeof(BlockEntry), hipHostMallocDefault) ==
                 hipSuccess &&
-            hipHostMalloc((void **)&s->h_bup, s->bmap_cap * sizeof(int2), hipHostMallocDefault) ==
+            hipHostMalloc((void **)&s->h_bup, s->bmap_cap * sizeof(BlockEntry), hipHostMallocDefault) ==
                 hipSuccess;
   if (ok) {
     ok = launch_fill(s->d_scal, (size_t)max_slots * S_COUNT * sizeof(double), s->stream) ==
