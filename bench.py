@@ -399,7 +399,8 @@ def workload_mbb_sdf(A, inputs, dev):
     shifted so that 40% of the elements exceed 0.5) -> density->SDF at 0.5 ->
     per-element volume fraction -> ersatz moduli E = max(vf, 1e-3) (penal 1,
     Emin 0) -> compliance and sensitivity, float32-inner/float64-refined and
-    float64, both to rtol 1e-8, against a float64 solve to 1e-10."""
+    float64, both to rtol 1e-8, against a float64 solve to 3e-10 (its stagnation
+    floor is near 2e-10)."""
     import torch
     dims = (192, 64, 32)
     x = torch.from_numpy(inputs.random_field(*dims, seed=2, ell=6.0, kappa=8.0,
@@ -416,7 +417,7 @@ def workload_mbb_sdf(A, inputs, dev):
     out = {"sdf_ms": round(t_sdf, 3), "triangles": ntri,
            "solid_fraction_vf": float(vf.mean().item())}
     res = {}
-    for name, prec, rtol in (("reference", A.PREC_FP64, 1e-10), ("fp32_refine", A.PREC_FP32_REFINE, 1e-8),
+    for name, prec, rtol in (("reference", A.PREC_FP64, 3e-10), ("fp32_refine", A.PREC_FP32_REFINE, 1e-8),
                              ("fp64", A.PREC_FP64, 1e-8)):
         ctx = A.to_create(A.Problem(*dims, bc=A.BC_MBB, penal=1.0, Emin=0.0, precision=prec,
                                     rtol=rtol, max_iters=10 ** 6))
