@@ -173,6 +173,10 @@ hipError_t launch_cg_update1(const CgDesc<T> &d, int parity, hipStream_t s);
 template <typename T>
 hipError_t build_cg_graph(const CgDesc<T> &d, int parity0, int iters, hipGraphExec_t *out);
 template <typename T>
+hipError_t build_cg_graph_batched(const CgDesc<T> *descs, const BlockEntry *bmv, int nb_mv,
+                                  const BlockEntry *bup, int nb_up, int parity0, int iters,
+                                  hipGraphExec_t *out);
+template <typename T>
 hipError_t launch_cg_matvec(const CgDesc<T> *descs, const BlockEntry *bmap_mv, int nb_mv, int parity,
                             hipStream_t s, hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 template <typename T>

@@ -838,6 +838,42 @@ hipError_t build_cg_graph(const CgDesc<T> &d, int parity0, int iters, hipGraphEx
   return e;
 }
 template hipError_t build_cg_graph<double>(const CgDesc<double> &, int, int, hipGraphExec_t *);
+
+// The same for the batched kernels over device tables (their contents may
+// change between replays only while no replay is queued).
+template <typename T>
+hipError_t build_cg_graph_batched(const CgDesc<T> *descs, const BlockEntry *bmv, int nb_mv,
+                                  const BlockEntry *bup, int nb_up, int parity0, int iters,
+                                  hipGraphExec_t *out) {
+  *out = nullptr;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipGraphCreate(&g, 0);
+  if (e != hipSuccess) return e;
+  hipGraphNode_t prev = nullptr;
+  for (int i = 0; i < 2 * iters && e == hipSuccess; ++i) {
+    int parity = parity0 ^ ((i >> 1) & 1);
+    const bool mv = (i & 1) == 0;
+    const CgDesc<T> *dp = descs;
+    const BlockEntry *bp = mv ? bmv : bup;
+    void *args[] = {&dp, &bp, &parity};
+    hipKernelNodeParams kp{};
+    kp.func = mv ? (void *)k_cg_matvec<T> : (void *)k_cg_update<T>;
+    kp.gridDim = dim3(mv ? nb_mv : nb_up);
+    kp.blockDim = dim3(mv ? MV_THREADS : 256);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    hipGraphNode_t node = nullptr;
+    e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+    prev = node;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  return e;
+}
+template hipError_t build_cg_graph_batched<float>(const CgDesc<float> *, const BlockEntry *, int,
+                                                  const BlockEntry *, int, int, int,
+                                                  hipGraphExec_t *);
 template hipError_t build_cg_graph<float>(const CgDesc<float> &, int, int, hipGraphExec_t *);
 
 template hipError_t launch_cg_matvec1<double>(const CgDesc<double> &, int, hipStream_t, hipEvent_t,

@@ -206,6 +206,11 @@ struct to_server {
   int nb_mv = 0, nb_up = 0;
   bool batch_dirty = true;
   int parity = 0;
+  // the chunk of batched iterations as a graph per starting parity, built
+  // once a batch has stayed unchanged for a tick and dropped when it changes
+  bool use_graph = true;
+  int stable_ticks = 0;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
   double eta = 1e-4;
   int chunk = 32;
   // queues
@@ -433,13 +438,33 @@ void server_loop(to_server *s) {
     if (s->hip_error) break;
     if (s->live == 0) continue;
     // ---- batched inner CG iterations for every design in an inner solve
-    if (s->batch_dirty && !rebuild_batch(s)) break;
+    if (s->batch_dirty) {
+      for (hipGraphExec_t &g : s->graph)
+        if (g) {
+          hipGraphExecDestroy(g);  // no replay is queued: the last tick synchronised
+          g = nullptr;
+        }
+      s->stable_ticks = 0;
+      if (!rebuild_batch(s)) break;
+    } else {
+      s->stable_ticks++;
+    }
     if (s->nb_mv > 0) {
-      for (int it = 0; it < s->chunk; ++it) {
-        if (!check(s, launch_cg_matvec<float>(s->d_desc, s->d_bmv, s->nb_mv, s->parity, s->stream)) ||
-            !check(s, launch_cg_update<float>(s->d_desc, s->d_bup, s->nb_up, s->parity, s->stream)))
+      hipGraphExec_t &gx = s->graph[s->parity];
+      if (s->use_graph && s->stable_ticks >= 1 && s->chunk % 2 == 0) {
+        if (!gx && !check(s, build_cg_graph_batched<float>(s->d_desc, s->d_bmv, s->nb_mv, s->d_bup,
+                                                           s->nb_up, s->parity, s->chunk, &gx)))
           break;
-        s->parity ^= 1;
+        if (!check(s, hipGraphLaunch(gx, s->stream))) break;  // an even chunk keeps the parity
+      } else {
+        for (int it = 0; it < s->chunk; ++it) {
+          if (!check(s, launch_cg_matvec<float>(s->d_desc, s->d_bmv, s->nb_mv, s->parity,
+                                                s->stream)) ||
+              !check(s, launch_cg_update<float>(s->d_desc, s->d_bup, s->nb_up, s->parity,
+                                                s->stream)))
+            break;
+          s->parity ^= 1;
+        }
       }
     }
     // ---- read back every slot's scalars and flags
@@ -549,6 +574,7 @@ to_status to_server_create(size_t hbm_budget_bytes, int32_t max_slots, void *str
   s->max_slots = max_slots;
   if (const char *e = std::getenv("TOPO_INNER_ETA")) s->eta = std::atof(e);
   if (const char *e = std::getenv("TOPO_CHUNK")) s->chunk = std::max(1, std::atoi(e));
+  if (const char *e = std::getenv("TOPO_GRAPH")) s->use_graph = std::atoi(e) != 0;
   s->bmap_cap = (size_t)max_slots * (MAXB + NXCD);
   bool ok = hipGetDevice(&s->device) == hipSuccess &&
             hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess &&
@@ -679,6 +705,8 @@ void to_server_destroy(to_server *s) {
   s->cv.notify_all();
   if (s->th.joinable()) s->th.join();
   if (s->stream) hipStreamSynchronize(s->stream);
+  for (hipGraphExec_t g : s->graph)
+    if (g) hipGraphExecDestroy(g);
   for (auto &sl : s->slots)
     if (sl.h_stage) hipHostFree(sl.h_stage);
   hipFree(s->arena_base);

@@ -118,3 +118,18 @@ def test_server_rejects_bad_requests():
         assert len(r) == 1 and r[0]["status"] == A.L.TO_E_NONFINITE
     finally:
         srv.close()
+
+
+def test_served_graph_replays_equal_separate_launches(monkeypatch):
+    """The server's chunks replayed as graphs (once a batch is stable) give
+    bit-for-bit the results of separate launches."""
+    reqs = _requests()
+    print("serving mix with and without graphs", flush=True)
+    monkeypatch.setenv("TOPO_GRAPH", "0")
+    eager = _serve(reqs)
+    monkeypatch.setenv("TOPO_GRAPH", "1")
+    graph = _serve(reqs)
+    for k, _, _ in reqs:
+        assert eager[k]["status"] == A.L.TO_OK and graph[k]["status"] == A.L.TO_OK
+        assert graph[k]["c"] == eager[k]["c"]
+        assert np.array_equal(graph[k]["dc"], eager[k]["dc"])
