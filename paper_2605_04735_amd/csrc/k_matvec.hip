@@ -272,170 +272,6 @@ __device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int b
   return 0.0;
 }
 
-// Variant of the product block for the float64 inner CG: the element's 8
-// corners are read from both staged planes and transformed in full, and the
-// node sums carry along z in node space.  It needs far fewer registers than
-// the transform-space carry (which, with the fused direction update, pushes
-// float64 to two waves per SIMD or to spills) and measured faster there.
-template <typename T, int MODE, typename PreFn, typename BetaFn>
-__device__ __forceinline__ double matvec_block_nodecarry(const MvArgs<T> &a, int bx, int by, int bz,
-                                                         PreFn &&pre, BetaFn &&get_beta,
-                                                         T (*pl)[3][TP * TP], T (*ex)[MV_THREADS],
-                                                         double *red) {
-  const int tid = threadIdx.x;
-  const int NX = a.nelx + 1, NY = a.nely + 1, NZ = a.nelz + 1;
-  const int i0 = bx * TN, j0 = by * TN;
-  const int k0 = bz * a.kz;
-  const int k1 = min(k0 + a.kz, NZ);
-
-  const int ei = tid % TE, ej = tid / TE;
-  const int gi = i0 - 1 + ei, gj = j0 - 1 + ej;
-  const bool e_xy = gi >= 0 && gi < a.nelx && gj >= 0 && gj < a.nely;
-  // the node owned by this lane: (i0 + ei, j0 + ej), interior of the tile
-  const int gni = i0 + ei, gnj = j0 + ej;
-  const bool own = ei < TN && ej < TN && gni < NX && gnj < NY;
-  const size_t plane = (size_t)NX * NY;
-
-  // register staging of one node plane (17 x 17 nodes, two slots per lane)
-  T rin[2][3], rpo[2][3];
-  unsigned rm[2];
-  bool rv[2];
-  auto fetch = [&](int kp) {
-#pragma unroll
-    for (int sl = 0; sl < 2; ++sl) {
-      const int idx = tid + sl * MV_THREADS;
-      const int li = idx % TP, lj = idx / TP;
-      const int gx = i0 - 1 + li, gy = j0 - 1 + lj;
-      rv[sl] = idx < TP * TP && kp >= 0 && kp < NZ && gx >= 0 && gx < NX && gy >= 0 && gy < NY;
-      rm[sl] = 7u;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        rin[sl][c] = 0;
-        rpo[sl][c] = 0;
-      }
-      if (rv[sl]) {
-        const size_t n = (size_t)gx + (size_t)NX * gy + plane * kp;
-        rm[sl] = a.mask[n];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          rin[sl][c] = a.in[3 * n + c];
-          if (MODE == MV_CG) rpo[sl][c] = a.pold[3 * n + c];
-        }
-      }
-    }
-  };
-  T beta = 0;
-  auto stage = [&](int kp) {
-    T(*dst)[TP * TP] = pl[kp & 1];
-#pragma unroll
-    for (int sl = 0; sl < 2; ++sl) {
-      const int idx = tid + sl * MV_THREADS;
-      if (idx >= TP * TP) continue;
-      T v[3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const bool fx = (rm[sl] >> c) & 1u;
-        v[c] = fx ? T(0) : rin[sl][c];
-        if (MODE == MV_CG) v[c] = fx ? T(0) : v[c] + beta * rpo[sl][c];
-        dst[c][idx] = v[c];
-      }
-      if (MODE == MV_CG && rv[sl]) {
-        const int li = idx % TP, lj = idx / TP;
-        if (li >= 1 && li <= TN && lj >= 1 && lj <= TN && kp >= k0 && kp < k1) {
-          const size_t n = (size_t)(i0 - 1 + li) + (size_t)NX * (j0 - 1 + lj) + plane * kp;
-#pragma unroll
-          for (int c = 0; c < 3; ++c) a.pout[3 * n + c] = v[c];
-        }
-      }
-    }
-  };
-  auto modulus = [&](int L) -> T {
-    return (e_xy && L >= 0 && L < a.nelz)
-               ? a.E[(size_t)gi + (size_t)a.nelx * ((size_t)gj + (size_t)a.nely * L)]
-               : T(0);
-  };
-
-  T carry[3] = {0, 0, 0};
-  double acc = 0.0;
-  pre();
-  fetch(k0 - 1);
-  if (!get_beta(beta)) return 0.0;
-  stage(k0 - 1);
-  fetch(k0);
-  T Ecur = modulus(k0 - 1);
-  for (int L = k0 - 1; L < k1; ++L) {
-    stage(L + 1);
-    if (L + 2 <= k1) fetch(L + 2);
-    const T Enext = modulus(L + 1);
-    __syncthreads();
-    T(*lo)[TP * TP] = pl[L & 1];
-    T(*hi)[TP * TP] = pl[(L + 1) & 1];
-    T pn[3] = {0, 0, 0};
-    if (MODE == MV_CG && own) {
-      const int idx = (ei + 1) + TP * (ej + 1);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) pn[c] = lo[c][idx];
-    }
-    T u[3][8];
-#pragma unroll
-    for (int an = 0; an < 8; ++an) {
-      const int idx = (ei + (an & 1)) + TP * (ej + ((an >> 1) & 1));
-#pragma unroll
-      for (int c = 0; c < 3; ++c) u[c][an] = (an >> 2) ? hi[c][idx] : lo[c][idx];
-    }
-    hex8_apply(u, Ecur, a.k);
-    // x: xc[ay][az][c] for the node at this lane's (ei, ej)
-    T xc[2][2][3];
-#pragma unroll
-    for (int ay = 0; ay < 2; ++ay)
-#pragma unroll
-      for (int az = 0; az < 2; ++az)
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-          xc[ay][az][c] = u[c][1 + 2 * ay + 4 * az] + from_next_lane(u[c][2 * ay + 4 * az]);
-    // y: the next tile row needs this row's ay = 0 corners
-#pragma unroll
-    for (int az = 0; az < 2; ++az)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) ex[3 * az + c][tid] = xc[0][az][c];
-    __syncthreads();
-    if (own) {
-      T bot[3], top[3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        bot[c] = carry[c] + (xc[1][0][c] + ex[c][tid + TE]);
-        top[c] = xc[1][1][c] + ex[3 + c][tid + TE];
-        carry[c] = top[c];
-      }
-      if (L >= k0) {
-        const size_t n = (size_t)gni + (size_t)NX * gnj + plane * L;
-        const unsigned m = a.mask[n];
-        if (MODE == MV_APPLY) {
-#pragma unroll
-          for (int c = 0; c < 3; ++c) a.out[3 * n + c] = ((m >> c) & 1u) ? a.in[3 * n + c] : bot[c];
-        } else if (MODE == MV_CG) {
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const T q = ((m >> c) & 1u) ? T(0) : bot[c];
-            a.out[3 * n + c] = q;
-            acc += (double)pn[c] * (double)q;
-          }
-        } else {
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const double r = ((m >> c) & 1u) ? 0.0 : a.f[3 * n + c] - (double)bot[c];
-            a.out[3 * n + c] = (T)r;
-            acc += r * r;
-          }
-        }
-      }
-    }
-    Ecur = Enext;
-  }
-  if (MODE != MV_APPLY) return block_sum_d(acc, red);
-  return 0.0;
-}
-
 template <typename T, int MODE>
 __global__ __launch_bounds__(MV_THREADS) __attribute__((amdgpu_waves_per_eu(3)))
 void k_matvec(const MvArgs<T> a, int tx, int ty) {
@@ -538,10 +374,7 @@ __device__ __forceinline__ void cg_matvec_block(const CgDesc<T> &d, double *scal
     return true;
   };
   double s;
-  if constexpr (sizeof(T) == 8)
-    s = matvec_block_nodecarry<T, MV_CG>(a, bx, by, bz, [] {}, get_beta, pl, ex, red);
-  else
-    s = matvec_block<T, MV_CG, ZBF>(a, bx, by, bz, [] {}, get_beta, pl, ex, red);
+  s = matvec_block<T, MV_CG, ZBF>(a, bx, by, bz, [] {}, get_beta, pl, ex, red);
   if (run && threadIdx.x == 0) cgp[CGP_PQ + lb] = s;
 }
 
