@@ -353,12 +353,20 @@ __global__ void k_udist(int nelx, int nely, int nelz, double h, const int *__res
                         const int *__restrict__ occ, const double *__restrict__ rho, double rho_t,
                         double *__restrict__ phi) {
   const int NX = nelx + 1, NY = nely + 1, NZ = nelz + 1;
-  const size_t nn = (size_t)NX * NY * NZ;
   const int cx = (nelx + CB - 1) / CB, cy = (nely + CB - 1) / CB, cz = (nelz + CB - 1) / CB;
   const int Rmax = max(cx, max(cy, cz));
-  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < nn;
-       n += (size_t)gridDim.x * blockDim.x) {
-    const int i = (int)(n % NX), j = (int)((n / NX) % NY), k = (int)(n / ((size_t)NX * NY));
+  // one 64-lane wave per CB^3 brick of nodes aligned with a coarse cell: the
+  // lanes share the ring centre and walk the same cells and voxels
+  const int bx = (NX + CB - 1) / CB, by = (NY + CB - 1) / CB, bz = (NZ + CB - 1) / CB;
+  const size_t nbr = (size_t)bx * by * bz;
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 3, lj = (lane >> 2) & 3, lk = lane >> 4;
+  for (size_t b = (blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 6; b < nbr;
+       b += ((size_t)gridDim.x * blockDim.x) >> 6) {
+    const int i = (int)(b % bx) * CB + li, j = (int)((b / bx) % by) * CB + lj,
+              k = (int)(b / ((size_t)bx * by)) * CB + lk;
+    if (i >= NX || j >= NY || k >= NZ) continue;
+    const size_t n = (size_t)i + (size_t)NX * ((size_t)j + (size_t)NY * k);
     const double p[3] = {(double)i * h, (double)j * h, (double)k * h};
     double best = INFINITY;
     // phase 1: voxels i-2 .. i+1 (gaps 0 and 1) per axis
@@ -419,7 +427,9 @@ hipError_t launch_udist(const Grid &g, double h, const int *count, const int *of
   const size_t nc = (size_t)cx * cy * cz;
   hipLaunchKernelGGL(k_occ, dim3((unsigned)std::min<size_t>((nc + 255) / 256, 8192)), dim3(256), 0,
                      s, g.nelx, g.nely, g.nelz, count, occ);
-  int blocks = (int)((g.nn + 127) / 128);
+  static_assert(CB * CB * CB == 64, "one wave per node brick");
+  const size_t nbr = (size_t)((g.nelx + CB) / CB) * ((g.nely + CB) / CB) * ((g.nelz + CB) / CB);
+  int blocks = (int)((nbr + 1) / 2);
   if (blocks > 65535) blocks = 65535;
   hipLaunchKernelGGL(k_udist, dim3(blocks), dim3(128), 0, s, g.nelx, g.nely, g.nelz, h, count,
                      offset, tri, occ, rho, rho_t, phi);
