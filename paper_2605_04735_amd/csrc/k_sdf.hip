@@ -18,6 +18,7 @@
 //  sign       Eq. 30: phi = -d if rho >= rho_t else +d
 //  vf         per voxel, the volume fraction of {phi_lin < 0} over the same
 //             six tets, in closed form from the edge crossing fractions
+#include <climits>
 #include <algorithm>
 
 #include "common.h"
@@ -347,7 +348,8 @@ __device__ __forceinline__ void scan_voxel(int vi, int vj, int vk, int nelx, int
 // a best distance <= 2 h is final).  Phase 2 scans rings of coarse cells
 // around the node's cell, skipping empty cells and cells or voxels whose box
 // is already farther than the best distance; after coarse ring R every
-// unvisited cell is farther than R CB h, which gives the stop rule.
+// unvisited cell lies beyond a face of the scanned box that the grid does not
+// clip, so the distance to the nearest such face gives the stop rule.
 __global__ void k_udist(int nelx, int nely, int nelz, double h, const int *__restrict__ count,
                         const int *__restrict__ offset, const double *__restrict__ tri,
                         const int *__restrict__ occ, const double *__restrict__ rho, double rho_t,
@@ -411,8 +413,17 @@ __global__ void k_udist(int nelx, int nely, int nelz, double h, const int *__res
             }
           }
         }
-        const double lim = (double)R * CB * h;
-        if (best <= lim * lim) break;
+        // unvisited voxels lie beyond a face of the scanned box that the grid
+        // does not clip; the nearest such face bounds their distance
+        int lim = INT_MAX;
+        if (c0i - R > 0) lim = min(lim, i - (c0i - R) * CB);
+        if (c0i + R < cx - 1) lim = min(lim, (c0i + R + 1) * CB - i);
+        if (c0j - R > 0) lim = min(lim, j - (c0j - R) * CB);
+        if (c0j + R < cy - 1) lim = min(lim, (c0j + R + 1) * CB - j);
+        if (c0k - R > 0) lim = min(lim, k - (c0k - R) * CB);
+        if (c0k + R < cz - 1) lim = min(lim, (c0k + R + 1) * CB - k);
+        if (lim == INT_MAX) break;  // the whole grid was scanned
+        if (best <= (double)lim * lim * h * h) break;
       }
     }
     const double d = sqrt(best);
