@@ -20,6 +20,9 @@ Everything is NumPy/SciPy in float64, one step per paper passage:
             point, unsigned/signed distance, ersatz
             volume fraction                              (Secs. 3.2-3.4,
                                                           Eqs. 25-30)
+  simp      optimality-criteria update with bisection on
+            the volume multiplier, and the SIMP loop     (Sec. 2.1, SIMP
+                                                          set-up of Sec. 4)
   api       the library's call names on host arrays with
             the same error contract                     (test helper)
 """
