@@ -149,6 +149,72 @@ to_status to_filter(to_ctx *ctx, double rmin, int32_t mode, const double *d_x, c
 to_status to_density_to_sdf(to_ctx *ctx, const double *d_x, double rho_t, double *d_phi,
                             double *d_rho_nodes, double *d_vf);
 
+/* Optimality-criteria update of the densities: the design update of the
+ * SIMP stage (Sec. 2.1 with the SIMP set-up of Sec. 4).  The paper names OC
+ * without its parameters; this is the textbook scheme (Bendsoe and Sigmund):
+ *   x_new_e = clamp(x_e (max(-dc_e, 0) / lam)^eta,
+ *                   [max(0, x_e - move), min(1, x_e + move)])
+ * (equal voxels: unit volume derivative), with lam by bisection on [0, 1e9]:
+ * the midpoint is evaluated; the lower end moves up when
+ * sum_e x_new_e > vf nel, else the upper end moves down; until
+ * (l2 - l1) / (l1 + l2) <= 1e-3.  x_new is the design of the last midpoint
+ * evaluated.  The volume sums are float64 in a fixed order, so the result is
+ * reproducible run to run.
+ *   d_x [nel] densities in [0,1]; d_dc [nel] sensitivities (filtered ones, in
+ *   the SIMP loop; a positive value counts as 0); d_xnew [nel] output, may
+ *   alias d_x but not d_dc.  0 < vf <= 1, 0 < move <= 1, 0 < eta <= 1.
+ *   info: host, may be NULL.  Synchronises the context stream.
+ * Errors, all before d_xnew is written: TO_E_NONFINITE (NaN/Inf in x or
+ * dc), TO_E_INVALID (x outside [0,1], bad parameters), TO_E_NOCONV (no
+ * multiplier within 200 midpoints: the volume target cannot be met from
+ * above, e.g. every dc is 0). */
+typedef struct {
+  double lambda;       /* the multiplier of the returned design */
+  double change;       /* max_e |x_new_e - x_e|  (Delta rho_max) */
+  double volume;       /* mean of x_new: its volume fraction */
+  int32_t bisections;  /* midpoints evaluated */
+  int32_t reserved;
+} to_oc_info;
+to_status to_oc_update(to_ctx *ctx, const double *d_x, const double *d_dc, double vf, double move,
+                       double eta, double *d_xnew, to_oc_info *info);
+
+/* The SIMP loop of the paper's first stage (Sec. 2.1, set-up of Sec. 4).  Per
+ * design iteration: the state solve (to_solve, warm-started from the previous
+ * displacement), compliance and sensitivity (to_compliance_sensitivity), the
+ * sensitivity filter of Eq. 4 at radius rmin (to_filter, SENS), and the OC
+ * update (to_oc_update, in place); it stops once the largest density change
+ * of an update is <= change_tol (Delta rho_max) or after max_iters updates.
+ *   d_x [nel]: in: the start design (ignored when init_uniform != 0: then
+ *     x = vf everywhere); out: the design after the last update.
+ *   d_u [ndof]: out: the displacement of the last design solved (the one
+ *     before the last update).
+ *   d_work [2 nel]: device scratch.
+ *   h_c_hist [max_iters]: host, may be NULL: compliance of each design solved.
+ *   info: host, may be NULL.
+ * A failing step returns its own status, with the design iteration named in
+ * to_last_error; d_x then holds the last complete update. */
+typedef struct {
+  double vf;           /* target volume fraction, 0 < vf <= 1 (paper: 0.4) */
+  double rmin;         /* sensitivity-filter radius, element units (paper: 2) */
+  double move;         /* OC move limit (0.2) */
+  double eta;          /* OC damping exponent (0.5) */
+  double change_tol;   /* Delta rho_max stop (paper: 0.005 .. 0.08) */
+  int32_t max_iters;   /* design iterations, >= 1 */
+  int32_t init_uniform;
+} to_simp_params;
+typedef struct {
+  int32_t iters;       /* design updates done */
+  int32_t converged;   /* 1 when the Delta rho_max stop was met */
+  int32_t inner_iters; /* inner CG iterations over all state solves */
+  int32_t reserved;
+  double c;            /* compliance of the last design solved */
+  double change;       /* Delta rho_max of the last update */
+  double volume;       /* volume fraction of the returned design */
+  double ms;           /* wall time of the call */
+} to_simp_info;
+to_status to_simp(to_ctx *ctx, const to_simp_params *sp, double *d_x, double *d_u, double *d_work,
+                  double *h_c_hist, to_simp_info *info);
+
 /* Matrix-free operator of Eq. 2, y = K(x) u with the fixed DOFs zeroed on
  * input and identity rows on output (y_fixed = u_fixed), float64.
  * d_u, d_y: [ndof], must not alias.  d_x NULL reuses the moduli of the

@@ -37,6 +37,25 @@ class ToSolveInfo(ctypes.Structure):
                 ("rel_res", ctypes.c_double), ("ms", ctypes.c_double)]
 
 
+class ToOcInfo(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("change", ctypes.c_double),
+                ("volume", ctypes.c_double), ("bisections", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class ToSimpParams(ctypes.Structure):
+    _fields_ = [("vf", ctypes.c_double), ("rmin", ctypes.c_double), ("move", ctypes.c_double),
+                ("eta", ctypes.c_double), ("change_tol", ctypes.c_double),
+                ("max_iters", ctypes.c_int32), ("init_uniform", ctypes.c_int32)]
+
+
+class ToSimpInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("inner_iters", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("c", ctypes.c_double), ("change", ctypes.c_double), ("volume", ctypes.c_double),
+                ("ms", ctypes.c_double)]
+
+
 _lib = None
 
 _P = ctypes.c_void_p
@@ -51,6 +70,9 @@ _SIGS = {
     "to_compliance_sensitivity": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(_D), _P]),
     "to_filter": (ctypes.c_int, [_P, _D, ctypes.c_int32, _P, _P, _P]),
     "to_density_to_sdf": (ctypes.c_int, [_P, _P, _D, _P, _P, _P]),
+    "to_oc_update": (ctypes.c_int, [_P, _P, _P, _D, _D, _D, _P, ctypes.POINTER(ToOcInfo)]),
+    "to_simp": (ctypes.c_int, [_P, ctypes.POINTER(ToSimpParams), _P, _P, _P, _P,
+                               ctypes.POINTER(ToSimpInfo)]),
     "to_matvec": (ctypes.c_int, [_P, _P, _P, _P]),
     "to_matvec_f32": (ctypes.c_int, [_P, _P, _P, _P]),
     "to_last_energy_sum": (_D, [_P]),

@@ -212,6 +212,52 @@ def last_triangle_count(ctx: Context) -> int:
     return L.lib().to_last_triangle_count(ctx.handle)
 
 
+def to_oc_update(ctx: Context, x, dc, vf, move=0.2, eta=0.5, xnew=None, raise_on_error=True):
+    """Returns (xnew, info, status); xnew may be x itself (in place)."""
+    p = ctx.prob
+    if xnew is None:
+        xnew = torch.empty(p.nel, dtype=torch.float64, device=x.device)
+    info = L.ToOcInfo()
+    st = L.lib().to_oc_update(ctx.handle, _dev(x, torch.float64, p.nel, "x"),
+                              _dev(dc, torch.float64, p.nel, "dc"), float(vf), float(move),
+                              float(eta), _dev(xnew, torch.float64, p.nel, "xnew"),
+                              ctypes.byref(info))
+    if raise_on_error:
+        _check(st, ctx.handle)
+    return xnew, {"lambda": info.lambda_, "change": info.change, "volume": info.volume,
+                  "bisections": info.bisections}, st
+
+
+def to_simp(ctx: Context, vf=0.4, rmin=2.0, move=0.2, eta=0.5, change_tol=0.01, max_iters=100,
+            x=None, u=None, work=None, init_uniform=None, raise_on_error=True):
+    """The SIMP loop.  x: start design (None: uniform vf); it is updated in
+    place.  Returns (x, u, info, c_history, status)."""
+    p = ctx.prob
+    dev = torch.device("cuda")
+    if init_uniform is None:
+        init_uniform = x is None
+    if x is None:
+        x = torch.empty(p.nel, dtype=torch.float64, device=dev)
+    if u is None:
+        u = torch.empty(p.ndof, dtype=torch.float64, device=x.device)
+    if work is None:
+        work = torch.empty(2 * p.nel, dtype=torch.float64, device=x.device)
+    hist = np.zeros(int(max_iters), dtype=np.float64)
+    sp = L.ToSimpParams(float(vf), float(rmin), float(move), float(eta), float(change_tol),
+                        int(max_iters), int(bool(init_uniform)))
+    info = L.ToSimpInfo()
+    st = L.lib().to_simp(ctx.handle, ctypes.byref(sp), _dev(x, torch.float64, p.nel, "x"),
+                         _dev(u, torch.float64, p.ndof, "u"),
+                         _dev(work, torch.float64, 2 * p.nel, "work"),
+                         ctypes.c_void_p(hist.ctypes.data), ctypes.byref(info))
+    if raise_on_error:
+        _check(st, ctx.handle)
+    out = {"iters": info.iters, "converged": bool(info.converged),
+           "inner_iters": info.inner_iters, "c": info.c, "change": info.change,
+           "volume": info.volume, "ms": info.ms}
+    return x, u, out, hist[:info.iters].copy(), st
+
+
 def to_profile(ctx: Context, enable: bool):
     """(ms, count) of inner-CG product launches since the previous call."""
     ms = ctypes.c_double(0.0)

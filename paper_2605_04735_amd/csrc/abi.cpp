@@ -424,7 +424,9 @@ to_status to_create(const to_problem *prob, void *d_workspace, size_t bytes, voi
     c->ws_bytes = need;
   }
   carve(c, c->g, prob->precision, c->ws);
-  if (hipHostMalloc((void **)&c->h_scal, S_COUNT * sizeof(double), hipHostMallocDefault) !=
+  // S_COUNT scalars, then OC_STATE + 8 doubles of optimality-criteria state
+  if (hipHostMalloc((void **)&c->h_scal, (S_COUNT + OC_STATE + 8) * sizeof(double),
+                    hipHostMallocDefault) !=
           hipSuccess ||
       hipHostMalloc((void **)&c->h_flags, F_COUNT * sizeof(int), hipHostMallocDefault) != hipSuccess)
     return bail(TO_E_OOM, "hipHostMalloc failed");
@@ -684,6 +686,116 @@ to_status to_density_to_sdf(to_ctx *c, const double *d_x, double rho_t, double *
 }
 
 int32_t to_last_triangle_count(const to_ctx *c) { return c ? c->last_tri : 0; }
+
+to_status to_oc_update(to_ctx *c, const double *d_x, const double *d_dc, double vf, double move,
+                       double eta, double *d_xnew, to_oc_info *info) {
+  if (!c) return fail(nullptr, TO_E_INVALID, "ctx is NULL");
+  if (!d_x || !d_dc || !d_xnew) return fail(c, TO_E_INVALID, "d_x, d_dc and d_xnew are required");
+  if (d_xnew == d_dc) return fail(c, TO_E_INVALID, "d_xnew must not alias d_dc");
+  if (!(vf > 0.0 && vf <= 1.0)) return fail(c, TO_E_INVALID, "need 0 < vf <= 1");
+  if (!(move > 0.0 && move <= 1.0)) return fail(c, TO_E_INVALID, "need 0 < move <= 1");
+  if (!(eta > 0.0 && eta <= 1.0)) return fail(c, TO_E_INVALID, "need 0 < eta <= 1");
+  static_assert(OC_SCRATCH <= 2 * MAXB, "OC scratch lives in the partial-sum array");
+  HIPCHK(hipSetDevice(c->device));
+  const size_t nel = c->g.nel;
+  double *scr = c->part, *h = c->h_scal + S_COUNT;
+  const double target = vf * (double)nel;
+  HIPCHK(launch_fill(c->flags, F_COUNT * sizeof(int), c->stream));
+  // one launch per midpoint plus the one that ends the loop; most updates
+  // take 40-50, so the first batch usually covers them and one host poll
+  // suffices
+  int k = 0;
+  for (int batch = 64;; batch = 32) {
+    HIPCHK(launch_oc_steps(d_x, d_dc, nel, move, eta, target, OC_TOL, OC_L2_0, OC_MAX_STEPS, scr,
+                           k, batch, c->flags, c->stream));
+    k += batch;
+    HIPCHK(hipMemcpyAsync(h, scr + OC_STATE_OFS + (k & 1) * OC_STATE, OC_STATE * sizeof(double),
+                          hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(c->h_flags, c->flags, F_COUNT * sizeof(int), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if ((c->h_flags[F_BADX] & 2) || c->h_flags[F_BADG])
+      return fail(c, TO_E_NONFINITE, "x or dc holds NaN or Inf");
+    if (c->h_flags[F_BADX] & 1) return fail(c, TO_E_INVALID, "x outside [0,1]");
+    if (h[OC_DONE] != 0.0) break;
+    if (k > OC_MAX_STEPS + 64) return fail(c, TO_E_HIP, "OC bisection state did not advance");
+  }
+  if (h[OC_DONE] != 1.0)
+    return fail(c, TO_E_NOCONV,
+                "OC bisection: no multiplier within 200 midpoints (volume target unreachable)");
+  HIPCHK(launch_oc_apply(d_x, d_dc, d_xnew, nel, move, eta, scr, k, c->stream));
+  HIPCHK(hipMemcpyAsync(h + OC_STATE, scr + OC_OUT_OFS, 8 * sizeof(double), hipMemcpyDeviceToHost,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (info) {
+    info->lambda = h[OC_STATE + 0];
+    info->change = h[OC_STATE + 1];
+    info->volume = h[OC_STATE + 2] / (double)nel;
+    info->bisections = (int32_t)h[OC_STATE + 3];
+    info->reserved = 0;
+  }
+  return TO_OK;
+}
+
+to_status to_simp(to_ctx *c, const to_simp_params *sp, double *d_x, double *d_u, double *d_work,
+                  double *h_c_hist, to_simp_info *info) {
+  if (!c) return fail(nullptr, TO_E_INVALID, "ctx is NULL");
+  if (!sp) return fail(c, TO_E_INVALID, "params are required");
+  if (!d_x || !d_u || !d_work) return fail(c, TO_E_INVALID, "d_x, d_u and d_work are required");
+  if (!(sp->vf > 0.0 && sp->vf <= 1.0)) return fail(c, TO_E_INVALID, "need 0 < vf <= 1");
+  if (!(sp->rmin > 0.0 && sp->rmin <= MAX_RMIN)) return fail(c, TO_E_INVALID, "need 0 < rmin <= 6");
+  if (!(sp->move > 0.0 && sp->move <= 1.0)) return fail(c, TO_E_INVALID, "need 0 < move <= 1");
+  if (!(sp->eta > 0.0 && sp->eta <= 1.0)) return fail(c, TO_E_INVALID, "need 0 < eta <= 1");
+  if (!(sp->change_tol >= 0.0)) return fail(c, TO_E_INVALID, "need change_tol >= 0");
+  if (sp->max_iters < 1) return fail(c, TO_E_INVALID, "max_iters must be >= 1");
+  const double t0 = now_ms();
+  HIPCHK(hipSetDevice(c->device));
+  const size_t nel = c->g.nel;
+  double *dc = d_work, *dcf = d_work + nel;
+  if (sp->init_uniform) HIPCHK(launch_set(d_x, nel, sp->vf, c->stream));
+  int it = 0, converged = 0, inner = 0;
+  double cval = 0.0, change = 0.0, volume = 0.0;
+  to_status st = TO_OK;
+  const char *step = "";
+  while (it < sp->max_iters) {
+    to_solve_info si{};
+    step = "state solve";
+    st = to_solve(c, d_x, it == 0 ? nullptr : d_u, d_u, &si);
+    inner += si.inner_iters;
+    if (st != TO_OK) break;
+    step = "compliance and sensitivity";
+    st = to_compliance_sensitivity(c, d_x, d_u, &cval, dc);
+    if (st != TO_OK) break;
+    step = "sensitivity filter";
+    st = to_filter(c, sp->rmin, TO_FILTER_SENS, d_x, dc, dcf);
+    if (st != TO_OK) break;
+    step = "OC update";
+    to_oc_info oi{};
+    st = to_oc_update(c, d_x, dcf, sp->vf, sp->move, sp->eta, d_x, &oi);
+    if (st != TO_OK) break;
+    if (h_c_hist) h_c_hist[it] = cval;
+    ++it;
+    change = oi.change;
+    volume = oi.volume;
+    if (change <= sp->change_tol) {
+      converged = 1;
+      break;
+    }
+  }
+  if (info) {
+    info->iters = it;
+    info->converged = converged;
+    info->inner_iters = inner;
+    info->reserved = 0;
+    info->c = cval;
+    info->change = change;
+    info->volume = volume;
+    info->ms = now_ms() - t0;
+  }
+  if (st != TO_OK)
+    return fail(c, st, "SIMP iteration " + std::to_string(it + 1) + ", " + step + ": " + c->err);
+  return TO_OK;
+}
 
 to_status to_matvec(to_ctx *c, const double *d_x, const double *d_u, double *d_y) {
   if (!c) return fail(nullptr, TO_E_INVALID, "ctx is NULL");

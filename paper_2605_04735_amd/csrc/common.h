@@ -33,11 +33,27 @@ enum Flag {
   F_ITERS,      // inner CG iterations of the current inner solve
   F_BADX,       // bit 0: some x outside [0,1]; bit 1: some x non-finite
   F_CAP,        // the inner CG stops (done) after this many iterations
+  F_BADG,       // some sensitivity handed to the OC update is non-finite
   F_COUNT = 8
 };
 
 constexpr int MAXB = 8192;         // capacity of the per-block partial-sum array
 constexpr int RED_THREADS = 256;
+
+// ---------------------------------------------------------------- OC update
+// Textbook optimality-criteria bisection: lam in [0, OC_L2_0], stop when
+// (l2 - l1) / (l1 + l2) <= OC_TOL, at most OC_MAX_STEPS midpoints.
+constexpr double OC_L2_0 = 1e9;
+constexpr double OC_TOL = 1e-3;
+constexpr int OC_MAX_STEPS = 200;
+constexpr int OC_THREADS = 256;
+constexpr int OC_MAXB = 1024;      // blocks of an OC launch
+// bracket state, two copies (alternate launches read one and write the other)
+enum OcState { OC_L1 = 0, OC_L2, OC_LAM, OC_DONE, OC_STEPS, OC_STATE = 8 };
+// OC scratch (doubles): partials [2][OC_MAXB], state [2][OC_STATE], output [8]
+constexpr int OC_STATE_OFS = 2 * OC_MAXB;
+constexpr int OC_OUT_OFS = OC_STATE_OFS + 2 * OC_STATE;
+constexpr int OC_SCRATCH = OC_OUT_OFS + 8;
 
 // Element tile of the matrix-free product: 16 x 16 elements per z layer, one
 // thread each; the tile owns the 15 x 15 nodes whose all adjacent elements lie
@@ -192,6 +208,17 @@ hipError_t launch_finish_init(const double *cgp, int nb_up, int slot, double tol
 hipError_t launch_finish_sum(const double *part, int nb, int comp, double *scal, int idx,
                              hipStream_t s);
 hipError_t launch_fill(void *p, size_t bytes, hipStream_t s);
+
+// optimality-criteria update (k_oc.hip); scratch: OC_SCRATCH doubles
+int oc_blocks(size_t nel);
+// launches k0 .. k0 + count - 1 of the bisection (launch 0 starts the bracket)
+hipError_t launch_oc_steps(const double *x, const double *dc, size_t nel, double move, double eta,
+                           double target, double tol, double l2_0, int max_steps, double *scratch,
+                           int k0, int count, int *flags, hipStream_t s);
+// after k bisection launches: writes x_new and the output block
+hipError_t launch_oc_apply(const double *x, const double *dc, double *xnew, size_t nel,
+                           double move, double eta, double *scratch, int k, hipStream_t s);
+hipError_t launch_set(double *p, size_t n, double v, hipStream_t s);
 hipError_t launch_set_scale(double *scal, hipStream_t s);
 hipError_t launch_dot(const double *a, const double *b, size_t n, double *part, int *nb,
                       hipStream_t s);

@@ -50,24 +50,28 @@ def test_workspace_size_validates_problem():
         A.to_workspace_size(A.Problem(4, 3, 2, bc=A.BC_CUSTOM))
 
 
+STRUCTS = [(L.ToProblem, "to_problem"), (L.ToSolveInfo, "to_solve_info"),
+           (L.ToOcInfo, "to_oc_info"), (L.ToSimpParams, "to_simp_params"),
+           (L.ToSimpInfo, "to_simp_info")]
+
+
 def test_struct_layout_matches_header(tmp_path):
-    """ctypes field offsets equal the C compiler's for include/to.h."""
-    fields = [f for f, _ in L.ToProblem._fields_]
+    """ctypes field offsets and sizes equal the C compiler's for include/to.h."""
+    body, expect = "", []
+    for cls, cname in STRUCTS:
+        for f, _ in cls._fields_:
+            body += 'printf("%%zu ", offsetof(%s, %s));' % (cname, f.rstrip("_"))
+            expect.append(getattr(cls, f).offset)
+        body += 'printf("%%zu ", sizeof(%s));' % cname
+        expect.append(ctypes.sizeof(cls))
     src = tmp_path / "lay.c"
-    ifields = [f for f, _ in L.ToSolveInfo._fields_]
-    body = "".join('printf("%%zu ", offsetof(to_problem, %s));' % f for f in fields)
-    body += "".join('printf("%%zu ", offsetof(to_solve_info, %s));' % f for f in ifields)
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "to.h"\n'
-                   'int main(void){ %s printf("%%zu %%zu\\n", sizeof(to_problem), '
-                   'sizeof(to_solve_info)); return 0; }' % body)
+                   'int main(void){ %s return 0; }' % body)
     exe = tmp_path / "lay"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
                                            check=True).stdout.split()]
-    assert vals[:len(fields)] == [getattr(L.ToProblem, f).offset for f in fields]
-    assert vals[len(fields):-2] == [getattr(L.ToSolveInfo, f).offset for f in ifields]
-    assert vals[-2] == ctypes.sizeof(L.ToProblem)
-    assert vals[-1] == ctypes.sizeof(L.ToSolveInfo)
+    assert vals == expect
 
 
 def test_last_error_without_context():
