@@ -58,6 +58,7 @@ def parse():
     ap.add_argument("--no-large", action="store_true", help="skip the 256x128x128 product timing")
     ap.add_argument("--cpu-iters", type=int, default=100)
     ap.add_argument("--no-serving", action="store_true", help="skip the request-stream benchmark")
+    ap.add_argument("--no-simp", action="store_true", help="skip the SIMP-loop workload")
     ap.add_argument("--requests", type=int, default=128)
     ap.add_argument("--probe", choices=["copy", "cg", "cg3", "product"], default=None,
                     help="short runs for hardware-counter passes: a device copy of known size, "
@@ -325,6 +326,8 @@ def main():
     if not args.no_large:
         workloads["mbb_sdf_ersatz_192x64x32"] = workload_mbb_sdf(A, inputs, dev)
         workloads["cantilever_256x128x128"] = workload_large(A, inputs, dev)
+    if not args.no_simp:
+        workloads["simp_cantilever_96x48x48"] = workload_simp(A, dev, rtol_mixed, rtol_fp64)
 
     # ---------------------------------------------------------- roofline
     # dominant kernel: the fused inner-CG product (p = z + beta p_old, q = K p,
@@ -433,6 +436,49 @@ def workload_mbb_sdf(A, inputs, dev):
         out[name]["err"] = {"u": rel2(u, ur), "c": abs(c - cr) / abs(cr), "dc": rel2(dc, dcr)}
     log("mbb+sdf 192x64x32: sdf %.1f ms (%d triangles); fp32+refine %s; fp64 %s"
         % (t_sdf, ntri, out["fp32_refine"], out["fp64"]))
+    return out
+
+
+def workload_simp(A, dev, rtol_mixed, rtol_fp64, iters=12):
+    """The SIMP stage on the cantilever 96x48x48: from x = V_f = 0.4, penal 3,
+    sensitivity filter R = 2 (Eq. 4), OC updates (move 0.2, eta 1/2), a fixed
+    number of design iterations (no Delta rho_max stop, so both precisions do
+    the same work), each precision at its calibrated tolerance.  The OC update
+    is also timed on its own, on the final design and its filtered
+    sensitivity."""
+    import torch
+    dims = (96, 48, 48)
+    out = {"iters": iters, "vf": 0.4, "rmin": 2.0}
+    for name, prec, rtol in (("fp32_refine", A.PREC_FP32_REFINE, rtol_mixed),
+                             ("fp64", A.PREC_FP64, rtol_fp64)):
+        ctx = A.to_create(A.Problem(*dims, precision=prec, rtol=rtol, max_iters=10 ** 6))
+        A.to_simp(ctx, vf=0.4, rmin=2.0, change_tol=0.0, max_iters=2)  # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, u, info, hist, _ = A.to_simp(ctx, vf=0.4, rmin=2.0, change_tol=0.0, max_iters=iters)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        rec = {"ms_per_iter": round(ms / iters, 3), "iters_per_s": round(iters / (ms * 1e-3), 3),
+               "inner_iters": info["inner_iters"], "c_first": float(hist[0]),
+               "c_last": float(hist[-1]), "change_last": info["change"],
+               "volume": info["volume"]}
+        if name == "fp32_refine":
+            _, dc = A.to_compliance_sensitivity(ctx, x, u)
+            dcf = A.to_filter(ctx, 2.0, A.FILTER_SENS, dc, x=x)
+            xn = torch.empty_like(x)
+            A.to_oc_update(ctx, x, dcf, 0.4, xnew=xn)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(10):
+                _, oi, _ = A.to_oc_update(ctx, x, dcf, 0.4, xnew=xn)
+            torch.cuda.synchronize()
+            rec["oc_update_ms"] = round((time.perf_counter() - t0) * 1e2, 4)
+            rec["oc_bisections"] = oi["bisections"]
+        out[name] = rec
+        ctx.close()
+    out["speedup_fp32_refine_vs_fp64"] = round(out["fp64"]["ms_per_iter"]
+                                               / out["fp32_refine"]["ms_per_iter"], 3)
+    log("simp 96x48x48: %s" % out)
     return out
 
 
