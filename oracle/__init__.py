@@ -23,6 +23,10 @@ Everything is NumPy/SciPy in float64, one step per paper passage:
   simp      optimality-criteria update with bisection on
             the volume multiplier, and the SIMP loop     (Sec. 2.1, SIMP
                                                           set-up of Sec. 4)
+  levelset  Hamilton-Jacobi evolution with the CFL step
+            and reinitialisation with the smeared sign,
+            first-order Godunov upwind on the node grid  (Secs. 2.2.4-2.2.5,
+                                                          Eqs. 21-24)
   api       the library's call names on host arrays with
             the same error contract                     (test helper)
 """
