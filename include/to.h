@@ -215,6 +215,37 @@ typedef struct {
 to_status to_simp(to_ctx *ctx, const to_simp_params *sp, double *d_x, double *d_u, double *d_work,
                   double *h_c_hist, to_simp_info *info);
 
+/* Level-set evolution (Sec. 2.2.4): nsteps forward-Euler steps of the
+ * Hamilton-Jacobi equation phi_t + v |grad phi| = 0 (Eq. 21) with the
+ * first-order Godunov upwind stencil on the node grid, at
+ * dt = gamma h / max|v| (the CFL bound of Eq. 22 times the CFL number gamma).
+ * With D-, D+ the one-sided differences along each axis (across a box face
+ * the difference is 0: the missing neighbour is the node itself):
+ *   g+ = sqrt(sum_axes max(D-,0)^2 + min(D+,0)^2),
+ *   g- = sqrt(sum_axes min(D-,0)^2 + max(D+,0)^2),
+ *   phi <- phi - dt (max(v,0) g+ + min(v,0) g-).
+ * d_phi [nn] in/out; d_v [nn] nodal normal speed, must not alias d_phi;
+ * 0 < gamma <= 1; nsteps >= 0.  h_dt (host, may be NULL) receives dt (0 when
+ * v = 0 everywhere: phi is left as it is).  TO_E_NONFINITE (NaN/Inf in phi or
+ * v) is returned before phi is touched.  Asynchronous after the input check. */
+to_status to_ls_advect(to_ctx *ctx, double *d_phi, const double *d_v, double gamma,
+                       int32_t nsteps, double *h_dt);
+
+/* Reinitialisation (Sec. 2.2.5): pseudo-steps of
+ * phi_t + S(phi)(|grad phi| - 1) = 0 (Eq. 23) with the same stencil and the
+ * smeared sign S = phi / sqrt(phi^2 + h^2 |grad phi|^2) (Eq. 24) taken from
+ * the current phi at every pseudo-step (|grad phi| by central differences,
+ * S = 0 where the root is 0):
+ *   phi <- phi - gamma h (max(S,0)(g+ - 1) + min(S,0)(g- - 1)),
+ * until the first pseudo-step whose largest |change| is < tol.
+ * d_phi [nn] in/out; 0 < gamma <= 1; tol > 0; max_steps >= 1.  h_steps and
+ * h_change (host, may be NULL): pseudo-steps taken and the last step's
+ * largest change.  TO_E_NOCONV when max_steps pass without reaching tol (phi
+ * holds the last iterate); TO_E_NONFINITE before phi is touched.
+ * Synchronises the context stream. */
+to_status to_ls_reinit(to_ctx *ctx, double *d_phi, double gamma, double tol, int32_t max_steps,
+                       int32_t *h_steps, double *h_change);
+
 /* Matrix-free operator of Eq. 2, y = K(x) u with the fixed DOFs zeroed on
  * input and identity rows on output (y_fixed = u_fixed), float64.
  * d_u, d_y: [ndof], must not alias.  d_x NULL reuses the moduli of the

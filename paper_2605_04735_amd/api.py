@@ -258,6 +258,31 @@ def to_simp(ctx: Context, vf=0.4, rmin=2.0, move=0.2, eta=0.5, change_tol=0.01, 
     return x, u, out, hist[:info.iters].copy(), st
 
 
+def to_ls_advect(ctx: Context, phi, v, gamma=0.5, nsteps=1, raise_on_error=True):
+    """Evolves phi in place.  Returns (phi, dt, status)."""
+    p = ctx.prob
+    dt = ctypes.c_double(0.0)
+    st = L.lib().to_ls_advect(ctx.handle, _dev(phi, torch.float64, p.nn, "phi"),
+                              _dev(v, torch.float64, p.nn, "v"), float(gamma), int(nsteps),
+                              ctypes.byref(dt))
+    if raise_on_error:
+        _check(st, ctx.handle)
+    return phi, dt.value, st
+
+
+def to_ls_reinit(ctx: Context, phi, gamma=0.5, tol=1e-3, max_steps=1000, raise_on_error=True):
+    """Reinitialises phi in place.  Returns (phi, steps, last change, status)."""
+    p = ctx.prob
+    steps = ctypes.c_int32(0)
+    change = ctypes.c_double(0.0)
+    st = L.lib().to_ls_reinit(ctx.handle, _dev(phi, torch.float64, p.nn, "phi"), float(gamma),
+                              float(tol), int(max_steps), ctypes.byref(steps),
+                              ctypes.byref(change))
+    if raise_on_error:
+        _check(st, ctx.handle)
+    return phi, steps.value, change.value, st
+
+
 def to_profile(ctx: Context, enable: bool):
     """(ms, count) of inner-CG product launches since the previous call."""
     ms = ctypes.c_double(0.0)

@@ -737,6 +737,87 @@ to_status to_oc_update(to_ctx *c, const double *d_x, const double *d_dc, double 
   return TO_OK;
 }
 
+// Level-set scratch: the second field buffer is the node-density scratch of
+// the SDF transfer (nn doubles, only used inside to_density_to_sdf); the
+// three change slots and the loop state live in the partial-sum array.
+to_status ls_check(to_ctx *c, const double *d_phi, const double *d_v, double *vmax) {
+  unsigned long long *slots = (unsigned long long *)c->part;
+  HIPCHK(launch_fill(c->flags, F_COUNT * sizeof(int), c->stream));
+  HIPCHK(launch_fill(c->part, 8 * sizeof(double), c->stream));
+  HIPCHK(launch_ls_check(c->g, d_phi, d_v, c->flags, slots + 3, c->stream));
+  double *h = c->h_scal + S_COUNT;
+  HIPCHK(hipMemcpyAsync(h, slots + 3, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(c->h_flags, c->flags, F_COUNT * sizeof(int), hipMemcpyDeviceToHost,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (c->h_flags[F_BADX] & 2) return fail(c, TO_E_NONFINITE, "phi or v holds NaN or Inf");
+  *vmax = h[0];
+  return TO_OK;
+}
+
+to_status to_ls_advect(to_ctx *c, double *d_phi, const double *d_v, double gamma, int32_t nsteps,
+                       double *h_dt) {
+  if (!c) return fail(nullptr, TO_E_INVALID, "ctx is NULL");
+  if (!d_phi || !d_v) return fail(c, TO_E_INVALID, "d_phi and d_v are required");
+  if (d_phi == d_v) return fail(c, TO_E_INVALID, "d_v must not alias d_phi");
+  if (!(gamma > 0.0 && gamma <= 1.0)) return fail(c, TO_E_INVALID, "need 0 < gamma <= 1");
+  if (nsteps < 0) return fail(c, TO_E_INVALID, "nsteps must be >= 0");
+  HIPCHK(hipSetDevice(c->device));
+  double vmax = 0.0;
+  to_status st = ls_check(c, d_phi, d_v, &vmax);
+  if (st != TO_OK) return st;
+  const double h = c->p.h;
+  const double dt = vmax == 0.0 ? 0.0 : gamma * h / vmax;
+  if (h_dt) *h_dt = dt;
+  if (dt == 0.0 || nsteps == 0) return TO_OK;
+  double *buf[2] = {d_phi, c->rho_scratch};
+  for (int k = 0; k < nsteps; ++k)
+    HIPCHK(launch_ls_advect(c->g, h, dt, buf[k & 1], d_v, buf[(k + 1) & 1], c->stream));
+  if (nsteps & 1)
+    HIPCHK(hipMemcpyAsync(d_phi, buf[1], c->g.nn * sizeof(double), hipMemcpyDeviceToDevice,
+                          c->stream));
+  return TO_OK;
+}
+
+to_status to_ls_reinit(to_ctx *c, double *d_phi, double gamma, double tol, int32_t max_steps,
+                       int32_t *h_steps, double *h_change) {
+  if (!c) return fail(nullptr, TO_E_INVALID, "ctx is NULL");
+  if (!d_phi) return fail(c, TO_E_INVALID, "d_phi is required");
+  if (!(gamma > 0.0 && gamma <= 1.0)) return fail(c, TO_E_INVALID, "need 0 < gamma <= 1");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(c, TO_E_INVALID, "need tol > 0");
+  if (max_steps < 1) return fail(c, TO_E_INVALID, "max_steps must be >= 1");
+  HIPCHK(hipSetDevice(c->device));
+  double vmax = 0.0;
+  to_status st = ls_check(c, d_phi, nullptr, &vmax);
+  if (st != TO_OK) return st;
+  const double h = c->p.h, dtau = gamma * h;
+  unsigned long long *slots = (unsigned long long *)c->part;
+  double *state = c->part + 4, *hs = c->h_scal + S_COUNT;
+  double *buf[2] = {d_phi, c->rho_scratch};
+  // one launch per pseudo-step plus the one that sees the stop; the host
+  // looks at the state once per batch
+  int k = 0;
+  for (;;) {
+    for (int b = 0; b < 64; ++b, ++k)
+      HIPCHK(launch_ls_reinit(c->g, h, dtau, tol, max_steps, k, buf[k & 1], buf[(k + 1) & 1],
+                              slots, state, c->stream));
+    HIPCHK(hipMemcpyAsync(hs, state, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (hs[0] != 0.0) break;
+    if (k > max_steps + 128) return fail(c, TO_E_HIP, "reinitialisation state did not advance");
+  }
+  const int steps = (int)hs[1];
+  if (steps & 1)
+    HIPCHK(hipMemcpyAsync(d_phi, buf[1], c->g.nn * sizeof(double), hipMemcpyDeviceToDevice,
+                          c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (h_steps) *h_steps = steps;
+  if (h_change) *h_change = hs[2];
+  if (hs[0] != 1.0)
+    return fail(c, TO_E_NOCONV, "reinitialisation: change still >= tol after max_steps");
+  return TO_OK;
+}
+
 to_status to_simp(to_ctx *c, const to_simp_params *sp, double *d_x, double *d_u, double *d_work,
                   double *h_c_hist, to_simp_info *info) {
   if (!c) return fail(nullptr, TO_E_INVALID, "ctx is NULL");

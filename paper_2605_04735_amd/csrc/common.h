@@ -219,6 +219,16 @@ hipError_t launch_oc_steps(const double *x, const double *dc, size_t nel, double
 hipError_t launch_oc_apply(const double *x, const double *dc, double *xnew, size_t nel,
                            double move, double eta, double *scratch, int k, hipStream_t s);
 hipError_t launch_set(double *p, size_t n, double v, hipStream_t s);
+
+// level-set evolution and reinitialisation (k_levelset.hip)
+hipError_t launch_ls_check(const Grid &g, const double *phi, const double *v, int *flags,
+                           unsigned long long *vmax, hipStream_t s);
+hipError_t launch_ls_advect(const Grid &g, double h, double dt, const double *in, const double *v,
+                            double *out, hipStream_t s);
+// launch k of the reinitialisation loop; slots: 3 words, state: 3 doubles
+hipError_t launch_ls_reinit(const Grid &g, double h, double dtau, double tol, int max_steps,
+                            int k, const double *in, double *out, unsigned long long *slots,
+                            double *state, hipStream_t s);
 hipError_t launch_set_scale(double *scal, hipStream_t s);
 hipError_t launch_dot(const double *a, const double *b, size_t n, double *part, int *nb,
                       hipStream_t s);

@@ -1,0 +1,145 @@
+"""GPU parity of level-set evolution (Sec. 2.2.4, Eqs. 21-22) and
+reinitialisation (Sec. 2.2.5, Eqs. 23-24), through the C ABI, against the
+oracle on the same seeded inputs.
+
+Both sides evaluate the same expressions in the same order with correctly
+rounded IEEE operations (the kernels are built without contraction), so the
+fields must be equal bit for bit, and so must the reinitialisation's step
+count and last change.  Inputs are analytic: a union of spheres (an exact signed
+distance outside the spheres), a distorted sphere (r^2 - R^2)/(2R), and smooth
+speed fields that change sign."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import levelset as LS
+from paper_2605_04735_amd import api as A
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def cpu(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def coords(dims):
+    nelx, nely, nelz = dims
+    k, j, i = np.meshgrid(np.arange(nelz + 1), np.arange(nely + 1), np.arange(nelx + 1),
+                          indexing="ij")
+    return i.ravel().astype(float), j.ravel().astype(float), k.ravel().astype(float)
+
+
+def spheres(dims, seed):
+    i, j, k = coords(dims)
+    rng = np.random.default_rng(seed)
+    phi = np.full(i.size, np.inf)
+    for _ in range(3):
+        c = rng.uniform(0, 1, 3) * np.array(dims)
+        R = rng.uniform(0.15, 0.3) * min(dims) + 0.7
+        phi = np.minimum(phi, np.sqrt((i - c[0]) ** 2 + (j - c[1]) ** 2 + (k - c[2]) ** 2) - R)
+    return phi
+
+
+def speed(dims, seed):
+    i, j, k = coords(dims)
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(0.05, 0.4, 4)
+    return 0.8 * np.sin(a[0] * i + 0.3) * np.cos(a[1] * j) + 0.5 * np.sin(a[2] * k + a[3] * j)
+
+
+def close(a, b, what):
+    d = np.abs(a - b)
+    print("%s: %d of %d entries differ, max %.3e" % (what, int(np.sum(d > 0)), d.size, d.max()),
+          flush=True)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("dims,nsteps", [((1, 1, 1), 3), ((7, 3, 2), 4), ((40, 33, 19), 3),
+                                         ((96, 48, 48), 4), ((256, 128, 128), 2)])
+def test_advect_vs_oracle(dims, nsteps):
+    print("advect", dims, nsteps, flush=True)
+    phi = spheres(dims, sum(dims))
+    v = speed(dims, 7)
+    ref, dt_ref = LS.advect(phi, v, *dims, h=1.0, gamma=0.5, nsteps=nsteps)
+    ctx = A.to_create(A.Problem(*dims))
+    p = gpu(phi)
+    _, dt, _ = A.to_ls_advect(ctx, p, gpu(v), gamma=0.5, nsteps=nsteps)
+    assert dt == dt_ref
+    close(cpu(p), ref, "advect %s" % (dims,))
+
+
+def test_advect_h_and_zero_speed():
+    dims = (12, 9, 7)
+    phi = spheres(dims, 3) * 0.25
+    v = speed(dims, 4)
+    ref, dt_ref = LS.advect(phi, v, *dims, h=0.25, gamma=0.3, nsteps=5)
+    ctx = A.to_create(A.Problem(*dims, h=0.25))
+    p = gpu(phi)
+    _, dt, _ = A.to_ls_advect(ctx, p, gpu(v), gamma=0.3, nsteps=5)
+    assert dt == dt_ref
+    close(cpu(p), ref, "advect h=0.25")
+    p = gpu(phi)
+    _, dt, _ = A.to_ls_advect(ctx, p, gpu(np.zeros_like(v)), gamma=0.5, nsteps=3)
+    assert dt == 0.0 and np.array_equal(cpu(p), phi)
+
+
+@pytest.mark.parametrize("dims,kind", [((1, 1, 1), "scaled"), ((2, 3, 2), "scaled"), ((24, 20, 16), "sphere"),
+                                       ((40, 33, 19), "scaled"), ((96, 48, 48), "scaled")])
+def test_reinit_vs_oracle(dims, kind):
+    print("reinit", dims, kind, flush=True)
+    i, j, k = coords(dims)
+    if kind == "sphere":
+        c = np.array(dims) * np.array([0.47, 0.49, 0.51])
+        R = 0.3 * min(dims) + 0.6
+        r = np.sqrt((i - c[0]) ** 2 + (j - c[1]) ** 2 + (k - c[2]) ** 2)
+        phi = (r ** 2 - R ** 2) / (2 * R)
+    else:
+        phi = 2.5 * spheres(dims, 5)
+    ref, steps_ref, change_ref = LS.reinit(phi, *dims, h=1.0, gamma=0.5, tol=1e-3, max_steps=600)
+    ctx = A.to_create(A.Problem(*dims))
+    p = gpu(phi)
+    _, steps, change, _ = A.to_ls_reinit(ctx, p, gamma=0.5, tol=1e-3, max_steps=600)
+    assert steps == steps_ref
+    assert change == change_ref
+    close(cpu(p), ref, "reinit %s" % (dims,))
+
+
+def test_reinit_cap_and_errors():
+    dims = (20, 14, 10)
+    i, j, k = coords(dims)
+    r = np.sqrt((i - 9.6) ** 2 + (j - 7.1) ** 2 + (k - 4.9) ** 2)
+    phi = (r ** 2 - 16.0) / 8.0
+    ctx = A.to_create(A.Problem(*dims))
+    p = gpu(phi)
+    _, steps, change, st = A.to_ls_reinit(ctx, p, gamma=0.5, tol=1e-6, max_steps=7,
+                                          raise_on_error=False)
+    assert st == A.L.TO_E_NOCONV and steps == 7
+    ref = phi.copy()
+    for _ in range(7):
+        ref = LS.reinit_step(ref, *dims, 1.0, 0.5)
+    close(cpu(p), ref, "reinit capped")
+    bad = phi.copy()
+    bad[5] = np.nan
+    p = gpu(bad)
+    _, _, _, st = A.to_ls_reinit(ctx, p, raise_on_error=False)
+    assert st == A.L.TO_E_NONFINITE
+    assert np.array_equal(np.isnan(cpu(p)), np.isnan(bad))
+    p = gpu(phi)
+    v = np.ones_like(phi)
+    v[3] = np.inf
+    _, _, st = A.to_ls_advect(ctx, p, gpu(v), raise_on_error=False)
+    assert st == A.L.TO_E_NONFINITE and np.array_equal(cpu(p), phi)
+    for kw in (dict(gamma=0.0), dict(gamma=1.5), dict(tol=0.0), dict(max_steps=0)):
+        _, _, _, st = A.to_ls_reinit(ctx, gpu(phi), raise_on_error=False, **kw)
+        assert st == A.L.TO_E_INVALID
+    _, _, st = A.to_ls_advect(ctx, gpu(phi), gpu(phi), nsteps=-1, raise_on_error=False)
+    assert st == A.L.TO_E_INVALID
+    # the context stays usable
+    _, steps, _, st = A.to_ls_reinit(ctx, gpu(phi), tol=1e-2)
+    assert st == A.L.TO_OK and steps > 0
