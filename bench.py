@@ -59,10 +59,13 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=100)
     ap.add_argument("--no-serving", action="store_true", help="skip the request-stream benchmark")
     ap.add_argument("--no-simp", action="store_true", help="skip the SIMP-loop workload")
+    ap.add_argument("--no-levelset", action="store_true",
+                    help="skip the level-set evolution/reinitialisation workload")
     ap.add_argument("--requests", type=int, default=128)
-    ap.add_argument("--probe", choices=["copy", "cg", "cg3", "product"], default=None,
+    ap.add_argument("--probe", choices=["copy", "cg", "cg3", "product", "levelset"], default=None,
                     help="short runs for hardware-counter passes: a device copy of known size, "
-                         "one workload solve, or products on 256x128x128")
+                         "one workload solve, products on 256x128x128, or level-set steps on "
+                         "its node grid")
     return ap.parse_args()
 
 
@@ -91,6 +94,15 @@ def probe(kind):
         u, info, _ = A.to_solve(ctx, x)
         torch.cuda.synchronize()
         log("cg probe: %s" % info)
+        return
+    if kind == "levelset":
+        ctx = A.to_create(A.Problem(*LARGE))
+        phi = torch.from_numpy(inputs.sphere_union(*LARGE, 5, scale=2.5)).to(dev)
+        v = torch.from_numpy(inputs.smooth_speed(*LARGE, 7)).to(dev)
+        A.to_ls_advect(ctx, phi, v, gamma=0.5, nsteps=10)
+        A.to_ls_reinit(ctx, phi, gamma=0.5, tol=1e-3, max_steps=40, raise_on_error=False)
+        torch.cuda.synchronize()
+        log("level-set probe done")
         return
     for f32 in (True, False):
         p = A.Problem(*LARGE, precision=A.PREC_FP32_REFINE if f32 else A.PREC_FP64)
@@ -328,6 +340,8 @@ def main():
         workloads["cantilever_256x128x128"] = workload_large(A, inputs, dev)
     if not args.no_simp:
         workloads["simp_cantilever_96x48x48"] = workload_simp(A, dev, rtol_mixed, rtol_fp64)
+    if not args.no_levelset:
+        workloads["levelset"] = workload_levelset(A, inputs, dev)
 
     # ---------------------------------------------------------- roofline
     # dominant kernel: the fused inner-CG product (p = z + beta p_old, q = K p,
@@ -479,6 +493,52 @@ def workload_simp(A, dev, rtol_mixed, rtol_fp64, iters=12):
     out["speedup_fp32_refine_vs_fp64"] = round(out["fp64"]["ms_per_iter"]
                                                / out["fp32_refine"]["ms_per_iter"], 3)
     log("simp 96x48x48: %s" % out)
+    return out
+
+
+def workload_levelset(A, inputs, dev, nsteps=40):
+    """Level-set evolution (Eqs. 21-22) and reinitialisation (Eqs. 23-24) on
+    the node grids of the 96x48x48 and 256x128x128 cantilevers: phi = 2.5 x the
+    distance to a union of three balls, a smooth speed of both signs, CFL
+    number 1/2.  Evolution: nsteps steps in one call, timed with events around
+    the call (one input check and host read, then the step launches).
+    Reinitialisation to max|change| < 1e-3 h.  Algorithmic bytes per node and
+    step: 24 (read phi and v, write phi) and 16 (read and write phi)."""
+    import torch
+    out = {}
+    for dims in ((96, 48, 48), (256, 128, 128)):
+        nn = (dims[0] + 1) * (dims[1] + 1) * (dims[2] + 1)
+        ctx = A.to_create(A.Problem(*dims))
+        phi0 = torch.from_numpy(inputs.sphere_union(*dims, 5, scale=2.5)).to(dev)
+        v = torch.from_numpy(inputs.smooth_speed(*dims, 7)).to(dev)
+        p = phi0.clone()
+        A.to_ls_advect(ctx, p, v, gamma=0.5, nsteps=2)  # warm
+        p.copy_(phi0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        A.to_ls_advect(ctx, p, v, gamma=0.5, nsteps=nsteps)
+        e1.record()
+        torch.cuda.synchronize()
+        us_adv = e0.elapsed_time(e1) * 1e3 / nsteps
+        p.copy_(phi0)
+        torch.cuda.synchronize()
+        e0.record()
+        _, steps, change, st = A.to_ls_reinit(ctx, p, gamma=0.5, tol=1e-3, max_steps=5000,
+                                              raise_on_error=False)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_re = e0.elapsed_time(e1)
+        us_re = ms_re * 1e3 / max(steps, 1)
+        rec = {"nodes": nn, "advect_us_per_step": round(us_adv, 3),
+               "advect_GBs": round(24 * nn / (us_adv * 1e-6) / 1e9, 1),
+               "advect_frac_hbm": round(24 * nn / (us_adv * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+               "reinit_steps": steps, "reinit_status": A.L.STATUS_NAMES.get(st, st),
+               "reinit_ms": round(ms_re, 3), "reinit_us_per_step": round(us_re, 3),
+               "reinit_GBs": round(16 * nn / (us_re * 1e-6) / 1e9, 1)}
+        out["%dx%dx%d" % dims] = rec
+        ctx.close()
+    log("levelset: %s" % out)
     return out
 
 

@@ -739,14 +739,17 @@ to_status to_oc_update(to_ctx *c, const double *d_x, const double *d_dc, double 
 
 // Level-set scratch: the second field buffer is the node-density scratch of
 // the SDF transfer (nn doubles, only used inside to_density_to_sdf); the
-// three change slots and the loop state live in the partial-sum array.
+// change slots, the loop state and the max|v| word live in the partial-sum
+// array, cleared here before every call.
 to_status ls_check(to_ctx *c, const double *d_phi, const double *d_v, double *vmax) {
-  unsigned long long *slots = (unsigned long long *)c->part;
+  static_assert(LS_SCRATCH <= 2 * MAXB, "level-set scratch lives in the partial-sum array");
+  unsigned long long *words = (unsigned long long *)c->part;
   HIPCHK(launch_fill(c->flags, F_COUNT * sizeof(int), c->stream));
-  HIPCHK(launch_fill(c->part, 8 * sizeof(double), c->stream));
-  HIPCHK(launch_ls_check(c->g, d_phi, d_v, c->flags, slots + 3, c->stream));
+  HIPCHK(launch_fill(c->part, LS_SCRATCH * sizeof(double), c->stream));
+  HIPCHK(launch_ls_check(c->g, d_phi, d_v, c->flags, words + LS_VMAX_OFS, c->stream));
   double *h = c->h_scal + S_COUNT;
-  HIPCHK(hipMemcpyAsync(h, slots + 3, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(h, words + LS_VMAX_OFS, sizeof(double), hipMemcpyDeviceToHost,
+                        c->stream));
   HIPCHK(hipMemcpyAsync(c->h_flags, c->flags, F_COUNT * sizeof(int), hipMemcpyDeviceToHost,
                         c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
@@ -792,7 +795,7 @@ to_status to_ls_reinit(to_ctx *c, double *d_phi, double gamma, double tol, int32
   if (st != TO_OK) return st;
   const double h = c->p.h, dtau = gamma * h;
   unsigned long long *slots = (unsigned long long *)c->part;
-  double *state = c->part + 4, *hs = c->h_scal + S_COUNT;
+  double *state = c->part + LS_STATE_OFS, *hs = c->h_scal + S_COUNT;
   double *buf[2] = {d_phi, c->rho_scratch};
   // one launch per pseudo-step plus the one that sees the stop; the host
   // looks at the state once per batch

@@ -220,12 +220,22 @@ hipError_t launch_oc_apply(const double *x, const double *dc, double *xnew, size
                            double move, double eta, double *scratch, int k, hipStream_t s);
 hipError_t launch_set(double *p, size_t n, double v, hipStream_t s);
 
-// level-set evolution and reinitialisation (k_levelset.hip)
+// level-set evolution and reinitialisation (k_levelset.hip).  The largest
+// |change| of a reinitialisation step is taken by atomic max over LS_SLOTS
+// words on separate 128-byte lines (a block picks one by its index), so the
+// atomics of thousands of blocks do not queue on one address; three such sets
+// rotate between launches.  Scratch (8-byte words): the sets, then the loop
+// state (3 doubles) and the max|v| word.
+constexpr int LS_SLOTS = 64, LS_SLOT_STRIDE = 16;
+constexpr int LS_SET_WORDS = LS_SLOTS * LS_SLOT_STRIDE;
+constexpr int LS_STATE_OFS = 3 * LS_SET_WORDS;
+constexpr int LS_VMAX_OFS = LS_STATE_OFS + 4;
+constexpr int LS_SCRATCH = LS_STATE_OFS + 8;
 hipError_t launch_ls_check(const Grid &g, const double *phi, const double *v, int *flags,
                            unsigned long long *vmax, hipStream_t s);
 hipError_t launch_ls_advect(const Grid &g, double h, double dt, const double *in, const double *v,
                             double *out, hipStream_t s);
-// launch k of the reinitialisation loop; slots: 3 words, state: 3 doubles
+// launch k of the reinitialisation loop; slots: 3 sets, state: 3 doubles
 hipError_t launch_ls_reinit(const Grid &g, double h, double dtau, double tol, int max_steps,
                             int k, const double *in, double *out, unsigned long long *slots,
                             double *state, hipStream_t s);

@@ -15,6 +15,8 @@
 // and every expression keeps the order written above, so the result is the
 // same number for number on any device that rounds IEEE operations
 // correctly.
+#include <algorithm>
+#include <cmath>
 #include <cstdint>
 
 #include "common.h"
@@ -30,38 +32,67 @@ struct Nb {
   double p, xm, xp, ym, yp, zm, zp;
 };
 
-__device__ __forceinline__ Nb ls_load(const double *__restrict__ f, int i, int j, int k, int NX,
-                                      int NY, int NZ) {
+// Walks planes k0 .. k1 - 1 of column (i, j), keeping the planes below, at and
+// above the current node in registers; x and y neighbours come from the same
+// plane (cache hits within the block's tile).  upd(neighbourhood, node index)
+// returns the node's |change|; the largest is returned.
+template <class F>
+__device__ __forceinline__ double ls_march(const double *__restrict__ f, int i, int j, int k0,
+                                           int k1, int NX, int NY, int NZ, F &&upd) {
   const size_t sy = (size_t)NX, sz = (size_t)NX * NY;
-  const size_t n = (size_t)i + sy * ((size_t)j + (size_t)NY * k);
-  Nb r;
-  r.p = f[n];
-  r.xm = i > 0 ? f[n - 1] : r.p;
-  r.xp = i < NX - 1 ? f[n + 1] : r.p;
-  r.ym = j > 0 ? f[n - sy] : r.p;
-  r.yp = j < NY - 1 ? f[n + sy] : r.p;
-  r.zm = k > 0 ? f[n - sz] : r.p;
-  r.zp = k < NZ - 1 ? f[n + sz] : r.p;
-  return r;
+  size_t n = (size_t)i + sy * ((size_t)j + (size_t)NY * k0);
+  double pc = f[n];
+  double pm = k0 > 0 ? f[n - sz] : pc;
+  double change = 0.0;
+  for (int k = k0; k < k1; ++k, n += sz) {
+    const double pn = k < NZ - 1 ? f[n + sz] : pc;
+    Nb a;
+    a.p = pc;
+    a.zm = pm;
+    a.zp = pn;
+    a.xm = i > 0 ? f[n - 1] : pc;
+    a.xp = i < NX - 1 ? f[n + 1] : pc;
+    a.ym = j > 0 ? f[n - sy] : pc;
+    a.yp = j < NY - 1 ? f[n + sy] : pc;
+    change = fmax(change, upd(a, n));
+    pm = pc;
+    pc = pn;
+  }
+  return change;
 }
 
-// (g+, g-) with the sums taken x, then y, then z
-__device__ __forceinline__ void godunov(const Nb &a, double h, double &gp, double &gm) {
-  double sp = 0.0, sm = 0.0, dm, dq, t;
-  dm = (a.p - a.xm) / h;
-  dq = (a.xp - a.p) / h;
+// Difference quotient (a - b) / d.  When h is a power of two, P2 multiplies
+// by the exact reciprocal instead, which gives the same number (scaling by a
+// power of two is exact, or rounds the same exact value in the subnormal
+// range) without a division sequence.
+template <bool P2>
+__device__ __forceinline__ double dq_over(double num, double d, double inv_d) {
+  return P2 ? num * inv_d : num / d;
+}
+
+// Sums of squares of the upwind one-sided differences for a positive (sp)
+// and a negative (sm) speed, taken x, then y, then z.  Only one of
+// g+ = sqrt(sp) and g- = sqrt(sm) enters an update: for a speed w > 0,
+// max(w, 0) g+ + min(w, 0) g- is w g+ plus an exact zero, and likewise for
+// w < 0, so the callers take a single root.
+template <bool P2>
+__device__ __forceinline__ void godunov_sums(const Nb &a, double h, double inv_h, double &sp,
+                                             double &sm) {
+  double dm, dq, t;
+  sp = 0.0;
+  sm = 0.0;
+  dm = dq_over<P2>(a.p - a.xm, h, inv_h);
+  dq = dq_over<P2>(a.xp - a.p, h, inv_h);
   t = fmax(dm, 0.0); sp = sp + t * t; t = fmin(dq, 0.0); sp = sp + t * t;
   t = fmin(dm, 0.0); sm = sm + t * t; t = fmax(dq, 0.0); sm = sm + t * t;
-  dm = (a.p - a.ym) / h;
-  dq = (a.yp - a.p) / h;
+  dm = dq_over<P2>(a.p - a.ym, h, inv_h);
+  dq = dq_over<P2>(a.yp - a.p, h, inv_h);
   t = fmax(dm, 0.0); sp = sp + t * t; t = fmin(dq, 0.0); sp = sp + t * t;
   t = fmin(dm, 0.0); sm = sm + t * t; t = fmax(dq, 0.0); sm = sm + t * t;
-  dm = (a.p - a.zm) / h;
-  dq = (a.zp - a.p) / h;
+  dm = dq_over<P2>(a.p - a.zm, h, inv_h);
+  dq = dq_over<P2>(a.zp - a.p, h, inv_h);
   t = fmax(dm, 0.0); sp = sp + t * t; t = fmin(dq, 0.0); sp = sp + t * t;
   t = fmin(dm, 0.0); sm = sm + t * t; t = fmax(dq, 0.0); sm = sm + t * t;
-  gp = sqrt(sp);
-  gm = sqrt(sm);
 }
 
 __device__ __forceinline__ double wave_max_u(double v) {
@@ -69,9 +100,9 @@ __device__ __forceinline__ double wave_max_u(double v) {
   return v;
 }
 
-// one block max of a non-negative value into *slot (bit patterns of
-// non-negative doubles order like the doubles)
-__device__ __forceinline__ void block_max_to(double v, unsigned long long *slot) {
+// one block max of a non-negative value into one word of a slot set (bit
+// patterns of non-negative doubles order like the doubles)
+__device__ __forceinline__ void block_max_to(double v, unsigned long long *set) {
   __shared__ double sh[LSX * LSY / 64];
   const int t = threadIdx.x + LSX * threadIdx.y;
   v = wave_max_u(v);
@@ -80,7 +111,9 @@ __device__ __forceinline__ void block_max_to(double v, unsigned long long *slot)
   if (t == 0) {
     double m = 0.0;
     for (int w = 0; w < LSX * LSY / 64; ++w) m = fmax(m, sh[w]);
-    if (m > 0.0) atomicMax(slot, (unsigned long long)__double_as_longlong(m));
+    if (m > 0.0)
+      atomicMax(&set[(blockIdx.x % LS_SLOTS) * LS_SLOT_STRIDE],
+                (unsigned long long)__double_as_longlong(m));
   }
 }
 
@@ -112,71 +145,116 @@ __global__ __launch_bounds__(256) void k_ls_check(const double *__restrict__ phi
   }
 }
 
-__global__ __launch_bounds__(LSX * LSY) void k_ls_advect(int NX, int NY, int NZ, double h,
-                                                         double dt,
+// The grid is 1D over tiles (LSX x LSY nodes by kz planes), ordered x, then
+// y, then z-chunk; xcd_local gives every XCD one contiguous range of them, so
+// the halo rows and planes a tile reads were mostly brought into the same L2
+// by its neighbours.
+struct Tile {
+  int i, j, k0, k1;
+};
+__device__ __forceinline__ Tile ls_tile(int NX, int NY, int NZ, int kz) {
+  const int ntx = (NX + LSX - 1) / LSX, nty = (NY + LSY - 1) / LSY;
+  const int nkz = (NZ + kz - 1) / kz;
+  const int lb = xcd_local((int)blockIdx.x, ntx * nty * nkz);
+  const int tx = lb % ntx, r = lb / ntx, ty = r % nty, tz = r / nty;
+  Tile t;
+  t.i = tx * LSX + threadIdx.x;
+  t.j = ty * LSY + threadIdx.y;
+  t.k0 = tz * kz;
+  t.k1 = min(t.k0 + kz, NZ);
+  return t;
+}
+
+template <bool P2>
+__global__ __launch_bounds__(LSX * LSY) void k_ls_advect(int NX, int NY, int NZ, int kz,
+                                                         double h, double inv_h, double dt,
                                                          const double *__restrict__ in,
                                                          const double *__restrict__ v,
                                                          double *__restrict__ out) {
-  const int i = blockIdx.x * LSX + threadIdx.x, j = blockIdx.y * LSY + threadIdx.y,
-            k = blockIdx.z;
+  const Tile tl = ls_tile(NX, NY, NZ, kz);
+  const int i = tl.i, j = tl.j, k0 = tl.k0, k1 = tl.k1;
   if (i >= NX || j >= NY) return;
-  const Nb a = ls_load(in, i, j, k, NX, NY, NZ);
-  double gp, gm;
-  godunov(a, h, gp, gm);
-  const size_t n = (size_t)i + (size_t)NX * ((size_t)j + (size_t)NY * k);
-  const double ve = v[n];
-  out[n] = a.p - dt * (fmax(ve, 0.0) * gp + fmin(ve, 0.0) * gm);
+  ls_march(in, i, j, k0, k1, NX, NY, NZ, [&](const Nb &a, size_t n) {
+    double sp, sm;
+    godunov_sums<P2>(a, h, inv_h, sp, sm);
+    const double ve = v[n];
+    const double g = sqrt(ve > 0.0 ? sp : sm);
+    out[n] = ve == 0.0 ? a.p : a.p - dt * (ve * g);
+    return 0.0;
+  });
 }
 
 // Launch k computes pseudo-step k + 1 from `in` into `out`, with its largest
-// |change| in slots[k % 3].  It first reads the previous step's slot: below
-// tol the loop has converged; at k == max_steps without that it is capped.
-// state[0]: 0 running, 1 converged, 2 capped; state[1]: steps computed;
-// state[2]: the last step's largest |change|.  Only block 0 writes the state,
-// and it also clears slots[(k + 1) % 3] for the next launch (that slot was
-// last read by launch k - 1).
+// |change| spread over slot set k % 3 (LS_SLOTS words).  It first takes the
+// previous step's largest change from set (k - 1) % 3 (first wave: one word
+// per lane, then a wave max): below tol the loop has converged; at
+// k == max_steps without that it is capped.  state[0]: 0 running,
+// 1 converged, 2 capped; state[1]: steps computed; state[2]: the last step's
+// largest |change|.  Only block 0 writes the state, and its first wave also
+// clears set (k + 1) % 3 for the next launch (that set was last read by
+// launch k - 1).
+template <bool P2>
 __global__ __launch_bounds__(LSX * LSY) void k_ls_reinit(
-    int NX, int NY, int NZ, double h, double dtau, double tol, int max_steps, int k_launch,
-    const double *__restrict__ in, double *__restrict__ out,
+    int NX, int NY, int NZ, int kz, double h, double inv_h, double dtau, double tol, int max_steps,
+    int k_launch, const double *__restrict__ in, double *__restrict__ out,
     unsigned long long *__restrict__ slots, double *__restrict__ state) {
-  const bool lead = blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0 &&
-                    threadIdx.y == 0;
+  __shared__ double prev_sh;
+  const int t = threadIdx.x + LSX * threadIdx.y;
+  const bool block0 = blockIdx.x == 0;
+  const size_t set = (size_t)LS_SLOTS * LS_SLOT_STRIDE;
+  if (t < 64) {
+    double m = 0.0;
+    if (k_launch > 0)
+      m = __longlong_as_double(
+          (long long)slots[((k_launch - 1) % 3) * set + (size_t)t * LS_SLOT_STRIDE]);
+    m = wave_max_u(m);
+    if (t == 0) prev_sh = k_launch > 0 ? m : INFINITY;
+    if (block0) slots[((k_launch + 1) % 3) * set + (size_t)t * LS_SLOT_STRIDE] = 0ull;
+  }
+  __syncthreads();
   const double st = state[0];
-  const double prev =
-      k_launch > 0 ? __longlong_as_double((long long)slots[(k_launch - 1) % 3]) : INFINITY;
+  const double prev = prev_sh;
   const bool conv = prev < tol;
   const bool capped = !conv && k_launch >= max_steps;
-  if (lead) {
-    if (st == 0.0 && (conv || capped)) {
-      state[0] = conv ? 1.0 : 2.0;
-      state[1] = (double)k_launch;
-      state[2] = prev;
-    }
-    slots[(k_launch + 1) % 3] = 0ull;
+  if (block0 && t == 0 && st == 0.0 && (conv || capped)) {
+    state[0] = conv ? 1.0 : 2.0;
+    state[1] = (double)k_launch;
+    state[2] = prev;
   }
   if (st != 0.0 || conv || capped) return;
-  const int i = blockIdx.x * LSX + threadIdx.x, j = blockIdx.y * LSY + threadIdx.y,
-            k = blockIdx.z;
+  const Tile tl = ls_tile(NX, NY, NZ, kz);
+  const int i = tl.i, j = tl.j, k0 = tl.k0, k1 = tl.k1;
   double change = 0.0;
-  if (i < NX && j < NY) {
-    const Nb a = ls_load(in, i, j, k, NX, NY, NZ);
-    double gp, gm;
-    godunov(a, h, gp, gm);
-    const double cx = (a.xp - a.xm) / (2.0 * h), cy = (a.yp - a.ym) / (2.0 * h),
-                 cz = (a.zp - a.zm) / (2.0 * h);
-    const double g2 = cx * cx + cy * cy + cz * cz;
-    const double den = sqrt(a.p * a.p + (h * h) * g2);
-    const double s = den > 0.0 ? a.p / den : 0.0;
-    const double nv = a.p - dtau * (fmax(s, 0.0) * (gp - 1.0) + fmin(s, 0.0) * (gm - 1.0));
-    out[(size_t)i + (size_t)NX * ((size_t)j + (size_t)NY * k)] = nv;
-    change = fabs(nv - a.p);
-  }
-  block_max_to(change, &slots[k_launch % 3]);
+  if (i < NX && j < NY)
+    change = ls_march(in, i, j, k0, k1, NX, NY, NZ, [&](const Nb &a, size_t n) {
+      double sp, sm;
+      godunov_sums<P2>(a, h, inv_h, sp, sm);
+      const double h2 = 2.0 * h, inv_h2 = 0.5 * inv_h;
+      const double cx = dq_over<P2>(a.xp - a.xm, h2, inv_h2),
+                   cy = dq_over<P2>(a.yp - a.ym, h2, inv_h2),
+                   cz = dq_over<P2>(a.zp - a.zm, h2, inv_h2);
+      const double g2 = cx * cx + cy * cy + cz * cz;
+      const double den = sqrt(a.p * a.p + (h * h) * g2);
+      const double s = den > 0.0 ? a.p / den : 0.0;
+      const double g = sqrt(s > 0.0 ? sp : sm);
+      const double nv = s == 0.0 ? a.p : a.p - dtau * (s * (g - 1.0));
+      out[n] = nv;
+      return fabs(nv - a.p);
+    });
+  block_max_to(change, &slots[(k_launch % 3) * set]);
 }
 
-static dim3 ls_grid(const Grid &g) {
-  return dim3((unsigned)((g.nelx + 1 + LSX - 1) / LSX), (unsigned)((g.nely + 1 + LSY - 1) / LSY),
-              (unsigned)(g.nelz + 1));
+// planes per block: enough blocks to fill the chip (about 2048), at most 16
+static int ls_kz(const Grid &g) {
+  const long long tiles = (long long)((g.nelx + 1 + LSX - 1) / LSX) *
+                          ((g.nely + 1 + LSY - 1) / LSY);
+  long long kz = (long long)(g.nelz + 1) * tiles / 2048;
+  return (int)std::max(1LL, std::min(16LL, kz));
+}
+
+static dim3 ls_grid(const Grid &g, int kz) {
+  return dim3((unsigned)(((g.nelx + 1 + LSX - 1) / LSX) * ((g.nely + 1 + LSY - 1) / LSY) *
+                         ((g.nelz + 1 + kz - 1) / kz)));
 }
 
 hipError_t launch_ls_check(const Grid &g, const double *phi, const double *v, int *flags,
@@ -187,18 +265,35 @@ hipError_t launch_ls_check(const Grid &g, const double *phi, const double *v, in
   return hipGetLastError();
 }
 
+static bool pow2(double h) {
+  int e = 0;
+  return std::frexp(h, &e) == 0.5;
+}
+
 hipError_t launch_ls_advect(const Grid &g, double h, double dt, const double *in, const double *v,
                             double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_ls_advect, ls_grid(g), dim3(LSX, LSY), 0, s, g.nelx + 1, g.nely + 1,
-                     g.nelz + 1, h, dt, in, v, out);
+  const int kz = ls_kz(g);
+  if (pow2(h))
+    hipLaunchKernelGGL(k_ls_advect<true>, ls_grid(g, kz), dim3(LSX, LSY), 0, s, g.nelx + 1,
+                       g.nely + 1, g.nelz + 1, kz, h, 1.0 / h, dt, in, v, out);
+  else
+    hipLaunchKernelGGL(k_ls_advect<false>, ls_grid(g, kz), dim3(LSX, LSY), 0, s, g.nelx + 1,
+                       g.nely + 1, g.nelz + 1, kz, h, 1.0 / h, dt, in, v, out);
   return hipGetLastError();
 }
 
 hipError_t launch_ls_reinit(const Grid &g, double h, double dtau, double tol, int max_steps,
                             int k, const double *in, double *out, unsigned long long *slots,
                             double *state, hipStream_t s) {
-  hipLaunchKernelGGL(k_ls_reinit, ls_grid(g), dim3(LSX, LSY), 0, s, g.nelx + 1, g.nely + 1,
-                     g.nelz + 1, h, dtau, tol, max_steps, k, in, out, slots, state);
+  const int kz = ls_kz(g);
+  if (pow2(h))
+    hipLaunchKernelGGL(k_ls_reinit<true>, ls_grid(g, kz), dim3(LSX, LSY), 0, s, g.nelx + 1,
+                       g.nely + 1, g.nelz + 1, kz, h, 1.0 / h, dtau, tol, max_steps, k, in, out,
+                       slots, state);
+  else
+    hipLaunchKernelGGL(k_ls_reinit<false>, ls_grid(g, kz), dim3(LSX, LSY), 0, s, g.nelx + 1,
+                       g.nely + 1, g.nelz + 1, kz, h, 1.0 / h, dtau, tol, max_steps, k, in, out,
+                       slots, state);
   return hipGetLastError();
 }
 

@@ -34,3 +34,34 @@ def uniform(nelx, nely, nelz, value=0.5):
 
 def random_vector(n, seed):
     return np.random.default_rng(seed).standard_normal(n)
+
+
+def _node_coords(nelx, nely, nelz):
+    k, j, i = np.meshgrid(np.arange(nelz + 1), np.arange(nely + 1), np.arange(nelx + 1),
+                          indexing="ij")
+    return i.ravel().astype(float), j.ravel().astype(float), k.ravel().astype(float)
+
+
+def sphere_union(nelx, nely, nelz, seed, count=3, scale=1.0):
+    """Level-set input on the (nelx+1)(nely+1)(nelz+1) nodes (node order
+    i + NX (j + NY k), unit spacing): `scale` times the distance to the union
+    of `count` balls with seeded centres and radii, negative inside (an exact
+    signed distance outside the balls when scale is 1)."""
+    i, j, k = _node_coords(nelx, nely, nelz)
+    dims = np.array([nelx, nely, nelz], dtype=float)
+    rng = np.random.default_rng(seed)
+    phi = np.full(i.size, np.inf)
+    for _ in range(count):
+        c = rng.uniform(0, 1, 3) * dims
+        R = rng.uniform(0.15, 0.3) * dims.min() + 0.7
+        phi = np.minimum(phi, np.sqrt((i - c[0]) ** 2 + (j - c[1]) ** 2 + (k - c[2]) ** 2) - R)
+    return np.ascontiguousarray(scale * phi)
+
+
+def smooth_speed(nelx, nely, nelz, seed):
+    """A smooth nodal normal speed of both signs, |v| <= 1.3."""
+    i, j, k = _node_coords(nelx, nely, nelz)
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(0.05, 0.4, 4)
+    return np.ascontiguousarray(0.8 * np.sin(a[0] * i + 0.3) * np.cos(a[1] * j)
+                                + 0.5 * np.sin(a[2] * k + a[3] * j))

@@ -14,6 +14,7 @@ import torch
 
 from oracle import levelset as LS
 from paper_2605_04735_amd import api as A
+from paper_2605_04735_amd import inputs
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -36,21 +37,11 @@ def coords(dims):
 
 
 def spheres(dims, seed):
-    i, j, k = coords(dims)
-    rng = np.random.default_rng(seed)
-    phi = np.full(i.size, np.inf)
-    for _ in range(3):
-        c = rng.uniform(0, 1, 3) * np.array(dims)
-        R = rng.uniform(0.15, 0.3) * min(dims) + 0.7
-        phi = np.minimum(phi, np.sqrt((i - c[0]) ** 2 + (j - c[1]) ** 2 + (k - c[2]) ** 2) - R)
-    return phi
+    return inputs.sphere_union(*dims, seed)
 
 
 def speed(dims, seed):
-    i, j, k = coords(dims)
-    rng = np.random.default_rng(seed)
-    a = rng.uniform(0.05, 0.4, 4)
-    return 0.8 * np.sin(a[0] * i + 0.3) * np.cos(a[1] * j) + 0.5 * np.sin(a[2] * k + a[3] * j)
+    return inputs.smooth_speed(*dims, seed)
 
 
 def close(a, b, what):
@@ -74,16 +65,24 @@ def test_advect_vs_oracle(dims, nsteps):
     close(cpu(p), ref, "advect %s" % (dims,))
 
 
-def test_advect_h_and_zero_speed():
+@pytest.mark.parametrize("h", [0.25, 0.3])
+def test_advect_h_and_zero_speed(h):
+    # h = 0.25: the kernels multiply by the exact reciprocal; h = 0.3: they divide
     dims = (12, 9, 7)
-    phi = spheres(dims, 3) * 0.25
+    phi = spheres(dims, 3) * h
     v = speed(dims, 4)
-    ref, dt_ref = LS.advect(phi, v, *dims, h=0.25, gamma=0.3, nsteps=5)
-    ctx = A.to_create(A.Problem(*dims, h=0.25))
+    ref, dt_ref = LS.advect(phi, v, *dims, h=h, gamma=0.3, nsteps=5)
+    ctx = A.to_create(A.Problem(*dims, h=h))
     p = gpu(phi)
     _, dt, _ = A.to_ls_advect(ctx, p, gpu(v), gamma=0.3, nsteps=5)
     assert dt == dt_ref
-    close(cpu(p), ref, "advect h=0.25")
+    close(cpu(p), ref, "advect h=%g" % h)
+    q = gpu(2.5 * phi)
+    ref, steps_ref, change_ref = LS.reinit(2.5 * phi, *dims, h=h, gamma=0.5, tol=1e-3 * h,
+                                           max_steps=600)
+    _, steps, change, _ = A.to_ls_reinit(ctx, q, gamma=0.5, tol=1e-3 * h, max_steps=600)
+    assert steps == steps_ref and change == change_ref
+    close(cpu(q), ref, "reinit h=%g" % h)
     p = gpu(phi)
     _, dt, _ = A.to_ls_advect(ctx, p, gpu(np.zeros_like(v)), gamma=0.5, nsteps=3)
     assert dt == 0.0 and np.array_equal(cpu(p), phi)
