@@ -27,6 +27,9 @@ Everything is NumPy/SciPy in float64, one step per paper passage:
             and reinitialisation with the smeared sign,
             first-order Godunov upwind on the node grid  (Secs. 2.2.4-2.2.5,
                                                           Eqs. 21-24)
+  shape     relaxed shape derivative (nodal vector) and
+            the Hilbertian extension A_H vbar = g        (Secs. 2.2.2-2.2.3,
+                                                          Eqs. 15-20)
   api       the library's call names on host arrays with
             the same error contract                     (test helper)
 """
