@@ -246,6 +246,34 @@ to_status to_ls_advect(to_ctx *ctx, double *d_phi, const double *d_v, double gam
 to_status to_ls_reinit(to_ctx *ctx, double *d_phi, double gamma, double tol, int32_t max_steps,
                        int32_t *h_steps, double *h_change);
 
+/* Relaxed shape derivative (Sec. 2.2.2): the nodal vector of Eqs. 15-17,
+ *   g_a = sum_e sum_q w_q h^3 N_a(q) (c_s s(q) + c_0) H'_eta(phi(q)) |grad phi(q)|,
+ * over the 2x2x2 Gauss points q of every voxel, with phi and u trilinear on
+ * it, s = sigma:eps = lambda (tr eps)^2 + 2 mu eps:eps at the solid's E0 and
+ * nu, and H'_eta(t) = (1 + cos(pi t / eta)) / (2 eta) for |t| <= eta, else 0
+ * (the derivative of Eq. 8).  (c_s, c_0) = (1, 0) gives J' (Eq. 15),
+ * (0, -1/V_D) gives C' (Eq. 16), (1, (lambda - Lambda C)/V_D) gives L'
+ * (Eqs. 17-18).
+ * d_u [ndof] displacements (interleaved 3n + c; may be NULL when c_s == 0);
+ * d_phi [nn] level set; d_g [nn] output, must not alias d_phi; eta > 0.
+ * Deterministic (fixed summation order).  Asynchronous. */
+to_status to_shape_rhs(to_ctx *ctx, const double *d_u, const double *d_phi, double eta,
+                       double c_s, double c_0, double *d_g);
+
+/* Hilbertian extension-regularisation (Sec. 2.2.3): solves
+ * A_H v = g (Eq. 20), A_H = ell^2 K + M with the trilinear Laplacian and mass
+ * of Eq. 19 on the voxel grid, and v = 0 on Gamma_N, the nodes where the
+ * context's load vector has a non-zero component (the natural condition
+ * elsewhere).  Jacobi-preconditioned CG in float64 from v = 0 to
+ * ||r|| <= rtol ||g_free||.
+ * d_g [nn] right-hand side; d_v [nn] output, must not alias d_g; ell >= 0;
+ * 0 < rtol < 1; max_iters >= 1.  h_iters, h_rel (host, may be NULL): CG
+ * iterations and the final relative residual.  TO_E_NOCONV at the cap (d_v =
+ * last iterate), TO_E_SINGULAR on breakdown.  Synchronises the context
+ * stream. */
+to_status to_hilbert_extend(to_ctx *ctx, double ell, const double *d_g, double *d_v, double rtol,
+                            int32_t max_iters, int32_t *h_iters, double *h_rel);
+
 /* Matrix-free operator of Eq. 2, y = K(x) u with the fixed DOFs zeroed on
  * input and identity rows on output (y_fixed = u_fixed), float64.
  * d_u, d_y: [ndof], must not alias.  d_x NULL reuses the moduli of the

@@ -76,6 +76,9 @@ _SIGS = {
     "to_ls_advect": (ctypes.c_int, [_P, _P, _P, _D, ctypes.c_int32, ctypes.POINTER(_D)]),
     "to_ls_reinit": (ctypes.c_int, [_P, _P, _D, _D, ctypes.c_int32,
                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_D)]),
+    "to_shape_rhs": (ctypes.c_int, [_P, _P, _P, _D, _D, _D, _P]),
+    "to_hilbert_extend": (ctypes.c_int, [_P, _D, _P, _P, _D, ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_D)]),
     "to_matvec": (ctypes.c_int, [_P, _P, _P, _P]),
     "to_matvec_f32": (ctypes.c_int, [_P, _P, _P, _P]),
     "to_last_energy_sum": (_D, [_P]),

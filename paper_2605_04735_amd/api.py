@@ -283,6 +283,33 @@ def to_ls_reinit(ctx: Context, phi, gamma=0.5, tol=1e-3, max_steps=1000, raise_o
     return phi, steps.value, change.value, st
 
 
+def to_shape_rhs(ctx: Context, phi, u=None, eta=2.0, c_s=1.0, c_0=0.0, g=None):
+    """Nodal relaxed shape-derivative vector; returns g."""
+    p = ctx.prob
+    if g is None:
+        g = torch.empty(p.nn, dtype=torch.float64, device=phi.device)
+    _check(L.lib().to_shape_rhs(ctx.handle, _dev(u, torch.float64, p.ndof, "u"),
+                                _dev(phi, torch.float64, p.nn, "phi"), float(eta), float(c_s),
+                                float(c_0), _dev(g, torch.float64, p.nn, "g")), ctx.handle)
+    return g
+
+
+def to_hilbert_extend(ctx: Context, g, ell=1.0, v=None, rtol=1e-8, max_iters=10000,
+                      raise_on_error=True):
+    """Returns (v, iterations, relative residual, status)."""
+    p = ctx.prob
+    if v is None:
+        v = torch.empty(p.nn, dtype=torch.float64, device=g.device)
+    it = ctypes.c_int32(0)
+    rel = ctypes.c_double(0.0)
+    st = L.lib().to_hilbert_extend(ctx.handle, float(ell), _dev(g, torch.float64, p.nn, "g"),
+                                   _dev(v, torch.float64, p.nn, "v"), float(rtol), int(max_iters),
+                                   ctypes.byref(it), ctypes.byref(rel))
+    if raise_on_error:
+        _check(st, ctx.handle)
+    return v, it.value, rel.value, st
+
+
 def to_profile(ctx: Context, enable: bool):
     """(ms, count) of inner-CG product launches since the previous call."""
     ms = ctypes.c_double(0.0)

@@ -4,6 +4,7 @@
 // host only validates, sequences launches and polls small device flags.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -818,6 +819,60 @@ to_status to_ls_reinit(to_ctx *c, double *d_phi, double gamma, double tol, int32
   if (h_change) *h_change = hs[2];
   if (hs[0] != 1.0)
     return fail(c, TO_E_NOCONV, "reinitialisation: change still >= tol after max_steps");
+  return TO_OK;
+}
+
+to_status to_shape_rhs(to_ctx *c, const double *d_u, const double *d_phi, double eta, double c_s,
+                       double c_0, double *d_g) {
+  if (!c) return fail(nullptr, TO_E_INVALID, "ctx is NULL");
+  if (!d_phi || !d_g) return fail(c, TO_E_INVALID, "d_phi and d_g are required");
+  if (c_s != 0.0 && !d_u) return fail(c, TO_E_INVALID, "d_u is required when c_s != 0");
+  if (d_g == d_phi) return fail(c, TO_E_INVALID, "d_g must not alias d_phi");
+  if (!(eta > 0.0) || !std::isfinite(eta)) return fail(c, TO_E_INVALID, "need eta > 0");
+  if (!std::isfinite(c_s) || !std::isfinite(c_0))
+    return fail(c, TO_E_INVALID, "c_s and c_0 must be finite");
+  HIPCHK(hipSetDevice(c->device));
+  const double nu = c->p.nu, E0 = c->p.E0;
+  const double lam = E0 * nu / ((1.0 + nu) * (1.0 - 2.0 * nu)), mu = E0 / (2.0 * (1.0 + nu));
+  HIPCHK(launch_shape_rhs(c->g, d_u, d_phi, c->p.h, lam, mu, eta, c_s, c_0, d_g, c->stream));
+  return TO_OK;
+}
+
+to_status to_hilbert_extend(to_ctx *c, double ell, const double *d_g, double *d_v, double rtol,
+                            int32_t max_iters, int32_t *h_iters, double *h_rel) {
+  if (!c) return fail(nullptr, TO_E_INVALID, "ctx is NULL");
+  if (!d_g || !d_v) return fail(c, TO_E_INVALID, "d_g and d_v are required");
+  if (d_g == d_v) return fail(c, TO_E_INVALID, "d_v must not alias d_g");
+  if (!(ell >= 0.0) || !std::isfinite(ell)) return fail(c, TO_E_INVALID, "need ell >= 0");
+  if (!(rtol > 0.0 && rtol < 1.0)) return fail(c, TO_E_INVALID, "need 0 < rtol < 1");
+  if (max_iters < 1) return fail(c, TO_E_INVALID, "max_iters must be >= 1");
+  static_assert(HCG_SCRATCH <= 2 * MAXB, "extension scratch lives in the partial-sum array");
+  HIPCHK(hipSetDevice(c->device));
+  // r, z, p, q: nn doubles each in the CG vector arrays (each holds at least
+  // 3 nn floats); the Gamma_N mask in the node scratch
+  double *vec[4];
+  for (int i = 0; i < 4; ++i)
+    vec[i] = c->p.precision == TO_PREC_FP64 ? c->v64[i] : (double *)c->v32[i];
+  uint8_t *gm = (uint8_t *)c->rho_scratch;
+  double *scal = c->part + HCG_SCAL_OFS, *hs = c->h_scal + S_COUNT;
+  HIPCHK(launch_fill(c->flags, F_COUNT * sizeof(int), c->stream));
+  int it = 0;
+  for (;;) {
+    const int n = std::min(32, max_iters + 1 - it);
+    HIPCHK(launch_hilbert(c->g, c->p.h, ell, rtol, max_iters, c->f, d_g, d_v, vec, gm, c->part,
+                          scal, c->flags, it, n, c->stream));
+    it += n;
+    HIPCHK(hipMemcpyAsync(hs, scal, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(c->h_flags, c->flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (c->h_flags[0] != 0) break;
+    if (it > max_iters) return fail(c, TO_E_HIP, "extension CG state did not advance");
+  }
+  const int st = c->h_flags[0];
+  if (h_iters) *h_iters = (int32_t)hs[2];
+  if (h_rel) *h_rel = hs[3] > 0.0 ? std::sqrt(hs[1] / hs[3]) : 0.0;
+  if (st == 2) return fail(c, TO_E_NOCONV, "extension CG: iteration cap reached");
+  if (st == 3) return fail(c, TO_E_SINGULAR, "extension CG breakdown: p^T A p <= 0");
   return TO_OK;
 }
 

@@ -220,6 +220,21 @@ hipError_t launch_oc_apply(const double *x, const double *dc, double *xnew, size
                            double move, double eta, double *scratch, int k, hipStream_t s);
 hipError_t launch_set(double *p, size_t n, double v, hipStream_t s);
 
+// shape derivative and Hilbertian extension (k_shape.hip).  The extension's
+// CG keeps 5 x HCG_MAXB block partials, then HCG_SCAL doubles of scalars.
+constexpr int HCG_MAXB = 1024;
+constexpr int HCG_SCAL_OFS = 5 * HCG_MAXB;
+constexpr int HCG_SCRATCH = HCG_SCAL_OFS + 8;
+hipError_t launch_shape_rhs(const Grid &g, const double *u, const double *phi, double h,
+                            double lam, double mu, double eta, double c_s, double c_0, double *out,
+                            hipStream_t s);
+// iterations it0 .. it0 + count - 1 of the extension's CG (it0 == 0 also
+// builds the Gamma_N mask from f and starts from x = 0); vec: r, z, p, q
+hipError_t launch_hilbert(const Grid &g, double h, double ell, double rtol, int max_iters,
+                          const double *f, const double *b, double *x, double *const vec[4],
+                          uint8_t *gm, double *part, double *scal, int *flags, int it0, int count,
+                          hipStream_t s);
+
 // level-set evolution and reinitialisation (k_levelset.hip).  The largest
 // |change| of a reinitialisation step is taken by atomic max over LS_SLOTS
 // words on separate 128-byte lines (a block picks one by its index), so the

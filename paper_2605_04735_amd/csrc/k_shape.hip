@@ -1,0 +1,396 @@
+// Relaxed shape derivative (Sec. 2.2.2, Eqs. 15-18) and Hilbertian
+// extension-regularisation (Sec. 2.2.3, Eqs. 19-20) on the voxel grid.
+//
+// Nodal shape-derivative vector: with trilinear phi and u on each voxel and
+// a 2x2x2 Gauss rule,
+//   g_a = sum_e sum_q w_q h^3 N_a(q) (c_s s(q) + c_0) H'_eta(phi(q)) |grad phi(q)|,
+//   s = sigma:eps = lambda (tr eps)^2 + 2 mu eps:eps with the solid's E0,
+//   H'_eta(t) = (1 + cos(pi t / eta)) / (2 eta) for |t| <= eta, else 0.
+// A node gathers its (up to 8) elements in a fixed order and recomputes each
+// element's Gauss-point factors; only elements that meet the band
+// |phi| <= eta do any work, and the sum is the same run to run.
+//
+// Extension: A_H = ell^2 K + M (Q1 Laplacian and mass).  On equal voxels both
+// are sums of Kronecker products of the 1D assembled stiffness
+// (1/h)[-1 2 -1] and mass (h/6)[1 4 1] (halved at the two end nodes), so the
+// product is a 27-point stencil whose coefficients are products of 1D
+// entries.  Nodes of Gamma_N (the loaded nodes) are identity rows.  It is
+// solved by Jacobi-preconditioned CG in float64; every kernel sums the
+// previous kernel's per-block partials itself, in one fixed order.
+#include "common.h"
+#include "device_common.h"
+
+namespace topo {
+
+constexpr double GA = 0.21132486540518711775;  // (1 - 1/sqrt(3)) / 2
+constexpr double GB = 0.78867513459481288225;  // (1 + 1/sqrt(3)) / 2
+
+__device__ __forceinline__ double hprime(double t, double eta) {
+  return fabs(t) <= eta ? (1.0 + cos(M_PI * t / eta)) / (2.0 * eta) : 0.0;
+}
+
+// Gauss factors F(q) = w_q h^3 (c_s s + c_0) H' |grad phi| of element
+// (ei, ej, ek); returns false when no Gauss point lies in the band.
+__device__ bool shape_elem_factors(int ei, int ej, int ek, int NX, int NY,
+                                   const double *__restrict__ u, const double *__restrict__ phi,
+                                   double h, double lam, double mu, double eta, double c_s,
+                                   double c_0, double F[8]) {
+  const size_t n0 = (size_t)ei + (size_t)NX * ((size_t)ej + (size_t)NY * ek);
+  size_t nd[8];
+  double ph[8];
+  for (int a = 0; a < 8; ++a) {
+    nd[a] = n0 + (size_t)(a & 1) + (size_t)NX * ((size_t)((a >> 1) & 1) + (size_t)NY * (a >> 2));
+    ph[a] = phi[nd[a]];
+  }
+  // quick reject: phi is trilinear, so it lies between its nodal extremes
+  double lo = ph[0], hi = ph[0];
+  for (int a = 1; a < 8; ++a) {
+    lo = fmin(lo, ph[a]);
+    hi = fmax(hi, ph[a]);
+  }
+  if (lo > eta || hi < -eta) return false;
+  double ue[8][3];
+  if (c_s != 0.0)
+    for (int a = 0; a < 8; ++a)
+      for (int c = 0; c < 3; ++c) ue[a][c] = u[3 * nd[a] + c];
+  const double w = 0.125 * h * h * h, ih = 1.0 / h;
+  bool any = false;
+  for (int q = 0; q < 8; ++q) {
+    const double r[3] = {(q & 1) ? GB : GA, ((q >> 1) & 1) ? GB : GA, (q >> 2) ? GB : GA};
+    double p = 0.0, gp[3] = {0.0, 0.0, 0.0};
+    double gu[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+    for (int a = 0; a < 8; ++a) {
+      const int bx = a & 1, by = (a >> 1) & 1, bz = a >> 2;
+      const double fx = bx ? r[0] : 1.0 - r[0], fy = by ? r[1] : 1.0 - r[1],
+                   fz = bz ? r[2] : 1.0 - r[2];
+      const double dx = (bx ? 1.0 : -1.0) * fy * fz * ih, dy = fx * (by ? 1.0 : -1.0) * fz * ih,
+                   dz = fx * fy * (bz ? 1.0 : -1.0) * ih;
+      p += fx * fy * fz * ph[a];
+      gp[0] += dx * ph[a];
+      gp[1] += dy * ph[a];
+      gp[2] += dz * ph[a];
+      if (c_s != 0.0)
+        for (int c = 0; c < 3; ++c) {
+          gu[c][0] += ue[a][c] * dx;
+          gu[c][1] += ue[a][c] * dy;
+          gu[c][2] += ue[a][c] * dz;
+        }
+    }
+    const double hp = hprime(p, eta);
+    if (hp == 0.0) {
+      F[q] = 0.0;
+      continue;
+    }
+    any = true;
+    double dens = c_0;
+    if (c_s != 0.0) {
+      const double tr = gu[0][0] + gu[1][1] + gu[2][2];
+      double ee = 0.0;
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          const double e = 0.5 * (gu[i][j] + gu[j][i]);
+          ee += e * e;
+        }
+      dens = c_s * (lam * tr * tr + 2.0 * mu * ee) + c_0;
+    }
+    F[q] = w * dens * hp * sqrt(gp[0] * gp[0] + gp[1] * gp[1] + gp[2] * gp[2]);
+  }
+  return any;
+}
+
+__global__ __launch_bounds__(256) void k_shape_rhs(int nelx, int nely, int nelz,
+                                                   const double *__restrict__ u,
+                                                   const double *__restrict__ phi, double h,
+                                                   double lam, double mu, double eta, double c_s,
+                                                   double c_0, double *__restrict__ g) {
+  const int NX = nelx + 1, NY = nely + 1;
+  const size_t nn = (size_t)NX * NY * (nelz + 1);
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < nn;
+       n += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(n % NX), j = (int)((n / NX) % NY), k = (int)(n / ((size_t)NX * NY));
+    double sum = 0.0;
+    for (int a = 0; a < 8; ++a) {  // the node is local node a of element (i-ax, j-ay, k-az)
+      const int bx = a & 1, by = (a >> 1) & 1, bz = a >> 2;
+      const int ei = i - bx, ej = j - by, ek = k - bz;
+      if (ei < 0 || ej < 0 || ek < 0 || ei >= nelx || ej >= nely || ek >= nelz) continue;
+      double F[8];
+      if (!shape_elem_factors(ei, ej, ek, NX, NY, u, phi, h, lam, mu, eta, c_s, c_0, F)) continue;
+      for (int q = 0; q < 8; ++q) {
+        const double r[3] = {(q & 1) ? GB : GA, ((q >> 1) & 1) ? GB : GA, (q >> 2) ? GB : GA};
+        const double N = (bx ? r[0] : 1.0 - r[0]) * (by ? r[1] : 1.0 - r[1]) *
+                         (bz ? r[2] : 1.0 - r[2]);
+        sum += N * F[q];
+      }
+    }
+    g[n] = sum;
+  }
+}
+
+hipError_t launch_shape_rhs(const Grid &g, const double *u, const double *phi, double h,
+                            double lam, double mu, double eta, double c_s, double c_0, double *out,
+                            hipStream_t s) {
+  size_t b = (g.nn + 255) / 256;
+  if (b > 8192) b = 8192;
+  hipLaunchKernelGGL(k_shape_rhs, dim3((unsigned)b), dim3(256), 0, s, g.nelx, g.nely, g.nelz, u,
+                     phi, h, lam, mu, eta, c_s, c_0, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- extension
+// 1D assembled stiffness and mass entries (neighbour -1, self, +1) at node i
+// of 0 .. N - 1; an end node has one element.
+struct Tri {
+  double k[3], m[3];
+};
+__device__ __forceinline__ Tri tri1d(int i, int N, double h) {
+  const double lo = i > 0 ? 1.0 : 0.0, hi = i < N - 1 ? 1.0 : 0.0;
+  Tri t;
+  t.k[0] = -lo / h;
+  t.k[1] = (lo + hi) / h;
+  t.k[2] = -hi / h;
+  t.m[0] = lo * h / 6.0;
+  t.m[1] = (lo + hi) * h / 3.0;
+  t.m[2] = hi * h / 6.0;
+  return t;
+}
+
+__device__ __forceinline__ double helm_diag(const Tri &x, const Tri &y, const Tri &z,
+                                            double ell2) {
+  return ell2 * (x.k[1] * y.m[1] * z.m[1] + x.m[1] * y.k[1] * z.m[1] + x.m[1] * y.m[1] * z.k[1]) +
+         x.m[1] * y.m[1] * z.m[1];
+}
+
+// Gamma_N: nodes with a non-zero load component (f interleaved 3n + c)
+__global__ void k_gamma_mask(size_t nn, const double *__restrict__ f, uint8_t *__restrict__ gm) {
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < nn;
+       n += (size_t)gridDim.x * blockDim.x)
+    gm[n] = (f[3 * n] != 0.0 || f[3 * n + 1] != 0.0 || f[3 * n + 2] != 0.0) ? 1 : 0;
+}
+
+struct HcgArgs {
+  int NX, NY, NZ;
+  double h, ell2;
+  int max_iters;
+  const uint8_t *gm;
+  double *x, *r, *z, *p, *q;
+  // block partials (HCG_MAXB each): [0] p^T q; [1 + par] r^T z and
+  // [3 + par] r^T r of the update of iteration parity par (the start counts
+  // as parity 1)
+  double *part;
+  double *scal;  // [0] stop threshold on r^T r, [1] last r^T r, [2] iterations, [3] b^T b
+  int *flags;    // [0] 0 running, 1 converged, 2 iteration cap, 3 breakdown
+  int nb;
+};
+
+__device__ double block_total(const double *__restrict__ part, int nb, double *sh) {
+  __shared__ double tot;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) v += part[i];
+  const double t = block_sum_d(v, sh);
+  if (threadIdx.x == 0) tot = t;
+  __syncthreads();
+  return tot;
+}
+
+__device__ __forceinline__ void node_ijk(size_t n, int NX, int NY, int &i, int &j, int &k) {
+  i = (int)(n % NX);
+  j = (int)((n / NX) % NY);
+  k = (int)(n / ((size_t)NX * NY));
+}
+
+// x = 0, r = b on free nodes, z = r / diag, p = z; partials of parity 1
+__global__ __launch_bounds__(256) void k_hcg_init(HcgArgs A, const double *__restrict__ b) {
+  __shared__ double sh[4];
+  const size_t nn = (size_t)A.NX * A.NY * A.NZ;
+  double rz = 0.0, rr = 0.0;
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < nn;
+       n += (size_t)gridDim.x * blockDim.x) {
+    int i, j, k;
+    node_ijk(n, A.NX, A.NY, i, j, k);
+    const double bn = A.gm[n] ? 0.0 : b[n];
+    const double d = helm_diag(tri1d(i, A.NX, A.h), tri1d(j, A.NY, A.h), tri1d(k, A.NZ, A.h),
+                               A.ell2);
+    const double zn = bn / d;
+    A.x[n] = 0.0;
+    A.r[n] = bn;
+    A.z[n] = zn;
+    A.p[n] = zn;
+    rz += bn * zn;
+    rr += bn * bn;
+  }
+  const double a = block_sum_d(rz, sh);
+  __syncthreads();
+  const double c = block_sum_d(rr, sh);
+  if (threadIdx.x == 0) {
+    A.part[2 * HCG_MAXB + blockIdx.x] = a;
+    A.part[4 * HCG_MAXB + blockIdx.x] = c;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_hcg_init_finish(HcgArgs A, double tol2_rel) {
+  __shared__ double sh[4];
+  const double rr = block_total(A.part + 4 * HCG_MAXB, A.nb, sh);
+  if (threadIdx.x == 0) {
+    A.scal[0] = tol2_rel * rr;
+    A.scal[1] = rr;
+    A.scal[2] = 0.0;
+    A.scal[3] = rr;
+    A.flags[0] = rr == 0.0 ? 1 : 0;
+  }
+}
+
+// q = A_H p (masked), partials p^T q
+__global__ __launch_bounds__(256) void k_hcg_apply(HcgArgs A) {
+  if (A.flags[0]) return;
+  __shared__ double sh[4];
+  const size_t nn = (size_t)A.NX * A.NY * A.NZ;
+  const size_t sy = (size_t)A.NX, sz = (size_t)A.NX * A.NY;
+  double pq = 0.0;
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < nn;
+       n += (size_t)gridDim.x * blockDim.x) {
+    int i, j, k;
+    node_ijk(n, A.NX, A.NY, i, j, k);
+    const double pn = A.p[n];
+    double acc;
+    if (A.gm[n]) {
+      acc = pn;
+    } else {
+      const Tri tx = tri1d(i, A.NX, A.h), ty = tri1d(j, A.NY, A.h), tz = tri1d(k, A.NZ, A.h);
+      acc = 0.0;
+      for (int dk = -1; dk <= 1; ++dk) {
+        if (tz.m[dk + 1] == 0.0) continue;
+        for (int dj = -1; dj <= 1; ++dj) {
+          if (ty.m[dj + 1] == 0.0) continue;
+          const size_t row = n + (ptrdiff_t)dk * (ptrdiff_t)sz + (ptrdiff_t)dj * (ptrdiff_t)sy;
+          double sk = 0.0, sm = 0.0;
+          for (int di = -1; di <= 1; ++di) {
+            if (tx.m[di + 1] == 0.0) continue;
+            const size_t m = row + (ptrdiff_t)di;
+            const double v = A.gm[m] ? 0.0 : A.p[m];
+            sk += tx.k[di + 1] * v;
+            sm += tx.m[di + 1] * v;
+          }
+          acc += tz.m[dk + 1] * (ty.m[dj + 1] * (A.ell2 * sk + sm) + A.ell2 * ty.k[dj + 1] * sm) +
+                 A.ell2 * tz.k[dk + 1] * ty.m[dj + 1] * sm;
+        }
+      }
+    }
+    A.q[n] = acc;
+    pq += pn * acc;
+  }
+  const double t = block_sum_d(pq, sh);
+  if (threadIdx.x == 0) A.part[blockIdx.x] = t;
+}
+
+// iteration it: alpha = r^T z / p^T q; x += alpha p, r -= alpha q,
+// z = r / diag; partials of parity it & 1
+__global__ __launch_bounds__(256) void k_hcg_update(HcgArgs A, int it) {
+  if (A.flags[0]) return;
+  __shared__ double sh[4];
+  const int cur = it & 1, old = cur ^ 1;
+  const double pq = block_total(A.part, A.nb, sh);
+  __syncthreads();
+  const double rz = block_total(A.part + (1 + old) * HCG_MAXB, A.nb, sh);
+  if (!(pq > 0.0)) {  // breakdown: every block sees the same pq
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      A.flags[0] = 3;
+      A.scal[2] = (double)it;
+    }
+    return;
+  }
+  const double alpha = rz / pq;
+  const size_t nn = (size_t)A.NX * A.NY * A.NZ;
+  double rzn = 0.0, rr = 0.0;
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < nn;
+       n += (size_t)gridDim.x * blockDim.x) {
+    int i, j, k;
+    node_ijk(n, A.NX, A.NY, i, j, k);
+    const double d = helm_diag(tri1d(i, A.NX, A.h), tri1d(j, A.NY, A.h), tri1d(k, A.NZ, A.h),
+                               A.ell2);
+    A.x[n] += alpha * A.p[n];
+    const double rn = A.gm[n] ? 0.0 : A.r[n] - alpha * A.q[n];
+    const double zn = rn / d;
+    A.r[n] = rn;
+    A.z[n] = zn;
+    rzn += rn * zn;
+    rr += rn * rn;
+  }
+  const double a = block_sum_d(rzn, sh);
+  __syncthreads();
+  const double c = block_sum_d(rr, sh);
+  if (threadIdx.x == 0) {
+    A.part[(1 + cur) * HCG_MAXB + blockIdx.x] = a;
+    A.part[(3 + cur) * HCG_MAXB + blockIdx.x] = c;
+  }
+}
+
+// iteration it: stop test on r^T r, else beta = r^T z (it) / r^T z (it - 1)
+// and p = z + beta p.  Every block takes the same decision; block 0 records
+// it.
+__global__ __launch_bounds__(256) void k_hcg_dir(HcgArgs A, int it) {
+  if (A.flags[0]) return;
+  __shared__ double sh[4];
+  const int cur = it & 1, old = cur ^ 1;
+  const double rzn = block_total(A.part + (1 + cur) * HCG_MAXB, A.nb, sh);
+  __syncthreads();
+  const double rzo = block_total(A.part + (1 + old) * HCG_MAXB, A.nb, sh);
+  __syncthreads();
+  const double rr = block_total(A.part + (3 + cur) * HCG_MAXB, A.nb, sh);
+  const bool conv = rr <= A.scal[0];
+  const bool capped = !conv && it + 1 >= A.max_iters;
+  if (conv || capped) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      A.scal[1] = rr;
+      A.scal[2] = (double)(it + 1);
+      A.flags[0] = conv ? 1 : 2;
+    }
+    return;
+  }
+  const double beta = rzn / rzo;
+  const size_t nn = (size_t)A.NX * A.NY * A.NZ;
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < nn;
+       n += (size_t)gridDim.x * blockDim.x)
+    A.p[n] = A.z[n] + beta * A.p[n];
+}
+
+hipError_t launch_hilbert(const Grid &g, double h, double ell, double rtol, int max_iters,
+                          const double *f, const double *b, double *x, double *const vec[4],
+                          uint8_t *gm, double *part, double *scal, int *flags, int it0, int count,
+                          hipStream_t s) {
+  HcgArgs A;
+  A.NX = g.nelx + 1;
+  A.NY = g.nely + 1;
+  A.NZ = g.nelz + 1;
+  A.h = h;
+  A.ell2 = ell * ell;
+  A.max_iters = max_iters;
+  A.gm = gm;
+  A.x = x;
+  A.r = vec[0];
+  A.z = vec[1];
+  A.p = vec[2];
+  A.q = vec[3];
+  A.part = part;
+  A.scal = scal;
+  A.flags = flags;
+  size_t nb = (g.nn + 1023) / 1024;
+  if (nb > (size_t)HCG_MAXB) nb = HCG_MAXB;
+  if (nb < 1) nb = 1;
+  A.nb = (int)nb;
+  const dim3 grid((unsigned)nb), blk(256);
+  if (it0 == 0) {
+    size_t b1 = (g.nn + 255) / 256;
+    if (b1 > 4096) b1 = 4096;
+    hipLaunchKernelGGL(k_gamma_mask, dim3((unsigned)b1), dim3(256), 0, s, g.nn, f, gm);
+    hipLaunchKernelGGL(k_hcg_init, grid, blk, 0, s, A, b);
+    hipLaunchKernelGGL(k_hcg_init_finish, dim3(1), blk, 0, s, A, rtol * rtol);
+  }
+  for (int it = it0; it < it0 + count; ++it) {
+    hipLaunchKernelGGL(k_hcg_apply, grid, blk, 0, s, A);
+    hipLaunchKernelGGL(k_hcg_update, grid, blk, 0, s, A, it);
+    hipLaunchKernelGGL(k_hcg_dir, grid, blk, 0, s, A, it);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace topo

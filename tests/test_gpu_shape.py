@@ -1,0 +1,111 @@
+"""GPU parity of the relaxed shape derivative (Sec. 2.2.2, Eqs. 15-18) and the
+Hilbertian extension (Sec. 2.2.3, Eqs. 19-20), through the C ABI, against the
+oracle on the same seeded inputs.
+
+  * nodal vector: the same Gauss sums in another order (the GPU writes the
+    energy density as lambda tr^2 + 2 mu eps:eps, the oracle as eps^T D eps),
+    so within 1e-13 of max|g|;
+  * extension: the GPU's float64 CG to rtol 1e-11 against the oracle's sparse
+    direct solve, within 1e-9 relative (A_H is well conditioned for these
+    ell); at 96x48x48 the oracle's assembled A_H gives the residual instead of
+    a direct solve;
+  * vbar = 0 on the loaded nodes, the iteration cap, bad parameters."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import shape as S, fem, grid
+from paper_2605_04735_amd import api as A
+from paper_2605_04735_amd import inputs
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def cpu(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def fields(dims, h, seed):
+    nn = (dims[0] + 1) * (dims[1] + 1) * (dims[2] + 1)
+    u = 1e-2 * inputs.random_vector(3 * nn, seed)
+    phi = h * inputs.sphere_union(*dims, seed)
+    return u, phi
+
+
+@pytest.mark.parametrize("dims,h,eta", [((1, 1, 1), 1.0, 2.0), ((7, 3, 2), 1.0, 1.0),
+                                        ((40, 33, 19), 1.0, 2.0), ((24, 12, 10), 0.5, 1.0),
+                                        ((96, 48, 48), 1.0, 2.0)])
+def test_shape_rhs_vs_oracle(dims, h, eta):
+    print("shape rhs", dims, h, eta, flush=True)
+    u, phi = fields(dims, h, sum(dims))
+    ref = S.shape_rhs(u, phi, *dims, h=h, E0=1.0, nu=0.3, eta=eta, c_s=1.0, c_0=-0.05)
+    ctx = A.to_create(A.Problem(*dims, h=h))
+    g = cpu(A.to_shape_rhs(ctx, gpu(phi), u=gpu(u), eta=eta, c_s=1.0, c_0=-0.05))
+    scale = max(np.abs(ref).max(), 1e-300)
+    print("max |diff| / max|g| = %.3e" % (np.abs(g - ref).max() / scale), flush=True)
+    assert np.abs(g - ref).max() <= 1e-13 * scale
+    ref0 = S.shape_rhs(u, phi, *dims, h=h, eta=eta, c_s=0.0, c_0=0.5)
+    g0 = cpu(A.to_shape_rhs(ctx, gpu(phi), eta=eta, c_s=0.0, c_0=0.5))
+    assert np.abs(g0 - ref0).max() <= 1e-13 * max(np.abs(ref0).max(), 1e-300)
+
+
+def _gamma_n(dims, bc):
+    _, f = fem.problem_arrays(*dims, bc)
+    return S.gamma_n_nodes(f)
+
+
+@pytest.mark.parametrize("dims,bc,ell,h", [((7, 3, 2), A.BC_CANTILEVER, 1.0, 1.0),
+                                           ((12, 5, 6), A.BC_MBB, 2.0, 1.0),
+                                           ((40, 33, 19), A.BC_CANTILEVER, 1.5, 1.0),
+                                           ((24, 12, 10), A.BC_CANTILEVER, 1.0, 0.5),
+                                           ((1, 1, 1), A.BC_CANTILEVER, 0.0, 1.0)])
+def test_hilbert_vs_oracle(dims, bc, ell, h):
+    print("hilbert", dims, bc, ell, h, flush=True)
+    u, phi = fields(dims, h, 3 + sum(dims))
+    b = S.shape_rhs(u, phi, *dims, h=h, eta=2.0 * h)
+    b += 0.1 * inputs.random_vector(b.size, 9) * np.abs(b).max()
+    dn = _gamma_n(dims, bc)
+    ref = S.hilbert_extend(b, *dims, h=h, ell=ell, dirichlet=dn)
+    ctx = A.to_create(A.Problem(*dims, h=h, bc=bc))
+    v, it, rel, st = A.to_hilbert_extend(ctx, gpu(b), ell=ell, rtol=1e-11)
+    v = cpu(v)
+    print("iterations %d, rel %.2e, max diff %.2e" % (it, rel, np.abs(v - ref).max()), flush=True)
+    assert st == A.L.TO_OK and rel <= 1e-11 and it > 0
+    assert np.all(v[dn] == 0.0)
+    assert np.abs(v - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
+def test_hilbert_config1_residual_and_errors():
+    dims = (96, 48, 48)
+    u, phi = fields(dims, 1.0, 5)
+    b = S.shape_rhs(u, phi, *dims, eta=2.0)
+    ctx = A.to_create(A.Problem(*dims))
+    v, it, rel, st = A.to_hilbert_extend(ctx, gpu(b), ell=2.0, rtol=1e-10)
+    v = cpu(v)
+    dn = _gamma_n(dims, A.BC_CANTILEVER)
+    H = S.hilbert_matrix(*dims, 1.0, 2.0)
+    free = ~dn
+    res = (H @ np.where(free, v, 0.0) - b)[free]
+    print("config-1 extension: %d iterations, oracle residual %.2e" %
+          (it, np.linalg.norm(res) / np.linalg.norm(b[free])), flush=True)
+    assert st == A.L.TO_OK and np.all(v[dn] == 0.0)
+    assert np.linalg.norm(res) <= 2e-10 * np.linalg.norm(b[free])
+    _, it2, _, st2 = A.to_hilbert_extend(ctx, gpu(b), ell=2.0, rtol=1e-10, max_iters=3,
+                                         raise_on_error=False)
+    assert st2 == A.L.TO_E_NOCONV and it2 == 3
+    for kw in (dict(ell=-1.0), dict(rtol=0.0), dict(rtol=1.0), dict(max_iters=0)):
+        _, _, _, st3 = A.to_hilbert_extend(ctx, gpu(b), raise_on_error=False, **kw)
+        assert st3 == A.L.TO_E_INVALID
+    with pytest.raises(A.TopoError):
+        A.to_shape_rhs(ctx, gpu(phi), u=None, c_s=1.0)
+    with pytest.raises(A.TopoError):
+        A.to_shape_rhs(ctx, gpu(phi), eta=0.0, c_s=0.0, c_0=1.0)
+    # the context stays usable
+    _, it4, _, st4 = A.to_hilbert_extend(ctx, gpu(b), ell=1.0, rtol=1e-6)
+    assert st4 == A.L.TO_OK and it4 > 0
