@@ -61,8 +61,11 @@ def parse():
     ap.add_argument("--no-simp", action="store_true", help="skip the SIMP-loop workload")
     ap.add_argument("--no-levelset", action="store_true",
                     help="skip the level-set evolution/reinitialisation workload")
+    ap.add_argument("--no-shape", action="store_true",
+                    help="skip the shape-derivative / Hilbertian-extension workload")
     ap.add_argument("--requests", type=int, default=128)
-    ap.add_argument("--probe", choices=["copy", "cg", "cg3", "product", "levelset"], default=None,
+    ap.add_argument("--probe", choices=["copy", "cg", "cg3", "product", "levelset", "shape"],
+                    default=None,
                     help="short runs for hardware-counter passes: a device copy of known size, "
                          "one workload solve, products on 256x128x128, or level-set steps on "
                          "its node grid")
@@ -94,6 +97,16 @@ def probe(kind):
         u, info, _ = A.to_solve(ctx, x)
         torch.cuda.synchronize()
         log("cg probe: %s" % info)
+        return
+    if kind == "shape":
+        ctx = A.to_create(A.Problem(*LARGE))
+        nn = (LARGE[0] + 1) * (LARGE[1] + 1) * (LARGE[2] + 1)
+        phi = torch.from_numpy(inputs.sphere_union(*LARGE, 5, scale=2.5)).to(dev)
+        u = torch.from_numpy(1e-2 * inputs.random_vector(3 * nn, 5)).to(dev)
+        g = A.to_shape_rhs(ctx, phi, u=u, eta=2.0)
+        A.to_hilbert_extend(ctx, g, ell=2.0, rtol=1e-8)
+        torch.cuda.synchronize()
+        log("shape probe done")
         return
     if kind == "levelset":
         ctx = A.to_create(A.Problem(*LARGE))
@@ -342,6 +355,9 @@ def main():
         workloads["simp_cantilever_96x48x48"] = workload_simp(A, dev, rtol_mixed, rtol_fp64)
     if not args.no_levelset:
         workloads["levelset"] = workload_levelset(A, inputs, dev)
+    if not args.no_shape:
+        workloads["shape_extension"] = workload_shape(A, inputs, dev, x,
+                                                      torch.from_numpy(u_m).to(dev))
 
     # ---------------------------------------------------------- roofline
     # dominant kernel: the fused inner-CG product (p = z + beta p_old, q = K p,
@@ -539,6 +555,56 @@ def workload_levelset(A, inputs, dev, nsteps=40):
         out["%dx%dx%d" % dims] = rec
         ctx.close()
     log("levelset: %s" % out)
+    return out
+
+
+def workload_shape(A, inputs, dev, x1, u1, reps=5):
+    """Relaxed shape derivative (Eqs. 15-17) and Hilbertian extension
+    (Eqs. 19-20).  On the 96x48x48 cantilever the inputs are the benchmark
+    design's own: phi = its density->SDF at 0.5, u its float32-refined
+    displacement; on 256x128x128, phi = 2.5 x the distance to three balls and
+    a seeded u.  eta = 2h, ell = 2h, extension to rtol 1e-8.  Algorithmic
+    bytes of one extension CG iteration: 97 per node (apply: read p and the
+    Gamma_N mask, write q; update: read x, p, r, q, write x, r, z; direction:
+    read z, p, write p)."""
+    import torch
+    out = {}
+    for dims in ((96, 48, 48), (256, 128, 128)):
+        nn = (dims[0] + 1) * (dims[1] + 1) * (dims[2] + 1)
+        ctx = A.to_create(A.Problem(*dims))
+        if dims == DIMS:
+            phi, _, _ = A.to_density_to_sdf(ctx, x1, 0.5)
+            u = u1
+        else:
+            phi = torch.from_numpy(inputs.sphere_union(*dims, 5, scale=2.5)).to(dev)
+            u = torch.from_numpy(1e-2 * inputs.random_vector(3 * nn, 5)).to(dev)
+        g = A.to_shape_rhs(ctx, phi, u=u, eta=2.0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            A.to_shape_rhs(ctx, phi, u=u, eta=2.0, g=g)
+        e1.record()
+        torch.cuda.synchronize()
+        us_rhs = e0.elapsed_time(e1) * 1e3 / reps
+        band = int((g != 0).sum().item())
+        v, it, rel, st = A.to_hilbert_extend(ctx, g, ell=2.0, rtol=1e-8, raise_on_error=False)
+        torch.cuda.synchronize()
+        e0.record()
+        v, it, rel, st = A.to_hilbert_extend(ctx, g, ell=2.0, rtol=1e-8, v=v,
+                                             raise_on_error=False)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        us_it = ms * 1e3 / max(it, 1)
+        out["%dx%dx%d" % dims] = {
+            "nodes": nn, "rhs_us": round(us_rhs, 2), "band_nodes": band,
+            "extension_ms": round(ms, 3), "extension_iters": it, "extension_rel": rel,
+            "extension_status": A.L.STATUS_NAMES.get(st, st),
+            "us_per_iter": round(us_it, 2),
+            "GBs_per_iter": round(97 * nn / (us_it * 1e-6) / 1e9, 1)}
+        ctx.close()
+    log("shape/extension: %s" % out)
     return out
 
 

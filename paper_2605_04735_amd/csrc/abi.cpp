@@ -834,7 +834,10 @@ to_status to_shape_rhs(to_ctx *c, const double *d_u, const double *d_phi, double
   HIPCHK(hipSetDevice(c->device));
   const double nu = c->p.nu, E0 = c->p.E0;
   const double lam = E0 * nu / ((1.0 + nu) * (1.0 - 2.0 * nu)), mu = E0 / (2.0 * (1.0 + nu));
-  HIPCHK(launch_shape_rhs(c->g, d_u, d_phi, c->p.h, lam, mu, eta, c_s, c_0, d_g, c->stream));
+  // the per-element band bytes use the triangle-count scratch of the SDF
+  // transfer (nel ints)
+  HIPCHK(launch_shape_rhs(c->g, d_u, d_phi, c->p.h, lam, mu, eta, c_s, c_0, (uint8_t *)c->cnt,
+                          d_g, c->stream));
   return TO_OK;
 }
 

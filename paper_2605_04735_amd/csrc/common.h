@@ -221,13 +221,15 @@ hipError_t launch_oc_apply(const double *x, const double *dc, double *xnew, size
 hipError_t launch_set(double *p, size_t n, double v, hipStream_t s);
 
 // shape derivative and Hilbertian extension (k_shape.hip).  The extension's
-// CG keeps 5 x HCG_MAXB block partials, then HCG_SCAL doubles of scalars.
+// CG keeps HCG_PQ_MAX + 4 x HCG_MAXB block partials, then 8 scalars.
 constexpr int HCG_MAXB = 1024;
-constexpr int HCG_SCAL_OFS = 5 * HCG_MAXB;
+constexpr int HCG_PQ_MAX = 8192;
+constexpr int HCG_SCAL_OFS = HCG_PQ_MAX + 4 * HCG_MAXB;
 constexpr int HCG_SCRATCH = HCG_SCAL_OFS + 8;
+// band: nel bytes of scratch (elements that meet |phi| <= eta)
 hipError_t launch_shape_rhs(const Grid &g, const double *u, const double *phi, double h,
-                            double lam, double mu, double eta, double c_s, double c_0, double *out,
-                            hipStream_t s);
+                            double lam, double mu, double eta, double c_s, double c_0,
+                            uint8_t *band, double *out, hipStream_t s);
 // iterations it0 .. it0 + count - 1 of the extension's CG (it0 == 0 also
 // builds the Gamma_N mask from f and starts from x = 0); vec: r, z, p, q
 hipError_t launch_hilbert(const Grid &g, double h, double ell, double rtol, int max_iters,

@@ -17,6 +17,8 @@
 // entries.  Nodes of Gamma_N (the loaded nodes) are identity rows.  It is
 // solved by Jacobi-preconditioned CG in float64; every kernel sums the
 // previous kernel's per-block partials itself, in one fixed order.
+#include <algorithm>
+
 #include "common.h"
 #include "device_common.h"
 
@@ -98,21 +100,54 @@ __device__ bool shape_elem_factors(int ei, int ej, int ek, int NX, int NY,
   return any;
 }
 
+// Node and element indices: grids hold fewer than 2^31 nodes, so 32-bit
+// unsigned division recovers (i, j, k) (64-bit division is a long sequence).
+__device__ __forceinline__ void split3(unsigned n, unsigned NX, unsigned NY, int &i, int &j,
+                                       int &k) {
+  const unsigned r = n / NX;
+  i = (int)(n - r * NX);
+  k = (int)(r / NY);
+  j = (int)(r - (unsigned)k * NY);
+}
+
+// band[e] = 1 when phi's nodal range on element e meets [-eta, eta] (phi is
+// trilinear, so it lies between its nodal extremes)
+__global__ __launch_bounds__(256) void k_shape_band(int nelx, int nely, int nelz,
+                                                    const double *__restrict__ phi, double eta,
+                                                    uint8_t *__restrict__ band) {
+  const unsigned nel = (unsigned)nelx * nely * nelz, NX = nelx + 1, NY = nely + 1;
+  for (unsigned e = blockIdx.x * blockDim.x + threadIdx.x; e < nel; e += gridDim.x * blockDim.x) {
+    int i, j, k;
+    split3(e, nelx, nely, i, j, k);
+    const size_t n0 = (size_t)i + (size_t)NX * ((size_t)j + (size_t)NY * k);
+    double lo = INFINITY, hi = -INFINITY;
+    for (int a = 0; a < 8; ++a) {
+      const double v =
+          phi[n0 + (size_t)(a & 1) + (size_t)NX * ((size_t)((a >> 1) & 1) + (size_t)NY * (a >> 2))];
+      lo = fmin(lo, v);
+      hi = fmax(hi, v);
+    }
+    band[e] = (lo > eta || hi < -eta) ? 0 : 1;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_shape_rhs(int nelx, int nely, int nelz,
                                                    const double *__restrict__ u,
                                                    const double *__restrict__ phi, double h,
                                                    double lam, double mu, double eta, double c_s,
-                                                   double c_0, double *__restrict__ g) {
+                                                   double c_0, const uint8_t *__restrict__ band,
+                                                   double *__restrict__ g) {
   const int NX = nelx + 1, NY = nely + 1;
-  const size_t nn = (size_t)NX * NY * (nelz + 1);
-  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < nn;
-       n += (size_t)gridDim.x * blockDim.x) {
-    const int i = (int)(n % NX), j = (int)((n / NX) % NY), k = (int)(n / ((size_t)NX * NY));
+  const unsigned nn = (unsigned)NX * NY * (nelz + 1);
+  for (unsigned n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x) {
+    int i, j, k;
+    split3(n, NX, NY, i, j, k);
     double sum = 0.0;
     for (int a = 0; a < 8; ++a) {  // the node is local node a of element (i-ax, j-ay, k-az)
       const int bx = a & 1, by = (a >> 1) & 1, bz = a >> 2;
       const int ei = i - bx, ej = j - by, ek = k - bz;
       if (ei < 0 || ej < 0 || ek < 0 || ei >= nelx || ej >= nely || ek >= nelz) continue;
+      if (!band[(size_t)ei + (size_t)nelx * ((size_t)ej + (size_t)nely * ek)]) continue;
       double F[8];
       if (!shape_elem_factors(ei, ej, ek, NX, NY, u, phi, h, lam, mu, eta, c_s, c_0, F)) continue;
       for (int q = 0; q < 8; ++q) {
@@ -127,12 +162,16 @@ __global__ __launch_bounds__(256) void k_shape_rhs(int nelx, int nely, int nelz,
 }
 
 hipError_t launch_shape_rhs(const Grid &g, const double *u, const double *phi, double h,
-                            double lam, double mu, double eta, double c_s, double c_0, double *out,
-                            hipStream_t s) {
-  size_t b = (g.nn + 255) / 256;
+                            double lam, double mu, double eta, double c_s, double c_0,
+                            uint8_t *band, double *out, hipStream_t s) {
+  size_t b = (g.nel + 255) / 256;
+  if (b > 8192) b = 8192;
+  hipLaunchKernelGGL(k_shape_band, dim3((unsigned)b), dim3(256), 0, s, g.nelx, g.nely, g.nelz,
+                     phi, eta, band);
+  b = (g.nn + 255) / 256;
   if (b > 8192) b = 8192;
   hipLaunchKernelGGL(k_shape_rhs, dim3((unsigned)b), dim3(256), 0, s, g.nelx, g.nely, g.nelz, u,
-                     phi, h, lam, mu, eta, c_s, c_0, out);
+                     phi, h, lam, mu, eta, c_s, c_0, band, out);
   return hipGetLastError();
 }
 
@@ -173,14 +212,22 @@ struct HcgArgs {
   int max_iters;
   const uint8_t *gm;
   double *x, *r, *z, *p, *q;
-  // block partials (HCG_MAXB each): [0] p^T q; [1 + par] r^T z and
-  // [3 + par] r^T r of the update of iteration parity par (the start counts
-  // as parity 1)
+  // block partials: [0, HCG_PQ_MAX) p^T q of the apply; from HCG_PQ_MAX,
+  // HCG_MAXB each: [par] r^T z and [2 + par] r^T r of the update of
+  // iteration parity par (the start counts as parity 1)
   double *part;
   double *scal;  // [0] stop threshold on r^T r, [1] last r^T r, [2] iterations, [3] b^T b
   int *flags;    // [0] 0 running, 1 converged, 2 iteration cap, 3 breakdown
-  int nb;
+  int nb;        // blocks of the streaming kernels
+  int nb_pq;     // blocks of the apply
+  int kz, ntile; // planes per tile and tiles of the apply
 };
+__device__ __forceinline__ double *rz_part(const HcgArgs &A, int par) {
+  return A.part + HCG_PQ_MAX + par * HCG_MAXB;
+}
+__device__ __forceinline__ double *rr_part(const HcgArgs &A, int par) {
+  return A.part + HCG_PQ_MAX + (2 + par) * HCG_MAXB;
+}
 
 __device__ double block_total(const double *__restrict__ part, int nb, double *sh) {
   __shared__ double tot;
@@ -193,9 +240,7 @@ __device__ double block_total(const double *__restrict__ part, int nb, double *s
 }
 
 __device__ __forceinline__ void node_ijk(size_t n, int NX, int NY, int &i, int &j, int &k) {
-  i = (int)(n % NX);
-  j = (int)((n / NX) % NY);
-  k = (int)(n / ((size_t)NX * NY));
+  split3((unsigned)n, (unsigned)NX, (unsigned)NY, i, j, k);
 }
 
 // x = 0, r = b on free nodes, z = r / diag, p = z; partials of parity 1
@@ -222,14 +267,14 @@ __global__ __launch_bounds__(256) void k_hcg_init(HcgArgs A, const double *__res
   __syncthreads();
   const double c = block_sum_d(rr, sh);
   if (threadIdx.x == 0) {
-    A.part[2 * HCG_MAXB + blockIdx.x] = a;
-    A.part[4 * HCG_MAXB + blockIdx.x] = c;
+    rz_part(A, 1)[blockIdx.x] = a;
+    rr_part(A, 1)[blockIdx.x] = c;
   }
 }
 
 __global__ __launch_bounds__(256) void k_hcg_init_finish(HcgArgs A, double tol2_rel) {
   __shared__ double sh[4];
-  const double rr = block_total(A.part + 4 * HCG_MAXB, A.nb, sh);
+  const double rr = block_total(rr_part(A, 1), A.nb, sh);
   if (threadIdx.x == 0) {
     A.scal[0] = tol2_rel * rr;
     A.scal[1] = rr;
@@ -239,47 +284,83 @@ __global__ __launch_bounds__(256) void k_hcg_init_finish(HcgArgs A, double tol2_
   }
 }
 
-// q = A_H p (masked), partials p^T q
-__global__ __launch_bounds__(256) void k_hcg_apply(HcgArgs A) {
+// q = A_H p (masked), partials p^T q.  A_H groups by its z factor as
+//   Mz (ell^2 (Kx My + Mx Ky) + Mx My) + ell^2 Kz (Mx My),
+// so each plane k' contributes two 9-point plane sums at (i, j):
+//   P1 = sum_dj [ell^2 my sum_di kx p + (ell^2 ky + my) sum_di mx p],
+//   P2 = sum_dj my sum_di mx p,
+// and q = sum_dk mz P1(k + dk) + ell^2 kz P2(k + dk).  A thread walks a z
+// column keeping P1, P2 of three planes in registers: 9 loads per node.
+// Tiles of HX x HY nodes by kz planes, 1D grid mapped by xcd_local.
+constexpr int HX = 64, HY = 4;
+
+__device__ __forceinline__ void plane_sums(const double *__restrict__ p, size_t n, size_t sy,
+                                           const Tri &tx, const Tri &ty, double ell2, double &P1,
+                                           double &P2) {
+  P1 = 0.0;
+  P2 = 0.0;
+  for (int dj = -1; dj <= 1; ++dj) {
+    if (ty.m[dj + 1] == 0.0) continue;
+    const size_t row = n + (ptrdiff_t)dj * (ptrdiff_t)sy;
+    double sk = 0.0, sm = 0.0;
+    for (int di = -1; di <= 1; ++di) {
+      if (tx.m[di + 1] == 0.0) continue;
+      const double v = p[row + (ptrdiff_t)di];
+      sk += tx.k[di + 1] * v;
+      sm += tx.m[di + 1] * v;
+    }
+    P1 += ell2 * ty.m[dj + 1] * sk + (ell2 * ty.k[dj + 1] + ty.m[dj + 1]) * sm;
+    P2 += ty.m[dj + 1] * sm;
+  }
+}
+
+__global__ __launch_bounds__(HX * HY) void k_hcg_apply(HcgArgs A) {
   if (A.flags[0]) return;
-  __shared__ double sh[4];
-  const size_t nn = (size_t)A.NX * A.NY * A.NZ;
-  const size_t sy = (size_t)A.NX, sz = (size_t)A.NX * A.NY;
+  __shared__ double sh[HX * HY / 64];
+  const int ntx = (A.NX + HX - 1) / HX, nty = (A.NY + HY - 1) / HY;
+  const int t = threadIdx.x + HX * threadIdx.y;
   double pq = 0.0;
-  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < nn;
-       n += (size_t)gridDim.x * blockDim.x) {
-    int i, j, k;
-    node_ijk(n, A.NX, A.NY, i, j, k);
-    const double pn = A.p[n];
-    double acc;
-    if (A.gm[n]) {
-      acc = pn;
-    } else {
-      const Tri tx = tri1d(i, A.NX, A.h), ty = tri1d(j, A.NY, A.h), tz = tri1d(k, A.NZ, A.h);
-      acc = 0.0;
-      for (int dk = -1; dk <= 1; ++dk) {
-        if (tz.m[dk + 1] == 0.0) continue;
-        for (int dj = -1; dj <= 1; ++dj) {
-          if (ty.m[dj + 1] == 0.0) continue;
-          const size_t row = n + (ptrdiff_t)dk * (ptrdiff_t)sz + (ptrdiff_t)dj * (ptrdiff_t)sy;
-          double sk = 0.0, sm = 0.0;
-          for (int di = -1; di <= 1; ++di) {
-            if (tx.m[di + 1] == 0.0) continue;
-            const size_t m = row + (ptrdiff_t)di;
-            const double v = A.gm[m] ? 0.0 : A.p[m];
-            sk += tx.k[di + 1] * v;
-            sm += tx.m[di + 1] * v;
-          }
-          acc += tz.m[dk + 1] * (ty.m[dj + 1] * (A.ell2 * sk + sm) + A.ell2 * ty.k[dj + 1] * sm) +
-                 A.ell2 * tz.k[dk + 1] * ty.m[dj + 1] * sm;
+  for (int b = blockIdx.x; b < A.ntile; b += gridDim.x) {
+    const int lb = xcd_local(b, A.ntile);
+    const int tx_ = lb % ntx, rr_ = lb / ntx, ty_ = rr_ % nty, tz_ = rr_ / nty;
+    const int i = tx_ * HX + threadIdx.x, j = ty_ * HY + threadIdx.y;
+    const int k0 = tz_ * A.kz, k1 = min(k0 + A.kz, A.NZ);
+    if (i < A.NX && j < A.NY) {
+      const size_t sy = (size_t)A.NX, sz = (size_t)A.NX * A.NY;
+      const Tri tx = tri1d(i, A.NX, A.h), ty = tri1d(j, A.NY, A.h);
+      size_t n = (size_t)i + sy * ((size_t)j + (size_t)A.NY * k0);
+      double m1 = 0.0, m2 = 0.0, c1, c2, n1 = 0.0, n2 = 0.0;
+      if (k0 > 0) plane_sums(A.p, n - sz, sy, tx, ty, A.ell2, m1, m2);
+      plane_sums(A.p, n, sy, tx, ty, A.ell2, c1, c2);
+      for (int k = k0; k < k1; ++k, n += sz) {
+        if (k + 1 < A.NZ) plane_sums(A.p, n + sz, sy, tx, ty, A.ell2, n1, n2);
+        else {
+          n1 = 0.0;
+          n2 = 0.0;
         }
+        const Tri tz = tri1d(k, A.NZ, A.h);
+        const double pn = A.p[n];
+        const double acc = A.gm[n] ? pn
+                                   : tz.m[0] * m1 + tz.m[1] * c1 + tz.m[2] * n1 +
+                                         A.ell2 * (tz.k[0] * m2 + tz.k[1] * c2 + tz.k[2] * n2);
+        A.q[n] = acc;
+        pq += pn * acc;
+        m1 = c1;
+        m2 = c2;
+        c1 = n1;
+        c2 = n2;
       }
     }
-    A.q[n] = acc;
-    pq += pn * acc;
   }
-  const double t = block_sum_d(pq, sh);
-  if (threadIdx.x == 0) A.part[blockIdx.x] = t;
+  // block sum (fixed order) of p^T q
+  double v = wave_sum_d(pq);
+  if ((t & 63) == 0) sh[t >> 6] = v;
+  __syncthreads();
+  if (t == 0) {
+    double s = 0.0;
+    for (int w = 0; w < HX * HY / 64; ++w) s += sh[w];
+    A.part[blockIdx.x] = s;
+  }
 }
 
 // iteration it: alpha = r^T z / p^T q; x += alpha p, r -= alpha q,
@@ -288,9 +369,9 @@ __global__ __launch_bounds__(256) void k_hcg_update(HcgArgs A, int it) {
   if (A.flags[0]) return;
   __shared__ double sh[4];
   const int cur = it & 1, old = cur ^ 1;
-  const double pq = block_total(A.part, A.nb, sh);
+  const double pq = block_total(A.part, A.nb_pq, sh);
   __syncthreads();
-  const double rz = block_total(A.part + (1 + old) * HCG_MAXB, A.nb, sh);
+  const double rz = block_total(rz_part(A, old), A.nb, sh);
   if (!(pq > 0.0)) {  // breakdown: every block sees the same pq
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       A.flags[0] = 3;
@@ -319,8 +400,8 @@ __global__ __launch_bounds__(256) void k_hcg_update(HcgArgs A, int it) {
   __syncthreads();
   const double c = block_sum_d(rr, sh);
   if (threadIdx.x == 0) {
-    A.part[(1 + cur) * HCG_MAXB + blockIdx.x] = a;
-    A.part[(3 + cur) * HCG_MAXB + blockIdx.x] = c;
+    rz_part(A, cur)[blockIdx.x] = a;
+    rr_part(A, cur)[blockIdx.x] = c;
   }
 }
 
@@ -331,11 +412,11 @@ __global__ __launch_bounds__(256) void k_hcg_dir(HcgArgs A, int it) {
   if (A.flags[0]) return;
   __shared__ double sh[4];
   const int cur = it & 1, old = cur ^ 1;
-  const double rzn = block_total(A.part + (1 + cur) * HCG_MAXB, A.nb, sh);
+  const double rzn = block_total(rz_part(A, cur), A.nb, sh);
   __syncthreads();
-  const double rzo = block_total(A.part + (1 + old) * HCG_MAXB, A.nb, sh);
+  const double rzo = block_total(rz_part(A, old), A.nb, sh);
   __syncthreads();
-  const double rr = block_total(A.part + (3 + cur) * HCG_MAXB, A.nb, sh);
+  const double rr = block_total(rr_part(A, cur), A.nb, sh);
   const bool conv = rr <= A.scal[0];
   const bool capped = !conv && it + 1 >= A.max_iters;
   if (conv || capped) {
@@ -373,6 +454,13 @@ hipError_t launch_hilbert(const Grid &g, double h, double ell, double rtol, int 
   A.part = part;
   A.scal = scal;
   A.flags = flags;
+  // the apply runs over tiles of up to 16 planes (about 2048 of them where
+  // the grid allows), at most HCG_PQ_MAX blocks that loop over the tiles; the
+  // streaming kernels over at most HCG_MAXB blocks
+  const int ntx = (A.NX + HX - 1) / HX, nty = (A.NY + HY - 1) / HY;
+  A.kz = (int)std::max(1L, std::min(16L, (long)A.NZ * ntx * nty / 2048));
+  A.ntile = ntx * nty * ((A.NZ + A.kz - 1) / A.kz);
+  A.nb_pq = std::min(A.ntile, HCG_PQ_MAX);
   size_t nb = (g.nn + 1023) / 1024;
   if (nb > (size_t)HCG_MAXB) nb = HCG_MAXB;
   if (nb < 1) nb = 1;
@@ -386,7 +474,7 @@ hipError_t launch_hilbert(const Grid &g, double h, double ell, double rtol, int 
     hipLaunchKernelGGL(k_hcg_init_finish, dim3(1), blk, 0, s, A, rtol * rtol);
   }
   for (int it = it0; it < it0 + count; ++it) {
-    hipLaunchKernelGGL(k_hcg_apply, grid, blk, 0, s, A);
+    hipLaunchKernelGGL(k_hcg_apply, dim3((unsigned)A.nb_pq), dim3(HX, HY), 0, s, A);
     hipLaunchKernelGGL(k_hcg_update, grid, blk, 0, s, A, it);
     hipLaunchKernelGGL(k_hcg_dir, grid, blk, 0, s, A, it);
   }
