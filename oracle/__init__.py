@@ -10,7 +10,9 @@ anything here, and this package imports nothing from the product.
 
 Everything is NumPy/SciPy in float64, one step per paper passage:
 
-  grid      numbering, boundary conditions and loads   (Sec. 2.1.1, Eq. 2)
+  grid      numbering, boundary conditions and loads,
+            the paper's own BC variants                 (Sec. 2.1.1, Eq. 2;
+                                                          Secs. 4.2-4.3)
   element   unit-modulus hex8 stiffness k_e^0           (Sec. 2.1.2, Eq. 3)
   fem       assembled K, masked operator, direct solve,
             Jacobi-PCG, compliance and sensitivity       (Eqs. 1-3)
@@ -30,6 +32,4 @@ Everything is NumPy/SciPy in float64, one step per paper passage:
   shape     relaxed shape derivative (nodal vector) and
             the Hilbertian extension A_H vbar = g        (Secs. 2.2.2-2.2.3,
                                                           Eqs. 15-20)
-  api       the library's call names on host arrays with
-            the same error contract                     (test helper)
 """

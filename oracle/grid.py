@@ -24,10 +24,30 @@ Built-in boundary conditions:
                   component, so the pin carries no reaction); the same line
                   load on the top edge at x = 0 (i = 0, k = nelz).
   CUSTOM (2)      mask and load supplied by the caller.
+
+The paper's own variants (Sec. 4.2, 4.3: a 2 x 1 x 1 domain on 40 x 20 x 20
+voxels), with the geometry scaled to the grid (Ly = nely h, Lz = nelz h,
+r = min(Ly, Lz) / 10):
+
+  CANTILEVER_CORNERS (3)  every DOF fixed on the x = 0 face nodes inside the
+                  four corner squares 0.3 Ly x 0.3 Lz (y <= 0.3 Ly or
+                  y >= 0.7 Ly, and likewise z); the load (0, 0, -1) on the
+                  disc of radius r centred on the x = Lx face.
+  MBB_STRIP (4)   u_x = 0 on x = 0 (symmetry); u_z = 0 on the bottom nodes of
+                  the last element strip (k = 0, i >= nelx - 1: one element
+                  wide); u_y = 0 at node (0,0,0) as for MBB; the load on the
+                  half disc of radius r centred at (0, Ly/2, Lz) on the top
+                  face.
+  The loaded region is read as the boundary-face quads whose centroid lies in
+  the disc (on grids too coarse for any, the quads nearest its centre), with
+  a uniform traction: each tagged quad passes a quarter of its share to each
+  of its four nodes, so a node carries -(load_total c) / (4 nq) in z, with c
+  its tagged quads and nq their total.  All the geometric tests are integer
+  arithmetic in half-element units.
 """
 import numpy as np
 
-BC_CANTILEVER, BC_MBB, BC_CUSTOM = 0, 1, 2
+BC_CANTILEVER, BC_MBB, BC_CUSTOM, BC_CANTILEVER_CORNERS, BC_MBB_STRIP = 0, 1, 2, 3, 4
 
 
 def sizes(nelx, nely, nelz):
@@ -99,7 +119,49 @@ def fixed_mask(nelx, nely, nelz, bc, custom_mask=None):
             m[3 * node_index(nelx, nely, nelx, j, 0) + 2] = True
         m[3 * node_index(nelx, nely, 0, 0, 0) + 1] = True
         return m
+    if bc == BC_CANTILEVER_CORNERS:
+        for k in range(nelz + 1):
+            for j in range(nely + 1):
+                if _corner(j, nely) and _corner(k, nelz):
+                    n = node_index(nelx, nely, 0, j, k)
+                    m[3 * n:3 * n + 3] = True
+        return m
+    if bc == BC_MBB_STRIP:
+        for k in range(nelz + 1):
+            for j in range(nely + 1):
+                m[3 * node_index(nelx, nely, 0, j, k) + 0] = True
+        for i in (nelx - 1, nelx):
+            for j in range(nely + 1):
+                m[3 * node_index(nelx, nely, i, j, 0) + 2] = True
+        m[3 * node_index(nelx, nely, 0, 0, 0) + 1] = True
+        return m
     raise ValueError("unknown bc")
+
+
+def _corner(j, n):
+    """Node j of 0..n lies in a corner band: j h <= 0.3 L or j h >= 0.7 L."""
+    return 10 * j <= 3 * n or 10 * j >= 7 * n
+
+
+def loaded_quads(nelx, nely, nelz, bc):
+    """Tagged boundary-face quads (a, b) of the disc (CANTILEVER_CORNERS: quad
+    (j, k) of the x = Lx face) or half disc (MBB_STRIP: quad (i, j) of the
+    z = Lz face).  4 d2 is the squared centroid distance to the centre in
+    half-element units; a quad is tagged when 25 d2 <= min(nely, nelz)^2, or,
+    when none is, when d2 is the smallest."""
+    m = min(nely, nelz)
+    if bc == BC_CANTILEVER_CORNERS:
+        cells = [((2 * j + 1 - nely) ** 2 + (2 * k + 1 - nelz) ** 2, (j, k))
+                 for k in range(nelz) for j in range(nely)]
+    elif bc == BC_MBB_STRIP:
+        cells = [((2 * i + 1) ** 2 + (2 * j + 1 - nely) ** 2, (i, j))
+                 for j in range(nely) for i in range(nelx)]
+    else:
+        raise ValueError("bc without a loaded region")
+    thr = m * m
+    if not any(25 * d2 <= thr for d2, _ in cells):
+        thr = 25 * min(d2 for d2, _ in cells)
+    return [q for d2, q in cells if 25 * d2 <= thr]
 
 
 def load_vector(nelx, nely, nelz, bc, load_total=1.0, custom_load=None):
@@ -110,6 +172,20 @@ def load_vector(nelx, nely, nelz, bc, load_total=1.0, custom_load=None):
         cl = np.asarray(custom_load, dtype=np.float64).ravel()
         assert cl.size == ndof
         return cl.copy()
+    if bc in (BC_CANTILEVER_CORNERS, BC_MBB_STRIP):
+        quads = loaded_quads(nelx, nely, nelz, bc)
+        cnt = {}
+        for a, b in quads:
+            for da in (0, 1):
+                for db in (0, 1):
+                    if bc == BC_CANTILEVER_CORNERS:
+                        n = node_index(nelx, nely, nelx, a + da, b + db)
+                    else:
+                        n = node_index(nelx, nely, a + da, b + db, nelz)
+                    cnt[n] = cnt.get(n, 0) + 1
+        for n, c in cnt.items():
+            f[3 * n + 2] = -(load_total * c) / (4 * len(quads))
+        return f
     if bc == BC_CANTILEVER:
         i, k = nelx, 0
     elif bc == BC_MBB:
