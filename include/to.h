@@ -46,7 +46,13 @@ typedef enum {
   TO_E_BUSY = -7        /* serving: no slot or memory for the request right now        */
 } to_status;
 
-typedef enum { TO_BC_CANTILEVER = 0, TO_BC_MBB = 1, TO_BC_CUSTOM = 2 } to_bc;
+typedef enum {
+  TO_BC_CANTILEVER = 0,
+  TO_BC_MBB = 1,
+  TO_BC_CUSTOM = 2,
+  TO_BC_CANTILEVER_CORNERS = 3,
+  TO_BC_MBB_STRIP = 4
+} to_bc;
 
 /* Arithmetic of the state solve.  FP64: Jacobi-PCG in float64 throughout.
  * FP32_REFINE: inner Jacobi-PCG with float32 vectors and float32 element
@@ -72,6 +78,18 @@ typedef enum { TO_FILTER_DENS = 0, TO_FILTER_DENS_T = 1, TO_FILTER_SENS = 2 } to
  *     u_y = 0 at node (0,0,0); the same line load on the edge i = 0, k = nelz.
  *   CUSTOM: fixed_mask (ndof bytes, nonzero = fixed) and load (ndof doubles)
  *     are host arrays read once by to_create.
+ *   The paper's own variants (Secs. 4.2-4.3), with its geometry scaled to the
+ *   grid (Ly = nely h, Lz = nelz h, r = min(Ly, Lz)/10):
+ *   CANTILEVER_CORNERS: all DOFs fixed on the x = 0 nodes inside the four
+ *     corner squares (y <= 0.3 Ly or y >= 0.7 Ly, and likewise z); load -z on
+ *     the disc of radius r centred on the x = Lx face.
+ *   MBB_STRIP: u_x = 0 on x = 0; u_z = 0 on the bottom nodes of the last
+ *     element strip (k = 0, i >= nelx - 1); u_y = 0 at node (0,0,0); load -z
+ *     on the half disc of radius r centred at (0, Ly/2, Lz) on the top face.
+ *   A loaded region is the set of boundary-face quads whose centroid lies in
+ *   it (on grids too coarse for any: the quads nearest its centre) under a
+ *   uniform traction, so a node carries -(load_total c)/(4 nq) with c its
+ *   tagged quads and nq their number.
  * Loads on fixed DOFs are ignored. */
 typedef struct {
   int32_t nelx, nely, nelz;    /* voxels per axis, each >= 1                      */

@@ -12,7 +12,7 @@ TO_OK, TO_E_INVALID, TO_E_OOM, TO_E_HIP, TO_E_NOCONV, TO_E_NONFINITE, TO_E_SINGU
     0, -1, -2, -3, -4, -5, -6, -7)
 STATUS_NAMES = {0: "TO_OK", -1: "TO_E_INVALID", -2: "TO_E_OOM", -3: "TO_E_HIP",
                 -4: "TO_E_NOCONV", -5: "TO_E_NONFINITE", -6: "TO_E_SINGULAR", -7: "TO_E_BUSY"}
-BC_CANTILEVER, BC_MBB, BC_CUSTOM = 0, 1, 2
+BC_CANTILEVER, BC_MBB, BC_CUSTOM, BC_CANTILEVER_CORNERS, BC_MBB_STRIP = 0, 1, 2, 3, 4
 PREC_FP64, PREC_FP32_REFINE, PREC_FP32_REFINE_BF16 = 0, 1, 2
 FILTER_DENS, FILTER_DENS_T, FILTER_SENS = 0, 1, 2
 

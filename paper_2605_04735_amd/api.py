@@ -11,8 +11,9 @@ import numpy as np
 import torch
 
 from . import _lib as L
-from ._lib import (BC_CANTILEVER, BC_MBB, BC_CUSTOM, PREC_FP64, PREC_FP32_REFINE,  # noqa: F401
-                   PREC_FP32_REFINE_BF16, FILTER_DENS, FILTER_DENS_T, FILTER_SENS)
+from ._lib import (BC_CANTILEVER, BC_MBB, BC_CUSTOM, BC_CANTILEVER_CORNERS,  # noqa: F401
+                   BC_MBB_STRIP, PREC_FP64, PREC_FP32_REFINE, PREC_FP32_REFINE_BF16,
+                   FILTER_DENS, FILTER_DENS_T, FILTER_SENS)
 
 
 class TopoError(RuntimeError):

@@ -124,7 +124,7 @@ bool validate_problem(const to_problem *p, std::string *why) {
   if (!(p->Emin >= 0) || !(p->Emin < p->E0)) { *why = "need 0 <= Emin < E0"; return false; }
   if (!(p->nu > -1.0 && p->nu < 0.5)) { *why = "need -1 < nu < 0.5"; return false; }
   if (!(p->penal >= 1.0) || !std::isfinite(p->penal)) { *why = "need penal >= 1"; return false; }
-  if (p->bc < 0 || p->bc > 2) { *why = "unknown bc"; return false; }
+  if (p->bc < 0 || p->bc > 4) { *why = "unknown bc"; return false; }
   if (p->bc == TO_BC_CUSTOM && (!p->fixed_mask || !p->load)) {
     *why = "CUSTOM bc needs fixed_mask and load"; return false;
   }

@@ -1,6 +1,8 @@
 // Element/node set-up kernels (Eq. 1 moduli, Jacobi diagonal, boundary mask,
 // load vector) and the streaming kernels of Jacobi-preconditioned CG with
 // deterministic two-stage reductions.
+#include <algorithm>
+
 #include "common.h"
 #include "device_common.h"
 
@@ -87,11 +89,19 @@ __global__ void k_mask_builtin(int nelx, int nely, int nelz, int bc, uint8_t *__
        n += (size_t)gridDim.x * blockDim.x) {
     const int i = (int)(n % NX), j = (int)((n / NX) % NY), k = (int)(n / ((size_t)NX * NY));
     unsigned m = 0;
-    if (bc == 0) {  // cantilever: clamp x = 0
+    if (bc == 0) {         // cantilever: clamp x = 0
       if (i == 0) m = 7u;
-    } else {        // MBB half beam
+    } else if (bc == 1) {  // MBB half beam
       if (i == 0) m |= 1u;
       if (i == nelx && k == 0) m |= 4u;
+      if (i == 0 && j == 0 && k == 0) m |= 2u;
+    } else if (bc == 3) {  // four corner squares 0.3 L x 0.3 L of x = 0
+      const bool cy = 10 * j <= 3 * nely || 10 * j >= 7 * nely;
+      const bool cz = 10 * k <= 3 * nelz || 10 * k >= 7 * nelz;
+      if (i == 0 && cy && cz) m = 7u;
+    } else {               // MBB with a one-element support strip
+      if (i == 0) m |= 1u;
+      if (i >= nelx - 1 && k == 0) m |= 4u;
       if (i == 0 && j == 0 && k == 0) m |= 2u;
     }
     mask[n] = (uint8_t)m;
@@ -106,18 +116,49 @@ hipError_t launch_mask_builtin(const Grid &g, int bc, uint8_t *mask, hipStream_t
   return hipGetLastError();
 }
 
+// Loaded quad of the corner-support cantilever (face x = Lx, quad (a, b) =
+// (j, k)) or of the strip MBB (face z = Lz, quad (a, b) = (i, j)): tagged when
+// 25 d2 <= thr, with 4 d2 the squared distance of its centroid to the region's
+// centre in half-element units.
+__device__ __forceinline__ bool quad_tagged(int bc, int a, int b, int nely, int nelz, long long thr) {
+  long long d2;
+  if (bc == 3) d2 = (long long)(2 * a + 1 - nely) * (2 * a + 1 - nely) +
+                    (long long)(2 * b + 1 - nelz) * (2 * b + 1 - nelz);
+  else d2 = (long long)(2 * a + 1) * (2 * a + 1) + (long long)(2 * b + 1 - nely) * (2 * b + 1 - nely);
+  return 25 * d2 <= thr;
+}
+
 __global__ void k_load_builtin(int nelx, int nely, int nelz, int bc, double load_total,
-                               const uint8_t *__restrict__ mask, double *__restrict__ f) {
+                               long long thr, int nq, const uint8_t *__restrict__ mask,
+                               double *__restrict__ f) {
   const int NX = nelx + 1, NY = nely + 1, NZ = nelz + 1;
   const size_t nn = (size_t)NX * NY * NZ;
   for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < nn;
        n += (size_t)gridDim.x * blockDim.x) {
     const int i = (int)(n % NX), j = (int)((n / NX) % NY), k = (int)(n / ((size_t)NX * NY));
     double fz = 0.0;
-    const bool on_edge = (bc == 0) ? (i == nelx && k == 0) : (i == 0 && k == nelz);
-    if (on_edge) {
-      const double w = (j == 0 || j == nely) ? 0.5 : 1.0;
-      fz = -(load_total * w) / (double)nely;
+    if (bc == 0 || bc == 1) {
+      const bool on_edge = (bc == 0) ? (i == nelx && k == 0) : (i == 0 && k == nelz);
+      if (on_edge) {
+        const double w = (j == 0 || j == nely) ? 0.5 : 1.0;
+        fz = -(load_total * w) / (double)nely;
+      }
+    } else {
+      // quarter shares of the tagged quads that touch the node
+      const bool on_face = (bc == 3) ? (i == nelx) : (k == nelz);
+      if (on_face) {
+        const int a = (bc == 3) ? j : i, b = (bc == 3) ? k : j;
+        const int na = (bc == 3) ? nely : nelx, nb = (bc == 3) ? nelz : nely;
+        int c = 0;
+        for (int da = -1; da <= 0; ++da)
+          for (int db = -1; db <= 0; ++db) {
+            const int qa = a + da, qb = b + db;
+            if (qa >= 0 && qa < na && qb >= 0 && qb < nb &&
+                quad_tagged(bc, qa, qb, nely, nelz, thr))
+              ++c;
+          }
+        if (c) fz = -(load_total * (double)c) / (double)(4 * nq);
+      }
     }
     const unsigned m = mask[n];
     f[3 * n + 0] = 0.0;
@@ -128,10 +169,35 @@ __global__ void k_load_builtin(int nelx, int nely, int nelz, int bc, double load
 
 hipError_t launch_load_builtin(const Grid &g, int bc, double load_total, const uint8_t *mask,
                                double *f, hipStream_t s) {
+  // the loaded region of bcs 3 and 4: threshold and quad count, by the same
+  // integer test as the kernel (on grids too coarse for any centroid to fall
+  // inside, the quads nearest the centre)
+  long long thr = 0;
+  int nq = 0;
+  if (bc == 3 || bc == 4) {
+    const long long m = std::min(g.nely, g.nelz);
+    const int na = bc == 3 ? g.nely : g.nelx, nb = bc == 3 ? g.nelz : g.nely;
+    long long dmin = -1;
+    auto d2of = [&](int a, int b) -> long long {
+      return bc == 3 ? (long long)(2 * a + 1 - g.nely) * (2 * a + 1 - g.nely) +
+                           (long long)(2 * b + 1 - g.nelz) * (2 * b + 1 - g.nelz)
+                     : (long long)(2 * a + 1) * (2 * a + 1) +
+                           (long long)(2 * b + 1 - g.nely) * (2 * b + 1 - g.nely);
+    };
+    for (int b = 0; b < nb; ++b)
+      for (int a = 0; a < na; ++a) {
+        const long long d2 = d2of(a, b);
+        if (dmin < 0 || d2 < dmin) dmin = d2;
+      }
+    thr = 25 * dmin <= m * m ? m * m : 25 * dmin;
+    for (int b = 0; b < nb; ++b)
+      for (int a = 0; a < na; ++a)
+        if (25 * d2of(a, b) <= thr) ++nq;
+  }
   int blocks = (int)((g.nn + 255) / 256);
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_load_builtin, dim3(blocks), dim3(256), 0, s, g.nelx, g.nely, g.nelz, bc,
-                     load_total, mask, f);
+                     load_total, thr, nq, mask, f);
   return hipGetLastError();
 }
 

@@ -142,6 +142,38 @@ def test_solve_vs_oracle(name, dims, bc, kind, prec):
     assert np.all(un[fixed] == 0.0)
 
 
+@pytest.mark.parametrize("dims,h,bc", [((40, 20, 20), 0.05, A.BC_CANTILEVER_CORNERS),
+                                       ((40, 20, 20), 0.05, A.BC_MBB_STRIP),
+                                       ((3, 2, 2), 1.0, A.BC_CANTILEVER_CORNERS),
+                                       ((5, 4, 3), 1.0, A.BC_MBB_STRIP)])
+def test_paper_bcs_vs_oracle(dims, h, bc):
+    """The paper's corner-support cantilever and strip MBB (Secs. 4.2-4.3) on
+    its 40x20x20 grid of a 2x1x1 domain, and on coarse grids where the loaded
+    region falls back to the quads nearest its centre."""
+    print("paper bc", dims, h, bc, flush=True)
+    nelx, nely, nelz = dims
+    x = inputs.random_field(nelx, nely, nelz, seed=7, ell=3.0)
+    prob = A.Problem(nelx, nely, nelz, h=h, bc=bc, precision=A.PREC_FP64, rtol=1e-10)
+    ctx = A.to_create(prob)
+    K, K0, E = oracle_K(nelx, nely, nelz, x, prob)
+    fixed, f = fem.problem_arrays(nelx, nely, nelz, bc, 1.0)
+    # the fixed DOFs: identity rows of the operator
+    v = np.random.default_rng(1).standard_normal(prob.ndof)
+    y = cpu(A.to_matvec(ctx, gpu(x), gpu(v)))
+    assert rel2(y, fem.apply_masked(K, fixed, v)) <= 1e-13
+    assert np.array_equal(y[fixed], v[fixed])
+    # the load: c = F^T u on the oracle's own u
+    uref, cref, dcref = _oracle_solution(nelx, nely, nelz, x, prob)
+    c, _ = A.to_compliance_sensitivity(ctx, gpu(x), gpu(uref))
+    assert abs(c - float(f @ uref)) <= 1e-13 * abs(cref)
+    for prec, tol in ((A.PREC_FP64, 1e-8), (A.PREC_FP32_REFINE, 1e-6)):
+        ctx = A.to_create(A.Problem(nelx, nely, nelz, h=h, bc=bc, precision=prec, rtol=1e-10))
+        u, info, st = A.to_solve(ctx, gpu(x))
+        c, dc = A.to_compliance_sensitivity(ctx, gpu(x), u)
+        assert abs(c - cref) <= tol * abs(cref)
+        assert rel2(cpu(dc), dcref) <= tol
+
+
 def test_warm_start_and_determinism():
     nelx, nely, nelz = 22, 11, 9
     x = inputs.random_field(nelx, nely, nelz, seed=3, ell=3.0)
