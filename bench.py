@@ -63,6 +63,8 @@ def parse():
                     help="skip the level-set evolution/reinitialisation workload")
     ap.add_argument("--no-shape", action="store_true",
                     help="skip the shape-derivative / Hilbertian-extension workload")
+    ap.add_argument("--no-paper", action="store_true",
+                    help="skip the SIMP stage on the paper's own two problems")
     ap.add_argument("--requests", type=int, default=128)
     ap.add_argument("--probe", choices=["copy", "cg", "cg3", "product", "levelset", "shape"],
                     default=None,
@@ -355,6 +357,8 @@ def main():
         workloads["simp_cantilever_96x48x48"] = workload_simp(A, dev, rtol_mixed, rtol_fp64)
     if not args.no_levelset:
         workloads["levelset"] = workload_levelset(A, inputs, dev)
+    if not args.no_paper:
+        workloads["paper_problems_40x20x20"] = workload_paper(A, dev)
     if not args.no_shape:
         workloads["shape_extension"] = workload_shape(A, inputs, dev, x,
                                                       torch.from_numpy(u_m).to(dev))
@@ -555,6 +559,49 @@ def workload_levelset(A, inputs, dev, nsteps=40):
         out["%dx%dx%d" % dims] = rec
         ctx.close()
     log("levelset: %s" % out)
+    return out
+
+
+def workload_paper(A, dev):
+    """The paper's two benchmark problems (Secs. 4.2-4.3): 40x20x20 voxels of
+    a 2x1x1 domain (h = 0.05, E0 = 1, nu = 0.3), the cantilever on four
+    corner supports with a disc load and the MBB with a one-element support
+    strip and a half-disc load.  The SIMP stage runs from x = V_f = 0.4 (p 3,
+    R = 2h, OC) to each Delta rho_max of the paper's tables, with
+    float32-inner solves to 1e-6, then density->SDF of the 0.5 % design.  The
+    paper's iteration counts and single-core times (its tables, stored in
+    tests/golden/paper_simp_table.json) are reported beside ours as context."""
+    import torch
+    table = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_simp_table.json")))
+    out = {}
+    for bc, name in ((A.BC_CANTILEVER_CORNERS, "cantilever_corners"), (A.BC_MBB_STRIP, "mbb_strip")):
+        ctx = A.to_create(A.Problem(40, 20, 20, h=0.05, bc=bc, precision=A.PREC_FP32_REFINE,
+                                    rtol=1e-6, max_iters=10 ** 6))
+        A.to_simp(ctx, vf=0.4, rmin=2.0, change_tol=0.0, max_iters=2)  # warm
+        rows = []
+        x = None
+        for tol, paper_it, paper_s in zip(table["delta_rho_max"], table[name]["iterations"],
+                                          table[name]["cpu_seconds"]):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, _, info, _, st = A.to_simp(ctx, vf=0.4, rmin=2.0, change_tol=tol, max_iters=2000,
+                                          raise_on_error=False)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            rows.append({"delta_rho_max": tol, "iterations": info["iters"],
+                         "converged": info["converged"], "seconds": round(sec, 4),
+                         "c_simp": round(info["c"], 4), "volume": round(info["volume"], 5),
+                         "status": A.L.STATUS_NAMES.get(st, st),
+                         "paper_iterations": paper_it, "paper_cpu_seconds": paper_s})
+        A.to_density_to_sdf(ctx, x, 0.5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        A.to_density_to_sdf(ctx, x, 0.5)
+        torch.cuda.synchronize()
+        out[name] = {"simp": rows, "sdf_ms_of_last_design": round((time.perf_counter() - t0) * 1e3, 3),
+                     "triangles": A.last_triangle_count(ctx)}
+        ctx.close()
+    log("paper problems: %s" % out)
     return out
 
 

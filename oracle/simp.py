@@ -79,17 +79,18 @@ def oc_update(x, dc, vf, move=OC_MOVE, eta=OC_ETA, l2=OC_L2, tol=OC_TOL, max_ste
 
 def simp_run(nelx, nely, nelz, *, vf=0.4, rmin=2.0, penal=3.0, E0=1.0, Emin=1e-9, nu=0.3,
              h=1.0, bc=0, load_total=1.0, move=OC_MOVE, eta=OC_ETA, change_tol=0.01,
-             max_iters=50, x0=None):
+             max_iters=50, x0=None, method="direct", rtol=1e-12):
     """The SIMP loop.  Returns (x, history) where history holds, per design
     iteration, the compliance of the design solved, the largest density
     change of the update that followed, the volume fraction after it, and the
-    OC multiplier."""
+    OC multiplier.  method: the state solve, "direct" or "pcg" (to rtol)."""
     nel = nelx * nely * nelz
     x = np.full(nel, float(vf)) if x0 is None else np.array(x0, dtype=np.float64)
     hist = []
     for _ in range(max_iters):
         _, c, dc, _ = fem.full_solve(nelx, nely, nelz, x, h=h, E0=E0, Emin=Emin, nu=nu,
-                                     penal=penal, bc=bc, load_total=load_total)
+                                     penal=penal, bc=bc, load_total=load_total, method=method,
+                                     rtol=rtol)
         dcf = filters.sensitivity_filter(x, dc, nelx, nely, nelz, rmin, h)
         xnew, lam, steps = oc_update(x, dcf, vf, move, eta)
         change = float(np.max(np.abs(xnew - x)))

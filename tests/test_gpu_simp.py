@@ -152,3 +152,25 @@ def test_simp_config1_size_properties():
     assert 0.0 < info["change"] <= 0.2 + 1e-15
     assert np.all(np.diff(chist) < 0.0)
     assert np.max(np.abs(g - g[:, ::-1, :])) <= 1e-4
+
+
+@pytest.mark.parametrize("name,bc", [("cantilever_corners", A.BC_CANTILEVER_CORNERS),
+                                     ("mbb_strip", A.BC_MBB_STRIP)])
+def test_paper_problems_vs_oracle_golden(name, bc):
+    """The SIMP loop on the paper's own problems (40x20x20, h = 0.05, Secs.
+    4.2-4.3) against the oracle's run stored by tests/golden/make_paper_simp.py
+    (its state solves: Jacobi-PCG to 1e-10): the same iteration count at the
+    8 % and 4 % stops and the compliance history within 1e-6."""
+    import json
+    import os
+    print("paper problem", name, flush=True)
+    orc = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                      "paper_simp_oracle.json")))
+    ctx = A.to_create(A.Problem(40, 20, 20, h=0.05, bc=bc, precision=A.PREC_FP64, rtol=1e-10,
+                                max_iters=10 ** 7))
+    for tol in (0.08, 0.04):
+        rec = orc[name][str(tol)]
+        _, _, info, chist, _ = A.to_simp(ctx, vf=0.4, rmin=2.0, change_tol=tol, max_iters=200)
+        assert info["converged"] and info["iters"] == rec["iterations"], (tol, info["iters"])
+        assert np.max(np.abs(chist / np.array(rec["c"]) - 1.0)) <= 1e-6
+        assert info["change"] == pytest.approx(rec["change"][-1], abs=1e-5)

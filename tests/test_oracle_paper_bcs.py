@@ -60,3 +60,23 @@ def test_equilibrium_and_symmetry(bc):
     assert np.max(np.abs(g - g[:, ::-1, :])) < 1e-9 * np.abs(g).max()
     if bc == grid.BC_CANTILEVER_CORNERS:
         assert np.max(np.abs(g - g[::-1, :, :])) < 1e-9 * np.abs(g).max()
+
+
+def test_oracle_simp_matches_paper_iteration_counts():
+    """The oracle's SIMP loop on the two problems, stopped at Delta rho_max =
+    8 % and 4 %, takes the iteration counts the paper prints in its tables
+    (Secs. 4.2-4.3), to within two.  The oracle's run takes about ten minutes
+    per case on one core, so it is stored: tests/golden/make_paper_simp.py
+    (which calls only the oracle) wrote paper_simp_oracle.json."""
+    import json
+    import os
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    table = json.load(open(os.path.join(here, "paper_simp_table.json")))
+    orc = json.load(open(os.path.join(here, "paper_simp_oracle.json")))
+    for name in ("cantilever_corners", "mbb_strip"):
+        paper = dict(zip(table["delta_rho_max"], table[name]["iterations"]))
+        for tol in (0.08, 0.04):
+            rec = orc[name][str(tol)]
+            assert abs(rec["iterations"] - paper[tol]) <= 2, (name, tol)
+            assert rec["change"][-1] <= tol < rec["change"][-2]
+            assert all(abs(v / 0.4 - 1.0) <= 1.5e-3 for v in rec["volume"])
