@@ -78,3 +78,31 @@ def test_last_error_without_context():
     with pytest.raises(A.TopoError):
         A.to_workspace_size(A.Problem(-1, 3, 2))
     assert "grid" in A.L.lib().to_last_error(None).decode()
+
+
+def test_null_context_is_rejected_before_any_device_work():
+    """Every call that takes a context returns TO_E_INVALID for NULL, with a
+    message, and touches no device (this runs without a GPU)."""
+    lib = L.lib()
+    P = ctypes.c_void_p
+    calls = {
+        "to_solve": (None, None, None, None, None),
+        "to_compliance_sensitivity": (None, None, None, None, None),
+        "to_filter": (None, ctypes.c_double(1.5), 0, None, None, None),
+        "to_density_to_sdf": (None, None, ctypes.c_double(0.5), None, None, None),
+        "to_oc_update": (None, None, None, ctypes.c_double(0.4), ctypes.c_double(0.2),
+                         ctypes.c_double(0.5), None, None),
+        "to_simp": (None, None, None, None, None, None, None),
+        "to_ls_advect": (None, None, None, ctypes.c_double(0.5), 1, None),
+        "to_ls_reinit": (None, None, ctypes.c_double(0.5), ctypes.c_double(1e-3), 10, None, None),
+        "to_shape_rhs": (None, None, None, ctypes.c_double(2.0), ctypes.c_double(1.0),
+                         ctypes.c_double(0.0), None),
+        "to_hilbert_extend": (None, ctypes.c_double(1.0), None, None, ctypes.c_double(1e-8), 10,
+                              None, None),
+        "to_matvec": (None, None, None, None),
+        "to_matvec_f32": (None, None, None, None),
+    }
+    for name, args in calls.items():
+        st = getattr(lib, name)(*args)
+        assert st == L.TO_E_INVALID, name
+        assert lib.to_last_error(None), name

@@ -81,7 +81,7 @@ def test_hilbert_vs_oracle(dims, bc, ell, h):
     assert np.abs(v - ref).max() <= 1e-9 * np.abs(ref).max()
 
 
-def test_hilbert_config1_residual_and_errors():
+def test_hilbert_96x48x48_residual_and_errors():
     dims = (96, 48, 48)
     u, phi = fields(dims, 1.0, 5)
     b = S.shape_rhs(u, phi, *dims, eta=2.0)
@@ -92,7 +92,7 @@ def test_hilbert_config1_residual_and_errors():
     H = S.hilbert_matrix(*dims, 1.0, 2.0)
     free = ~dn
     res = (H @ np.where(free, v, 0.0) - b)[free]
-    print("config-1 extension: %d iterations, oracle residual %.2e" %
+    print("96x48x48 extension: %d iterations, oracle residual %.2e" %
           (it, np.linalg.norm(res) / np.linalg.norm(b[free])), flush=True)
     assert st == A.L.TO_OK and np.all(v[dn] == 0.0)
     assert np.linalg.norm(res) <= 2e-10 * np.linalg.norm(b[free])

@@ -140,7 +140,7 @@ def test_simp_stop_rule_and_errors():
         assert st == A.L.TO_E_INVALID
 
 
-def test_simp_config1_size_properties():
+def test_simp_96x48x48_properties():
     dims = (96, 48, 48)
     print("simp", dims, flush=True)
     ctx = A.to_create(A.Problem(*dims, precision=A.PREC_FP32_REFINE, rtol=1e-6))
