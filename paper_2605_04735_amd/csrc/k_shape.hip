@@ -294,20 +294,34 @@ __global__ __launch_bounds__(256) void k_hcg_init_finish(HcgArgs A, double tol2_
 // Tiles of HX x HY nodes by kz planes, 1D grid mapped by xcd_local.
 constexpr int HX = 64, HY = 4;
 
-__device__ __forceinline__ void plane_sums(const double *__restrict__ p, size_t n, size_t sy,
-                                           const Tri &tx, const Tri &ty, double ell2, double &P1,
-                                           double &P2) {
+// the 3 x 3 neighbourhood of node n in its plane (0 where a neighbour does
+// not exist: its 1D coefficients are 0 as well)
+__device__ __forceinline__ void plane_load(const double *__restrict__ p, size_t n, size_t sy,
+                                           const Tri &tx, const Tri &ty, double (&v)[9]) {
+#pragma unroll
+  for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+    for (int di = -1; di <= 1; ++di)
+      v[3 * (dj + 1) + di + 1] =
+          (ty.m[dj + 1] != 0.0 && tx.m[di + 1] != 0.0)
+              ? p[n + (ptrdiff_t)dj * (ptrdiff_t)sy + (ptrdiff_t)di]
+              : 0.0;
+}
+
+__device__ __forceinline__ void plane_sums(const double (&v)[9], const Tri &tx, const Tri &ty,
+                                           double ell2, double &P1, double &P2) {
   P1 = 0.0;
   P2 = 0.0;
+#pragma unroll
   for (int dj = -1; dj <= 1; ++dj) {
     if (ty.m[dj + 1] == 0.0) continue;
-    const size_t row = n + (ptrdiff_t)dj * (ptrdiff_t)sy;
     double sk = 0.0, sm = 0.0;
+#pragma unroll
     for (int di = -1; di <= 1; ++di) {
       if (tx.m[di + 1] == 0.0) continue;
-      const double v = p[row + (ptrdiff_t)di];
-      sk += tx.k[di + 1] * v;
-      sm += tx.m[di + 1] * v;
+      const double x = v[3 * (dj + 1) + di + 1];
+      sk += tx.k[di + 1] * x;
+      sm += tx.m[di + 1] * x;
     }
     P1 += ell2 * ty.m[dj + 1] * sk + (ell2 * ty.k[dj + 1] + ty.m[dj + 1]) * sm;
     P2 += ty.m[dj + 1] * sm;
@@ -330,11 +344,21 @@ __global__ __launch_bounds__(HX * HY) void k_hcg_apply(HcgArgs A) {
       const Tri tx = tri1d(i, A.NX, A.h), ty = tri1d(j, A.NY, A.h);
       size_t n = (size_t)i + sy * ((size_t)j + (size_t)A.NY * k0);
       double m1 = 0.0, m2 = 0.0, c1, c2, n1 = 0.0, n2 = 0.0;
-      if (k0 > 0) plane_sums(A.p, n - sz, sy, tx, ty, A.ell2, m1, m2);
-      plane_sums(A.p, n, sy, tx, ty, A.ell2, c1, c2);
+      double va[9], vb[9];
+      if (k0 > 0) {
+        plane_load(A.p, n - sz, sy, tx, ty, va);
+        plane_sums(va, tx, ty, A.ell2, m1, m2);
+      }
+      plane_load(A.p, n, sy, tx, ty, va);
+      plane_sums(va, tx, ty, A.ell2, c1, c2);
+      // the neighbourhood of plane k + 1 is loaded one step ahead
+      if (k0 + 1 < A.NZ) plane_load(A.p, n + sz, sy, tx, ty, vb);
       for (int k = k0; k < k1; ++k, n += sz) {
-        if (k + 1 < A.NZ) plane_sums(A.p, n + sz, sy, tx, ty, A.ell2, n1, n2);
-        else {
+        if (k + 1 < A.NZ) {
+          for (int q = 0; q < 9; ++q) va[q] = vb[q];
+          if (k + 2 < A.NZ && k + 1 < k1) plane_load(A.p, n + 2 * sz, sy, tx, ty, vb);
+          plane_sums(va, tx, ty, A.ell2, n1, n2);
+        } else {
           n1 = 0.0;
           n2 = 0.0;
         }
