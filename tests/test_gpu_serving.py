@@ -15,7 +15,8 @@ from paper_2605_04735_amd import inputs
 pytestmark = pytest.mark.gpu
 
 MIX = [((24, 12, 8), A.BC_CANTILEVER), ((16, 8, 8), A.BC_MBB), ((32, 16, 12), A.BC_MBB),
-       ((20, 10, 10), A.BC_CANTILEVER), ((12, 12, 6), A.BC_MBB), ((28, 14, 10), A.BC_CANTILEVER)]
+       ((20, 10, 10), A.BC_CANTILEVER), ((12, 12, 6), A.BC_MBB), ((28, 14, 10), A.BC_CANTILEVER),
+       ((20, 10, 10), A.BC_CANTILEVER_CORNERS), ((16, 8, 8), A.BC_MBB_STRIP)]
 
 
 def _requests():
