@@ -167,6 +167,13 @@ to_status to_filter(to_ctx *ctx, double rmin, int32_t mode, const double *d_x, c
 to_status to_density_to_sdf(to_ctx *ctx, const double *d_x, double rho_t, double *d_phi,
                             double *d_rho_nodes, double *d_vf);
 
+/* Ersatz weights of a level set (Sec. 4.1: cut elements weighted by their
+ * solid volume fraction): per element, the volume fraction where the
+ * piecewise-linear interpolant of phi on the six-tet split is < 0 (the vf of
+ * to_density_to_sdf, for any nodal phi).  d_phi [nn]; d_vf [nel] output.
+ * Asynchronous. */
+to_status to_volume_fraction(to_ctx *ctx, const double *d_phi, double *d_vf);
+
 /* Optimality-criteria update of the densities: the design update of the
  * SIMP stage (Sec. 2.1 with the SIMP set-up of Sec. 4).  The paper names OC
  * without its parameters; this is the textbook scheme (Bendsoe and Sigmund):

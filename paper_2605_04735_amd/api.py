@@ -213,6 +213,16 @@ def last_triangle_count(ctx: Context) -> int:
     return L.lib().to_last_triangle_count(ctx.handle)
 
 
+def to_volume_fraction(ctx: Context, phi, vf=None):
+    """Per-element solid volume fraction of a nodal level set; returns vf."""
+    p = ctx.prob
+    if vf is None:
+        vf = torch.empty(p.nel, dtype=torch.float64, device=phi.device)
+    _check(L.lib().to_volume_fraction(ctx.handle, _dev(phi, torch.float64, p.nn, "phi"),
+                                      _dev(vf, torch.float64, p.nel, "vf")), ctx.handle)
+    return vf
+
+
 def to_oc_update(ctx: Context, x, dc, vf, move=0.2, eta=0.5, xnew=None, raise_on_error=True):
     """Returns (xnew, info, status); xnew may be x itself (in place)."""
     p = ctx.prob

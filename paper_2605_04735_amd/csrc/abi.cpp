@@ -688,6 +688,14 @@ to_status to_density_to_sdf(to_ctx *c, const double *d_x, double rho_t, double *
 
 int32_t to_last_triangle_count(const to_ctx *c) { return c ? c->last_tri : 0; }
 
+to_status to_volume_fraction(to_ctx *c, const double *d_phi, double *d_vf) {
+  if (!c) return fail(nullptr, TO_E_INVALID, "ctx is NULL");
+  if (!d_phi || !d_vf) return fail(c, TO_E_INVALID, "d_phi and d_vf are required");
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(launch_vf(c->g, d_phi, d_vf, c->stream));
+  return TO_OK;
+}
+
 to_status to_oc_update(to_ctx *c, const double *d_x, const double *d_dc, double vf, double move,
                        double eta, double *d_xnew, to_oc_info *info) {
   if (!c) return fail(nullptr, TO_E_INVALID, "ctx is NULL");

@@ -99,6 +99,7 @@ def test_null_context_is_rejected_before_any_device_work():
                          ctypes.c_double(0.0), None),
         "to_hilbert_extend": (None, ctypes.c_double(1.0), None, None, ctypes.c_double(1e-8), 10,
                               None, None),
+        "to_volume_fraction": (None, None, None),
         "to_matvec": (None, None, None, None),
         "to_matvec_f32": (None, None, None, None),
     }

@@ -142,3 +142,19 @@ def test_reinit_cap_and_errors():
     # the context stays usable
     _, steps, _, st = A.to_ls_reinit(ctx, gpu(phi), tol=1e-2)
     assert st == A.L.TO_OK and steps > 0
+
+
+@pytest.mark.parametrize("dims,h", [((1, 1, 1), 1.0), ((9, 7, 5), 1.0), ((24, 12, 10), 0.5)])
+def test_volume_fraction_vs_oracle(dims, h):
+    """Ersatz weights of an arbitrary nodal level set (the vf of the
+    density->SDF transfer, Sec. 4.1) against the oracle's tet-by-tet sum,
+    including nodes with phi exactly 0."""
+    from oracle import sdf
+    print("volume fraction", dims, h, flush=True)
+    phi = h * inputs.sphere_union(*dims, sum(dims))
+    phi[::7] = 0.0
+    ref = sdf.volume_fraction(phi, *dims, h=h)
+    ctx = A.to_create(A.Problem(*dims, h=h))
+    vf = cpu(A.to_volume_fraction(ctx, gpu(phi)))
+    assert np.max(np.abs(vf - ref)) <= 1e-12
+    assert np.all(vf >= 0.0) and np.all(vf <= 1.0)
