@@ -94,6 +94,49 @@ def test_matvec_full_size_sampled_rows():
     assert np.max(np.abs(y[picks] - ref)) <= 1e-13 * scale
 
 
+def test_product_and_solve_256x128x128():
+    """256 x 128 x 128 (12.8M DOF) in the launch set-up the benchmark times:
+    sampled rows of the float64 and float32 products from the element
+    definition, and the float32-refined solve checked by properties that hold
+    at any size: the oracle's residual rows at sampled nodes within the solve's
+    tolerance, and F^T u = sum_e E_e u_e^T k0 u_e."""
+    nelx, nely, nelz = 256, 128, 128
+    print("full size", (nelx, nely, nelz), flush=True)
+    x = inputs.random_field(nelx, nely, nelz, seed=3, ell=6.0, kappa=2.0)
+    xg = gpu(x)
+    rng = np.random.default_rng(3)
+    NX, NY = nelx + 1, nely + 1
+    nn = NX * NY * (nelz + 1)
+    picks = [0, NX - 1, NX * NY - 1, nn - 1, 14 + NX * 15, 128 + NX * (64 + NY * 64)]
+    picks += list(rng.choice(nn, 120, replace=False))
+    E = fem.modulus(x, 1.0, 1e-9, 3.0)
+    K0 = element.k0(0.3, 1.0)
+    fixed, f = fem.problem_arrays(nelx, nely, nelz, A.BC_CANTILEVER)
+    u = rng.standard_normal(3 * nn)
+    ref = fem.apply_rows(nelx, nely, nelz, E, K0, u, fixed, picks)
+    scale = np.abs(ref).max()
+    ctx64 = A.to_create(A.Problem(nelx, nely, nelz, precision=A.PREC_FP64))
+    y = cpu(A.to_matvec(ctx64, xg, gpu(u))).reshape(-1, 3)
+    assert np.max(np.abs(y[picks] - ref)) <= 1e-13 * scale
+    del ctx64
+    u32 = u.astype(np.float32)
+    ref32 = fem.apply_rows(nelx, nely, nelz, E, K0, u32.astype(np.float64), fixed, picks)
+    ctx = A.to_create(A.Problem(nelx, nely, nelz, precision=A.PREC_FP32_REFINE, rtol=1e-8))
+    y32 = A.to_matvec_f32(ctx, xg, torch.from_numpy(u32).to(DEV)).cpu().numpy().reshape(-1, 3)
+    # float32 moduli and arithmetic: ~1e-6 of the largest row term
+    assert np.max(np.abs(y32[picks] - ref32)) <= 1e-5 * scale
+    ud, info, st = A.to_solve(ctx, xg)
+    assert st == A.L.TO_OK and info["rel_res"] <= 1e-8
+    un = cpu(ud)
+    r = f.reshape(-1, 3)[picks] - fem.apply_rows(nelx, nely, nelz, E, K0, un, fixed, picks)
+    r[fixed.reshape(-1, 3)[picks]] = 0.0
+    assert np.max(np.abs(r)) <= 1e-8 * np.linalg.norm(f)
+    c, _ = A.to_compliance_sensitivity(ctx, xg, ud, want_dc=False)
+    assert abs(A.last_energy_sum(ctx) - c) <= 1e-7 * abs(c)
+    print("full size solve: %d inner iterations, rel %.2e, c %.6e" % (info["inner_iters"],
+                                                                   info["rel_res"], c), flush=True)
+
+
 # ------------------------------------------------------------------ solves
 def _oracle_solution(nelx, nely, nelz, x, prob):
     K, K0, E = oracle_K(nelx, nely, nelz, x, prob)
