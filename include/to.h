@@ -294,8 +294,8 @@ to_status to_shape_rhs(to_ctx *ctx, const double *d_u, const double *d_phi, doub
  * d_g [nn] right-hand side; d_v [nn] output, must not alias d_g; ell >= 0;
  * 0 < rtol < 1; max_iters >= 1.  h_iters, h_rel (host, may be NULL): CG
  * iterations and the final relative residual.  TO_E_NOCONV at the cap (d_v =
- * last iterate), TO_E_SINGULAR on breakdown.  Synchronises the context
- * stream. */
+ * last iterate), TO_E_SINGULAR on breakdown, TO_E_NONFINITE when d_g holds a
+ * NaN or Inf (d_v untouched).  Synchronises the context stream. */
 to_status to_hilbert_extend(to_ctx *ctx, double ell, const double *d_g, double *d_v, double rtol,
                             int32_t max_iters, int32_t *h_iters, double *h_rel);
 

@@ -750,7 +750,10 @@ to_status to_oc_update(to_ctx *c, const double *d_x, const double *d_dc, double 
 // the SDF transfer (nn doubles, only used inside to_density_to_sdf); the
 // change slots, the loop state and the max|v| word live in the partial-sum
 // array, cleared here before every call.
-to_status ls_check(to_ctx *c, const double *d_phi, const double *d_v, double *vmax) {
+// NaN/Inf check of d_phi (and d_v) with max|v|; `what` names the inputs in
+// the error message
+to_status ls_check(to_ctx *c, const double *d_phi, const double *d_v, double *vmax,
+                   const char *what = "phi or v holds NaN or Inf") {
   static_assert(LS_SCRATCH <= 2 * MAXB, "level-set scratch lives in the partial-sum array");
   unsigned long long *words = (unsigned long long *)c->part;
   HIPCHK(launch_fill(c->flags, F_COUNT * sizeof(int), c->stream));
@@ -762,7 +765,7 @@ to_status ls_check(to_ctx *c, const double *d_phi, const double *d_v, double *vm
   HIPCHK(hipMemcpyAsync(c->h_flags, c->flags, F_COUNT * sizeof(int), hipMemcpyDeviceToHost,
                         c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
-  if (c->h_flags[F_BADX] & 2) return fail(c, TO_E_NONFINITE, "phi or v holds NaN or Inf");
+  if (c->h_flags[F_BADX] & 2) return fail(c, TO_E_NONFINITE, what);
   *vmax = h[0];
   return TO_OK;
 }
@@ -859,6 +862,9 @@ to_status to_hilbert_extend(to_ctx *c, double ell, const double *d_g, double *d_
   if (max_iters < 1) return fail(c, TO_E_INVALID, "max_iters must be >= 1");
   static_assert(HCG_SCRATCH <= 2 * MAXB, "extension scratch lives in the partial-sum array");
   HIPCHK(hipSetDevice(c->device));
+  double gmax = 0.0;
+  to_status chk = ls_check(c, d_g, nullptr, &gmax, "g holds NaN or Inf");
+  if (chk != TO_OK) return chk;
   // r, z, p, q: nn doubles each in the CG vector arrays (each holds at least
   // 3 nn floats); the Gamma_N mask in the node scratch
   double *vec[4];

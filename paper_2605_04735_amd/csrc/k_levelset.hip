@@ -26,7 +26,12 @@
 
 namespace topo {
 
-constexpr int LSX = 64, LSY = 4;
+constexpr int LS_BLOCK = 256;
+// blocks per launch the plane chunks aim at (measured on the 257x129x129 node
+// grid: the evolution step, light on arithmetic, gains from shorter chunks;
+// the reinitialisation step, with two roots and a division per node, from
+// fewer, longer ones)
+constexpr long long LS_ADVECT_BLOCKS = 4096, LS_REINIT_BLOCKS = 2048;
 
 struct Nb {
   double p, xm, xp, ym, yp, zm, zp;
@@ -103,14 +108,14 @@ __device__ __forceinline__ double wave_max_u(double v) {
 // one block max of a non-negative value into one word of a slot set (bit
 // patterns of non-negative doubles order like the doubles)
 __device__ __forceinline__ void block_max_to(double v, unsigned long long *set) {
-  __shared__ double sh[LSX * LSY / 64];
-  const int t = threadIdx.x + LSX * threadIdx.y;
+  __shared__ double sh[LS_BLOCK / 64];
+  const int t = threadIdx.x;
   v = wave_max_u(v);
   if ((t & 63) == 0) sh[t >> 6] = v;
   __syncthreads();
   if (t == 0) {
     double m = 0.0;
-    for (int w = 0; w < LSX * LSY / 64; ++w) m = fmax(m, sh[w]);
+    for (int w = 0; w < LS_BLOCK / 64; ++w) m = fmax(m, sh[w]);
     if (m > 0.0)
       atomicMax(&set[(blockIdx.x % LS_SLOTS) * LS_SLOT_STRIDE],
                 (unsigned long long)__double_as_longlong(m));
@@ -145,35 +150,42 @@ __global__ __launch_bounds__(256) void k_ls_check(const double *__restrict__ phi
   }
 }
 
-// The grid is 1D over tiles (LSX x LSY nodes by kz planes), ordered x, then
-// y, then z-chunk; xcd_local gives every XCD one contiguous range of them, so
-// the halo rows and planes a tile reads were mostly brought into the same L2
-// by its neighbours.
+// The grid is 1D over tiles: a run of LS_BLOCK consecutive nodes of one z
+// plane (row-major, so a run may wrap from one y row to the next) by kz
+// planes, ordered run, then z-chunk.  Every lane but those past a plane's
+// last node holds a node, whatever NX is, and loads stay contiguous;
+// xcd_local gives every XCD one contiguous range of tiles, so the rows and
+// planes beside a run were mostly brought into the same L2 by its
+// neighbours.
 struct Tile {
   int i, j, k0, k1;
+  bool valid;
 };
 __device__ __forceinline__ Tile ls_tile(int NX, int NY, int NZ, int kz) {
-  const int ntx = (NX + LSX - 1) / LSX, nty = (NY + LSY - 1) / LSY;
+  const int plane = NX * NY;
+  const int nseg = (plane + LS_BLOCK - 1) / LS_BLOCK;
   const int nkz = (NZ + kz - 1) / kz;
-  const int lb = xcd_local((int)blockIdx.x, ntx * nty * nkz);
-  const int tx = lb % ntx, r = lb / ntx, ty = r % nty, tz = r / nty;
+  const int lb = xcd_local((int)blockIdx.x, nseg * nkz);
+  const int seg = lb % nseg, tz = lb / nseg;
+  const int p = seg * LS_BLOCK + (int)threadIdx.x;
   Tile t;
-  t.i = tx * LSX + threadIdx.x;
-  t.j = ty * LSY + threadIdx.y;
+  t.valid = p < plane;
+  t.j = p / NX;
+  t.i = p - t.j * NX;
   t.k0 = tz * kz;
   t.k1 = min(t.k0 + kz, NZ);
   return t;
 }
 
 template <bool P2>
-__global__ __launch_bounds__(LSX * LSY) void k_ls_advect(int NX, int NY, int NZ, int kz,
+__global__ __launch_bounds__(LS_BLOCK) void k_ls_advect(int NX, int NY, int NZ, int kz,
                                                          double h, double inv_h, double dt,
                                                          const double *__restrict__ in,
                                                          const double *__restrict__ v,
                                                          double *__restrict__ out) {
   const Tile tl = ls_tile(NX, NY, NZ, kz);
   const int i = tl.i, j = tl.j, k0 = tl.k0, k1 = tl.k1;
-  if (i >= NX || j >= NY) return;
+  if (!tl.valid) return;
   ls_march(in, i, j, k0, k1, NX, NY, NZ, [&](const Nb &a, size_t n) {
     double sp, sm;
     godunov_sums<P2>(a, h, inv_h, sp, sm);
@@ -194,12 +206,12 @@ __global__ __launch_bounds__(LSX * LSY) void k_ls_advect(int NX, int NY, int NZ,
 // clears set (k + 1) % 3 for the next launch (that set was last read by
 // launch k - 1).
 template <bool P2>
-__global__ __launch_bounds__(LSX * LSY) void k_ls_reinit(
+__global__ __launch_bounds__(LS_BLOCK) void k_ls_reinit(
     int NX, int NY, int NZ, int kz, double h, double inv_h, double dtau, double tol, int max_steps,
     int k_launch, const double *__restrict__ in, double *__restrict__ out,
     unsigned long long *__restrict__ slots, double *__restrict__ state) {
   __shared__ double prev_sh;
-  const int t = threadIdx.x + LSX * threadIdx.y;
+  const int t = threadIdx.x;
   const bool block0 = blockIdx.x == 0;
   const size_t set = (size_t)LS_SLOTS * LS_SLOT_STRIDE;
   if (t < 64) {
@@ -225,7 +237,7 @@ __global__ __launch_bounds__(LSX * LSY) void k_ls_reinit(
   const Tile tl = ls_tile(NX, NY, NZ, kz);
   const int i = tl.i, j = tl.j, k0 = tl.k0, k1 = tl.k1;
   double change = 0.0;
-  if (i < NX && j < NY)
+  if (tl.valid)
     change = ls_march(in, i, j, k0, k1, NX, NY, NZ, [&](const Nb &a, size_t n) {
       double sp, sm;
       godunov_sums<P2>(a, h, inv_h, sp, sm);
@@ -244,17 +256,17 @@ __global__ __launch_bounds__(LSX * LSY) void k_ls_reinit(
   block_max_to(change, &slots[(k_launch % 3) * set]);
 }
 
-// planes per block: enough blocks to fill the chip (about 2048), at most 16
-static int ls_kz(const Grid &g) {
-  const long long tiles = (long long)((g.nelx + 1 + LSX - 1) / LSX) *
-                          ((g.nely + 1 + LSY - 1) / LSY);
-  long long kz = (long long)(g.nelz + 1) * tiles / 2048;
+// planes per block: about `target` blocks (2048 of 4 waves fill the chip's
+// 1024 SIMDs twice over), at most 16 planes
+static int ls_kz(const Grid &g, long long target) {
+  const long long runs = ((long long)(g.nelx + 1) * (g.nely + 1) + LS_BLOCK - 1) / LS_BLOCK;
+  long long kz = (long long)(g.nelz + 1) * runs / target;
   return (int)std::max(1LL, std::min(16LL, kz));
 }
 
 static dim3 ls_grid(const Grid &g, int kz) {
-  return dim3((unsigned)(((g.nelx + 1 + LSX - 1) / LSX) * ((g.nely + 1 + LSY - 1) / LSY) *
-                         ((g.nelz + 1 + kz - 1) / kz)));
+  const long long runs = ((long long)(g.nelx + 1) * (g.nely + 1) + LS_BLOCK - 1) / LS_BLOCK;
+  return dim3((unsigned)(runs * ((g.nelz + 1 + kz - 1) / kz)));
 }
 
 hipError_t launch_ls_check(const Grid &g, const double *phi, const double *v, int *flags,
@@ -272,12 +284,12 @@ static bool pow2(double h) {
 
 hipError_t launch_ls_advect(const Grid &g, double h, double dt, const double *in, const double *v,
                             double *out, hipStream_t s) {
-  const int kz = ls_kz(g);
+  const int kz = ls_kz(g, LS_ADVECT_BLOCKS);
   if (pow2(h))
-    hipLaunchKernelGGL(k_ls_advect<true>, ls_grid(g, kz), dim3(LSX, LSY), 0, s, g.nelx + 1,
+    hipLaunchKernelGGL(k_ls_advect<true>, ls_grid(g, kz), dim3(LS_BLOCK), 0, s, g.nelx + 1,
                        g.nely + 1, g.nelz + 1, kz, h, 1.0 / h, dt, in, v, out);
   else
-    hipLaunchKernelGGL(k_ls_advect<false>, ls_grid(g, kz), dim3(LSX, LSY), 0, s, g.nelx + 1,
+    hipLaunchKernelGGL(k_ls_advect<false>, ls_grid(g, kz), dim3(LS_BLOCK), 0, s, g.nelx + 1,
                        g.nely + 1, g.nelz + 1, kz, h, 1.0 / h, dt, in, v, out);
   return hipGetLastError();
 }
@@ -285,13 +297,13 @@ hipError_t launch_ls_advect(const Grid &g, double h, double dt, const double *in
 hipError_t launch_ls_reinit(const Grid &g, double h, double dtau, double tol, int max_steps,
                             int k, const double *in, double *out, unsigned long long *slots,
                             double *state, hipStream_t s) {
-  const int kz = ls_kz(g);
+  const int kz = ls_kz(g, LS_REINIT_BLOCKS);
   if (pow2(h))
-    hipLaunchKernelGGL(k_ls_reinit<true>, ls_grid(g, kz), dim3(LSX, LSY), 0, s, g.nelx + 1,
+    hipLaunchKernelGGL(k_ls_reinit<true>, ls_grid(g, kz), dim3(LS_BLOCK), 0, s, g.nelx + 1,
                        g.nely + 1, g.nelz + 1, kz, h, 1.0 / h, dtau, tol, max_steps, k, in, out,
                        slots, state);
   else
-    hipLaunchKernelGGL(k_ls_reinit<false>, ls_grid(g, kz), dim3(LSX, LSY), 0, s, g.nelx + 1,
+    hipLaunchKernelGGL(k_ls_reinit<false>, ls_grid(g, kz), dim3(LS_BLOCK), 0, s, g.nelx + 1,
                        g.nely + 1, g.nelz + 1, kz, h, 1.0 / h, dtau, tol, max_steps, k, in, out,
                        slots, state);
   return hipGetLastError();

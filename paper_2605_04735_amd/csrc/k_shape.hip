@@ -177,19 +177,20 @@ hipError_t launch_shape_rhs(const Grid &g, const double *u, const double *phi, d
 
 // ---------------------------------------------------------------- extension
 // 1D assembled stiffness and mass entries (neighbour -1, self, +1) at node i
-// of 0 .. N - 1; an end node has one element.
+// of 0 .. N - 1; an end node has one element.  ih = 1/h, h6 = h/6 and
+// h3 = h/3 come from the host, so an entry costs a multiplication.
 struct Tri {
   double k[3], m[3];
 };
-__device__ __forceinline__ Tri tri1d(int i, int N, double h) {
+__device__ __forceinline__ Tri tri1d(int i, int N, double ih, double h6, double h3) {
   const double lo = i > 0 ? 1.0 : 0.0, hi = i < N - 1 ? 1.0 : 0.0;
   Tri t;
-  t.k[0] = -lo / h;
-  t.k[1] = (lo + hi) / h;
-  t.k[2] = -hi / h;
-  t.m[0] = lo * h / 6.0;
-  t.m[1] = (lo + hi) * h / 3.0;
-  t.m[2] = hi * h / 6.0;
+  t.k[0] = -lo * ih;
+  t.k[1] = (lo + hi) * ih;
+  t.k[2] = -hi * ih;
+  t.m[0] = lo * h6;
+  t.m[1] = (lo + hi) * h3;
+  t.m[2] = hi * h6;
   return t;
 }
 
@@ -209,6 +210,7 @@ __global__ void k_gamma_mask(size_t nn, const double *__restrict__ f, uint8_t *_
 struct HcgArgs {
   int NX, NY, NZ;
   double h, ell2;
+  double ih, h6, h3;  // 1/h, h/6, h/3
   int max_iters;
   const uint8_t *gm;
   double *x, *r, *z, *p, *q;
@@ -222,6 +224,19 @@ struct HcgArgs {
   int nb_pq;     // blocks of the apply
   int kz, ntile; // planes per tile and tiles of the apply
 };
+__device__ __forceinline__ Tri tri_x(const HcgArgs &A, int i) {
+  return tri1d(i, A.NX, A.ih, A.h6, A.h3);
+}
+__device__ __forceinline__ Tri tri_y(const HcgArgs &A, int j) {
+  return tri1d(j, A.NY, A.ih, A.h6, A.h3);
+}
+__device__ __forceinline__ Tri tri_z(const HcgArgs &A, int k) {
+  return tri1d(k, A.NZ, A.ih, A.h6, A.h3);
+}
+// the diagonal of A_H at node (i, j, k)
+__device__ __forceinline__ double node_diag(const HcgArgs &A, int i, int j, int k) {
+  return helm_diag(tri_x(A, i), tri_y(A, j), tri_z(A, k), A.ell2);
+}
 __device__ __forceinline__ double *rz_part(const HcgArgs &A, int par) {
   return A.part + HCG_PQ_MAX + par * HCG_MAXB;
 }
@@ -253,8 +268,7 @@ __global__ __launch_bounds__(256) void k_hcg_init(HcgArgs A, const double *__res
     int i, j, k;
     node_ijk(n, A.NX, A.NY, i, j, k);
     const double bn = A.gm[n] ? 0.0 : b[n];
-    const double d = helm_diag(tri1d(i, A.NX, A.h), tri1d(j, A.NY, A.h), tri1d(k, A.NZ, A.h),
-                               A.ell2);
+    const double d = node_diag(A, i, j, k);
     const double zn = bn / d;
     A.x[n] = 0.0;
     A.r[n] = bn;
@@ -291,21 +305,26 @@ __global__ __launch_bounds__(256) void k_hcg_init_finish(HcgArgs A, double tol2_
 //   P2 = sum_dj my sum_di mx p,
 // and q = sum_dk mz P1(k + dk) + ell^2 kz P2(k + dk).  A thread walks a z
 // column keeping P1, P2 of three planes in registers: 9 loads per node.
-// Tiles of HX x HY nodes by kz planes, 1D grid mapped by xcd_local.
-constexpr int HX = 64, HY = 4;
+// A tile is a run of HB consecutive nodes of one plane (row-major, so it may
+// wrap from one y row to the next) by kz planes: every lane holds a node
+// whatever NX is.  The tiles are ordered run, then z-chunk, and mapped by
+// xcd_local.
+constexpr int HB = 256;
 
-// the 3 x 3 neighbourhood of node n in its plane (0 where a neighbour does
-// not exist: its 1D coefficients are 0 as well)
-__device__ __forceinline__ void plane_load(const double *__restrict__ p, size_t n, size_t sy,
-                                           const Tri &tx, const Tri &ty, double (&v)[9]) {
+// the 3 x 3 neighbourhood of node n in its plane.  A neighbour beyond a face
+// is read as the node itself (ox, oy: the clamped offsets); its 1D
+// coefficients are 0, and p is finite, so it adds exact zeros.  The loads
+// and sums are then straight-line code.
+struct Off {
+  ptrdiff_t lo, hi;
+};
+__device__ __forceinline__ void plane_load(const double *__restrict__ p, size_t n, const Off &ox,
+                                           const Off &oy, double (&v)[9]) {
+  const ptrdiff_t dx[3] = {ox.lo, 0, ox.hi}, dy[3] = {oy.lo, 0, oy.hi};
 #pragma unroll
-  for (int dj = -1; dj <= 1; ++dj)
+  for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int di = -1; di <= 1; ++di)
-      v[3 * (dj + 1) + di + 1] =
-          (ty.m[dj + 1] != 0.0 && tx.m[di + 1] != 0.0)
-              ? p[n + (ptrdiff_t)dj * (ptrdiff_t)sy + (ptrdiff_t)di]
-              : 0.0;
+    for (int c = 0; c < 3; ++c) v[3 * a + c] = p[(ptrdiff_t)n + dy[a] + dx[c]];
 }
 
 __device__ __forceinline__ void plane_sums(const double (&v)[9], const Tri &tx, const Tri &ty,
@@ -313,56 +332,57 @@ __device__ __forceinline__ void plane_sums(const double (&v)[9], const Tri &tx, 
   P1 = 0.0;
   P2 = 0.0;
 #pragma unroll
-  for (int dj = -1; dj <= 1; ++dj) {
-    if (ty.m[dj + 1] == 0.0) continue;
+  for (int a = 0; a < 3; ++a) {
     double sk = 0.0, sm = 0.0;
 #pragma unroll
-    for (int di = -1; di <= 1; ++di) {
-      if (tx.m[di + 1] == 0.0) continue;
-      const double x = v[3 * (dj + 1) + di + 1];
-      sk += tx.k[di + 1] * x;
-      sm += tx.m[di + 1] * x;
+    for (int c = 0; c < 3; ++c) {
+      const double x = v[3 * a + c];
+      sk += tx.k[c] * x;
+      sm += tx.m[c] * x;
     }
-    P1 += ell2 * ty.m[dj + 1] * sk + (ell2 * ty.k[dj + 1] + ty.m[dj + 1]) * sm;
-    P2 += ty.m[dj + 1] * sm;
+    P1 += ell2 * ty.m[a] * sk + (ell2 * ty.k[a] + ty.m[a]) * sm;
+    P2 += ty.m[a] * sm;
   }
 }
 
-__global__ __launch_bounds__(HX * HY) void k_hcg_apply(HcgArgs A) {
+__global__ __launch_bounds__(HB) void k_hcg_apply(HcgArgs A) {
   if (A.flags[0]) return;
-  __shared__ double sh[HX * HY / 64];
-  const int ntx = (A.NX + HX - 1) / HX, nty = (A.NY + HY - 1) / HY;
-  const int t = threadIdx.x + HX * threadIdx.y;
+  __shared__ double sh[HB / 64];
+  const int plane = A.NX * A.NY;
+  const int nseg = (plane + HB - 1) / HB;
+  const int t = threadIdx.x;
   double pq = 0.0;
   for (int b = blockIdx.x; b < A.ntile; b += gridDim.x) {
     const int lb = xcd_local(b, A.ntile);
-    const int tx_ = lb % ntx, rr_ = lb / ntx, ty_ = rr_ % nty, tz_ = rr_ / nty;
-    const int i = tx_ * HX + threadIdx.x, j = ty_ * HY + threadIdx.y;
+    const int pp = (lb % nseg) * HB + t, tz_ = lb / nseg;
+    const int j = pp / A.NX, i = pp - j * A.NX;
     const int k0 = tz_ * A.kz, k1 = min(k0 + A.kz, A.NZ);
-    if (i < A.NX && j < A.NY) {
+    if (pp < plane) {
       const size_t sy = (size_t)A.NX, sz = (size_t)A.NX * A.NY;
-      const Tri tx = tri1d(i, A.NX, A.h), ty = tri1d(j, A.NY, A.h);
+      const Tri tx = tri_x(A, i), ty = tri_y(A, j);
+      const Off ox = {i > 0 ? -1 : 0, i < A.NX - 1 ? 1 : 0};
+      const Off oy = {j > 0 ? -(ptrdiff_t)sy : 0, j < A.NY - 1 ? (ptrdiff_t)sy : 0};
       size_t n = (size_t)i + sy * ((size_t)j + (size_t)A.NY * k0);
       double m1 = 0.0, m2 = 0.0, c1, c2, n1 = 0.0, n2 = 0.0;
       double va[9], vb[9];
       if (k0 > 0) {
-        plane_load(A.p, n - sz, sy, tx, ty, va);
+        plane_load(A.p, n - sz, ox, oy, va);
         plane_sums(va, tx, ty, A.ell2, m1, m2);
       }
-      plane_load(A.p, n, sy, tx, ty, va);
+      plane_load(A.p, n, ox, oy, va);
       plane_sums(va, tx, ty, A.ell2, c1, c2);
       // the neighbourhood of plane k + 1 is loaded one step ahead
-      if (k0 + 1 < A.NZ) plane_load(A.p, n + sz, sy, tx, ty, vb);
+      if (k0 + 1 < A.NZ) plane_load(A.p, n + sz, ox, oy, vb);
       for (int k = k0; k < k1; ++k, n += sz) {
         if (k + 1 < A.NZ) {
           for (int q = 0; q < 9; ++q) va[q] = vb[q];
-          if (k + 2 < A.NZ && k + 1 < k1) plane_load(A.p, n + 2 * sz, sy, tx, ty, vb);
+          if (k + 2 < A.NZ && k + 1 < k1) plane_load(A.p, n + 2 * sz, ox, oy, vb);
           plane_sums(va, tx, ty, A.ell2, n1, n2);
         } else {
           n1 = 0.0;
           n2 = 0.0;
         }
-        const Tri tz = tri1d(k, A.NZ, A.h);
+        const Tri tz = tri_z(A, k);
         const double pn = A.p[n];
         const double acc = A.gm[n] ? pn
                                    : tz.m[0] * m1 + tz.m[1] * c1 + tz.m[2] * n1 +
@@ -382,7 +402,7 @@ __global__ __launch_bounds__(HX * HY) void k_hcg_apply(HcgArgs A) {
   __syncthreads();
   if (t == 0) {
     double s = 0.0;
-    for (int w = 0; w < HX * HY / 64; ++w) s += sh[w];
+    for (int w = 0; w < HB / 64; ++w) s += sh[w];
     A.part[blockIdx.x] = s;
   }
 }
@@ -410,8 +430,7 @@ __global__ __launch_bounds__(256) void k_hcg_update(HcgArgs A, int it) {
        n += (size_t)gridDim.x * blockDim.x) {
     int i, j, k;
     node_ijk(n, A.NX, A.NY, i, j, k);
-    const double d = helm_diag(tri1d(i, A.NX, A.h), tri1d(j, A.NY, A.h), tri1d(k, A.NZ, A.h),
-                               A.ell2);
+    const double d = node_diag(A, i, j, k);
     A.x[n] += alpha * A.p[n];
     const double rn = A.gm[n] ? 0.0 : A.r[n] - alpha * A.q[n];
     const double zn = rn / d;
@@ -468,6 +487,9 @@ hipError_t launch_hilbert(const Grid &g, double h, double ell, double rtol, int 
   A.NZ = g.nelz + 1;
   A.h = h;
   A.ell2 = ell * ell;
+  A.ih = 1.0 / h;
+  A.h6 = h / 6.0;
+  A.h3 = h / 3.0;
   A.max_iters = max_iters;
   A.gm = gm;
   A.x = x;
@@ -481,9 +503,9 @@ hipError_t launch_hilbert(const Grid &g, double h, double ell, double rtol, int 
   // the apply runs over tiles of up to 16 planes (about 2048 of them where
   // the grid allows), at most HCG_PQ_MAX blocks that loop over the tiles; the
   // streaming kernels over at most HCG_MAXB blocks
-  const int ntx = (A.NX + HX - 1) / HX, nty = (A.NY + HY - 1) / HY;
-  A.kz = (int)std::max(1L, std::min(16L, (long)A.NZ * ntx * nty / 2048));
-  A.ntile = ntx * nty * ((A.NZ + A.kz - 1) / A.kz);
+  const long nseg = ((long)A.NX * A.NY + HB - 1) / HB;
+  A.kz = (int)std::max(1L, std::min(16L, (long)A.NZ * nseg / 2048));
+  A.ntile = (int)(nseg * ((A.NZ + A.kz - 1) / A.kz));
   A.nb_pq = std::min(A.ntile, HCG_PQ_MAX);
   size_t nb = (g.nn + 1023) / 1024;
   if (nb > (size_t)HCG_MAXB) nb = HCG_MAXB;
@@ -498,7 +520,7 @@ hipError_t launch_hilbert(const Grid &g, double h, double ell, double rtol, int 
     hipLaunchKernelGGL(k_hcg_init_finish, dim3(1), blk, 0, s, A, rtol * rtol);
   }
   for (int it = it0; it < it0 + count; ++it) {
-    hipLaunchKernelGGL(k_hcg_apply, dim3((unsigned)A.nb_pq), dim3(HX, HY), 0, s, A);
+    hipLaunchKernelGGL(k_hcg_apply, dim3((unsigned)A.nb_pq), dim3(HB), 0, s, A);
     hipLaunchKernelGGL(k_hcg_update, grid, blk, 0, s, A, it);
     hipLaunchKernelGGL(k_hcg_dir, grid, blk, 0, s, A, it);
   }

@@ -102,6 +102,11 @@ def test_hilbert_96x48x48_residual_and_errors():
     for kw in (dict(ell=-1.0), dict(rtol=0.0), dict(rtol=1.0), dict(max_iters=0)):
         _, _, _, st3 = A.to_hilbert_extend(ctx, gpu(b), raise_on_error=False, **kw)
         assert st3 == A.L.TO_E_INVALID
+    bad = b.copy()
+    bad[17] = np.nan
+    v5 = gpu(np.full_like(b, 7.0))
+    _, _, _, st5 = A.to_hilbert_extend(ctx, gpu(bad), v=v5, raise_on_error=False)
+    assert st5 == A.L.TO_E_NONFINITE and np.all(cpu(v5) == 7.0)
     with pytest.raises(A.TopoError):
         A.to_shape_rhs(ctx, gpu(phi), u=None, c_s=1.0)
     with pytest.raises(A.TopoError):
