@@ -281,7 +281,9 @@ to_status to_ls_reinit(to_ctx *ctx, double *d_phi, double gamma, double tol, int
  * (Eqs. 17-18).
  * d_u [ndof] displacements (interleaved 3n + c; may be NULL when c_s == 0);
  * d_phi [nn] level set; d_g [nn] output, must not alias d_phi; eta > 0.
- * Deterministic (fixed summation order).  Asynchronous. */
+ * Deterministic (fixed summation order).  Asynchronous.  The first call on a
+ * context allocates 64 bytes per element of device scratch (kept until
+ * to_destroy; TO_E_OOM if that fails). */
 to_status to_shape_rhs(to_ctx *ctx, const double *d_u, const double *d_phi, double eta,
                        double c_s, double c_0, double *d_g);
 

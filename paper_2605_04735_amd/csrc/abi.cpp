@@ -68,6 +68,7 @@ struct to_ctx {
 
   double *tri = nullptr;  // triangles, grown on demand by to_density_to_sdf
   size_t tri_cap = 0;
+  double *shp = nullptr;  // 8 nel element contributions, allocated by the first to_shape_rhs
 
   double *h_scal = nullptr;
   int *h_flags = nullptr;
@@ -481,6 +482,7 @@ void to_destroy(to_ctx *c) {
       if (g) hipGraphExecDestroy(g);
   if (c->owns_ws && c->ws) hipFree(c->ws);
   if (c->tri) hipFree(c->tri);
+  if (c->shp) hipFree(c->shp);
   if (c->h_scal) hipHostFree(c->h_scal);
   if (c->h_flags) hipHostFree(c->h_flags);
   delete c;
@@ -845,10 +847,14 @@ to_status to_shape_rhs(to_ctx *c, const double *d_u, const double *d_phi, double
   HIPCHK(hipSetDevice(c->device));
   const double nu = c->p.nu, E0 = c->p.E0;
   const double lam = E0 * nu / ((1.0 + nu) * (1.0 - 2.0 * nu)), mu = E0 / (2.0 * (1.0 + nu));
+  if (!c->shp && hipMalloc((void **)&c->shp, 8 * c->g.nel * sizeof(double)) != hipSuccess) {
+    c->shp = nullptr;
+    return fail(c, TO_E_OOM, "cannot allocate the shape-derivative element buffer");
+  }
   // the per-element band bytes use the triangle-count scratch of the SDF
   // transfer (nel ints)
   HIPCHK(launch_shape_rhs(c->g, d_u, d_phi, c->p.h, lam, mu, eta, c_s, c_0, (uint8_t *)c->cnt,
-                          d_g, c->stream));
+                          c->shp, d_g, c->stream));
   return TO_OK;
 }
 

@@ -229,7 +229,7 @@ constexpr int HCG_SCRATCH = HCG_SCAL_OFS + 8;
 // band: nel bytes of scratch (elements that meet |phi| <= eta)
 hipError_t launch_shape_rhs(const Grid &g, const double *u, const double *phi, double h,
                             double lam, double mu, double eta, double c_s, double c_0,
-                            uint8_t *band, double *out, hipStream_t s);
+                            uint8_t *band, double *contrib, double *out, hipStream_t s);
 // iterations it0 .. it0 + count - 1 of the extension's CG (it0 == 0 also
 // builds the Gamma_N mask from f and starts from x = 0); vec: r, z, p, q
 hipError_t launch_hilbert(const Grid &g, double h, double ell, double rtol, int max_iters,

@@ -6,9 +6,10 @@
 //   g_a = sum_e sum_q w_q h^3 N_a(q) (c_s s(q) + c_0) H'_eta(phi(q)) |grad phi(q)|,
 //   s = sigma:eps = lambda (tr eps)^2 + 2 mu eps:eps with the solid's E0,
 //   H'_eta(t) = (1 + cos(pi t / eta)) / (2 eta) for |t| <= eta, else 0.
-// A node gathers its (up to 8) elements in a fixed order and recomputes each
-// element's Gauss-point factors; only elements that meet the band
-// |phi| <= eta do any work, and the sum is the same run to run.
+// Two passes: each element whose nodal phi range meets [-eta, eta] (the band)
+// evaluates its Gauss-point factors once and stores its eight nodal
+// contributions; then every node sums those of its (up to 8) band elements in
+// a fixed order, so the vector is the same run to run.
 //
 // Extension: A_H = ell^2 K + M (Q1 Laplacian and mass).  On equal voxels both
 // are sums of Kronecker products of the 1D assembled stiffness
@@ -110,68 +111,127 @@ __device__ __forceinline__ void split3(unsigned n, unsigned NX, unsigned NY, int
   j = (int)(r - (unsigned)k * NY);
 }
 
-// band[e] = 1 when phi's nodal range on element e meets [-eta, eta] (phi is
-// trilinear, so it lies between its nodal extremes)
-__global__ __launch_bounds__(256) void k_shape_band(int nelx, int nely, int nelz,
-                                                    const double *__restrict__ phi, double eta,
-                                                    uint8_t *__restrict__ band) {
-  const unsigned nel = (unsigned)nelx * nely * nelz, NX = nelx + 1, NY = nely + 1;
-  for (unsigned e = blockIdx.x * blockDim.x + threadIdx.x; e < nel; e += gridDim.x * blockDim.x) {
-    int i, j, k;
-    split3(e, nelx, nely, i, j, k);
-    const size_t n0 = (size_t)i + (size_t)NX * ((size_t)j + (size_t)NY * k);
-    double lo = INFINITY, hi = -INFINITY;
-    for (int a = 0; a < 8; ++a) {
-      const double v =
-          phi[n0 + (size_t)(a & 1) + (size_t)NX * ((size_t)((a >> 1) & 1) + (size_t)NY * (a >> 2))];
-      lo = fmin(lo, v);
-      hi = fmax(hi, v);
+// Element pass.  A block owns SH_RANGE consecutive elements (grid-stride over
+// such ranges).  Its lanes first test their elements: band[e] = 1 when phi's
+// nodal range on e meets [-eta, eta] (phi is trilinear, so it lies between
+// its nodal extremes), and the band elements are appended to a list in LDS.
+// The lanes then take the list densely, so a wave evaluates 64 band elements
+// at once however thinly the band crosses the range.  Element e stores
+// c_a = sum_q N_a(q) F(q) at contrib[a * nel + e], a = 0..7; the list order
+// decides only which lane computes what.
+constexpr int SH_THREADS = 256, SH_RANGE = 2048;
+
+__global__ __launch_bounds__(SH_THREADS) void k_shape_elem(
+    int nelx, int nely, int nelz, const double *__restrict__ u, const double *__restrict__ phi,
+    double h, double lam, double mu, double eta, double c_s, double c_0,
+    uint8_t *__restrict__ band, double *__restrict__ contrib) {
+  __shared__ unsigned list[SH_RANGE];
+  __shared__ unsigned count;
+  const unsigned nel = (unsigned)nelx * nely * nelz;
+  const int NX = nelx + 1, NY = nely + 1;
+  for (unsigned base = blockIdx.x * (unsigned)SH_RANGE; base < nel;
+       base += gridDim.x * (unsigned)SH_RANGE) {
+    if (threadIdx.x == 0) count = 0;
+    __syncthreads();
+    // every lane loads the nodal phi of all its elements before testing any
+    constexpr int PER = SH_RANGE / SH_THREADS;
+    double lo[PER], hi[PER];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const unsigned e = base + threadIdx.x + (unsigned)r * SH_THREADS;
+      lo[r] = INFINITY;
+      hi[r] = -INFINITY;
+      if (e < nel) {
+        int i, j, k;
+        split3(e, nelx, nely, i, j, k);
+        const size_t n0 = (size_t)i + (size_t)NX * ((size_t)j + (size_t)NY * k);
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+          const double v = phi[n0 + (size_t)(a & 1) +
+                               (size_t)NX * ((size_t)((a >> 1) & 1) + (size_t)NY * (a >> 2))];
+          lo[r] = fmin(lo[r], v);
+          hi[r] = fmax(hi[r], v);
+        }
+      }
     }
-    band[e] = (lo > eta || hi < -eta) ? 0 : 1;
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const unsigned e = base + threadIdx.x + (unsigned)r * SH_THREADS;
+      if (e < nel) {
+        const bool in = !(lo[r] > eta || hi[r] < -eta);
+        band[e] = in ? 1 : 0;
+        if (in) list[atomicAdd(&count, 1u)] = e;
+      }
+    }
+    __syncthreads();
+    const unsigned m = count;
+    for (unsigned q = threadIdx.x; q < m; q += SH_THREADS) {
+      const unsigned e = list[q];
+      int i, j, k;
+      split3(e, nelx, nely, i, j, k);
+      double F[8];
+      for (int r = 0; r < 8; ++r) F[r] = 0.0;
+      shape_elem_factors(i, j, k, NX, NY, u, phi, h, lam, mu, eta, c_s, c_0, F);
+      for (int a = 0; a < 8; ++a) {
+        const int bx = a & 1, by = (a >> 1) & 1, bz = a >> 2;
+        double c = 0.0;
+        for (int r = 0; r < 8; ++r) {
+          const double x = (r & 1) ? GB : GA, y = ((r >> 1) & 1) ? GB : GA, z = (r >> 2) ? GB : GA;
+          c += (bx ? x : 1.0 - x) * (by ? y : 1.0 - y) * (bz ? z : 1.0 - z) * F[r];
+        }
+        contrib[(size_t)a * nel + e] = c;
+      }
+    }
+    __syncthreads();
   }
 }
 
-__global__ __launch_bounds__(256) void k_shape_rhs(int nelx, int nely, int nelz,
-                                                   const double *__restrict__ u,
-                                                   const double *__restrict__ phi, double h,
-                                                   double lam, double mu, double eta, double c_s,
-                                                   double c_0, const uint8_t *__restrict__ band,
-                                                   double *__restrict__ g) {
+// Node pass: g_n = sum over its elements in the order a = 0..7 (the node is
+// local node a of element (i - ax, j - ay, k - az)) of their stored
+// contributions; elements outside the band add nothing.
+__global__ __launch_bounds__(256) void k_shape_gather(int nelx, int nely, int nelz,
+                                                      const uint8_t *__restrict__ band,
+                                                      const double *__restrict__ contrib,
+                                                      double *__restrict__ g) {
   const int NX = nelx + 1, NY = nely + 1;
   const unsigned nn = (unsigned)NX * NY * (nelz + 1);
+  const size_t nel = (size_t)nelx * nely * nelz;
   for (unsigned n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x) {
     int i, j, k;
     split3(n, NX, NY, i, j, k);
-    double sum = 0.0;
-    for (int a = 0; a < 8; ++a) {  // the node is local node a of element (i-ax, j-ay, k-az)
-      const int bx = a & 1, by = (a >> 1) & 1, bz = a >> 2;
-      const int ei = i - bx, ej = j - by, ek = k - bz;
-      if (ei < 0 || ej < 0 || ek < 0 || ei >= nelx || ej >= nely || ek >= nelz) continue;
-      if (!band[(size_t)ei + (size_t)nelx * ((size_t)ej + (size_t)nely * ek)]) continue;
-      double F[8];
-      if (!shape_elem_factors(ei, ej, ek, NX, NY, u, phi, h, lam, mu, eta, c_s, c_0, F)) continue;
-      for (int q = 0; q < 8; ++q) {
-        const double r[3] = {(q & 1) ? GB : GA, ((q >> 1) & 1) ? GB : GA, (q >> 2) ? GB : GA};
-        const double N = (bx ? r[0] : 1.0 - r[0]) * (by ? r[1] : 1.0 - r[1]) *
-                         (bz ? r[2] : 1.0 - r[2]);
-        sum += N * F[q];
-      }
+    // the eight band bytes first, then the stored contributions of the band
+    // elements, then the sum in the order a = 0..7
+    size_t e[8];
+    bool in[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const int ei = i - (a & 1), ej = j - ((a >> 1) & 1), ek = k - (a >> 2);
+      const bool ok = ei >= 0 && ej >= 0 && ek >= 0 && ei < nelx && ej < nely && ek < nelz;
+      e[a] = ok ? (size_t)ei + (size_t)nelx * ((size_t)ej + (size_t)nely * ek) : 0;
+      in[a] = ok && band[e[a]] != 0;
     }
+    double c[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) c[a] = in[a] ? contrib[(size_t)a * nel + e[a]] : 0.0;
+    double sum = 0.0;
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+      if (in[a]) sum += c[a];
     g[n] = sum;
   }
 }
 
 hipError_t launch_shape_rhs(const Grid &g, const double *u, const double *phi, double h,
                             double lam, double mu, double eta, double c_s, double c_0,
-                            uint8_t *band, double *out, hipStream_t s) {
-  size_t b = (g.nel + 255) / 256;
-  if (b > 8192) b = 8192;
-  hipLaunchKernelGGL(k_shape_band, dim3((unsigned)b), dim3(256), 0, s, g.nelx, g.nely, g.nelz,
-                     phi, eta, band);
+                            uint8_t *band, double *contrib, double *out, hipStream_t s) {
+  size_t b = (g.nel + SH_RANGE - 1) / SH_RANGE;
+  if (b > 65535) b = 65535;
+  hipLaunchKernelGGL(k_shape_elem, dim3((unsigned)b), dim3(SH_THREADS), 0, s, g.nelx, g.nely,
+                     g.nelz, u, phi, h, lam, mu, eta, c_s, c_0, band, contrib);
   b = (g.nn + 255) / 256;
   if (b > 8192) b = 8192;
-  hipLaunchKernelGGL(k_shape_rhs, dim3((unsigned)b), dim3(256), 0, s, g.nelx, g.nely, g.nelz, u,
-                     phi, h, lam, mu, eta, c_s, c_0, band, out);
+  hipLaunchKernelGGL(k_shape_gather, dim3((unsigned)b), dim3(256), 0, s, g.nelx, g.nely, g.nelz,
+                     band, contrib, out);
   return hipGetLastError();
 }
 
@@ -345,7 +405,7 @@ __device__ __forceinline__ void plane_sums(const double (&v)[9], const Tri &tx, 
   }
 }
 
-__global__ __launch_bounds__(HB) void k_hcg_apply(HcgArgs A) {
+__global__ __launch_bounds__(HB, 4) void k_hcg_apply(HcgArgs A) {
   if (A.flags[0]) return;
   __shared__ double sh[HB / 64];
   const int plane = A.NX * A.NY;
