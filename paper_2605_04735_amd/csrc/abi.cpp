@@ -167,7 +167,8 @@ size_t carve(to_ctx *c, const Grid &g, int precision, char *base) {
   const size_t oRho = L.take<double>(g.nn);
   const size_t oCnt = L.take<int>(g.nel), oToff = L.take<int>(g.nel);
   const size_t oBs = L.take<int>(g.nel / 1024 + 4);
-  const int nbm = matvec_blocks(g, matvec_kz(g)), nbu = update_blocks(g.nn);
+  const int nbm = matvec_blocks(g, matvec_kz(g, precision == TO_PREC_FP64));
+  const int nbu = update_blocks(g.nn);
   const size_t oCgp = L.take<double>(CGP_SIZE);
   const size_t total = (L.off + 255) & ~size_t(255);
   if (base) {
@@ -277,8 +278,8 @@ CgDesc<T> make_desc(to_ctx *c, T *const v[6], const T *E, const T *dinv, const C
   d.nely = g.nely;
   d.nelz = g.nelz;
   d.kz = c->kz;
-  d.tx = (g.nelx + 1 + TN - 1) / TN;
-  d.ty = (g.nely + 1 + TN - 1) / TN;
+  d.tx = (g.nelx + 1 + TNX - 1) / TNX;
+  d.ty = (g.nely + 1 + TNY - 1) / TNY;
   d.nb_mv = c->nb_mv;
   d.nb_up = c->nb_up;
   d.zbf16 = sizeof(T) == 4 && c->p.precision == TO_PREC_FP32_REFINE_BF16;
@@ -439,7 +440,7 @@ to_status to_create(const to_problem *prob, void *d_workspace, size_t bytes, voi
     const double mu = 1.0 / (2.0 * (1.0 + prob->nu));
     c->kd = prob->h * (lam + 4.0 * mu) / 9.0;
   }
-  c->kz = matvec_kz(c->g);
+  c->kz = matvec_kz(c->g, prob->precision == TO_PREC_FP64);
   hipStream_t s = c->stream;
   // descriptors of the CG kernels (passed by value at each launch)
   if (prob->precision == TO_PREC_FP64) c->hd64 = make_desc<double>(c, c->v64, c->E64, c->dinv64, c->k64);

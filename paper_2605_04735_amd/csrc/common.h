@@ -55,13 +55,21 @@ constexpr int OC_STATE_OFS = 2 * OC_MAXB;
 constexpr int OC_OUT_OFS = OC_STATE_OFS + 2 * OC_STATE;
 constexpr int OC_SCRATCH = OC_OUT_OFS + 8;
 
-// Element tile of the matrix-free product: 16 x 16 elements per z layer, one
-// thread each; the tile owns the 15 x 15 nodes whose all adjacent elements lie
-// in it, and marches up a z range of node planes.
-constexpr int TE = 16;
-constexpr int TN = TE - 1;
-constexpr int TP = TE + 1;
-constexpr int MV_THREADS = TE * TE;
+// Element tile of the matrix-free product: TEX x TEY elements per z layer, one
+// thread each; the tile owns the TNX x TNY nodes whose all adjacent elements
+// lie in it, and marches up a z range of node planes.  Its node plane is
+// TPX x TPY.
+#ifndef TOPO_TEX
+#define TOPO_TEX 32
+#define TOPO_TEY 8
+#endif
+constexpr int TEX = TOPO_TEX, TEY = TOPO_TEY;
+constexpr int TNX = TEX - 1, TNY = TEY - 1;
+constexpr int TPX = TEX + 1, TPY = TEY + 1;
+constexpr int MV_THREADS = TEX * TEY;
+static_assert(MV_THREADS == 256, "one 256-thread block per tile");
+static_assert(TEX == 16 || TEX == 32 || TEX == 64, "x rows of 16, 32 or 64 lanes");
+static_assert(TPX * TPY <= 2 * MV_THREADS, "a node plane is staged in two slots per thread");
 
 enum MvMode { MV_APPLY = 0, MV_CG = 1, MV_RESID = 2 };
 
@@ -155,7 +163,7 @@ struct Grid {
 // ---------------------------------------------------------------- launchers
 template <typename T, int MODE>
 hipError_t launch_matvec(const MvArgs<T> &a, int *nblocks, hipStream_t s);
-int matvec_kz(const Grid &g);
+int matvec_kz(const Grid &g, bool fp64);
 int matvec_blocks(const Grid &g, int kz);
 
 hipError_t launch_modulus(const Grid &g, const double *x, double E0, double Emin, double penal,

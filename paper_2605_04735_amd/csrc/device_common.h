@@ -109,10 +109,10 @@ __device__ __forceinline__ void hex8_apply(T (&u)[3][8], T E, const Coef<T> &k) 
 // in LDS): F[m], m = mx + 2 my, the x and y butterflies of the 8-point
 // transform.
 template <typename T>
-__device__ __forceinline__ void face_forward(const T (*P)[TP * TP], int idx, T (&F)[3][4]) {
+__device__ __forceinline__ void face_forward(const T (*P)[TPX * TPY], int idx, T (&F)[3][4]) {
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const T v00 = P[c][idx], v10 = P[c][idx + 1], v01 = P[c][idx + TP], v11 = P[c][idx + TP + 1];
+    const T v00 = P[c][idx], v10 = P[c][idx + 1], v01 = P[c][idx + TPX], v11 = P[c][idx + TPX + 1];
     const T s0 = v10 + v00, d0 = v10 - v00, s1 = v11 + v01, d1 = v11 - v01;
     F[c][0] = s1 + s0;
     F[c][1] = d1 + d0;
@@ -179,14 +179,19 @@ __device__ __forceinline__ void block_sum_d2(double a, double b, double *sh, dou
   }
 }
 
-// Value of lane + 1 within each row of 16 lanes (0 for the last lane of a
-// row): the DPP row shift, no LDS traffic.
+// Value of lane + 1 (0 for the last lane): a DPP shift, no LDS traffic.  With
+// 16-element tile rows the shift stays within each row of 16 lanes
+// (row_shl:1); wider rows span DPP rows and take the whole-wave shift
+// (wave_shl:1).  Either way the last element of a tile row, which owns no
+// node, is the only lane whose value is not its right neighbour's.
+constexpr int DPP_NEXT_LANE = TEX == 16 ? 0x101 : 0x130;
 __device__ __forceinline__ float from_next_lane(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x101, 0xF, 0xF, true));
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(0, __float_as_int(v), DPP_NEXT_LANE, 0xF, 0xF, true));
 }
 __device__ __forceinline__ double from_next_lane(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x101, 0xF, 0xF, true);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x101, 0xF, 0xF, true);
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), DPP_NEXT_LANE, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), DPP_NEXT_LANE, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 

@@ -50,7 +50,7 @@ namespace topo {
 template <typename T, int MODE, bool ZBF = false, typename PreFn, typename BetaFn>
 __device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int by, int bz,
                                                PreFn &&pre, BetaFn &&get_beta,
-                                               T (*pl)[3][TP * TP], T (*ex)[MV_THREADS],
+                                               T (*pl)[3][TPX * TPY], T (*ex)[MV_THREADS],
                                                double *red) {
   // CG inputs (z, p) are zero on fixed DOFs by construction and q there is
   // never used (the update masks r), so only APPLY and RESID read the mask.
@@ -63,7 +63,7 @@ __device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int b
   constexpr unsigned S = sizeof(T);
   const int tid = threadIdx.x;
   const int NX = a.nelx + 1, NY = a.nely + 1, NZ = a.nelz + 1;
-  const int i0 = bx * TN, j0 = by * TN;
+  const int i0 = bx * TNX, j0 = by * TNY;
   const int k0 = bz * a.kz;
   const int k1 = min(k0 + a.kz, NZ);
   const unsigned plane = (unsigned)NX * (unsigned)NY;
@@ -78,12 +78,12 @@ __device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int b
   const rsrc_t rM = make_rsrc(a.mask, MASKED ? nn : 0u);
   const rsrc_t rF = make_rsrc(a.f, MODE == MV_RESID ? 3u * nn * 8u : 0u);
 
-  const int ei = tid % TE, ej = tid / TE;
+  const int ei = tid % TEX, ej = tid / TEX;
   const int gi = i0 - 1 + ei, gj = j0 - 1 + ej;
   const bool e_xy = gi >= 0 && gi < a.nelx && gj >= 0 && gj < a.nely;
   // the node owned by this lane: (i0 + ei, j0 + ej), interior of the tile
   const int gni = i0 + ei, gnj = j0 + ej;
-  const bool own = ei < TN && ej < TN && gni < NX && gnj < NY;
+  const bool own = ei < TNX && ej < TNY && gni < NX && gnj < NY;
   const unsigned nown = (unsigned)gni + (unsigned)NX * (unsigned)gnj;
   const unsigned voE = e_xy ? ((unsigned)gi + (unsigned)a.nelx * (unsigned)gj) * S : OOB;
   const unsigned voOwn = own ? 3u * S * nown : OOB;
@@ -93,10 +93,10 @@ __device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int b
 #pragma unroll
   for (int sl = 0; sl < 2; ++sl) {
     const int idx = tid + sl * MV_THREADS;
-    const int li = idx % TP, lj = idx / TP;
+    const int li = idx % TPX, lj = idx / TPX;
     const int gx = i0 - 1 + li, gy = j0 - 1 + lj;
-    const bool v = idx < TP * TP && gx >= 0 && gx < NX && gy >= 0 && gy < NY;
-    const bool mine = li >= 1 && li <= TN && lj >= 1 && lj <= TN;
+    const bool v = idx < TPX * TPY && gx >= 0 && gx < NX && gy >= 0 && gy < NY;
+    const bool mine = li >= 1 && li <= TNX && lj >= 1 && lj <= TNY;
     const unsigned n = (unsigned)gx + (unsigned)NX * (unsigned)gy;
     voN[sl] = v ? 3u * S * n : OOB;
     voM[sl] = v ? n : OOB;
@@ -135,12 +135,12 @@ __device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int b
   // plane kp into LDS (CG: p = z + beta p_old, and p written out for the
   // nodes this block owns); returns the moduli of element layer kp
   auto stage = [&](Plane &R, int kp) -> T {
-    T(*dst)[TP * TP] = pl[kp & 1];
+    T(*dst)[TPX * TPY] = pl[kp & 1];
     const bool wr = CG && kp >= k0 && kp < k1;
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
       const int idx = tid + sl * MV_THREADS;
-      if (idx >= TP * TP) continue;
+      if (idx >= TPX * TPY) continue;
       T v[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -153,7 +153,7 @@ __device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int b
     return R.e;
   };
 
-  const int fidx = ei + TP * ej;  // corner (0,0) of this lane's element face in a plane
+  const int fidx = ei + TPX * ej;  // corner (0,0) of this lane's element face in a plane
   double acc = 0.0;
   T acc_t = 0;  // CG: this lane's p^T q terms (at most 3 kz), in the product's precision
   // one element layer L: faces Fb (plane L, transformed) -> Ft (plane L+1),
@@ -161,7 +161,7 @@ __device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int b
   auto layer = [&](int L, T E, T (&Fb)[3][4], T (&Ft)[3][4], T (&Gb)[3][4], T (&Gt)[3][4]) {
     T pn[3] = {0, 0, 0};
     if (CG && own) {
-      const int idx = (ei + 1) + TP * (ej + 1);
+      const int idx = (ei + 1) + TPX * (ej + 1);
 #pragma unroll
       for (int c = 0; c < 3; ++c) pn[c] = pl[L & 1][c][idx];
     }
@@ -202,7 +202,7 @@ __device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int b
       const unsigned so = (unsigned)L * plane * 3u * S;
       T val[3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) val[c] = xc[c][1] + ex[c][tid + TE];
+      for (int c = 0; c < 3; ++c) val[c] = xc[c][1] + ex[c][tid + TEX];
       if constexpr (MODE == MV_CG) {
         bstore3(rOut, voOwn, so, val);
 #pragma unroll
@@ -275,7 +275,7 @@ __device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int b
 template <typename T, int MODE>
 __global__ __launch_bounds__(MV_THREADS) __attribute__((amdgpu_waves_per_eu(3)))
 void k_matvec(const MvArgs<T> a, int tx, int ty) {
-  __shared__ T pl[2][3][TP * TP];
+  __shared__ T pl[2][3][TPX * TPY];
   __shared__ T ex[3][MV_THREADS];
   __shared__ double red[MV_THREADS / 64];
   const int lb = xcd_local(blockIdx.x, gridDim.x);
@@ -293,7 +293,7 @@ void k_matvec(const MvArgs<T> a, int tx, int ty) {
 template <typename T, bool ZBF = false>
 __device__ __forceinline__ void cg_matvec_block(const CgDesc<T> &d, double *scal, int *flags,
                                                 double *cgp, int nparts, int lb_in, int parity) {
-  __shared__ T pl[2][3][TP * TP];
+  __shared__ T pl[2][3][TPX * TPY];
   __shared__ T ex[6][MV_THREADS];
   __shared__ double red[16];
   bool run = false;
@@ -532,9 +532,22 @@ __global__ __launch_bounds__(256) void k_cg_update1(double *scal, int *flags, do
   cg_update_block<T, ZBF>(d, scal, flags, cgp, nparts, blockIdx.x, parity);
 }
 
-int matvec_kz(const Grid &g) {
+namespace {
+// the kz whose equal-sized chunks give about `target` blocks, at least 2
+int kz_for_target(int NZ, int tiles, int target) {
+  int chunks = std::max(1, target / tiles);
+  int kz = (NZ + chunks - 1) / chunks;
+  if (kz < 2) kz = 2;
+  if (kz > 32) kz = 32;
+  chunks = (NZ + kz - 1) / kz;
+  kz = (NZ + chunks - 1) / chunks;
+  return kz < 2 ? 2 : kz;
+}
+}  // namespace
+
+int matvec_kz(const Grid &g, bool fp64) {
   const int NX = g.nelx + 1, NY = g.nely + 1, NZ = g.nelz + 1;
-  const int tiles = ((NX + TN - 1) / TN) * ((NY + TN - 1) / TN);
+  const int tiles = ((NX + TNX - 1) / TNX) * ((NY + TNY - 1) / TNY);
   if (const char *e = getenv("TOPO_KZ")) {
     int v = atoi(e);
     if (v >= 1) {
@@ -542,29 +555,30 @@ int matvec_kz(const Grid &g) {
       return v;
     }
   }
-  // about 8 blocks per CU while keeping the z recompute (kz + 1)/kz small,
-  // with the node planes split into chunks of (nearly) equal size: a short
-  // last chunk leaves its blocks idle for most of the launch
-  int chunks = std::max(1, 2048 / tiles);
-  int kz = (NZ + chunks - 1) / chunks;
-  if (kz < 2) kz = 2;
-  if (kz > 32) kz = 32;
-  chunks = (NZ + kz - 1) / kz;
-  kz = (NZ + chunks - 1) / chunks;
-  if (kz < 2) kz = 2;
+  // About 8 blocks per CU on large grids, with the node planes split into
+  // chunks of (nearly) equal size: a short last chunk leaves its blocks idle
+  // for most of the launch.  A chunk of kz planes recomputes (kz + 1)/kz
+  // element layers, so small grids trade blocks for longer chunks:
+  // - float32 (five blocks of the product resident per CU): kz = 3 while that
+  //   still leaves about 2.5 blocks per CU;
+  // - float64 (two resident per CU): about 512 blocks, one round of the
+  //   resident blocks, with kz at most 12 (the large-grid optimum).
+  int kz = kz_for_target(NZ, tiles, 2048);
+  if (!fp64 && kz < 3 && tiles * ((NZ + 2) / 3) >= 640) kz = 3;
+  if (fp64) kz = std::max(kz, std::min(kz_for_target(NZ, tiles, 512), 12));
   while (tiles * ((NZ + kz - 1) / kz) > MAXB) ++kz;  // partial sums must fit
   return kz;
 }
 
 int matvec_blocks(const Grid &g, int kz) {
   const int NX = g.nelx + 1, NY = g.nely + 1, NZ = g.nelz + 1;
-  return ((NX + TN - 1) / TN) * ((NY + TN - 1) / TN) * ((NZ + kz - 1) / kz);
+  return ((NX + TNX - 1) / TNX) * ((NY + TNY - 1) / TNY) * ((NZ + kz - 1) / kz);
 }
 
 template <typename T, int MODE>
 hipError_t launch_matvec(const MvArgs<T> &a, int *nblocks, hipStream_t s) {
   const int NX = a.nelx + 1, NY = a.nely + 1, NZ = a.nelz + 1;
-  const int tx = (NX + TN - 1) / TN, ty = (NY + TN - 1) / TN, tz = (NZ + a.kz - 1) / a.kz;
+  const int tx = (NX + TNX - 1) / TNX, ty = (NY + TNY - 1) / TNY, tz = (NZ + a.kz - 1) / a.kz;
   const int nb = tx * ty * tz;
   if (nblocks) *nblocks = nb;
   if (MODE != MV_APPLY && nb > MAXB) return hipErrorInvalidConfiguration;

@@ -291,9 +291,9 @@ bool admit(to_server *s, Slot &sl, Request &&rq) {
   sl.g.nel = (size_t)p.nelx * p.nely * p.nelz;
   sl.g.nn = (size_t)(p.nelx + 1) * (p.nely + 1) * (p.nelz + 1);
   sl.g.ndof = 3 * sl.g.nn;
-  sl.kz = matvec_kz(sl.g);
-  sl.tx = (p.nelx + 1 + TN - 1) / TN;
-  sl.ty = (p.nely + 1 + TN - 1) / TN;
+  sl.kz = matvec_kz(sl.g, false);  // float32 inner solves
+  sl.tx = (p.nelx + 1 + TNX - 1) / TNX;
+  sl.ty = (p.nely + 1 + TNY - 1) / TNY;
   sl.nb_mv = matvec_blocks(sl.g, sl.kz);
   sl.nb_up = update_blocks(sl.g.nn);
   carve_slot(sl.g, s->arena_base + sl.off, &sl);
@@ -632,7 +632,7 @@ to_status to_server_submit(to_server *s, const to_problem *prob, const double *h
   g.nel = (size_t)g.nelx * g.nely * g.nelz;
   g.nn = (size_t)(g.nelx + 1) * (g.nely + 1) * (g.nelz + 1);
   g.ndof = 3 * g.nn;
-  if (matvec_blocks(g, matvec_kz(g)) > MAXB)
+  if (matvec_blocks(g, matvec_kz(g, false)) > MAXB)
     return srv_fail(s, TO_E_INVALID, "grid too large for serving");
   if (carve_slot(g, nullptr, nullptr) > s->budget)
     return srv_fail(s, TO_E_OOM, "request footprint exceeds the server's HBM budget");
