@@ -15,14 +15,17 @@
 // per element instead of 576 multiply-adds for the dense 24 x 24 product; it
 // equals the Gauss-integrated k0 to rounding.
 //
-// Tiling.  A 256-thread block holds a 16 x 16 element tile of one z layer and
-// owns the 15 x 15 nodes interior to it; it marches up a range of node planes.
-// Per element layer L: node plane L+1 of the input (17 x 17 nodes) is staged
+// Tiling.  A 256-thread block holds a 32 x 8 element tile of one z layer and
+// owns the 31 x 7 nodes interior to it; it marches up a range of node planes.
+// Per element layer L: node plane L+1 of the input (33 x 9 nodes) is staged
 // in LDS next to plane L, every thread applies its element and writes its 24
 // outputs to LDS, then every owned node sums, in a fixed order, the
 // contributions of layer L-1 (kept in registers) and layer L.  No atomics: the
 // result is deterministic.  Each element is computed by one block only in z
-// and by up to four blocks in x/y (halo), 256/225 ~ 1.14x element work.
+// and by up to four blocks in x/y (halo), 256/217 ~ 1.18x element work.  The
+// tile is wide in x because the product is bound by its memory access pattern
+// more than by its arithmetic: rows of 33 nodes (396 bytes of a float32
+// vector) are fewer and longer segments per plane than rows of 17.
 #include <hip/hip_ext.h>
 
 #include <algorithm>
@@ -32,7 +35,7 @@
 
 namespace topo {
 
-// One block of the product: the 16 x 16 element tile (bx, by) marching over
+// One block of the product: the TEX x TEY element tile (bx, by) marching over
 // node planes [bz kz, bz kz + kz).  Returns the block's partial sum (CG:
 // p^T q, RESID: ||r||^2) in thread 0.
 //
@@ -88,7 +91,7 @@ __device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int b
   const unsigned voE = e_xy ? ((unsigned)gi + (unsigned)a.nelx * (unsigned)gj) * S : OOB;
   const unsigned voOwn = own ? 3u * S * nown : OOB;
 
-  // per lane, two slots of the 17 x 17 node plane; their buffer offsets
+  // per lane, two slots of the TPX x TPY node plane; their buffer offsets
   unsigned voN[2], voM[2], voP[2], voZ[2];  // voZ: the input vector (SZ bytes per component)
 #pragma unroll
   for (int sl = 0; sl < 2; ++sl) {
