@@ -307,25 +307,38 @@ __device__ double tri_dist2(const double *p, const double *a, const double *b, c
 
 constexpr int CB = 4;  // coarse cell edge (voxels) of the occupancy grid
 
-// occupancy of the CB^3 coarse cells: 1 when any voxel in it has triangles
+// occupancy of the CB^3 coarse cells as a bitmask: bit (c & 31) of word c / 32
+// is 1 when any voxel of cell c has triangles.  One lane per cell; the wave's
+// 64 bits (64-aligned cells) are written by lanes 0 and 1.
 __global__ void k_occ(int nelx, int nely, int nelz, const int *__restrict__ count,
-                      int *__restrict__ occ) {
+                      unsigned *__restrict__ occ) {
   const int cx = (nelx + CB - 1) / CB, cy = (nely + CB - 1) / CB, cz = (nelz + CB - 1) / CB;
   const size_t nc = (size_t)cx * cy * cz;
-  for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < nc;
-       c += (size_t)gridDim.x * blockDim.x) {
-    const int ci = (int)(c % cx), cj = (int)((c / cx) % cy), ck = (int)(c / ((size_t)cx * cy));
+  const int lane = threadIdx.x & 63;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t c0 = blockIdx.x * (size_t)blockDim.x + (threadIdx.x & ~63u); c0 < nc; c0 += stride) {
+    const size_t c = c0 + lane;
     int any = 0;
-    for (int k = ck * CB; k < min((ck + 1) * CB, nelz) && !any; ++k)
-      for (int j = cj * CB; j < min((cj + 1) * CB, nely) && !any; ++j)
-        for (int i = ci * CB; i < min((ci + 1) * CB, nelx); ++i)
-          if (count[(size_t)i + (size_t)nelx * ((size_t)j + (size_t)nely * k)]) {
-            any = 1;
-            break;
-          }
-    occ[c] = any;
+    if (c < nc) {
+      const int ci = (int)(c % cx), cj = (int)((c / cx) % cy), ck = (int)(c / ((size_t)cx * cy));
+      for (int k = ck * CB; k < min((ck + 1) * CB, nelz) && !any; ++k)
+        for (int j = cj * CB; j < min((cj + 1) * CB, nely) && !any; ++j)
+          for (int i = ci * CB; i < min((ci + 1) * CB, nelx); ++i)
+            if (count[(size_t)i + (size_t)nelx * ((size_t)j + (size_t)nely * k)]) {
+              any = 1;
+              break;
+            }
+    }
+    const unsigned long long m = __ballot(any);
+    const size_t w = c0 >> 5;
+    if (lane == 0) occ[w] = (unsigned)m;
+    if (lane == 1 && c0 + 32 < nc) occ[w + 1] = (unsigned)(m >> 32);
   }
 }
+
+// occupancy words held in LDS by the distance search (grids with more coarse
+// cells read them from memory)
+constexpr int OCC_LDS_WORDS = 4096;
 
 __device__ __forceinline__ int axis_gap(int lo, int hi, int i) {  // voxels [lo, hi) vs node i
   return max(0, max(lo - i, i - hi));
@@ -343,6 +356,16 @@ __device__ __forceinline__ void scan_voxel(int vi, int vj, int vk, int nelx, int
   for (int q = 0; q < c; ++q, t += 9) best = fmin(best, tri_dist2(p, t, t + 3, t + 6));
 }
 
+// whether the node (i, j, k) still needs voxel (vi, vj, vk) in phase 2: not
+// stopped, not one of its phase-1 voxels, and the voxel's box is nearer than
+// its best distance so far
+__device__ __forceinline__ bool need_voxel(int vi, int vj, int vk, int i, int j, int k, double h,
+                                           bool done, double best) {
+  const int vx = axis_gap(vi, vi + 1, i), vy = axis_gap(vj, vj + 1, j), vz = axis_gap(vk, vk + 1, k);
+  if (done || (vx <= 1 && vy <= 1 && vz <= 1)) return false;
+  return ((double)vx * vx + (double)vy * vy + (double)vz * vz) * h * h < best;
+}
+
 // Exact Eq. 29 distance per node.  Phase 1 scans the voxels at Chebyshev gap
 // 0 and 1 from the node (no point of a voxel at gap g is closer than g h, so
 // a best distance <= 2 h is final).  Phase 2 scans rings of coarse cells
@@ -350,84 +373,104 @@ __device__ __forceinline__ void scan_voxel(int vi, int vj, int vk, int nelx, int
 // is already farther than the best distance; after coarse ring R every
 // unvisited cell lies beyond a face of the scanned box that the grid does not
 // clip, so the distance to the nearest such face gives the stop rule.
-__global__ void k_udist(int nelx, int nely, int nelz, double h, const int *__restrict__ count,
-                        const int *__restrict__ offset, const double *__restrict__ tri,
-                        const int *__restrict__ occ, const double *__restrict__ rho, double rho_t,
-                        double *__restrict__ phi) {
+//
+// One 64-lane wave per CB^3 brick of nodes aligned with a coarse cell: the
+// lanes share the ring centre, so phase 2 walks the rings and cells in step
+// (a cell is entered when any unfinished lane may find a closer triangle in
+// it) and a cell's 64 voxel counts and offsets arrive in one wave-wide load,
+// one voxel per lane, read back voxel by voxel with readlane.  Each lane keeps
+// its own best distance, its own voxel pruning and its own stop rule; the
+// wave leaves the ring loop when every lane has stopped.
+__global__ __launch_bounds__(128) void k_udist(int nelx, int nely, int nelz, double h,
+                                               const int *__restrict__ count,
+                                               const int *__restrict__ offset,
+                                               const double *__restrict__ tri,
+                                               const unsigned *__restrict__ occ,
+                                               const double *__restrict__ rho, double rho_t,
+                                               double *__restrict__ phi) {
   const int NX = nelx + 1, NY = nely + 1, NZ = nelz + 1;
   const int cx = (nelx + CB - 1) / CB, cy = (nely + CB - 1) / CB, cz = (nelz + CB - 1) / CB;
   const int Rmax = max(cx, max(cy, cz));
-  // one 64-lane wave per CB^3 brick of nodes aligned with a coarse cell: the
-  // lanes share the ring centre and walk the same cells and voxels
+  // the occupancy bitmask, staged in LDS when it fits
+  __shared__ unsigned occ_lds[OCC_LDS_WORDS];
+  const size_t nwords = ((size_t)cx * cy * cz + 31) / 32;
+  const bool occ_in_lds = nwords <= (size_t)OCC_LDS_WORDS;
+  if (occ_in_lds) {
+    for (size_t w = threadIdx.x; w < nwords; w += blockDim.x) occ_lds[w] = occ[w];
+    __syncthreads();
+  }
   const int bx = (NX + CB - 1) / CB, by = (NY + CB - 1) / CB, bz = (NZ + CB - 1) / CB;
   const size_t nbr = (size_t)bx * by * bz;
   const int lane = threadIdx.x & 63;
   const int li = lane & 3, lj = (lane >> 2) & 3, lk = lane >> 4;
+  // b is the same for the 64 lanes of a wave
   for (size_t b = (blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 6; b < nbr;
        b += ((size_t)gridDim.x * blockDim.x) >> 6) {
-    const int i = (int)(b % bx) * CB + li, j = (int)((b / bx) % by) * CB + lj,
-              k = (int)(b / ((size_t)bx * by)) * CB + lk;
-    if (i >= NX || j >= NY || k >= NZ) continue;
-    const size_t n = (size_t)i + (size_t)NX * ((size_t)j + (size_t)NY * k);
+    const int ib = (int)(b % bx), jb = (int)((b / bx) % by), kb = (int)(b / ((size_t)bx * by));
+    const int i = ib * CB + li, j = jb * CB + lj, k = kb * CB + lk;
+    const bool valid = i < NX && j < NY && k < NZ;
     const double p[3] = {(double)i * h, (double)j * h, (double)k * h};
     double best = INFINITY;
-    // phase 1: voxels i-2 .. i+1 (gaps 0 and 1) per axis
-    for (int vk = max(k - 2, 0); vk <= min(k + 1, nelz - 1); ++vk)
-      for (int vj = max(j - 2, 0); vj <= min(j + 1, nely - 1); ++vj)
-        for (int vi = max(i - 2, 0); vi <= min(i + 1, nelx - 1); ++vi)
-          scan_voxel(vi, vj, vk, nelx, nely, count, offset, tri, p, best);
-    if (!(best <= 4.0 * h * h)) {
-      const int c0i = min(i / CB, cx - 1), c0j = min(j / CB, cy - 1), c0k = min(k / CB, cz - 1);
-      for (int R = 0; R <= Rmax; ++R) {
-        for (int ck = c0k - R; ck <= c0k + R; ++ck) {
-          if (ck < 0 || ck >= cz) continue;
-          const bool zs = (ck == c0k - R) || (ck == c0k + R);
-          const int gz = axis_gap(ck * CB, min((ck + 1) * CB, nelz), k);
-          for (int cj = c0j - R; cj <= c0j + R; ++cj) {
-            if (cj < 0 || cj >= cy) continue;
-            const bool ys = zs || (cj == c0j - R) || (cj == c0j + R);
-            const int gy = axis_gap(cj * CB, min((cj + 1) * CB, nely), j);
-            for (int ci = c0i - R; ci <= c0i + R; ++ci) {
-              if (!ys && ci != c0i - R && ci != c0i + R) {  // ring interior: far side only
-                ci = c0i + R - 1;
+    if (valid) {
+      // phase 1: voxels i-2 .. i+1 (gaps 0 and 1) per axis
+      for (int vk = max(k - 2, 0); vk <= min(k + 1, nelz - 1); ++vk)
+        for (int vj = max(j - 2, 0); vj <= min(j + 1, nely - 1); ++vj)
+          for (int vi = max(i - 2, 0); vi <= min(i + 1, nelx - 1); ++vi)
+            scan_voxel(vi, vj, vk, nelx, nely, count, offset, tri, p, best);
+    }
+    bool done = !valid || best <= 4.0 * h * h;
+    // the ring centre: the brick's own coarse cell (clamped for the nodes on
+    // the grid's far faces), the same for every lane
+    const int c0i = min(ib, cx - 1), c0j = min(jb, cy - 1), c0k = min(kb, cz - 1);
+    for (int R = 0; R <= Rmax && __ballot(!done) != 0; ++R) {
+      for (int ck = max(c0k - R, 0); ck <= min(c0k + R, cz - 1); ++ck) {
+        const bool zs = (ck == c0k - R) || (ck == c0k + R);
+        const int gz = axis_gap(ck * CB, min((ck + 1) * CB, nelz), k);
+        for (int cj = max(c0j - R, 0); cj <= min(c0j + R, cy - 1); ++cj) {
+          const bool ys = zs || (cj == c0j - R) || (cj == c0j + R);
+          const int gy = axis_gap(cj * CB, min((cj + 1) * CB, nely), j);
+          for (int ci = c0i - R; ci <= c0i + R; ci += (ys || ci == c0i + R) ? 1 : 2 * R) {
+            if (ci < 0 || ci >= cx) continue;  // ring interior: only its two x faces
+            const int gx = axis_gap(ci * CB, min((ci + 1) * CB, nelx), i);
+            const double cd = ((double)gx * gx + (double)gy * gy + (double)gz * gz) * h * h;
+            if (__ballot(!done && cd < best) == 0) continue;
+            const size_t cell = (size_t)ci + (size_t)cx * ((size_t)cj + (size_t)cy * ck);
+            const unsigned ow = occ_in_lds ? occ_lds[cell >> 5] : occ[cell >> 5];
+            if (!((ow >> (cell & 31)) & 1u)) continue;
+            // the cell's voxel counts and offsets, voxel (li, lj, lk) in lane
+            const int ui = ci * CB + li, uj = cj * CB + lj, uk = ck * CB + lk;
+            const bool uin = ui < nelx && uj < nely && uk < nelz;
+            const size_t ue = uin ? (size_t)ui + (size_t)nelx * ((size_t)uj + (size_t)nely * uk) : 0;
+            const int ucnt = uin ? count[ue] : 0;
+            const int uoff = uin ? offset[ue] : 0;
+            for (int v = 0; v < CB * CB * CB; ++v) {
+              const int c = __builtin_amdgcn_readlane(ucnt, v);
+              if (c == 0) continue;
+              if (!need_voxel(ci * CB + (v & 3), cj * CB + ((v >> 2) & 3), ck * CB + (v >> 4), i, j,
+                              k, h, done, best))
                 continue;
-              }
-              if (ci < 0 || ci >= cx) continue;
-              const int gx = axis_gap(ci * CB, min((ci + 1) * CB, nelx), i);
-              const double cd = ((double)gx * gx + (double)gy * gy + (double)gz * gz) * h * h;
-              if (cd >= best) continue;
-              if (!occ[(size_t)ci + (size_t)cx * ((size_t)cj + (size_t)cy * ck)]) continue;
-              for (int vk = ck * CB; vk < min((ck + 1) * CB, nelz); ++vk) {
-                const int vz = axis_gap(vk, vk + 1, k);
-                for (int vj = cj * CB; vj < min((cj + 1) * CB, nely); ++vj) {
-                  const int vy = axis_gap(vj, vj + 1, j);
-                  for (int vi = ci * CB; vi < min((ci + 1) * CB, nelx); ++vi) {
-                    const int vx = axis_gap(vi, vi + 1, i);
-                    if (vx <= 1 && vy <= 1 && vz <= 1) continue;  // done in phase 1
-                    const double vd = ((double)vx * vx + (double)vy * vy + (double)vz * vz) * h * h;
-                    if (vd >= best) continue;
-                    scan_voxel(vi, vj, vk, nelx, nely, count, offset, tri, p, best);
-                  }
-                }
-              }
+              const double *t = tri + 9 * (size_t)__builtin_amdgcn_readlane(uoff, v);
+              for (int q = 0; q < c; ++q, t += 9) best = fmin(best, tri_dist2(p, t, t + 3, t + 6));
             }
           }
         }
-        // unvisited voxels lie beyond a face of the scanned box that the grid
-        // does not clip; the nearest such face bounds their distance
-        int lim = INT_MAX;
-        if (c0i - R > 0) lim = min(lim, i - (c0i - R) * CB);
-        if (c0i + R < cx - 1) lim = min(lim, (c0i + R + 1) * CB - i);
-        if (c0j - R > 0) lim = min(lim, j - (c0j - R) * CB);
-        if (c0j + R < cy - 1) lim = min(lim, (c0j + R + 1) * CB - j);
-        if (c0k - R > 0) lim = min(lim, k - (c0k - R) * CB);
-        if (c0k + R < cz - 1) lim = min(lim, (c0k + R + 1) * CB - k);
-        if (lim == INT_MAX) break;  // the whole grid was scanned
-        if (best <= (double)lim * lim * h * h) break;
       }
+      // unvisited voxels lie beyond a face of the scanned box that the grid
+      // does not clip; the nearest such face bounds their distance
+      int lim = INT_MAX;
+      if (c0i - R > 0) lim = min(lim, i - (c0i - R) * CB);
+      if (c0i + R < cx - 1) lim = min(lim, (c0i + R + 1) * CB - i);
+      if (c0j - R > 0) lim = min(lim, j - (c0j - R) * CB);
+      if (c0j + R < cy - 1) lim = min(lim, (c0j + R + 1) * CB - j);
+      if (c0k - R > 0) lim = min(lim, k - (c0k - R) * CB);
+      if (c0k + R < cz - 1) lim = min(lim, (c0k + R + 1) * CB - k);
+      if (lim == INT_MAX || best <= (double)lim * lim * h * h) done = true;
     }
-    const double d = sqrt(best);
-    phi[n] = (rho[n] >= rho_t) ? -d : d;
+    if (valid) {
+      const size_t n = (size_t)i + (size_t)NX * ((size_t)j + (size_t)NY * k);
+      const double d = sqrt(best);
+      phi[n] = (rho[n] >= rho_t) ? -d : d;
+    }
   }
 }
 
@@ -437,13 +480,14 @@ hipError_t launch_udist(const Grid &g, double h, const int *count, const int *of
   const int cx = (g.nelx + CB - 1) / CB, cy = (g.nely + CB - 1) / CB, cz = (g.nelz + CB - 1) / CB;
   const size_t nc = (size_t)cx * cy * cz;
   hipLaunchKernelGGL(k_occ, dim3((unsigned)std::min<size_t>((nc + 255) / 256, 8192)), dim3(256), 0,
-                     s, g.nelx, g.nely, g.nelz, count, occ);
+                     s, g.nelx, g.nely, g.nelz, count, (unsigned *)occ);
   static_assert(CB * CB * CB == 64, "one wave per node brick");
   const size_t nbr = (size_t)((g.nelx + CB) / CB) * ((g.nely + CB) / CB) * ((g.nelz + CB) / CB);
-  int blocks = (int)((nbr + 1) / 2);
-  if (blocks > 65535) blocks = 65535;
+  // two bricks per block; at most 8192 blocks, so the occupancy staged per
+  // block is reused over several bricks on large grids
+  int blocks = (int)std::min<size_t>((nbr + 1) / 2, 8192);
   hipLaunchKernelGGL(k_udist, dim3(blocks), dim3(128), 0, s, g.nelx, g.nely, g.nelz, h, count,
-                     offset, tri, occ, rho, rho_t, phi);
+                     offset, tri, (const unsigned *)occ, rho, rho_t, phi);
   return hipGetLastError();
 }
 
