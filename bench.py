@@ -139,9 +139,10 @@ def probe(kind):
 KERNEL_SOURCES = ("k_matvec.hip", "device_common.h", "common.h")
 
 
-def measured_traffic(summary, section_kernel):
-    """HBM bytes per launch from a committed rocprofv3 counter summary, or
-    None when the kernel source changed since the counters were taken."""
+def measured_traffic(summary, section_kernel, title=None):
+    """HBM bytes per launch from a committed rocprofv3 counter summary (the
+    first section for the kernel whose title contains `title`), or None when
+    the kernel source changed since the counters were taken."""
     import hashlib
     try:
         text = open(os.path.join(ROOT, "profiles", summary)).read()
@@ -153,6 +154,8 @@ def measured_traffic(summary, section_kernel):
     sha = h.hexdigest()[:16]
     for sec in text.split("## ")[1:]:
         if ("kernel: " + section_kernel) not in sec:
+            continue
+        if title is not None and title not in sec.splitlines()[0]:
             continue
         fields = dict(l.split(": ", 1) for l in sec.splitlines() if ": " in l)
         if sha not in fields.get("source", ""):
@@ -745,12 +748,30 @@ def workload_large(A, inputs, dev):
     for name, prec in (("fp64", A.PREC_FP64), ("fp32_refine", A.PREC_FP32_REFINE),
                        ("fp32_refine_bf16", A.PREC_FP32_REFINE_BF16)):
         ctx = A.to_create(A.Problem(*dims, precision=prec, rtol=1e-8, max_iters=10 ** 6))
+        if prec == A.PREC_FP32_REFINE:
+            A.to_profile(ctx, True)
         u, c, dc, info, st, ms = _timed_solve(A, ctx, x)
         res[name] = (u.cpu().numpy(), c, dc.cpu().numpy())
         out[name] = {"ms": round(ms, 1), "status": A.L.STATUS_NAMES.get(st, st),
                      "inner_iters": info["inner_iters"], "outer_iters": info["outer_iters"],
                      "rel_res": info["rel_res"],
                      "cg_iters_per_s": round(info["inner_iters"] / (ms * 1e-3), 1)}
+        if prec == A.PREC_FP32_REFINE:
+            # the inner-CG product inside this solve: its roofline at a size
+            # whose working set does not fit in the caches
+            mv_ms, mv_n = A.to_profile(ctx, False)
+            mv_us = 1e3 * mv_ms / max(mv_n, 1)
+            nn = (dims[0] + 1) * (dims[1] + 1) * (dims[2] + 1)
+            byt = 48 * nn + 4 * dims[0] * dims[1] * dims[2]
+            ach = byt / (mv_us * 1e-6) / 1e9
+            out["roofline_cg_product"] = {
+                "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic("pmc_cg_matvec_f32_cantilever_96x48x48.txt",
+                                            "void topo::k_cg_matvec1<float, false>",
+                                            title="256x128x128"),
+                "kernel": "k_cg_matvec1<float, false>", "avg_us": round(mv_us, 3),
+                "launches_sampled": mv_n, "bytes_per_launch": byt}
         ctx.close()
         del u, dc
         torch.cuda.empty_cache()
