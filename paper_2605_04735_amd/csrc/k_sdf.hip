@@ -19,6 +19,7 @@
 //  vf         per voxel, the volume fraction of {phi_lin < 0} over the same
 //             six tets, in closed form from the edge crossing fractions
 #include <climits>
+#include <cstdlib>
 #include <algorithm>
 
 #include "common.h"
@@ -387,14 +388,14 @@ __global__ __launch_bounds__(128) void k_udist(int nelx, int nely, int nelz, dou
                                                const double *__restrict__ tri,
                                                const unsigned *__restrict__ occ,
                                                const double *__restrict__ rho, double rho_t,
-                                               double *__restrict__ phi) {
+                                               double *__restrict__ phi, int occ_lds_allowed) {
   const int NX = nelx + 1, NY = nely + 1, NZ = nelz + 1;
   const int cx = (nelx + CB - 1) / CB, cy = (nely + CB - 1) / CB, cz = (nelz + CB - 1) / CB;
   const int Rmax = max(cx, max(cy, cz));
   // the occupancy bitmask, staged in LDS when it fits
   __shared__ unsigned occ_lds[OCC_LDS_WORDS];
   const size_t nwords = ((size_t)cx * cy * cz + 31) / 32;
-  const bool occ_in_lds = nwords <= (size_t)OCC_LDS_WORDS;
+  const bool occ_in_lds = occ_lds_allowed && nwords <= (size_t)OCC_LDS_WORDS;
   if (occ_in_lds) {
     for (size_t w = threadIdx.x; w < nwords; w += blockDim.x) occ_lds[w] = occ[w];
     __syncthreads();
@@ -486,8 +487,12 @@ hipError_t launch_udist(const Grid &g, double h, const int *count, const int *of
   // two bricks per block; at most 8192 blocks, so the occupancy staged per
   // block is reused over several bricks on large grids
   int blocks = (int)std::min<size_t>((nbr + 1) / 2, 8192);
+  // TOPO_SDF_OCC_GLOBAL=1 reads the occupancy from memory at any size (the
+  // path of grids whose bitmask exceeds the LDS copy), for testing
+  const char *e = getenv("TOPO_SDF_OCC_GLOBAL");
+  const int occ_lds_allowed = (e && atoi(e) != 0) ? 0 : 1;
   hipLaunchKernelGGL(k_udist, dim3(blocks), dim3(128), 0, s, g.nelx, g.nely, g.nelz, h, count,
-                     offset, tri, (const unsigned *)occ, rho, rho_t, phi);
+                     offset, tri, (const unsigned *)occ, rho, rho_t, phi, occ_lds_allowed);
   return hipGetLastError();
 }
 

@@ -311,6 +311,27 @@ def test_density_to_sdf_vs_bruteforce(kind, dims, seed):
     assert np.max(np.abs(cpu(vf) - vf_r)) <= 1e-12
 
 
+def test_sdf_occupancy_from_memory_equals_lds(monkeypatch):
+    # the distance search reads the coarse occupancy from an LDS copy when it
+    # fits and from memory on larger grids; both give the same field
+    nelx, nely, nelz = 40, 36, 33
+    print("sdf occupancy paths", (nelx, nely, nelz), flush=True)
+    x = _sdf_case("ball", (nelx, nely, nelz), 0)
+    ctx = A.to_create(A.Problem(nelx, nely, nelz))
+    phi_lds = cpu(A.to_density_to_sdf(ctx, gpu(x), 0.5)[0])
+    monkeypatch.setenv("TOPO_SDF_OCC_GLOBAL", "1")
+    phi_mem = cpu(A.to_density_to_sdf(ctx, gpu(x), 0.5)[0])
+    monkeypatch.delenv("TOPO_SDF_OCC_GLOBAL")
+    assert np.array_equal(phi_lds, phi_mem)
+    x = _sdf_case("field", (17, 13, 11), 1)
+    ctx = A.to_create(A.Problem(17, 13, 11))
+    monkeypatch.setenv("TOPO_SDF_OCC_GLOBAL", "1")
+    phi = cpu(A.to_density_to_sdf(ctx, gpu(x), 0.5)[0])
+    monkeypatch.delenv("TOPO_SDF_OCC_GLOBAL")
+    phi_r = sdf.density_to_sdf(x, 17, 13, 11, 1.0, 0.5)[0]
+    assert np.max(np.abs(phi - phi_r)) <= 1e-12
+
+
 def test_sdf_planar_closed_form_and_empty_surface():
     nelx, nely, nelz = 20, 6, 5
     c = grid.element_centroids(nelx, nely, nelz, 1.0)
