@@ -424,19 +424,23 @@ __global__ __launch_bounds__(HB, 4) void k_hcg_apply(HcgArgs A) {
       const Off oy = {j > 0 ? -(ptrdiff_t)sy : 0, j < A.NY - 1 ? (ptrdiff_t)sy : 0};
       size_t n = (size_t)i + sy * ((size_t)j + (size_t)A.NY * k0);
       double m1 = 0.0, m2 = 0.0, c1, c2, n1 = 0.0, n2 = 0.0;
-      double va[9], vb[9];
+      double va[9], vb[9], vc[9];
       if (k0 > 0) {
         plane_load(A.p, n - sz, ox, oy, va);
         plane_sums(va, tx, ty, A.ell2, m1, m2);
       }
       plane_load(A.p, n, ox, oy, va);
       plane_sums(va, tx, ty, A.ell2, c1, c2);
-      // the neighbourhood of plane k + 1 is loaded one step ahead
+      // the neighbourhoods of planes k + 1 and k + 2 are loaded ahead
       if (k0 + 1 < A.NZ) plane_load(A.p, n + sz, ox, oy, vb);
+      if (k0 + 2 < A.NZ && k0 + 1 < k1) plane_load(A.p, n + 2 * sz, ox, oy, vc);
       for (int k = k0; k < k1; ++k, n += sz) {
         if (k + 1 < A.NZ) {
-          for (int q = 0; q < 9; ++q) va[q] = vb[q];
-          if (k + 2 < A.NZ && k + 1 < k1) plane_load(A.p, n + 2 * sz, ox, oy, vb);
+          for (int q = 0; q < 9; ++q) {
+            va[q] = vb[q];
+            vb[q] = vc[q];
+          }
+          if (k + 3 < A.NZ && k + 2 < k1) plane_load(A.p, n + 3 * sz, ox, oy, vc);
           plane_sums(va, tx, ty, A.ell2, n1, n2);
         } else {
           n1 = 0.0;
