@@ -137,6 +137,58 @@ def test_product_and_solve_256x128x128():
                                                                    info["rel_res"], c), flush=True)
 
 
+def test_bench_step_96x48x48():
+    """The benchmark's step at its full size and in its launch set-up
+    (cantilever 96 x 48 x 48, random field l = 6, kappa = 2, seed 1,
+    float32-inner / float64-refined solve), against the oracle on outputs it
+    can compute one by one: residual rows at sampled nodes; the compliance and
+    every sensitivity from the oracle's element energies of the returned u;
+    both filters over the whole grid; the nodal densities, the triangle count,
+    brute-force distances at sampled and at the farthest nodes, and the volume
+    fraction of the returned field."""
+    nelx, nely, nelz = 96, 48, 48
+    print("bench step", (nelx, nely, nelz), flush=True)
+    x = inputs.random_field(nelx, nely, nelz, seed=1, ell=6.0, kappa=2.0)
+    xg = gpu(x)
+    ctx = A.to_create(A.Problem(nelx, nely, nelz, precision=A.PREC_FP32_REFINE, rtol=1e-8))
+    u, info, st = A.to_solve(ctx, xg)
+    assert st == A.L.TO_OK and info["rel_res"] <= 1e-8
+    un = cpu(u)
+    E = fem.modulus(x, 1.0, 1e-9, 3.0)
+    K0 = element.k0(0.3, 1.0)
+    fixed, f = fem.problem_arrays(nelx, nely, nelz, A.BC_CANTILEVER)
+    NX, NY = nelx + 1, nely + 1
+    nn = NX * NY * (nelz + 1)
+    rng = np.random.default_rng(11)
+    picks = [0, NX - 1, NX * NY - 1, nn - 1, 31 + NX * 7, 62 + NX * (14 + NY * 30)]
+    picks += list(rng.choice(nn, 200, replace=False))
+    r = f.reshape(-1, 3)[picks] - fem.apply_rows(nelx, nely, nelz, E, K0, un, fixed, picks)
+    r[fixed.reshape(-1, 3)[picks]] = 0.0
+    assert np.max(np.abs(r)) <= 1e-8 * np.linalg.norm(f)
+    c, dc = A.to_compliance_sensitivity(ctx, xg, u)
+    assert abs(c - fem.compliance(f, un)) <= 1e-12 * abs(c)
+    dref = fem.sensitivity(x, fem.element_energy(nelx, nely, nelz, K0, un), 1.0, 1e-9, 3.0)
+    dcn = cpu(dc)
+    assert np.max(np.abs(dcn - dref)) <= 1e-12 * np.abs(dref).max()
+    xf = cpu(A.to_filter(ctx, 1.5, A.FILTER_DENS, xg))
+    assert np.array_equal(xf, filters.density_filter(x, nelx, nely, nelz, 1.5))
+    dcf = cpu(A.to_filter(ctx, 2.0, A.FILTER_SENS, dc, x=xg))
+    assert np.array_equal(dcf, filters.sensitivity_filter(x, dcn, nelx, nely, nelz, 2.0))
+    phi, rho, vf = A.to_density_to_sdf(ctx, xg, 0.5)
+    phin, rhon, vfn = cpu(phi), cpu(rho), cpu(vf)
+    rho_r = sdf.nodal_density_mean(x, nelx, nely, nelz)
+    assert np.array_equal(rhon, rho_r)
+    T, _, _ = sdf.marching_tets(rho_r, nelx, nely, nelz, 1.0, 0.5)
+    assert A.last_triangle_count(ctx) == len(T)
+    npk = np.concatenate([rng.choice(nn, 30, replace=False), np.argsort(-np.abs(phin))[:10]])
+    pts = grid.node_coords(nelx, nely, nelz, 1.0)[npk]
+    phi_r = sdf.signed_distance(sdf.unsigned_distance_vec(pts, T), rho_r[npk], 0.5)
+    assert np.max(np.abs(phin[npk] - phi_r)) <= 1e-12
+    assert np.max(np.abs(vfn - sdf.volume_fraction(phin, nelx, nely, nelz, 1.0))) <= 1e-12
+    print("bench step: %d inner iterations, c %.9e, %d triangles, max |phi| %.3f"
+          % (info["inner_iters"], c, len(T), np.abs(phin).max()), flush=True)
+
+
 # ------------------------------------------------------------------ solves
 def _oracle_solution(nelx, nely, nelz, x, prob):
     K, K0, E = oracle_K(nelx, nely, nelz, x, prob)
