@@ -189,6 +189,53 @@ def test_bench_step_96x48x48():
           % (info["inner_iters"], c, len(T), np.abs(phin).max()), flush=True)
 
 
+def test_mbb_ersatz_pipeline_192x64x32():
+    """The MBB workload at its full size (192 x 64 x 32, SIMP-like field
+    l = 6, kappa = 8, seed 2, 40% solid): density -> SDF -> per-element volume
+    fraction -> ersatz moduli max(vf, 1e-3) (penal 1, Emin 0) -> the
+    float32-inner / float64-refined solve, against the oracle on outputs it
+    can compute one by one."""
+    nelx, nely, nelz = 192, 64, 32
+    print("mbb pipeline", (nelx, nely, nelz), flush=True)
+    x = inputs.random_field(nelx, nely, nelz, seed=2, ell=6.0, kappa=8.0, solid_fraction=0.4)
+    geo = A.to_create(A.Problem(nelx, nely, nelz, bc=A.BC_MBB))
+    phi, rho, vf = A.to_density_to_sdf(geo, gpu(x), 0.5)
+    phin, vfn = cpu(phi), cpu(vf)
+    rho_r = sdf.nodal_density_mean(x, nelx, nely, nelz)
+    assert np.array_equal(cpu(rho), rho_r)
+    T, _, _ = sdf.marching_tets(rho_r, nelx, nely, nelz, 1.0, 0.5)
+    assert A.last_triangle_count(geo) == len(T)
+    NX, NY = nelx + 1, nely + 1
+    nn = NX * NY * (nelz + 1)
+    rng = np.random.default_rng(12)
+    npk = np.concatenate([rng.choice(nn, 30, replace=False), np.argsort(-np.abs(phin))[:10]])
+    pts = grid.node_coords(nelx, nely, nelz, 1.0)[npk]
+    phi_r = sdf.signed_distance(sdf.unsigned_distance_vec(pts, T), rho_r[npk], 0.5)
+    assert np.max(np.abs(phin[npk] - phi_r)) <= 1e-12
+    assert np.max(np.abs(vfn - sdf.volume_fraction(phin, nelx, nely, nelz, 1.0))) <= 1e-12
+    xe = np.maximum(vfn, 1e-3)
+    ctx = A.to_create(A.Problem(nelx, nely, nelz, bc=A.BC_MBB, penal=1.0, Emin=0.0,
+                                precision=A.PREC_FP32_REFINE, rtol=1e-8, max_iters=10 ** 6))
+    xg = gpu(xe)
+    u, info, st = A.to_solve(ctx, xg)
+    assert st == A.L.TO_OK and info["rel_res"] <= 1e-8
+    un = cpu(u)
+    E = fem.modulus(xe, 1.0, 0.0, 1.0)
+    K0 = element.k0(0.3, 1.0)
+    fixed, f = fem.problem_arrays(nelx, nely, nelz, A.BC_MBB)
+    picks = [0, NX - 1, NX * NY - 1, nn - 1, 31 + NX * 7, 96 + NX * (32 + NY * 16)]
+    picks += list(rng.choice(nn, 200, replace=False))
+    r = f.reshape(-1, 3)[picks] - fem.apply_rows(nelx, nely, nelz, E, K0, un, fixed, picks)
+    r[fixed.reshape(-1, 3)[picks]] = 0.0
+    assert np.max(np.abs(r)) <= 1e-8 * np.linalg.norm(f)
+    c, dc = A.to_compliance_sensitivity(ctx, xg, u)
+    assert abs(c - fem.compliance(f, un)) <= 1e-12 * abs(c)
+    dref = fem.sensitivity(xe, fem.element_energy(nelx, nely, nelz, K0, un), 1.0, 0.0, 1.0)
+    assert np.max(np.abs(cpu(dc) - dref)) <= 1e-12 * np.abs(dref).max()
+    print("mbb pipeline: %d triangles, %d inner iterations, c %.9e"
+          % (len(T), info["inner_iters"], c), flush=True)
+
+
 # ------------------------------------------------------------------ solves
 def _oracle_solution(nelx, nely, nelz, x, prob):
     K, K0, E = oracle_K(nelx, nely, nelz, x, prob)

@@ -66,6 +66,30 @@ def test_alone_equals_mixed_and_single_design_path():
         assert np.max(np.abs(dc.cpu().numpy() - m["dc"])) <= 1e-12 * np.abs(m["dc"]).max()
 
 
+def test_serving_grid_sizes_equal_single_design_path():
+    """One request of each grid size of the benchmark's request stream
+    (32 x 16 x 16 up to 128 x 64 x 64, cantilever and MBB alternating),
+    served together: each result equals the single-design C-ABI path."""
+    reqs = []
+    for k, dims in enumerate([(32, 16, 16), (64, 32, 32), (96, 48, 48), (128, 64, 64)]):
+        bc = A.BC_CANTILEVER if k % 2 == 0 else A.BC_MBB
+        x = inputs.random_field(*dims, seed=1000 + k, ell=min(6.0, dims[2] / 4), kappa=2.0)
+        reqs.append((k, A.Problem(*dims, bc=bc, precision=A.PREC_FP32_REFINE, rtol=1e-6), x))
+    print("serving grid sizes", flush=True)
+    served = _serve(reqs)
+    for k, prob, x in reqs:
+        m = served[k]
+        assert m["status"] == A.L.TO_OK
+        ctx = A.to_create(prob)
+        xg = torch.from_numpy(x).cuda()
+        u, info, _ = A.to_solve(ctx, xg)
+        c, dc = A.to_compliance_sensitivity(ctx, xg, u)
+        assert abs(c - m["c"]) <= 1e-12 * abs(c)
+        assert np.max(np.abs(dc.cpu().numpy() - m["dc"])) <= 1e-12 * np.abs(m["dc"]).max()
+        print("tag", k, (prob.nelx, prob.nely, prob.nelz), "identical:",
+              c == m["c"] and np.array_equal(dc.cpu().numpy(), m["dc"]), flush=True)
+
+
 def test_served_results_match_oracle():
     k, prob, x = _requests()[1]
     r = _serve([(k, prob, x)])[k]
