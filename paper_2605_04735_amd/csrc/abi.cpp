@@ -679,7 +679,8 @@ to_status to_density_to_sdf(to_ctx *c, const double *d_x, double rho_t, double *
       c->tri_cap = cap;
     }
     HIPCHK(launch_mt_emit(g, rho, rho_t, c->p.h, c->toff, c->cnt, c->tri, c->stream));
-    // the coarse occupancy grid reuses the filter scratch (nel doubles >= nel/64 ints)
+    // the coarse occupancy bitmask reuses the filter scratch (nel doubles, far more than
+    // the nel/2048 words it needs)
     HIPCHK(launch_udist(g, c->p.h, c->cnt, c->toff, c->tri, (int *)c->ftmp, rho, rho_t, d_phi,
                         c->stream));
   } else {

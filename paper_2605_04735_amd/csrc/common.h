@@ -283,7 +283,8 @@ hipError_t launch_mt_count(const Grid &g, const double *rho, double rho_t, int *
 hipError_t launch_scan(const int *in, int *out, size_t n, int *block_sums, hipStream_t s);
 hipError_t launch_mt_emit(const Grid &g, const double *rho, double rho_t, double h,
                           const int *offset, const int *count, double *tri, hipStream_t s);
-// occ: scratch of ceil(nelx/4) ceil(nely/4) ceil(nelz/4) ints
+// occ: scratch for the coarse occupancy bitmask, one bit per cell of
+// ceil(nelx/4) ceil(nely/4) ceil(nelz/4) (at least ceil(cells / 32) ints)
 hipError_t launch_udist(const Grid &g, double h, const int *count, const int *offset,
                         const double *tri, int *occ, const double *rho, double rho_t, double *phi,
                         hipStream_t s);
