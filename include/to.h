@@ -112,7 +112,11 @@ typedef struct {
 } to_solve_info;
 
 /* Device workspace (bytes) a context for this problem needs.  Lets the caller
- * allocate it (e.g. as a torch uint8 tensor) and admit work by footprint. */
+ * allocate it (e.g. as a torch uint8 tensor) and admit work by footprint.
+ * Grid limits (TO_E_INVALID beyond them, here and in to_create): a float64
+ * vector of 3 nn values below 2^31 bytes (nn < 89,478,486 nodes), and at most
+ * 8192 product tiles of 31 x 7 nodes in x and y,
+ * ceil((nelx + 1) / 31) * ceil((nely + 1) / 7) <= 8192. */
 to_status to_workspace_size(const to_problem *prob, size_t *bytes);
 
 /* Create a context.  d_workspace: caller-owned device memory of at least

@@ -119,7 +119,16 @@ bool validate_problem(const to_problem *p, std::string *why) {
   if (!p) { *why = "problem is NULL"; return false; }
   if (p->nelx < 1 || p->nely < 1 || p->nelz < 1) { *why = "grid sizes must be >= 1"; return false; }
   const double nn = double(p->nelx + 1) * (p->nely + 1) * (p->nelz + 1);
-  if (nn * 3 > 2.0e9) { *why = "grid too large"; return false; }
+  // kernels address a vector with 32-bit byte offsets (2^31 marks a lane
+  // outside the grid), so a float64 vector of 3 nn values stays below 2^31 bytes
+  if (nn * 24.0 >= 2147483648.0) {
+    *why = "grid too large (a float64 vector must stay below 2^31 bytes)";
+    return false;
+  }
+  // the product keeps one partial sum per block: its x-y tiles must fit
+  const double tiles =
+      std::ceil((p->nelx + 1) / double(TNX)) * std::ceil((p->nely + 1) / double(TNY));
+  if (tiles > MAXB) { *why = "grid too wide in x and y for the product's block bound"; return false; }
   if (!(p->h > 0) || !std::isfinite(p->h)) { *why = "h must be > 0"; return false; }
   if (!(p->E0 > 0) || !std::isfinite(p->E0)) { *why = "E0 must be > 0"; return false; }
   if (!(p->Emin >= 0) || !(p->Emin < p->E0)) { *why = "need 0 <= Emin < E0"; return false; }

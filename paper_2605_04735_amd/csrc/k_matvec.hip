@@ -554,7 +554,7 @@ int matvec_kz(const Grid &g, bool fp64) {
   if (const char *e = getenv("TOPO_KZ")) {
     int v = atoi(e);
     if (v >= 1) {
-      while (tiles * ((NZ + v - 1) / v) > MAXB) ++v;
+      while (v < NZ && tiles * ((NZ + v - 1) / v) > MAXB) ++v;
       return v;
     }
   }
@@ -569,7 +569,9 @@ int matvec_kz(const Grid &g, bool fp64) {
   int kz = kz_for_target(NZ, tiles, 2048);
   if (!fp64 && kz < 3 && tiles * ((NZ + 2) / 3) >= 640) kz = 3;
   if (fp64) kz = std::max(kz, std::min(kz_for_target(NZ, tiles, 512), 12));
-  while (tiles * ((NZ + kz - 1) / kz) > MAXB) ++kz;  // partial sums must fit
+  // partial sums must fit (a grid whose tiles alone exceed the bound is
+  // rejected before this is reached)
+  while (kz < NZ && tiles * ((NZ + kz - 1) / kz) > MAXB) ++kz;
   return kz;
 }
 

@@ -48,6 +48,15 @@ def test_workspace_size_validates_problem():
         assert e.value.status == L.TO_E_INVALID
     with pytest.raises(A.TopoError):
         A.to_workspace_size(A.Problem(4, 3, 2, bc=A.BC_CUSTOM))
+    # limits: float64 vectors below 2^31 bytes, the product's x-y tiles within
+    # its block bound; both rejected before any device work
+    for dims in [(500, 500, 400), (2000, 2000, 1)]:
+        with pytest.raises(A.TopoError) as e:
+            A.to_workspace_size(A.Problem(*dims))
+        assert e.value.status == L.TO_E_INVALID
+    # the largest accepted grids size normally
+    assert A.to_workspace_size(A.Problem(440, 440, 440)) > 0
+    assert A.to_workspace_size(A.Problem(1200, 1200, 2)) > 0
 
 
 STRUCTS = [(L.ToProblem, "to_problem"), (L.ToSolveInfo, "to_solve_info"),
