@@ -150,10 +150,6 @@ def test_bench_step_96x48x48():
     print("bench step", (nelx, nely, nelz), flush=True)
     x = inputs.random_field(nelx, nely, nelz, seed=1, ell=6.0, kappa=2.0)
     xg = gpu(x)
-    ctx = A.to_create(A.Problem(nelx, nely, nelz, precision=A.PREC_FP32_REFINE, rtol=1e-8))
-    u, info, st = A.to_solve(ctx, xg)
-    assert st == A.L.TO_OK and info["rel_res"] <= 1e-8
-    un = cpu(u)
     E = fem.modulus(x, 1.0, 1e-9, 3.0)
     K0 = element.k0(0.3, 1.0)
     fixed, f = fem.problem_arrays(nelx, nely, nelz, A.BC_CANTILEVER)
@@ -162,14 +158,20 @@ def test_bench_step_96x48x48():
     rng = np.random.default_rng(11)
     picks = [0, NX - 1, NX * NY - 1, nn - 1, 31 + NX * 7, 62 + NX * (14 + NY * 30)]
     picks += list(rng.choice(nn, 200, replace=False))
-    r = f.reshape(-1, 3)[picks] - fem.apply_rows(nelx, nely, nelz, E, K0, un, fixed, picks)
-    r[fixed.reshape(-1, 3)[picks]] = 0.0
-    assert np.max(np.abs(r)) <= 1e-8 * np.linalg.norm(f)
-    c, dc = A.to_compliance_sensitivity(ctx, xg, u)
-    assert abs(c - fem.compliance(f, un)) <= 1e-12 * abs(c)
-    dref = fem.sensitivity(x, fem.element_energy(nelx, nely, nelz, K0, un), 1.0, 1e-9, 3.0)
-    dcn = cpu(dc)
-    assert np.max(np.abs(dcn - dref)) <= 1e-12 * np.abs(dref).max()
+    # the float64 path (its own z chunks) first, then the benchmark's path
+    for prec in (A.PREC_FP64, A.PREC_FP32_REFINE):
+        ctx = A.to_create(A.Problem(nelx, nely, nelz, precision=prec, rtol=1e-8))
+        u, info, st = A.to_solve(ctx, xg)
+        assert st == A.L.TO_OK and info["rel_res"] <= 1e-8
+        un = cpu(u)
+        r = f.reshape(-1, 3)[picks] - fem.apply_rows(nelx, nely, nelz, E, K0, un, fixed, picks)
+        r[fixed.reshape(-1, 3)[picks]] = 0.0
+        assert np.max(np.abs(r)) <= 1e-8 * np.linalg.norm(f)
+        c, dc = A.to_compliance_sensitivity(ctx, xg, u)
+        assert abs(c - fem.compliance(f, un)) <= 1e-12 * abs(c)
+        dref = fem.sensitivity(x, fem.element_energy(nelx, nely, nelz, K0, un), 1.0, 1e-9, 3.0)
+        dcn = cpu(dc)
+        assert np.max(np.abs(dcn - dref)) <= 1e-12 * np.abs(dref).max()
     xf = cpu(A.to_filter(ctx, 1.5, A.FILTER_DENS, xg))
     assert np.array_equal(xf, filters.density_filter(x, nelx, nely, nelz, 1.5))
     dcf = cpu(A.to_filter(ctx, 2.0, A.FILTER_SENS, dc, x=xg))
@@ -214,24 +216,25 @@ def test_mbb_ersatz_pipeline_192x64x32():
     assert np.max(np.abs(phin[npk] - phi_r)) <= 1e-12
     assert np.max(np.abs(vfn - sdf.volume_fraction(phin, nelx, nely, nelz, 1.0))) <= 1e-12
     xe = np.maximum(vfn, 1e-3)
-    ctx = A.to_create(A.Problem(nelx, nely, nelz, bc=A.BC_MBB, penal=1.0, Emin=0.0,
-                                precision=A.PREC_FP32_REFINE, rtol=1e-8, max_iters=10 ** 6))
     xg = gpu(xe)
-    u, info, st = A.to_solve(ctx, xg)
-    assert st == A.L.TO_OK and info["rel_res"] <= 1e-8
-    un = cpu(u)
     E = fem.modulus(xe, 1.0, 0.0, 1.0)
     K0 = element.k0(0.3, 1.0)
     fixed, f = fem.problem_arrays(nelx, nely, nelz, A.BC_MBB)
     picks = [0, NX - 1, NX * NY - 1, nn - 1, 31 + NX * 7, 96 + NX * (32 + NY * 16)]
     picks += list(rng.choice(nn, 200, replace=False))
-    r = f.reshape(-1, 3)[picks] - fem.apply_rows(nelx, nely, nelz, E, K0, un, fixed, picks)
-    r[fixed.reshape(-1, 3)[picks]] = 0.0
-    assert np.max(np.abs(r)) <= 1e-8 * np.linalg.norm(f)
-    c, dc = A.to_compliance_sensitivity(ctx, xg, u)
-    assert abs(c - fem.compliance(f, un)) <= 1e-12 * abs(c)
-    dref = fem.sensitivity(xe, fem.element_energy(nelx, nely, nelz, K0, un), 1.0, 0.0, 1.0)
-    assert np.max(np.abs(cpu(dc) - dref)) <= 1e-12 * np.abs(dref).max()
+    for prec in (A.PREC_FP64, A.PREC_FP32_REFINE):
+        ctx = A.to_create(A.Problem(nelx, nely, nelz, bc=A.BC_MBB, penal=1.0, Emin=0.0,
+                                    precision=prec, rtol=1e-8, max_iters=10 ** 6))
+        u, info, st = A.to_solve(ctx, xg)
+        assert st == A.L.TO_OK and info["rel_res"] <= 1e-8
+        un = cpu(u)
+        r = f.reshape(-1, 3)[picks] - fem.apply_rows(nelx, nely, nelz, E, K0, un, fixed, picks)
+        r[fixed.reshape(-1, 3)[picks]] = 0.0
+        assert np.max(np.abs(r)) <= 1e-8 * np.linalg.norm(f)
+        c, dc = A.to_compliance_sensitivity(ctx, xg, u)
+        assert abs(c - fem.compliance(f, un)) <= 1e-12 * abs(c)
+        dref = fem.sensitivity(xe, fem.element_energy(nelx, nely, nelz, K0, un), 1.0, 0.0, 1.0)
+        assert np.max(np.abs(cpu(dc) - dref)) <= 1e-12 * np.abs(dref).max()
     print("mbb pipeline: %d triangles, %d inner iterations, c %.9e"
           % (len(T), info["inner_iters"], c), flush=True)
 
