@@ -155,6 +155,35 @@ __host__ __device__ inline int xcd_local(int b, int nb) {
   return x * base + (x < extra ? x : extra) + slot;
 }
 
+// Large product launches place their blocks in bands: XCD x (blocks b with
+// b % 8 == x) takes a contiguous band of the x-y tiles of every z chunk,
+// chunks in order, so all XCDs work in the same z slab at a time while
+// neighbouring tiles still share an L2 (2-4% faster than one contiguous range
+// of blocks per XCD at 256 x 128 x 128).  band_local returns the local block
+// chunk * tiles + tile, or -1 for the padding blocks of the last, partial
+// band; band_grid is the launch size.  Smaller launches keep xcd_local: there
+// the padding costs more than the placement gains (6% per FP32 CG iteration
+// at 96 x 48 x 48, and an FP64 grid beyond one round of resident blocks).
+__host__ __device__ inline int band_local(int b, int tiles, int nchunks) {
+  const int band = (tiles + NXCD - 1) / NXCD;
+  const int x = b % NXCD, sl = b / NXCD;
+  const int chunk = sl / band, tile = x * band + sl % band;
+  return (tile < tiles && chunk < nchunks) ? chunk * tiles + tile : -1;
+}
+__host__ __device__ inline int band_grid(int tiles, int nchunks) {
+  return NXCD * ((tiles + NXCD - 1) / NXCD) * nchunks;
+}
+constexpr int BAND_MIN_BLOCKS = 1536;
+// the product's local block of launch block b (or -1), and its launch size
+__host__ __device__ inline int mv_local(int b, int tiles, int nchunks) {
+  const int nb = tiles * nchunks;
+  return nb >= BAND_MIN_BLOCKS ? band_local(b, tiles, nchunks) : xcd_local(b, nb);
+}
+__host__ __device__ inline int mv_grid(int tiles, int nchunks) {
+  const int nb = tiles * nchunks;
+  return nb >= BAND_MIN_BLOCKS ? band_grid(tiles, nchunks) : nb;
+}
+
 struct Grid {
   int nelx, nely, nelz;
   size_t nel, nn, ndof;

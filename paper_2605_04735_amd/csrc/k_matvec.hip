@@ -281,7 +281,9 @@ void k_matvec(const MvArgs<T> a, int tx, int ty) {
   __shared__ T pl[2][3][TPX * TPY];
   __shared__ T ex[3][MV_THREADS];
   __shared__ double red[MV_THREADS / 64];
-  const int lb = xcd_local(blockIdx.x, gridDim.x);
+  const int NZ = a.nelz + 1, tz = (NZ + a.kz - 1) / a.kz;
+  const int lb = mv_local((int)blockIdx.x, tx * ty, tz);
+  if (lb < 0) return;  // padding of the last band
   const double s = matvec_block<T, MODE>(
       a, lb % tx, (lb / tx) % ty, lb / (tx * ty), [] {}, [](T &b) { b = T(0); return true; }, pl,
       ex, red);
@@ -342,8 +344,9 @@ __device__ __forceinline__ void cg_matvec_block(const CgDesc<T> &d, double *scal
   a.mask = d.mask;
   a.k = d.k;
   const int tx = d.tx, ty = d.ty;
-  // local block: from the table (batched), or this block's XCD-contiguous tile
-  const int lb = lb_in >= 0 ? lb_in : xcd_local((int)blockIdx.x, d.nb_mv);
+  // local block: from the table (batched), or this block's place (mv_local)
+  const int lb = lb_in >= 0 ? lb_in : mv_local((int)blockIdx.x, tx * ty, d.nb_mv / (tx * ty));
+  if (lb < 0) return;  // padding of the last band: nothing loaded is used
   asm volatile("" ::"s"(a.nelx), "s"(a.nely), "s"(a.nelz), "s"(a.kz), "s"(tx), "s"(ty), "s"(a.E),
                "s"(a.in), "s"(p0), "s"(p1), "s"(a.out), "s"(a.k.L2), "s"(a.k.M4), "s"(a.k.M2),
                "s"(a.k.L2_3), "s"(a.k.M2_3), "s"(a.k.B9));
@@ -587,7 +590,8 @@ hipError_t launch_matvec(const MvArgs<T> &a, int *nblocks, hipStream_t s) {
   const int nb = tx * ty * tz;
   if (nblocks) *nblocks = nb;
   if (MODE != MV_APPLY && nb > MAXB) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((k_matvec<T, MODE>), dim3(nb), dim3(MV_THREADS), 0, s, a, tx, ty);
+  hipLaunchKernelGGL((k_matvec<T, MODE>), dim3(mv_grid(tx * ty, tz)), dim3(MV_THREADS), 0, s, a,
+                     tx, ty);
   return hipGetLastError();
 }
 
@@ -618,19 +622,19 @@ hipError_t launch_cg_matvec1(const CgDesc<T> &d, int parity, hipStream_t s, hipE
   if constexpr (sizeof(T) == 4) {
     if (d.zbf16) {
       if (start && stop)
-        hipExtLaunchKernelGGL((k_cg_matvec1<T, true>), dim3(d.nb_mv), dim3(MV_THREADS), 0, s, start,
+        hipExtLaunchKernelGGL((k_cg_matvec1<T, true>), dim3(mv_grid(d.tx * d.ty, d.nb_mv / (d.tx * d.ty))), dim3(MV_THREADS), 0, s, start,
                               stop, 0, d.scal, d.flags, d.cgp, parity, d.nb_up, d);
       else
-        hipLaunchKernelGGL((k_cg_matvec1<T, true>), dim3(d.nb_mv), dim3(MV_THREADS), 0, s, d.scal,
+        hipLaunchKernelGGL((k_cg_matvec1<T, true>), dim3(mv_grid(d.tx * d.ty, d.nb_mv / (d.tx * d.ty))), dim3(MV_THREADS), 0, s, d.scal,
                            d.flags, d.cgp, parity, d.nb_up, d);
       return hipGetLastError();
     }
   }
   if (start && stop)
-    hipExtLaunchKernelGGL((k_cg_matvec1<T, false>), dim3(d.nb_mv), dim3(MV_THREADS), 0, s, start,
+    hipExtLaunchKernelGGL((k_cg_matvec1<T, false>), dim3(mv_grid(d.tx * d.ty, d.nb_mv / (d.tx * d.ty))), dim3(MV_THREADS), 0, s, start,
                           stop, 0, d.scal, d.flags, d.cgp, parity, d.nb_up, d);
   else
-    hipLaunchKernelGGL((k_cg_matvec1<T, false>), dim3(d.nb_mv), dim3(MV_THREADS), 0, s, d.scal,
+    hipLaunchKernelGGL((k_cg_matvec1<T, false>), dim3(mv_grid(d.tx * d.ty, d.nb_mv / (d.tx * d.ty))), dim3(MV_THREADS), 0, s, d.scal,
                        d.flags, d.cgp, parity, d.nb_up, d);
   return hipGetLastError();
 }
@@ -676,7 +680,7 @@ hipError_t build_cg_graph(const CgDesc<T> &d, int parity0, int iters, hipGraphEx
     void *args[] = {&scal, &flags, &cgp, &parity, &nparts, &dd};
     hipKernelNodeParams kp{};
     kp.func = mv ? fmv : fup;
-    kp.gridDim = dim3(mv ? d.nb_mv : d.nb_up);
+    kp.gridDim = dim3(mv ? mv_grid(d.tx * d.ty, d.nb_mv / (d.tx * d.ty)) : d.nb_up);
     kp.blockDim = dim3(mv ? MV_THREADS : 256);
     kp.sharedMemBytes = 0;
     kp.kernelParams = args;
