@@ -43,6 +43,11 @@ CAL_SAFETY = 1e-2         # and use a tolerance two decades below the calibrated
 RTOL_FLOOR = 1e-8         # but not below 1e-8: float64 itself cannot resolve residuals much
                           # below ~1e-9 of designs whose stiff parts float in near-void
 HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per node of one float32 inner-CG iteration (large-grid
+# limit): the product reads r, the Jacobi diagonal, p_old, x and E and writes
+# p, q and x; the update reads r, q, the diagonal and the mask and writes r
+CG_PRODUCT_BYTES_F32 = 48
+CG_UPDATE_BYTES_F32 = 89
 
 
 def log(*a):
@@ -66,11 +71,18 @@ def parse():
     ap.add_argument("--no-paper", action="store_true",
                     help="skip the SIMP stage on the paper's own two problems")
     ap.add_argument("--requests", type=int, default=128)
+    ap.add_argument("--no-config0", action="store_true", help="skip the 24x12x6 latency line")
     ap.add_argument("--probe", choices=["copy", "cg", "cg3", "product", "levelset", "shape"],
                     default=None,
                     help="short runs for hardware-counter passes: a device copy of known size, "
                          "one workload solve, products on 256x128x128, or level-set steps on "
                          "its node grid")
+    ap.add_argument("--profile-commands", metavar="DIR", default=None,
+                    help="print the rocprofv3 commands whose CSV output (under DIR) "
+                         "--summarize reduces, one per line, and exit")
+    ap.add_argument("--summarize", metavar="DIR", default=None,
+                    help="reduce the rocprofv3 CSV output under DIR to the summaries in "
+                         "profiles/ and exit (no GPU needed)")
     return ap.parse_args()
 
 
@@ -134,30 +146,18 @@ def probe(kind):
     log("product probe done")
 
 
-# the product kernels' sources: counters taken before a change to any of them
-# no longer describe the built kernel
-KERNEL_SOURCES = ("k_matvec.hip", "device_common.h", "common.h")
-
-
-def measured_traffic(summary, section_kernel, title=None):
-    """HBM bytes per launch from a committed rocprofv3 counter summary (the
-    first section for the kernel whose title contains `title`), or None when
-    the kernel source changed since the counters were taken."""
-    import hashlib
+def measured_traffic(summary, kernel):
+    """HBM bytes per launch of `kernel` from a committed counter summary, or
+    None when the product's sources changed since the counters were taken."""
     try:
         text = open(os.path.join(ROOT, "profiles", summary)).read()
     except OSError:
         return None
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, "paper_2605_04735_amd", "csrc", f), "rb").read())
-    sha = h.hexdigest()[:16]
+    sha = _source_sha(PRODUCT_SOURCES)
     for sec in text.split("## ")[1:]:
-        if ("kernel: " + section_kernel) not in sec:
-            continue
-        if title is not None and title not in sec.splitlines()[0]:
-            continue
         fields = dict(l.split(": ", 1) for l in sec.splitlines() if ": " in l)
+        if fields.get("kernel", "").strip() != kernel or "traffic_bytes_per_launch" not in fields:
+            continue
         if sha not in fields.get("source", ""):
             return None
         return float(fields["traffic_bytes_per_launch"])
@@ -168,12 +168,307 @@ def rel2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+# ---------------------------------------------------------------- profiles
+# The rocprofv3 runs behind profiles/, and their reduction.  Every run is one
+# committed command (a probe of this file, or the bench step itself); the
+# summaries are regenerated with --summarize from the CSV files the runs wrote.
+SQ_COUNTERS = ("SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_INSTS_SALU SQ_LDS_BANK_CONFLICT "
+               "SQ_ACTIVE_INST_VALU SQ_BUSY_CYCLES SQ_WAVE_CYCLES")
+SQ_MFMA_COUNTERS = "SQ_INSTS_VALU_MFMA_MOPS_BF16 SQ_VALU_MFMA_BUSY_CYCLES SQ_INSTS_MFMA SQ_BUSY_CU_CYCLES"
+BENCH_TRACE_ARGS = ("--steps 5 --warmup 1 --no-cpu-baseline --no-serving --no-large --no-simp "
+                    "--no-levelset --no-shape --no-paper --no-config0")
+PROFILE_RUNS = {  # -o name: (rocprofv3 options, bench.py arguments)
+    "copy_fetch": ("--pmc FETCH_SIZE", "--probe copy"),
+    "copy_write": ("--pmc WRITE_SIZE", "--probe copy"),
+    "product_trace": ("--kernel-trace --stats", "--probe product"),
+    "product_fetch": ("--pmc FETCH_SIZE", "--probe product"),
+    "product_write": ("--pmc WRITE_SIZE", "--probe product"),
+    "product_sq": ("--pmc " + SQ_COUNTERS, "--probe product"),
+    "product_mfma": ("--pmc " + SQ_MFMA_COUNTERS, "--probe product"),
+    "cg_fetch": ("--pmc FETCH_SIZE", "--probe cg"),
+    "cg_write": ("--pmc WRITE_SIZE", "--probe cg"),
+    "cg3_trace": ("--kernel-trace --stats", "--probe cg3"),
+    "cg3_fetch": ("--pmc FETCH_SIZE", "--probe cg3"),
+    "cg3_write": ("--pmc WRITE_SIZE", "--probe cg3"),
+    "cg3_sq": ("--pmc " + SQ_COUNTERS, "--probe cg3"),
+    "bench_trace": ("--kernel-trace --stats", BENCH_TRACE_ARGS),
+    "ls_trace": ("--kernel-trace --stats", "--probe levelset"),
+    "ls_fetch": ("--pmc FETCH_SIZE", "--probe levelset"),
+    "ls_write": ("--pmc WRITE_SIZE", "--probe levelset"),
+    "shape_trace": ("--kernel-trace --stats", "--probe shape"),
+    "shape_fetch": ("--pmc FETCH_SIZE", "--probe shape"),
+    "shape_write": ("--pmc WRITE_SIZE", "--probe shape"),
+}
+PRODUCT_SOURCES = ("k_matvec.hip", "k_mfma.hip", "device_common.h", "common.h")
+LS_SOURCES = ("k_levelset.hip", "device_common.h", "common.h")
+SHAPE_SOURCES = ("k_shape.hip", "device_common.h", "common.h")
+
+
+def _nodes(d):
+    return (d[0] + 1) * (d[1] + 1) * (d[2] + 1), d[0] * d[1] * d[2]
+
+
+def algorithmic_bytes(kernel, dims):
+    """Bytes one launch of `kernel` must move on grid `dims` (nel voxels, nn
+    nodes): every input read once, every output written once."""
+    nn, nel = _nodes(dims)
+    table = [  # (name fragment, bytes per node, bytes per element)
+        ("k_matvec<float, 0>", 25, 4),         # read u (12) and the mask byte, E; write y (12)
+        ("k_matvec_mfma<0>", 25, 4),
+        ("k_matvec<double, 0>", 49, 8),
+        ("k_cg_matvec1<float, false>", CG_PRODUCT_BYTES_F32, 4),
+        ("k_cg_mfma1", CG_PRODUCT_BYTES_F32, 4),
+        ("k_cg_update1<float, false>", CG_UPDATE_BYTES_F32, 0),
+        ("k_ls_advect", 24, 0), ("k_ls_reinit", 16, 0),
+        ("k_hcg_apply", 17, 0), ("k_hcg_update", 56, 0), ("k_hcg_dir", 24, 0),
+        ("__amd_rocclr_copyBuffer", None, None),
+    ]
+    for frag, bn, be in table:
+        if frag in kernel and bn is not None:
+            return bn * nn + be * nel
+    return None
+
+
+def profile_commands(outdir):
+    return ["rocprofv3 %s --output-format csv -d %s -o %s -- python3 bench.py %s"
+            % (opts, outdir, name, args) for name, (opts, args) in PROFILE_RUNS.items()]
+
+
+def _csv_rows(root, name, suffix):
+    import csv
+    import glob
+    rows = []
+    for f in sorted(glob.glob(os.path.join(root, "**", "%s*%s" % (name, suffix)), recursive=True)):
+        with open(f, newline="") as fh:
+            rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def _durations(root, name):
+    """{kernel name: [duration us, ...]} from a kernel-trace run."""
+    out = {}
+    for r in _csv_rows(root, name, "kernel_trace.csv"):
+        k = r.get("Kernel_Name", "")
+        out.setdefault(k, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+    return out
+
+
+def _counter(root, name, counter):
+    """{kernel name: [value per dispatch, ...]} of one counter."""
+    out = {}
+    for r in _csv_rows(root, name, "counter_collection.csv"):
+        if r.get("Counter_Name") != counter:
+            continue
+        out.setdefault(r.get("Kernel_Name", ""), []).append(float(r["Counter_Value"]))
+    return out
+
+
+def _working(vals):
+    """Median over the upper half: launches after a solve's stop return at
+    once, so the lower half of a CG kernel's launches measures no work."""
+    v = sorted(vals)
+    return float(np.median(v[len(v) // 2:])) if v else float("nan")
+
+
+def _source_sha(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        path = os.path.join(ROOT, "paper_2605_04735_amd", "csrc", f)
+        if os.path.exists(path):
+            h.update(open(path, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _source_line(files):
+    return "source: sha256[:16] of paper_2605_04735_amd/csrc/{%s} = %s" % (",".join(files),
+                                                                           _source_sha(files))
+
+
+def _cmd_lines(names, outdir="gpurun_out/prof"):
+    return ["  rocprofv3 %s --output-format csv -d %s -o %s -- python3 bench.py %s"
+            % (PROFILE_RUNS[n][0], outdir, n, PROFILE_RUNS[n][1]) for n in names]
+
+
+def _copy_scales(root):
+    """FETCH_SIZE and WRITE_SIZE scale factors from the copy probe: a copy of
+    COPY_BYTES reads and writes COPY_BYTES; each counter is scaled to that."""
+    f = _counter(root, "copy_fetch", "FETCH_SIZE")
+    w = _counter(root, "copy_write", "WRITE_SIZE")
+    kf = [k for k in f if "copyBuffer" in k]
+    kw = [k for k in w if "copyBuffer" in k]
+    if not kf or not kw:
+        return None
+    fk, wk = _working(f[kf[0]]), _working(w[kw[0]])
+    exp = COPY_BYTES / 1024.0
+    return {"fetch_scale": exp / fk, "write_scale": exp / wk, "fetch_kib": fk, "write_kib": wk,
+            "kernel": kf[0], "dispatches": (len(f[kf[0]]), len(w[kw[0]]))}
+
+
+def _committed_scales():
+    try:
+        text = open(os.path.join(ROOT, "profiles", "pmc_copy_calibration.txt")).read()
+    except OSError:
+        return None
+    out = {}
+    for line in text.splitlines():
+        for key in ("fetch_scale", "write_scale"):
+            if line.startswith(key + ":"):
+                out[key] = float(line.split(":")[1])
+    return out if len(out) == 2 else None
+
+
+# (file, title, dims, trace run, fetch run, write run, sq runs, sources, kernels of interest)
+SUMMARIES = [
+    ("pmc_product_256x128x128.txt",
+     "products y = K u (plain form, fixed DOFs as identity rows) at 256x128x128, random-field "
+     "moduli (seed 3); 1 + 10 launches per kernel", LARGE, "product_trace", "product_fetch",
+     "product_write", ("product_sq", "product_mfma"), PRODUCT_SOURCES,
+     ("k_matvec<float, 0>", "k_matvec_mfma<0>", "k_matvec<double, 0>")),
+    ("kernel_trace_cg_256x128x128.txt",
+     "one fp32+refine solve of the 256x128x128 cantilever (random-field densities, seed 3) to "
+     "rtol 1e-2: inner-CG product and update", LARGE, "cg3_trace", "cg3_fetch", "cg3_write",
+     ("cg3_sq",), PRODUCT_SOURCES,
+     ("k_cg_matvec1<float, false>", "k_cg_mfma1", "k_cg_update1<float, false>")),
+    ("pmc_cg_matvec_f32_cantilever_96x48x48.txt",
+     "one fp32+refine solve of the 96x48x48 cantilever (seed 1) to rtol 1e-4: inner-CG product "
+     "and update (working set resident in the 256 MB Infinity Cache)", DIMS, None, "cg_fetch",
+     "cg_write", (), PRODUCT_SOURCES,
+     ("k_cg_matvec1<float, false>", "k_cg_mfma1", "k_cg_update1<float, false>")),
+    ("levelset_256x128x128.txt",
+     "level-set evolution (10 steps) and reinitialisation (to 1e-3, at most 40 pseudo-steps) on "
+     "the 257x129x129 node grid; phi = 2.5 x the distance to three balls, smooth speed of both "
+     "signs, CFL number 1/2", LARGE, "ls_trace", "ls_fetch", "ls_write", (), LS_SOURCES,
+     ("k_ls_advect", "k_ls_reinit")),
+    ("shape_extension_256x128x128.txt",
+     "shape-derivative vector and Hilbertian extension (ell = 2, extension CG to rtol 1e-8) on "
+     "the 257x129x129 node grid; phi = 2.5 x the distance to three balls, seeded u", LARGE,
+     "shape_trace", "shape_fetch", "shape_write", (), SHAPE_SOURCES,
+     ("k_hcg_apply", "k_hcg_update", "k_hcg_dir", "k_shape_elem", "k_shape_gather")),
+]
+
+
+def summarize(root):
+    """Writes the profiles/ summaries from the CSV output of the runs of
+    profile_commands() found under `root`; a summary whose runs are absent is
+    left as it is."""
+    out_dir = os.path.join(ROOT, "profiles")
+    cal = _copy_scales(root)
+    if cal is not None:
+        with open(os.path.join(out_dir, "pmc_copy_calibration.txt"), "w") as fh:
+            fh.write("# HBM traffic calibration (plain device copy of known size)\n")
+            fh.write("commands (from the repository root, TMPDIR=/tmp):\n")
+            fh.write("\n".join(_cmd_lines(("copy_fetch", "copy_write"))) + "\n")
+            fh.write("copy: torch copy_ of %d bytes (reads %d, writes %d) -> %s, %d/%d dispatches\n"
+                     % (COPY_BYTES, COPY_BYTES, COPY_BYTES, cal["kernel"], *cal["dispatches"]))
+            fh.write("FETCH_SIZE_KiB_per_dispatch: %.1f   (expected %.1f) -> fetch_scale %.4f\n"
+                     % (cal["fetch_kib"], COPY_BYTES / 1024.0, cal["fetch_scale"]))
+            fh.write("WRITE_SIZE_KiB_per_dispatch: %.1f   (expected %.1f) -> write_scale %.4f\n"
+                     % (cal["write_kib"], COPY_BYTES / 1024.0, cal["write_scale"]))
+            fh.write("fetch_scale: %.4f\nwrite_scale: %.4f\n" % (cal["fetch_scale"],
+                                                                 cal["write_scale"]))
+        log("wrote profiles/pmc_copy_calibration.txt")
+    scales = cal or _committed_scales() or {"fetch_scale": 1.0, "write_scale": 1.0}
+    for (fname, title, dims, tr, fe, wr, sqs, srcs, kernels) in SUMMARIES:
+        dur = _durations(root, tr) if tr else {}
+        fet = _counter(root, fe, "FETCH_SIZE") if fe else {}
+        wri = _counter(root, wr, "WRITE_SIZE") if wr else {}
+        if not dur and not fet:
+            continue
+        runs = [r for r in (tr, fe, wr) + tuple(sqs) if r]
+        lines = ["# " + title, _source_line(srcs),
+                 "commands (from the repository root, TMPDIR=/tmp):"] + _cmd_lines(runs)
+        lines.append("counter scaling (pmc_copy_calibration.txt): FETCH_SIZE x %.4f, WRITE_SIZE x %.4f"
+                     % (scales["fetch_scale"], scales["write_scale"]))
+        if dur:
+            lines += ["", "%-62s %7s %10s %10s %12s %10s" % ("kernel", "calls", "avg_us", "median_us",
+                                                              "working_us", "total_ms")]
+            for k, v in sorted(dur.items(), key=lambda kv: -sum(kv[1])):
+                lines.append("%-62s %7d %10.3f %10.3f %12.3f %10.3f"
+                             % (k[:62], len(v), np.mean(v), np.median(v), _working(v), sum(v) * 1e-3))
+        for frag in kernels:
+            names = sorted({k for k in list(dur) + list(fet) if frag in k})
+            for k in names:
+                sec = ["", "## %s, %s" % (frag, "x".join(map(str, dims))), "kernel: " + k.split("(")[0],
+                       _source_line(srcs)]
+                d = dur.get(k)
+                if d:
+                    sec.append("launches: %d, avg_us: %.3f, working_median_us: %.3f"
+                               % (len(d), np.mean(d), _working(d)))
+                alg = algorithmic_bytes(k, dims)
+                if k in fet and k in wri:
+                    fk, wk = _working(fet[k]), _working(wri[k])
+                    traffic = 1024.0 * (fk * scales["fetch_scale"] + wk * scales["write_scale"])
+                    sec += ["dispatches: %d (FETCH_SIZE), %d (WRITE_SIZE)" % (len(fet[k]), len(wri[k])),
+                            "FETCH_SIZE_KiB_per_dispatch: %.1f" % fk,
+                            "WRITE_SIZE_KiB_per_dispatch: %.1f" % wk,
+                            "traffic_bytes_per_launch: %d" % round(traffic)]
+                    if alg:
+                        sec.append("traffic_over_algorithmic: %.3f" % (traffic / alg))
+                if alg:
+                    sec.append("algorithmic_bytes_per_launch: %d" % alg)
+                    if d:
+                        sec.append("algorithmic_GBs_at_working_median: %.1f (%.3f of %.0f)"
+                                   % (alg / (_working(d) * 1e-6) / 1e9,
+                                      alg / (_working(d) * 1e-6) / 1e9 / HBM_PEAK_GBS, HBM_PEAK_GBS))
+                for sq in sqs:
+                    rows = {}
+                    for r in _csv_rows(root, sq, "counter_collection.csv"):
+                        if r.get("Kernel_Name", "") == k:
+                            rows.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+                    if rows:
+                        sec.append("%s: %s" % (sq, ", ".join("%s=%.0f" % (c, _working(v))
+                                                              for c, v in sorted(rows.items()))))
+                lines += sec
+        lines += ["", "reading: traffic = FETCH_SIZE and WRITE_SIZE (KiB per dispatch, the median "
+                  "of the working launches) times the copy-calibrated scales; SQ_INSTS_VALU counts "
+                  "wave instructions, and one CU issues about one wave64 VALU instruction per "
+                  "cycle, so VALU issue alone is SQ_INSTS_VALU / 256 CUs / 2.4 GHz."]
+        with open(os.path.join(out_dir, fname), "w") as fh:
+            fh.write("\n".join(lines) + "\n")
+        log("wrote profiles/%s" % fname)
+    bt = _durations(root, "bench_trace")
+    if bt:
+        lines = ["# rocprofv3 kernel trace of the bench step (cantilever 96x48x48, random-field "
+                 "densities, seed 1): calibration, 1 warm-up and 5 timed steps of each precision "
+                 "path, product timings at 96x48x48", _source_line(PRODUCT_SOURCES),
+                 "command (from the repository root, TMPDIR=/tmp):"] + _cmd_lines(("bench_trace",))
+        lines += ["", "%-62s %7s %10s %10s %10s %7s" % ("kernel", "calls", "avg_us", "median_us",
+                                                        "total_ms", "pct")]
+        tot = sum(sum(v) for v in bt.values())
+        for k, v in sorted(bt.items(), key=lambda kv: -sum(kv[1])):
+            lines.append("%-62s %7d %10.3f %10.3f %10.3f %7.2f"
+                         % (k.split("(")[0][:62], len(v), np.mean(v), np.median(v), sum(v) * 1e-3,
+                            100.0 * sum(v) / tot))
+        with open(os.path.join(out_dir, "kernel_trace_cantilever_96x48x48.txt"), "w") as fh:
+            fh.write("\n".join(lines) + "\n")
+        log("wrote profiles/kernel_trace_cantilever_96x48x48.txt")
+
+
+def energy_norm_err(A, ctx, x, u, uref):
+    """||u - u_ref||_K / ||u_ref||_K (Eq. 2's energy norm) with the float64
+    product on ctx; both vanish on the fixed DOFs, whose identity rows then
+    contribute nothing."""
+    import torch
+    ur = torch.as_tensor(uref, device=u.device)
+    e = u - ur
+    ke = A.to_matvec(ctx, x, e)
+    ku = A.to_matvec(ctx, None, ur)
+    return float(torch.sqrt(torch.clamp(torch.dot(e, ke), min=0.0) / torch.dot(ur, ku)).item())
+
+
+def within_target(A, ctx, x, u, c, dc, ur, cr, dcr, lim=CAL_MARGIN * TARGET):
+    """c, dc (2-norm) and u (energy norm) within lim of the reference."""
+    return (abs(c - cr) / abs(cr) <= lim and rel2(dc.cpu().numpy(), dcr) <= lim
+            and energy_norm_err(A, ctx, x, u, ur) <= lim)
+
+
 class Calibrator:
     """Chooses, per request class (grid, boundary condition) and precision
-    path, the loosest outer residual tolerance on RTOL_LADDER whose compliance
-    and sensitivity are within TARGET of a float64 reference solved to 1e-11
-    (with a 2x margin: CAL_MARGIN), on three calibration seeds per class that
-    are never timed."""
+    path, the loosest outer residual tolerance on RTOL_LADDER whose compliance,
+    sensitivity (2-norm) and displacement (energy norm) are within TARGET of a
+    float64 reference solved to 1e-11 (with a 2x margin: CAL_MARGIN), on three
+    calibration seeds per class that are never timed."""
 
     def __init__(self, A, inputs, dev):
         self.A, self.inputs, self.dev = A, inputs, dev
@@ -213,9 +508,8 @@ class Calibrator:
                 x = self.field(dims, sd)
                 u, info, _ = A.to_solve(ctx, x)
                 c, dc = A.to_compliance_sensitivity(ctx, x, u)
-                _, cr, dcr = self.reference(dims, bc, sd)
-                lim = CAL_MARGIN * TARGET
-                ok &= abs(c - cr) / abs(cr) <= lim and rel2(dc.cpu().numpy(), dcr) <= lim
+                ur, cr, dcr = self.reference(dims, bc, sd)
+                ok &= within_target(A, ctx, x, u, c, dc, ur, cr, dcr)
             ctx.close()
             if ok:
                 chosen = rt
@@ -228,10 +522,81 @@ class Calibrator:
         return chosen
 
 
+def golden(name):
+    """Values written by the oracle (tests/golden/make_bench_golden.py)."""
+    meta = json.load(open(os.path.join(ROOT, "tests", "golden", name + ".json")))
+    npz = os.path.join(ROOT, "tests", "golden", name + ".npz")
+    arr = np.load(npz) if os.path.exists(npz) else None
+    return meta, arr
+
+
+def copy_rate(dev, reps=10):
+    """Achievable HBM bandwidth: a device copy of COPY_BYTES (read + write)."""
+    import torch
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s = torch.cuda.current_stream()
+    e0.record(s)
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record(s)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * COPY_BYTES / (us * 1e-6) / 1e9
+
+
+def config0(A, dev, reps=20):
+    """The 24x12x6 cantilever at uniform x = 0.5: latency of the step (solve to
+    1e-10, compliance and sensitivity, density filter rmin 1.5, its adjoint and
+    the sensitivity filter R = 2 on dc) in both precisions, and the errors of c
+    and dc against the oracle's direct solve (tests/golden)."""
+    import torch
+    meta, _ = golden("cantilever_24x12x6_uniform")
+    dcr = np.array(meta["dc"])
+    x = torch.full((24 * 12 * 6,), 0.5, dtype=torch.float64, device=dev)
+    out = {"workload": "cantilever 24x12x6, x = 0.5, rtol 1e-10"}
+    for name, prec in (("fp64", A.PREC_FP64), ("fp32_refine", A.PREC_FP32_REFINE)):
+        ctx = A.to_create(A.Problem(24, 12, 6, precision=prec, rtol=1e-10))
+        u = torch.empty(ctx.prob.ndof, dtype=torch.float64, device=dev)
+        dc = torch.empty(ctx.prob.nel, dtype=torch.float64, device=dev)
+        xf, g1, g2 = torch.empty_like(dc), torch.empty_like(dc), torch.empty_like(dc)
+        lat = []
+        for r in range(reps + 2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info, _ = A.to_solve(ctx, x, u=u)
+            c, _ = A.to_compliance_sensitivity(ctx, x, u, dc=dc)
+            A.to_filter(ctx, 1.5, A.FILTER_DENS, x, out=xf)
+            A.to_filter(ctx, 1.5, A.FILTER_DENS_T, dc, out=g1)
+            A.to_filter(ctx, 2.0, A.FILTER_SENS, dc, x=x, out=g2)
+            torch.cuda.synchronize()
+            if r >= 2:
+                lat.append((time.perf_counter() - t0) * 1e3)
+        out[name] = {"ms_p50": round(float(np.median(lat)), 4), "ms_max": round(max(lat), 4),
+                     "inner_iters": info["inner_iters"], "c": c,
+                     "err_vs_oracle": {"c": abs(c - meta["c"]) / abs(meta["c"]),
+                                       "dc": rel2(dc.cpu().numpy(), dcr)}}
+        ctx.close()
+    log("config 0: %s" % out)
+    return out
+
+
 def main():
     args = parse()
     if args.probe:
         probe(args.probe)
+        return
+    if args.profile_commands:
+        for cmd in profile_commands(args.profile_commands):
+            print(cmd)
+        return
+    if args.summarize:
+        summarize(args.summarize)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (requests shard "
@@ -329,7 +694,9 @@ def main():
         us = e0.elapsed_time(e1) * 1e3 / reps
         return us, prob.ndof / (us * 1e-6) / 1e9
 
-    products = {}
+    copy_gbs = copy_rate(dev)
+    log("device copy: %.0f GB/s" % copy_gbs)
+    products = {"hbm_copy_GBs_measured": round(copy_gbs, 1), "hbm_peak_GBs_nominal": HBM_PEAK_GBS}
     us, g = product_rate(ctx_m, prob_m, True)
     products["96x48x48_f32"] = {"us": us, "gdofs": g}
     us, g = product_rate(ctx_d, prob_d, False)
@@ -339,12 +706,14 @@ def main():
             pl = A.Problem(*LARGE, precision=A.PREC_FP32_REFINE if f32 else A.PREC_FP64)
             cl = A.to_create(pl)
             us, g = product_rate(cl, pl, f32, reps=50)
-            byt = (24 if f32 else 48) * pl.nn + (4 if f32 else 8) * pl.nel
-            tr = measured_traffic("pmc_product_256x128x128.txt",
-                                  "void topo::k_matvec<%s, 0>" % ("float" if f32 else "double"))
+            kern = A.product_kernel_name(f32)
+            byt = algorithmic_bytes(kern, LARGE)
+            gbs = byt / (us * 1e-6) / 1e9
             products["256x128x128_%s" % ("f32" if f32 else "f64")] = {
-                "us": us, "gdofs": g, "algorithmic_GBs": byt / (us * 1e-6) / 1e9,
-                "frac_hbm": byt / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, "traffic_bytes": tr}
+                "us": us, "gdofs": g, "kernel": kern, "algorithmic_bytes": byt,
+                "algorithmic_GBs": gbs, "frac_hbm": gbs / HBM_PEAK_GBS,
+                "frac_measured_copy": gbs / copy_gbs,
+                "traffic_bytes": measured_traffic("pmc_product_256x128x128.txt", "void topo::" + kern)}
             cl.close()
             del cl
             torch.cuda.empty_cache()
@@ -354,8 +723,8 @@ def main():
     # ---------------------------------------------------------- workloads
     workloads = {}
     if not args.no_large:
-        workloads["mbb_sdf_ersatz_192x64x32"] = workload_mbb_sdf(A, inputs, dev)
-        workloads["cantilever_256x128x128"] = workload_large(A, inputs, dev)
+        workloads["mbb_sdf_ersatz_192x64x32"] = workload_mbb_sdf(A, inputs, dev, cal)
+        workloads["cantilever_256x128x128"] = workload_large(A, inputs, dev, copy_gbs)
     if not args.no_simp:
         workloads["simp_cantilever_96x48x48"] = workload_simp(A, dev, rtol_mixed, rtol_fp64)
     if not args.no_levelset:
@@ -368,27 +737,49 @@ def main():
                                                       torch.from_numpy(u_m).to(dev))
 
     # ---------------------------------------------------------- roofline
-    # dominant kernel: the fused inner-CG product (p = z + beta p_old, q = K p,
-    # p^T q) in float32; algorithmic bytes per launch: read z and p_old
-    # (12 B/node each), read E (4 B/element), write p and q (12 B/node each)
+    # dominant kernel: the fused inner-CG product in float32.  Its HBM
+    # roofline is taken at 256x128x128, where the working set (about 0.7 GB)
+    # cannot stay in the caches; at the benchmark's 96x48x48 the CG working
+    # set (about 30 MB) sits in the 256 MB Infinity Cache and every launch is
+    # a few microseconds, so that figure (given beside it) measures launch
+    # latency, not HBM.
+    kern = A.cg_product_kernel_name()
     mv_us = 1e3 * res_m["mv_ms"] / max(res_m["mv_n"], 1)
-    bytes_launch = 48 * nn + 4 * nel
+    bytes_launch = algorithmic_bytes(kern, DIMS)
     achieved = bytes_launch / (mv_us * 1e-6) / 1e9
-    traffic = measured_traffic("pmc_cg_matvec_f32_cantilever_96x48x48.txt",
-                               "void topo::k_cg_matvec1<float, false>")
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_cg_matvec1<float, false>", "avg_us": round(mv_us, 3),
-                "bytes_per_launch": bytes_launch}
+    small = {"grid": "96x48x48", "achieved": round(achieved, 1), "frac": round(achieved / HBM_PEAK_GBS, 4),
+             "avg_us": round(mv_us, 3), "bytes_per_launch": bytes_launch,
+             "traffic": measured_traffic("pmc_cg_matvec_f32_cantilever_96x48x48.txt", "void topo::" + kern),
+             "note": "working set resident in the Infinity Cache: launch-latency bound"}
+    big = workloads.get("cantilever_256x128x128", {}).get("roofline_cg_product")
+    if big is not None:
+        roofline = dict(big)
+        roofline["grid"] = "256x128x128 (inner-CG product inside the fp32+refine solve)"
+        roofline["cache_resident_96x48x48"] = small
+    else:
+        roofline = {"bound": "hbm", "achieved": small["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": small["frac"], "traffic": small["traffic"], "kernel": kern,
+                    "avg_us": small["avg_us"], "bytes_per_launch": bytes_launch, "grid": "96x48x48"}
+    roofline["measured_copy_GBs"] = round(copy_gbs, 1)
+    roofline["frac_of_measured_copy"] = round(roofline["achieved"] / copy_gbs, 4)
 
     # ---------------------------------------------------------- errors
+    gmeta, garr = golden("cantilever_96x48x48_seed1")
+
+    def errs(u, c, dc, ur, cr, dcr):
+        return {"u": rel2(u, ur), "c": abs(c - cr) / abs(cr), "dc": rel2(dc, dcr),
+                "dc_max": float(np.abs(dc - dcr).max() / np.abs(dcr).max())}
     errors = {
-        "fp32_refine": {"u": rel2(u_m, uref), "c": abs(c_m - cref) / abs(cref), "dc": rel2(dc_m, dcref),
-                        "dc_max": float(np.abs(dc_m - dcref).max() / np.abs(dcref).max())},
-        "fp64": {"u": rel2(u_d, uref), "c": abs(c_d - cref) / abs(cref), "dc": rel2(dc_d, dcref),
-                 "dc_max": float(np.abs(dc_d - dcref).max() / np.abs(dcref).max())},
-        "reference": "float64 GPU solve to rel. residual 1e-11 (validated against the oracle "
-                     "on smaller grids by the parity tests)"}
+        "vs_oracle": {
+            "fp32_refine": errs(u_m, c_m, dc_m, garr["u"], gmeta["c"], garr["dc"]),
+            "fp64": errs(u_d, c_d, dc_d, garr["u"], gmeta["c"], garr["dc"]),
+            "reference": "the oracle's float64 Jacobi-PCG solve of the same design to 1e-10 "
+                         "(tests/golden/cantilever_96x48x48_seed1, written by "
+                         "tests/golden/make_bench_golden.py)"},
+        "vs_gpu_fp64_1e-11": {
+            "fp32_refine": errs(u_m, c_m, dc_m, uref, cref, dcref),
+            "fp64": errs(u_d, c_d, dc_d, uref, cref, dcref)}}
+    log("errors vs oracle: %s" % errors["vs_oracle"])
 
     sps_m = args.steps / res_m["sec"]
     sps_d = args.steps / res_d["sec"]
@@ -414,6 +805,8 @@ def main():
         "products": products, "errors": errors, "triangles": ntri, "roofline": roofline,
         "workloads": workloads,
     }
+    if not args.no_config0:
+        out["config0"] = config0(A, dev)
 
     # ---------------------------------------------------------- serving
     if not args.no_serving:
@@ -435,18 +828,33 @@ def _timed_solve(A, ctx, x, u=None):
     return u, c, dc, info, st, (time.perf_counter() - t0) * 1e3
 
 
-def workload_mbb_sdf(A, inputs, dev):
+def workload_mbb_sdf(A, inputs, dev, cal):
     """MBB half-beam 192x64x32: SIMP-like densities (l = 6, kappa = 8, seed 2,
     shifted so that 40% of the elements exceed 0.5) -> density->SDF at 0.5 ->
     per-element volume fraction -> ersatz moduli E = max(vf, 1e-3) (penal 1,
     Emin 0) -> compliance and sensitivity, float32-inner/float64-refined and
-    float64, both to rtol 1e-8, against a float64 solve to 3e-10 (its stagnation
-    floor is near 2e-10)."""
+    float64.  Each path runs at the tolerance calibrated for this workload the
+    way the headline's is (the loosest ladder rung whose c, dc and energy-norm
+    u errors are within half the target on three designs of the same recipe,
+    seeds 21-23, times the safety factor, floored), and both also at 1e-8;
+    errors against a float64 solve to 3e-10 (its stagnation floor is near
+    2e-10)."""
     import torch
     dims = (192, 64, 32)
+
+    def make(geo, seed):
+        x = torch.from_numpy(inputs.random_field(*dims, seed=seed, ell=6.0, kappa=8.0,
+                                                 solid_fraction=0.4)).to(dev)
+        _, _, vf = A.to_density_to_sdf(geo, x, 0.5)
+        return torch.clamp(vf, min=1e-3)
+
+    def problem(prec, rtol):
+        return A.Problem(*dims, bc=A.BC_MBB, penal=1.0, Emin=0.0, precision=prec, rtol=rtol,
+                         max_iters=10 ** 6)
+
+    geo = A.to_create(A.Problem(*dims, bc=A.BC_MBB))
     x = torch.from_numpy(inputs.random_field(*dims, seed=2, ell=6.0, kappa=8.0,
                                              solid_fraction=0.4)).to(dev)
-    geo = A.to_create(A.Problem(*dims, bc=A.BC_MBB))
     A.to_density_to_sdf(geo, x, 0.5)  # warm
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -457,21 +865,52 @@ def workload_mbb_sdf(A, inputs, dev):
     xe = torch.clamp(vf, min=1e-3)
     out = {"sdf_ms": round(t_sdf, 3), "triangles": ntri,
            "solid_fraction_vf": float(vf.mean().item())}
-    res = {}
-    for name, prec, rtol in (("reference", A.PREC_FP64, 3e-10), ("fp32_refine", A.PREC_FP32_REFINE, 1e-8),
-                             ("fp64", A.PREC_FP64, 1e-8)):
-        ctx = A.to_create(A.Problem(*dims, bc=A.BC_MBB, penal=1.0, Emin=0.0, precision=prec,
-                                    rtol=rtol, max_iters=10 ** 6))
-        _timed_solve(A, ctx, xe)  # warm
-        u, c, dc, info, st, ms = _timed_solve(A, ctx, xe)
-        res[name] = (u.cpu().numpy(), c, dc.cpu().numpy())
-        out[name] = {"ms": round(ms, 2), "status": A.L.STATUS_NAMES.get(st, st),
-                     "inner_iters": info["inner_iters"], "rel_res": info["rel_res"]}
-        ctx.close()
-    ur, cr, dcr = res["reference"]
-    for name in ("fp32_refine", "fp64"):
-        u, c, dc = res[name]
-        out[name]["err"] = {"u": rel2(u, ur), "c": abs(c - cr) / abs(cr), "dc": rel2(dc, dcr)}
+    # references: float64 to 3e-10
+    refc = A.to_create(problem(A.PREC_FP64, 3e-10))
+    refs, designs = {}, {}
+    for sd in (2, 21, 22, 23):
+        designs[sd] = xe if sd == 2 else make(geo, sd)
+        u, c, dc, info, st, ms = _timed_solve(A, refc, designs[sd])
+        refs[sd] = (u.clone(), c, dc.cpu().numpy())
+    # calibration
+    rt_cal = {}
+    for name, prec in (("fp32_refine", A.PREC_FP32_REFINE), ("fp64", A.PREC_FP64)):
+        chosen = RTOL_LADDER[-1]
+        for rt in RTOL_LADDER:
+            ctx = A.to_create(problem(prec, rt))
+            ok = True
+            for sd in (21, 22, 23):
+                u, c, dc, _, _, _ = _timed_solve(A, ctx, designs[sd])
+                ur, cr, dcr = refs[sd]
+                ok &= within_target(A, ctx, designs[sd], u, c, dc, ur, cr, dcr)
+            ctx.close()
+            if ok:
+                chosen = rt
+                break
+        rt_cal[name] = max(chosen * CAL_SAFETY, RTOL_FLOOR)
+    out["rtol_calibrated"] = rt_cal
+    ur, cr, dcr = refs[2]
+    for name, prec in (("fp32_refine", A.PREC_FP32_REFINE), ("fp64", A.PREC_FP64)):
+        for tag, rtol in (("calibrated", rt_cal[name]), ("rtol_1e-8", 1e-8)):
+            ctx = A.to_create(problem(prec, rtol))
+            _timed_solve(A, ctx, xe)  # warm
+            ms_all = []
+            for _ in range(3):
+                u, c, dc, info, st, ms = _timed_solve(A, ctx, xe)
+                ms_all.append(ms)
+            rec = {"rtol": rtol, "ms": round(float(np.median(ms_all)), 2),
+                   "status": A.L.STATUS_NAMES.get(st, st), "inner_iters": info["inner_iters"],
+                   "outer_iters": info["outer_iters"], "rel_res": info["rel_res"],
+                   "err": {"u": rel2(u.cpu().numpy(), ur.cpu().numpy()),
+                           "u_energy": energy_norm_err(A, ctx, xe, u, ur),
+                           "c": abs(c - cr) / abs(cr), "dc": rel2(dc.cpu().numpy(), dcr)}}
+            out.setdefault(name, {})[tag] = rec
+            ctx.close()
+    for tag in ("calibrated", "rtol_1e-8"):
+        out["speedup_fp32_refine_vs_fp64_" + tag] = round(out["fp64"][tag]["ms"]
+                                                          / out["fp32_refine"][tag]["ms"], 3)
+    refc.close()
+    geo.close()
     log("mbb+sdf 192x64x32: sdf %.1f ms (%d triangles); fp32+refine %s; fp64 %s"
         % (t_sdf, ntri, out["fp32_refine"], out["fp64"]))
     return out
@@ -736,11 +1175,14 @@ def workload_shape(A, inputs, dev, x1, u1, reps=5):
     return out
 
 
-def workload_large(A, inputs, dev):
+def workload_large(A, inputs, dev, copy_gbs):
     """Cantilever 256x128x128 (12.8M DOF), random-field densities (l = 6,
     kappa = 2, seed 3): float64, float32-inner/float64-refined, and the same
     with the inner z stored in bfloat16, each to rtol 1e-8 with compliance and
-    sensitivity; errors of the mixed paths against the float64 one."""
+    sensitivity; errors of the mixed paths against the float64 one.  The
+    float32 solve also samples its inner-CG product launches (dispatch
+    timestamps), which gives the product's HBM roofline at a size whose
+    working set does not fit in the caches."""
     import torch
     dims = LARGE
     x = torch.from_numpy(inputs.random_field(*dims, seed=3, ell=6.0, kappa=2.0)).to(dev)
@@ -755,23 +1197,23 @@ def workload_large(A, inputs, dev):
         out[name] = {"ms": round(ms, 1), "status": A.L.STATUS_NAMES.get(st, st),
                      "inner_iters": info["inner_iters"], "outer_iters": info["outer_iters"],
                      "rel_res": info["rel_res"],
-                     "cg_iters_per_s": round(info["inner_iters"] / (ms * 1e-3), 1)}
+                     "cg_iters_per_s": round(info["inner_iters"] / (ms * 1e-3), 1),
+                     "us_per_cg_iter": round(ms * 1e3 / max(info["inner_iters"], 1), 2)}
         if prec == A.PREC_FP32_REFINE:
-            # the inner-CG product inside this solve: its roofline at a size
-            # whose working set does not fit in the caches
             mv_ms, mv_n = A.to_profile(ctx, False)
             mv_us = 1e3 * mv_ms / max(mv_n, 1)
-            nn = (dims[0] + 1) * (dims[1] + 1) * (dims[2] + 1)
-            byt = 48 * nn + 4 * dims[0] * dims[1] * dims[2]
+            kern = A.cg_product_kernel_name()
+            byt = algorithmic_bytes(kern, dims)
             ach = byt / (mv_us * 1e-6) / 1e9
             out["roofline_cg_product"] = {
                 "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic("pmc_cg_matvec_f32_cantilever_96x48x48.txt",
-                                            "void topo::k_cg_matvec1<float, false>",
-                                            title="256x128x128"),
-                "kernel": "k_cg_matvec1<float, false>", "avg_us": round(mv_us, 3),
-                "launches_sampled": mv_n, "bytes_per_launch": byt}
+                "frac_of_measured_copy": round(ach / copy_gbs, 4),
+                "traffic": measured_traffic("kernel_trace_cg_256x128x128.txt", "void topo::" + kern),
+                "kernel": kern, "avg_us": round(mv_us, 3), "launches_sampled": mv_n,
+                "bytes_per_launch": byt}
+            out["cg_algorithmic_bytes_per_node_per_iteration"] = (CG_PRODUCT_BYTES_F32
+                                                                  + CG_UPDATE_BYTES_F32)
         ctx.close()
         del u, dc
         torch.cuda.empty_cache()
@@ -901,11 +1343,14 @@ def tight_reference(cal, dims, bc, x):
 
 
 def cpu_baseline(x, n_iters, ntri, cpu_iters):
-    """The oracle, single-threaded, on a bounded sample of the same step:
-    assembly, `cpu_iters` Jacobi-PCG iterations (extrapolated to the float64
-    GPU iteration count of the same algorithm), sensitivity, both filters on
-    the full grid, and the brute-force SDF on a 24x12x12 crop scaled by
-    nodes x triangles."""
+    """The oracle, single-threaded, on a bounded sample of the same step, in
+    two legs.  Measured: assembly of K, `cpu_iters` Jacobi-PCG iterations
+    (their time per iteration extrapolated to the float64 GPU iteration count
+    of the same algorithm), the sensitivity and both filters on the full grid.
+    Extrapolated: the brute-force density->SDF (all nodes against all
+    triangles) on a 24x12x12 crop, scaled by nodes x triangles to the full
+    grid.  `value` is the whole step; `value_solve_sens_filters` leaves the
+    SDF leg out."""
     try:
         from threadpoolctl import threadpool_limits
         limiter = threadpool_limits(1)
@@ -937,14 +1382,25 @@ def cpu_baseline(x, n_iters, ntri, cpu_iters):
     nn_crop = (cx + 1) * (cy + 1) * (cz + 1)
     scale = (nn_full * max(ntri, 1)) / (nn_crop * max(len(Tc), 1))
     t_sdf = t_sdf_crop * scale
-    total = t_asm + n_iters * t_pcg + t_post + t_sdf
+    t_solve = t_asm + n_iters * t_pcg
+    measured = t_asm + it * t_pcg + t_post + t_sdf_crop
     if limiter is not None:
         limiter.unregister() if hasattr(limiter, "unregister") else None
-    return {"value": 1.0 / total, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": ("96x48x48: assembly %.2fs + %d PCG iterations at %.4fs each (extrapolated "
-                       "to %d, the float64 GPU count) + sensitivity/filters %.2fs + brute-force "
-                       "SDF on a 24x12x12 crop %.2fs scaled by nodes x triangles to %.0fs"
-                       % (t_asm, it, t_pcg, n_iters, t_post, t_sdf_crop, t_sdf)),
+    return {"value": 1.0 / (t_solve + t_post + t_sdf), "unit": "solves/s", "cores": 1,
+            "kind": "oracle",
+            "value_solve_sens_filters": 1.0 / (t_solve + t_post),
+            "legs_s": {"assembly": round(t_asm, 3), "pcg_per_iteration": round(t_pcg, 5),
+                       "solve_extrapolated": round(t_solve, 2),
+                       "sensitivity_and_filters": round(t_post, 3),
+                       "sdf_crop_measured": round(t_sdf_crop, 3),
+                       "sdf_extrapolated": round(t_sdf, 1)},
+            "cpu_seconds_measured": round(measured, 2),
+            "sample": ("96x48x48, one thread. Measured: assembly %.2fs, %d PCG iterations at "
+                       "%.4fs each, sensitivity and both filters %.2fs (full grid), brute-force "
+                       "SDF of a 24x12x12 crop %.2fs. Extrapolated: the solve to %d iterations "
+                       "(the float64 GPU count of the same algorithm) = %.0fs; the SDF by nodes x "
+                       "triangles (%d) to %.0fs"
+                       % (t_asm, it, t_pcg, t_post, t_sdf_crop, n_iters, t_solve, ntri, t_sdf)),
             "host": platform.processor() or platform.machine(), "os_cpu_count": os.cpu_count()}
 
 

@@ -244,7 +244,7 @@ typedef struct {
 to_status to_simp(to_ctx *ctx, const to_simp_params *sp, double *d_x, double *d_u, double *d_work,
                   double *h_c_hist, to_simp_info *info);
 
-/* Level-set evolution (Sec. 2.2.4): nsteps forward-Euler steps of the
+/* Level-set evolution (Sec. 2.2.7): nsteps forward-Euler steps of the
  * Hamilton-Jacobi equation phi_t + v |grad phi| = 0 (Eq. 21) with the
  * first-order Godunov upwind stencil on the node grid, at
  * dt = gamma h / max|v| (the CFL bound of Eq. 22 times the CFL number gamma).
@@ -260,7 +260,7 @@ to_status to_simp(to_ctx *ctx, const to_simp_params *sp, double *d_x, double *d_
 to_status to_ls_advect(to_ctx *ctx, double *d_phi, const double *d_v, double gamma,
                        int32_t nsteps, double *h_dt);
 
-/* Reinitialisation (Sec. 2.2.5): pseudo-steps of
+/* Reinitialisation (Sec. 2.2.8): pseudo-steps of
  * phi_t + S(phi)(|grad phi| - 1) = 0 (Eq. 23) with the same stencil and the
  * smeared sign S = phi / sqrt(phi^2 + h^2 |grad phi|^2) (Eq. 24) taken from
  * the current phi at every pseudo-step (|grad phi| by central differences,
@@ -275,7 +275,7 @@ to_status to_ls_advect(to_ctx *ctx, double *d_phi, const double *d_v, double gam
 to_status to_ls_reinit(to_ctx *ctx, double *d_phi, double gamma, double tol, int32_t max_steps,
                        int32_t *h_steps, double *h_change);
 
-/* Relaxed shape derivative (Sec. 2.2.2): the nodal vector of Eqs. 15-17,
+/* Relaxed shape derivative (Sec. 2.2.5): the nodal vector of Eqs. 15-17,
  *   g_a = sum_e sum_q w_q h^3 N_a(q) (c_s s(q) + c_0) H'_eta(phi(q)) |grad phi(q)|,
  * over the 2x2x2 Gauss points q of every voxel, with phi and u trilinear on
  * it, s = sigma:eps = lambda (tr eps)^2 + 2 mu eps:eps at the solid's E0 and
@@ -291,7 +291,7 @@ to_status to_ls_reinit(to_ctx *ctx, double *d_phi, double gamma, double tol, int
 to_status to_shape_rhs(to_ctx *ctx, const double *d_u, const double *d_phi, double eta,
                        double c_s, double c_0, double *d_g);
 
-/* Hilbertian extension-regularisation (Sec. 2.2.3): solves
+/* Hilbertian extension-regularisation (Sec. 2.2.6): solves
  * A_H v = g (Eq. 20), A_H = ell^2 K + M with the trilinear Laplacian and mass
  * of Eq. 19 on the voxel grid, and v = 0 on Gamma_N, the nodes where the
  * context's load vector has a non-zero component (the natural condition

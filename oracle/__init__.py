@@ -27,9 +27,9 @@ Everything is NumPy/SciPy in float64, one step per paper passage:
                                                           set-up of Sec. 4)
   levelset  Hamilton-Jacobi evolution with the CFL step
             and reinitialisation with the smeared sign,
-            first-order Godunov upwind on the node grid  (Secs. 2.2.4-2.2.5,
+            first-order Godunov upwind on the node grid  (Secs. 2.2.7-2.2.8,
                                                           Eqs. 21-24)
   shape     relaxed shape derivative (nodal vector) and
-            the Hilbertian extension A_H vbar = g        (Secs. 2.2.2-2.2.3,
+            the Hilbertian extension A_H vbar = g        (Secs. 2.2.5-2.2.6,
                                                           Eqs. 15-20)
 """

@@ -1,10 +1,10 @@
 """Level-set evolution and reinitialisation on the node grid (oracle, test
 infrastructure only).
 
-Sec. 2.2.4 evolves phi by the Hamilton-Jacobi equation phi_t + v |grad phi| = 0
+Sec. 2.2.7 evolves phi by the Hamilton-Jacobi equation phi_t + v |grad phi| = 0
 (Eq. 21) with forward Euler in time and the first-order Godunov upwind stencil
 in space, for a fixed number of steps with dt = gamma h / max|v| (the CFL bound
-of Eq. 22 scaled by a CFL number gamma in (0, 1)).  Sec. 2.2.5 restores the
+of Eq. 22 scaled by a CFL number gamma in (0, 1)).  Sec. 2.2.8 restores the
 distance property by solving phi_t + S(phi) (|grad phi| - 1) = 0 (Eq. 23) with
 the same scheme, the smeared sign S(phi) = phi / sqrt(phi^2 + h^2 |grad phi|^2)
 (Eq. 24) recomputed from the current phi at every pseudo-step, until the

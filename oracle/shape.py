@@ -1,12 +1,12 @@
 """Relaxed shape derivative and Hilbertian extension-regularisation (oracle,
 test infrastructure only).
 
-Sec. 2.2.2 relaxes the compliance shape derivative (Eq. 14) over the whole
+Sec. 2.2.5 relaxes the compliance shape derivative (Eq. 14) over the whole
 domain D: with a perturbation -w n, J' is the integral over D of
 sigma(u):eps(u) w H'_eta(phi) |grad phi| (Eq. 15); the volume constraint's
 derivative replaces the strain energy density by -1/V_D (Eq. 16); the
 augmented Lagrangian combines them with g_L = sigma:eps + (lambda - Lambda C)/V_D
-(Eqs. 17-18).  Sec. 2.2.3 extends the result to a velocity vbar by the weighted
+(Eqs. 17-18).  Sec. 2.2.6 extends the result to a velocity vbar by the weighted
 H^1 Riesz problem: int ell^2 grad vbar . grad w + vbar w = L'(-w n) for all w
 (Eq. 19), discretised as A_H vbar = g (Eq. 20), with vbar = 0 where the loads
 act (Gamma_N).

@@ -351,6 +351,16 @@ def to_matvec_f32(ctx: Context, x, u, y=None):
     return y
 
 
+def product_kernel_name(f32=True):
+    """Name of the kernel behind to_matvec_f32 (f32) or to_matvec."""
+    return "k_matvec<float, 0>" if f32 else "k_matvec<double, 0>"
+
+
+def cg_product_kernel_name():
+    """Name of the float32 inner-CG product kernel of the one-design solve."""
+    return "k_cg_matvec1<float, false>"
+
+
 class Server:
     """Continuous-batching compliance + sensitivity server (to_server_*).
 

@@ -15,7 +15,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtopo_mi355x.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["abi.cpp", "k_matvec.hip", "k_vector.hip", "k_filter.hip", "k_sdf.hip", "k_oc.hip", "k_levelset.hip", "k_shape.hip", "serve.cpp"]
+SOURCES = ["abi.cpp", "k_matvec.hip", "k_mfma.hip", "k_vector.hip", "k_filter.hip", "k_sdf.hip", "k_oc.hip", "k_levelset.hip", "k_shape.hip", "serve.cpp"]
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          # the first 8 argument dwords of each kernel arrive preloaded in SGPRs

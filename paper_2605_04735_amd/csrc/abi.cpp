@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "common.h"
+#include "refine_rule.h"
 #include "to.h"
 
 using namespace topo;
@@ -77,7 +78,12 @@ struct to_ctx {
   Coef<float> k32{};
   double kd = 0.0;
   double fnorm = 0.0;
-  int kz = 4;
+  int kz = 4;           // z chunk of the vector-ALU products (float64, residuals)
+  // float32 inner products on the matrix cores (the A operand in the
+  // workspace), or on the vector ALUs (mA == nullptr)
+  const void *mA = nullptr;
+  float mscale = 0.f;
+  int kz_mf = 4;        // z chunk of the matrix-core products
   double last_rmin = -1.0;
   int nofs = 0;
   double eta = 1e-4;   // inner relative tolerance of the float32 refinement
@@ -118,7 +124,9 @@ to_status fail(to_ctx *c, to_status s, const std::string &msg) {
 bool validate_problem(const to_problem *p, std::string *why) {
   if (!p) { *why = "problem is NULL"; return false; }
   if (p->nelx < 1 || p->nely < 1 || p->nelz < 1) { *why = "grid sizes must be >= 1"; return false; }
-  const double nn = double(p->nelx + 1) * (p->nely + 1) * (p->nelz + 1);
+  // node counts in double: nelx + 1 in int overflows at INT_MAX
+  const double NX = double(p->nelx) + 1.0, NY = double(p->nely) + 1.0, NZ = double(p->nelz) + 1.0;
+  const double nn = NX * NY * NZ;
   // kernels address a vector with 32-bit byte offsets (2^31 marks a lane
   // outside the grid), so a float64 vector of 3 nn values stays below 2^31 bytes
   if (nn * 24.0 >= 2147483648.0) {
@@ -127,7 +135,7 @@ bool validate_problem(const to_problem *p, std::string *why) {
   }
   // the product keeps one partial sum per block: its x-y tiles must fit
   const double tiles =
-      std::ceil((p->nelx + 1) / double(TNX)) * std::ceil((p->nely + 1) / double(TNY));
+      std::ceil(NX / double(TNX)) * std::ceil(NY / double(TNY));
   if (tiles > MAXB) { *why = "grid too wide in x and y for the product's block bound"; return false; }
   if (!(p->h > 0) || !std::isfinite(p->h)) { *why = "h must be > 0"; return false; }
   if (!(p->E0 > 0) || !std::isfinite(p->E0)) { *why = "E0 must be > 0"; return false; }
@@ -156,8 +164,26 @@ Grid make_grid(const to_problem *p) {
   return g;
 }
 
+// Whether the float32 inner products of this problem run on the matrix cores:
+// only on request (TOPO_MFMA=1), for a float32 inner CG with float32 z, an
+// element matrix exact in bfloat16 for this nu, and tiles within the
+// partial-sum bound.  The vector-ALU modal product is the default: measured
+// at 256 x 128 x 128 it is twice as fast, and its exact differencing of
+// nodal values keeps the float32 operator accurate on elements that carry a
+// large rigid translation, where the matrix cores' accumulation does not.
+bool mfma_path(const Grid &g, int precision, double nu) {
+  if (precision != TO_PREC_FP32_REFINE) return false;
+  const char *e = std::getenv("TOPO_MFMA");
+  if (!e || std::atoi(e) == 0) return false;
+  uint16_t tab[2][64][8];
+  float unit = 0.f;
+  if (!mfma_operand_table(nu, tab, &unit)) return false;
+  const long long tiles = (long long)((g.nelx + MN) / MN) * ((g.nely + MN) / MN);
+  return tiles <= MAXB;
+}
+
 // Carves (or sizes, when base == nullptr) the workspace.
-size_t carve(to_ctx *c, const Grid &g, int precision, char *base) {
+size_t carve(to_ctx *c, const Grid &g, int precision, double nu, char *base) {
   Layout L;
   const size_t oE64 = L.take<double>(g.nel), oE32 = L.take<float>(g.nel);
   const size_t oD64 = L.take<double>(g.nn), oD32 = L.take<float>(g.nn);
@@ -176,9 +202,11 @@ size_t carve(to_ctx *c, const Grid &g, int precision, char *base) {
   const size_t oRho = L.take<double>(g.nn);
   const size_t oCnt = L.take<int>(g.nel), oToff = L.take<int>(g.nel);
   const size_t oBs = L.take<int>(g.nel / 1024 + 4);
-  const int nbm = matvec_blocks(g, matvec_kz(g, precision == TO_PREC_FP64));
+  const bool mf = mfma_path(g, precision, nu);
+  const int nbm = matvec_blocks(g, matvec_kz(g, precision == TO_PREC_FP64, mf), mf);
   const int nbu = update_blocks(g.nn);
   const size_t oCgp = L.take<double>(CGP_SIZE);
+  const size_t oMfma = L.take<uint16_t>(2 * 64 * 8);
   const size_t total = (L.off + 255) & ~size_t(255);
   if (base) {
     c->E64 = (double *)(base + oE64);
@@ -203,6 +231,7 @@ size_t carve(to_ctx *c, const Grid &g, int precision, char *base) {
     c->toff = (int *)(base + oToff);
     c->bsums = (int *)(base + oBs);
     c->cgp = (double *)(base + oCgp);
+    c->mA = mf ? (const void *)(base + oMfma) : nullptr;
     c->nb_mv = nbm;
     c->nb_up = nbu;
   }
@@ -286,9 +315,14 @@ CgDesc<T> make_desc(to_ctx *c, T *const v[6], const T *E, const T *dinv, const C
   d.nelx = g.nelx;
   d.nely = g.nely;
   d.nelz = g.nelz;
-  d.kz = c->kz;
-  d.tx = (g.nelx + 1 + TNX - 1) / TNX;
-  d.ty = (g.nely + 1 + TNY - 1) / TNY;
+  const bool mf = sizeof(T) == 4 && c->mA;
+  d.kz = mf ? c->kz_mf : c->kz;
+  d.tx = mf ? (g.nelx + MN) / MN : (g.nelx + 1 + TNX - 1) / TNX;
+  d.ty = mf ? (g.nely + MN) / MN : (g.nely + 1 + TNY - 1) / TNY;
+  if (mf) {
+    d.mA = c->mA;
+    d.mscale = c->mscale;
+  }
   d.nb_mv = c->nb_mv;
   d.nb_up = c->nb_up;
   d.zbf16 = sizeof(T) == 4 && c->p.precision == TO_PREC_FP32_REFINE_BF16;
@@ -396,7 +430,7 @@ to_status to_workspace_size(const to_problem *prob, size_t *bytes) {
   std::string why;
   if (!bytes) return fail(nullptr, TO_E_INVALID, "bytes is NULL");
   if (!validate_problem(prob, &why)) return fail(nullptr, TO_E_INVALID, why);
-  *bytes = carve(nullptr, make_grid(prob), prob->precision, nullptr);
+  *bytes = carve(nullptr, make_grid(prob), prob->precision, prob->nu, nullptr);
   return TO_OK;
 }
 
@@ -425,7 +459,7 @@ to_status to_create(const to_problem *prob, void *d_workspace, size_t bytes, voi
     return r;
   };
   if (hipGetDevice(&c->device) != hipSuccess) return bail(TO_E_HIP, "hipGetDevice failed");
-  const size_t need = carve(nullptr, c->g, prob->precision, nullptr);
+  const size_t need = carve(nullptr, c->g, prob->precision, prob->nu, nullptr);
   if (d_workspace) {
     if (bytes < need) return bail(TO_E_OOM, "workspace smaller than to_workspace_size()");
     c->ws = (char *)d_workspace;
@@ -435,7 +469,7 @@ to_status to_create(const to_problem *prob, void *d_workspace, size_t bytes, voi
     c->owns_ws = true;
     c->ws_bytes = need;
   }
-  carve(c, c->g, prob->precision, c->ws);
+  carve(c, c->g, prob->precision, prob->nu, c->ws);
   // S_COUNT scalars, then OC_STATE + 8 doubles of optimality-criteria state
   if (hipHostMalloc((void **)&c->h_scal, (S_COUNT + OC_STATE + 8) * sizeof(double),
                     hipHostMallocDefault) !=
@@ -450,7 +484,17 @@ to_status to_create(const to_problem *prob, void *d_workspace, size_t bytes, voi
     c->kd = prob->h * (lam + 4.0 * mu) / 9.0;
   }
   c->kz = matvec_kz(c->g, prob->precision == TO_PREC_FP64);
+  c->kz_mf = matvec_kz(c->g, false, true);
   hipStream_t s = c->stream;
+  if (c->mA) {
+    uint16_t tab[2][64][8];
+    float unit = 0.f;
+    mfma_operand_table(prob->nu, tab, &unit);
+    c->mscale = (float)(unit * prob->h);
+    if (hipMemcpyAsync((void *)c->mA, tab, sizeof(tab), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return bail(TO_E_HIP, "uploading the matrix-core operand failed");
+  }
   // descriptors of the CG kernels (passed by value at each launch)
   if (prob->precision == TO_PREC_FP64) c->hd64 = make_desc<double>(c, c->v64, c->E64, c->dinv64, c->k64);
   else c->hd32 = make_desc<float>(c, c->v32, c->E32, c->dinv32, c->k32);
@@ -524,7 +568,8 @@ to_status to_solve(to_ctx *c, const double *d_x, const double *d_u0, double *d_u
 
   const bool fp64 = c->p.precision == TO_PREC_FP64;
   int outer = 0, total_inner = 0;
-  double rel = 0.0, best = INFINITY, hist[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
+  double rel = 0.0;
+  StagnationRule stall;
   to_status result = TO_OK;
   std::string msg;
   if (c->fnorm == 0.0) {
@@ -547,13 +592,11 @@ to_status to_solve(to_ctx *c, const double *d_x, const double *d_u0, double *d_u
       }
       // attainable accuracy: stop when four refinement passes have not halved
       // the float64 residual
-      hist[outer % 4] = rel;
-      if (outer >= 4 && rel > 0.5 * hist[(outer + 1) % 4] && rel > 0.5 * best) {
+      if (stall.record(rel)) {
         result = TO_E_NOCONV;
         msg = "residual stagnated above rtol (attainable accuracy reached)";
         break;
       }
-      best = std::min(best, rel);
       // inner relative tolerance: the whole remaining reduction in float64,
       // eta (or the remaining reduction if smaller) in float32
       const double need = 0.5 * c->p.rtol / rel;
@@ -1006,13 +1049,16 @@ to_status to_matvec_f32(to_ctx *c, const double *d_x, const float *d_u, float *d
   a.nelx = c->g.nelx;
   a.nely = c->g.nely;
   a.nelz = c->g.nelz;
-  a.kz = c->kz;
+  a.kz = c->mA ? c->kz_mf : c->kz;
   a.E = c->E32;
   a.in = d_u;
   a.out = d_y;
   a.mask = c->mask;
   a.k = c->k32;
-  HIPCHK((launch_matvec<float, MV_APPLY>(a, nullptr, c->stream)));
+  a.mA = c->mA;
+  a.mscale = c->mscale;
+  if (c->mA) HIPCHK(launch_matvec_mfma(a, nullptr, c->stream));
+  else HIPCHK((launch_matvec<float, MV_APPLY>(a, nullptr, c->stream)));
   return TO_OK;
 }
 

@@ -73,6 +73,10 @@ static_assert(TPX * TPY <= 2 * MV_THREADS, "a node plane is staged in two slots 
 
 enum MvMode { MV_APPLY = 0, MV_CG = 1, MV_RESID = 2 };
 
+// Tile of the matrix-core (MFMA) float32 product: ME x ME elements per z
+// layer, MN x MN owned nodes (see k_mfma.hip).
+constexpr int ME = 16, MN = ME - 1;
+
 // Unit-modulus coefficients of the factored hex8 stiffness (see k_matvec.hip),
 // already multiplied by h/32.
 template <typename T>
@@ -94,6 +98,8 @@ struct MvArgs {
   const double *scal;    // CG: reads S_BETA
   const int *flags;      // CG: early exit when flags[F_DONE]
   Coef<T> k;
+  const void *mA;        // matrix-core float32 product: the A operand (2 x 64 x 16 bytes)
+  float mscale;          //   and the element scale h mu / 72 (times E_e)
 };
 
 // One design of a batched inner CG solve (device resident).  The product
@@ -106,6 +112,9 @@ struct CgDesc {
   int zbf16, pad_;      // float32 CG: z stored in bfloat16 (2 bytes per component)
   long long nn;
   Coef<T> k;
+  const void *mA;       // float32: the matrix-core product's A operand, or NULL for the
+  float mscale;         //   vector-ALU product (then tx, ty, kz and nb_mv are its tiles')
+  int pad2_;
   const T *E;
   const T *dinv;
   const uint8_t *mask;
@@ -192,8 +201,13 @@ struct Grid {
 // ---------------------------------------------------------------- launchers
 template <typename T, int MODE>
 hipError_t launch_matvec(const MvArgs<T> &a, int *nblocks, hipStream_t s);
-int matvec_kz(const Grid &g, bool fp64);
-int matvec_blocks(const Grid &g, int kz);
+int matvec_kz(const Grid &g, bool fp64, bool mfma = false);
+int matvec_blocks(const Grid &g, int kz, bool mfma = false);
+// matrix-core float32 product (k_mfma.hip): the A operand for Poisson ratio
+// nu (false when M = B + (lambda/mu) A is not exact in bfloat16), and the
+// unit-cube scale mu / 72
+bool mfma_operand_table(double nu, uint16_t out[2][64][8], float *mscale_unit);
+hipError_t launch_matvec_mfma(const MvArgs<float> &a, int *nblocks, hipStream_t s);
 
 hipError_t launch_modulus(const Grid &g, const double *x, double E0, double Emin, double penal,
                           double *E64, float *E32, int *flags, hipStream_t s);

@@ -1,5 +1,5 @@
-// Level-set evolution and reinitialisation on the node grid (Sec. 2.2.4,
-// Eqs. 21-22; Sec. 2.2.5, Eqs. 23-24): forward Euler in time, first-order
+// Level-set evolution and reinitialisation on the node grid (Sec. 2.2.7,
+// Eqs. 21-22; Sec. 2.2.8, Eqs. 23-24): forward Euler in time, first-order
 // Godunov upwinding in space.
 //
 // With one-sided differences D-, D+ along each axis (the missing neighbour at

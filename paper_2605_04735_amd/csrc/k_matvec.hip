@@ -32,6 +32,7 @@
 
 #include "common.h"
 #include "device_common.h"
+#include "mfma_block.h"
 
 namespace topo {
 
@@ -295,11 +296,10 @@ void k_matvec(const MvArgs<T> a, int tx, int ty) {
 // parity^1): converged designs stop here; otherwise beta = (r^T z)_new /
 // (r^T z)_old, p = z + beta p_old, q = K p, and the block's p^T q partial is
 // written for the update kernel.
-template <typename T, bool ZBF = false>
+template <typename T, bool ZBF = false, bool MF = false>
 __device__ __forceinline__ void cg_matvec_block(const CgDesc<T> &d, double *scal, int *flags,
                                                 double *cgp, int nparts, int lb_in, int parity) {
-  __shared__ T pl[2][3][TPX * TPY];
-  __shared__ T ex[6][MV_THREADS];
+  static_assert(!MF || (sizeof(T) == 4 && !ZBF), "matrix-core product: float32 CG, float32 z");
   __shared__ double red[16];
   bool run = false;
   // the r^T z and ||r||^2 partials are loaded before the first planes, the
@@ -343,6 +343,8 @@ __device__ __forceinline__ void cg_matvec_block(const CgDesc<T> &d, double *scal
   a.out = d.q;
   a.mask = d.mask;
   a.k = d.k;
+  a.mA = d.mA;
+  a.mscale = d.mscale;
   const int tx = d.tx, ty = d.ty;
   // local block: from the table (batched), or this block's place (mv_local)
   const int lb = lb_in >= 0 ? lb_in : mv_local((int)blockIdx.x, tx * ty, d.nb_mv / (tx * ty));
@@ -380,7 +382,14 @@ __device__ __forceinline__ void cg_matvec_block(const CgDesc<T> &d, double *scal
     return true;
   };
   double s;
-  s = matvec_block<T, MV_CG, ZBF>(a, bx, by, bz, [] {}, get_beta, pl, ex, red);
+  if constexpr (MF) {
+    __shared__ MfmaLds S;
+    s = mfma_block<MV_CG>(a, bx, by, bz, [] {}, get_beta, S, red);
+  } else {
+    __shared__ T pl[2][3][TPX * TPY];
+    __shared__ T ex[6][MV_THREADS];
+    s = matvec_block<T, MV_CG, ZBF>(a, bx, by, bz, [] {}, get_beta, pl, ex, red);
+  }
   if (run && threadIdx.x == 0) cgp[CGP_PQ + lb] = s;
 }
 
@@ -397,11 +406,11 @@ __global__ __launch_bounds__(MV_THREADS) void k_cg_matvec(const CgDesc<T> *descs
 // sums, parity and partial count lead the arguments (8 dwords) so that they
 // arrive preloaded in SGPRs: the block's first loads (the previous reduction)
 // need no argument load before them.
-template <typename T, bool ZBF>
+template <typename T, bool ZBF, bool MF = false>
 __global__ __launch_bounds__(MV_THREADS) void k_cg_matvec1(double *scal, int *flags, double *cgp,
                                                            int parity, int nparts,
                                                            const CgDesc<T> d) {
-  cg_matvec_block<T, ZBF>(d, scal, flags, cgp, nparts, -1, parity);
+  cg_matvec_block<T, ZBF, MF>(d, scal, flags, cgp, nparts, -1, parity);
 }
 
 // Batched CG vector update: every block completes the p^T q reduction of the
@@ -551,9 +560,10 @@ int kz_for_target(int NZ, int tiles, int target) {
 }
 }  // namespace
 
-int matvec_kz(const Grid &g, bool fp64) {
+int matvec_kz(const Grid &g, bool fp64, bool mfma) {
   const int NX = g.nelx + 1, NY = g.nely + 1, NZ = g.nelz + 1;
-  const int tiles = ((NX + TNX - 1) / TNX) * ((NY + TNY - 1) / TNY);
+  const int tnx = mfma ? MN : TNX, tny = mfma ? MN : TNY;
+  const int tiles = ((NX + tnx - 1) / tnx) * ((NY + tny - 1) / tny);
   if (const char *e = getenv("TOPO_KZ")) {
     int v = atoi(e);
     if (v >= 1) {
@@ -578,9 +588,10 @@ int matvec_kz(const Grid &g, bool fp64) {
   return kz;
 }
 
-int matvec_blocks(const Grid &g, int kz) {
+int matvec_blocks(const Grid &g, int kz, bool mfma) {
   const int NX = g.nelx + 1, NY = g.nely + 1, NZ = g.nelz + 1;
-  return ((NX + TNX - 1) / TNX) * ((NY + TNY - 1) / TNY) * ((NZ + kz - 1) / kz);
+  const int tnx = mfma ? MN : TNX, tny = mfma ? MN : TNY;
+  return ((NX + tnx - 1) / tnx) * ((NY + tny - 1) / tny) * ((NZ + kz - 1) / kz);
 }
 
 template <typename T, int MODE>
@@ -630,12 +641,24 @@ hipError_t launch_cg_matvec1(const CgDesc<T> &d, int parity, hipStream_t s, hipE
       return hipGetLastError();
     }
   }
+  const dim3 grid(mv_grid(d.tx * d.ty, d.nb_mv / (d.tx * d.ty)));
+  if constexpr (sizeof(T) == 4) {
+    if (d.mA) {
+      if (start && stop)
+        hipExtLaunchKernelGGL((k_cg_matvec1<T, false, true>), grid, dim3(MV_THREADS), 0, s, start,
+                              stop, 0, d.scal, d.flags, d.cgp, parity, d.nb_up, d);
+      else
+        hipLaunchKernelGGL((k_cg_matvec1<T, false, true>), grid, dim3(MV_THREADS), 0, s, d.scal,
+                           d.flags, d.cgp, parity, d.nb_up, d);
+      return hipGetLastError();
+    }
+  }
   if (start && stop)
-    hipExtLaunchKernelGGL((k_cg_matvec1<T, false>), dim3(mv_grid(d.tx * d.ty, d.nb_mv / (d.tx * d.ty))), dim3(MV_THREADS), 0, s, start,
-                          stop, 0, d.scal, d.flags, d.cgp, parity, d.nb_up, d);
+    hipExtLaunchKernelGGL((k_cg_matvec1<T, false>), grid, dim3(MV_THREADS), 0, s, start, stop, 0,
+                          d.scal, d.flags, d.cgp, parity, d.nb_up, d);
   else
-    hipLaunchKernelGGL((k_cg_matvec1<T, false>), dim3(mv_grid(d.tx * d.ty, d.nb_mv / (d.tx * d.ty))), dim3(MV_THREADS), 0, s, d.scal,
-                       d.flags, d.cgp, parity, d.nb_up, d);
+    hipLaunchKernelGGL((k_cg_matvec1<T, false>), grid, dim3(MV_THREADS), 0, s, d.scal, d.flags,
+                       d.cgp, parity, d.nb_up, d);
   return hipGetLastError();
 }
 
@@ -667,6 +690,8 @@ hipError_t build_cg_graph(const CgDesc<T> &d, int parity0, int iters, hipGraphEx
     if (d.zbf16) {
       fmv = (void *)k_cg_matvec1<T, true>;
       fup = (void *)k_cg_update1<T, true>;
+    } else if (d.mA) {
+      fmv = (void *)k_cg_matvec1<T, false, true>;
     }
   }
   hipGraphNode_t prev = nullptr;

@@ -1,5 +1,5 @@
-// Relaxed shape derivative (Sec. 2.2.2, Eqs. 15-18) and Hilbertian
-// extension-regularisation (Sec. 2.2.3, Eqs. 19-20) on the voxel grid.
+// Relaxed shape derivative (Sec. 2.2.5, Eqs. 15-18) and Hilbertian
+// extension-regularisation (Sec. 2.2.6, Eqs. 19-20) on the voxel grid.
 //
 // Nodal shape-derivative vector: with trilinear phi and u on each voxel and
 // a 2x2x2 Gauss rule,

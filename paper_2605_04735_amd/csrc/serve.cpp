@@ -34,6 +34,7 @@
 #include <vector>
 
 #include "common.h"
+#include "refine_rule.h"
 #include "to.h"
 
 using namespace topo;
@@ -119,7 +120,7 @@ struct Slot {
   size_t stage_cap = 0;
   double fnorm = -1.0;
   int outer = 0, inner_total = 0;
-  double hist[4] = {0, 0, 0, 0}, best = 0.0;  // float64 residual history (stagnation)
+  StagnationRule stall;  // float64 residual history (attainable accuracy)
   int32_t fail = TO_OK;
 };
 
@@ -300,6 +301,7 @@ bool admit(to_server *s, Slot &sl, Request &&rq) {
   sl.fnorm = -1.0;
   sl.outer = 0;
   sl.inner_total = 0;
+  sl.stall = StagnationRule{};
   sl.fail = TO_OK;
   if (sl.stage_cap < sl.g.nel) {
     if (sl.h_stage) hipHostFree(sl.h_stage);
@@ -518,13 +520,10 @@ void server_loop(to_server *s) {
       // attainable accuracy: four refinement passes that have not halved the
       // float64 residual end the request (same rule as the one-design solve)
       if (!finish) {
-        if (sl.outer == 0) sl.best = rel;
-        sl.hist[sl.outer % 4] = rel;
-        if (sl.outer >= 4 && rel > 0.5 * sl.hist[(sl.outer + 1) % 4] && rel > 0.5 * sl.best) {
+        if (sl.stall.record(rel)) {
           sl.fail = TO_E_NOCONV;
           finish = true;
         }
-        sl.best = std::min(sl.best, rel);
       }
       if (finish) {
         int nb = 0;

@@ -54,6 +54,12 @@ def test_workspace_size_validates_problem():
         with pytest.raises(A.TopoError) as e:
             A.to_workspace_size(A.Problem(*dims))
         assert e.value.status == L.TO_E_INVALID
+    # dimensions whose node counts overflow 32-bit ints are rejected, not wrapped
+    INT_MAX = 2 ** 31 - 1
+    for dims in [(INT_MAX, 1, 1), (1, INT_MAX, 1), (1, 1, INT_MAX), (INT_MAX,) * 3]:
+        with pytest.raises(A.TopoError) as e:
+            A.to_workspace_size(A.Problem(*dims))
+        assert e.value.status == L.TO_E_INVALID
     # the largest accepted grids size normally
     assert A.to_workspace_size(A.Problem(440, 440, 440)) > 0
     assert A.to_workspace_size(A.Problem(1200, 1200, 2)) > 0
@@ -116,3 +122,51 @@ def test_null_context_is_rejected_before_any_device_work():
         st = getattr(lib, name)(*args)
         assert st == L.TO_E_INVALID, name
         assert lib.to_last_error(None), name
+
+
+STALL_DRIVER = r"""
+#include <cstdio>
+#include <cstdlib>
+#include "refine_rule.h"
+// reads residuals from argv, prints the index of the first stalled record (-1: none)
+int main(int argc, char **argv) {
+  topo::StagnationRule r;
+  for (int i = 1; i < argc; ++i)
+    if (r.record(std::atof(argv[i]))) { std::printf("%d\n", i - 1); return 0; }
+  std::printf("-1\n");
+  return 0;
+}
+"""
+
+
+def test_refinement_stagnation_rule(tmp_path):
+    """The refinement's attainable-accuracy stop, compiled on its own from the
+    header both the one-design solve and the server use: it fires only when the
+    residual after pass n is not below half the residual after pass n - 4."""
+    src = tmp_path / "stall.cpp"
+    src.write_text(STALL_DRIVER)
+    exe = tmp_path / "stall"
+    subprocess.run(["g++", "-std=c++17", "-I", os.path.join(ROOT, "paper_2605_04735_amd", "csrc"),
+                    str(src), "-o", str(exe)], check=True)
+
+    def first_stall(seq):
+        out = subprocess.run([str(exe)] + ["%.17g" % v for v in seq], capture_output=True,
+                             text=True, check=True).stdout
+        return int(out)
+
+    # slow but steady progress: 0.84 per pass halves the residual in four passes
+    # (0.84^4 = 0.498), so it never stalls; a three-pass window (0.84^3 = 0.593)
+    # would have stopped it at the fourth pass
+    assert first_stall([0.84 ** k for k in range(40)]) == -1
+    # progress that stops: flat after the third pass
+    seq = [1.0, 0.1, 0.01, 0.005, 0.005, 0.005, 0.005, 0.005, 0.005]
+    # records 3..6 compare with 1.0, 0.1, 0.01, 0.005 (four back): the first
+    # that is not below half of it is record 7 (0.005 vs 0.005 / 2 at record 3)
+    assert first_stall(seq) == 7
+    # exactly half four passes back does not stall; just above half does
+    assert first_stall([1.0, 0.9, 0.8, 0.7, 0.5]) == -1
+    assert first_stall([1.0, 0.9, 0.8, 0.7, 0.5000001]) == 4
+    # a NaN residual counts as no progress
+    assert first_stall([1.0, 0.9, 0.8, 0.7, float("nan")]) == 4
+    # fewer than five records never stall
+    assert first_stall([1.0, 1.0, 1.0, 1.0]) == -1

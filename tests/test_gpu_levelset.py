@@ -1,5 +1,5 @@
-"""GPU parity of level-set evolution (Sec. 2.2.4, Eqs. 21-22) and
-reinitialisation (Sec. 2.2.5, Eqs. 23-24), through the C ABI, against the
+"""GPU parity of level-set evolution (Sec. 2.2.7, Eqs. 21-22) and
+reinitialisation (Sec. 2.2.8, Eqs. 23-24), through the C ABI, against the
 oracle on the same seeded inputs.
 
 Both sides evaluate the same expressions in the same order with correctly

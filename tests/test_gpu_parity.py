@@ -2,7 +2,8 @@
 the same seeded inputs.
 
 Tolerances: operator products in float64 <= 1e-13 (relative 2-norm); float64
-solve u, c <= 1e-8; float32-inner/float64-refined solve u, c, dc <= 1e-6;
+solve u, c <= 1e-8; float32-inner/float64-refined solve c, dc and u (energy
+norm) <= 1e-6;
 compliance/sensitivity kernels on the oracle's own u <= 1e-12; filters, node
 densities and triangle counts exact; signed distance <= 1e-12 h; vf <= 1e-12.
 """
@@ -31,6 +32,13 @@ def rel2(a, b):
     return np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300)
 
 
+def knorm_rel(K, u, uref):
+    """||u - u_ref||_K / ||u_ref||_K with the oracle's assembled K (u and
+    u_ref vanish on the fixed DOFs, so this is the reduced system's norm)."""
+    e = np.asarray(u) - np.asarray(uref)
+    return float(np.sqrt(max(e @ (K @ e), 0.0) / (uref @ (K @ uref))))
+
+
 def oracle_K(nelx, nely, nelz, x, prob):
     K0 = element.k0(prob.nu, prob.h)
     E = fem.modulus(x, prob.E0, prob.Emin, prob.penal)
@@ -41,7 +49,7 @@ def oracle_K(nelx, nely, nelz, x, prob):
 @pytest.mark.parametrize("dims,bc", [((40, 33, 19), A.BC_CANTILEVER), ((40, 33, 19), A.BC_MBB),
                                      ((24, 12, 6), A.BC_CANTILEVER), ((3, 2, 5), A.BC_MBB),
                                      ((31, 16, 7), A.BC_CUSTOM)])
-def test_matvec_f64_and_f32_vs_oracle(dims, bc):
+def test_matvec_f64_and_f32_vs_oracle(dims, bc, monkeypatch):
     nelx, nely, nelz = dims
     print("matvec", dims, bc, flush=True)
     rng = np.random.default_rng(sum(dims) + bc)
@@ -59,13 +67,23 @@ def test_matvec_f64_and_f32_vs_oracle(dims, bc):
     yref = fem.apply_masked(K, fixed, u)
     assert rel2(y, yref) <= 1e-13
     assert np.array_equal(y[fixed], u[fixed])
-    y32 = cpu(A.to_matvec_f32(ctx, gpu(x), gpu(u.astype(np.float32)))).astype(np.float64)
+    # float32: on a float64 context and a float32-inner one (vector-ALU
+    # product), and with the matrix-core product requested (used where its
+    # element matrix is exact in bfloat16, as for nu = 0.3)
     yref32 = fem.apply_masked(K, fixed, u.astype(np.float32).astype(np.float64))
-    assert rel2(y32, yref32) <= 2e-6
+    ctx32 = A.to_create(A.Problem(nelx, nely, nelz, bc=bc, precision=A.PREC_FP32_REFINE, **kw))
+    monkeypatch.setenv("TOPO_MFMA", "1")
+    ctxmf = A.to_create(A.Problem(nelx, nely, nelz, bc=bc, precision=A.PREC_FP32_REFINE, **kw))
+    monkeypatch.delenv("TOPO_MFMA")
+    for c in (ctx, ctx32, ctxmf):
+        y32 = cpu(A.to_matvec_f32(c, gpu(x), gpu(u.astype(np.float32)))).astype(np.float64)
+        assert rel2(y32, yref32) <= 2e-6
+        assert np.array_equal(y32[fixed], u.astype(np.float32)[fixed].astype(np.float64))
 
 
-def test_element_apply_reproduces_k0_columns():
+def test_element_apply_reproduces_k0_columns(monkeypatch):
     """On one voxel with nothing fixed and E = 1 the operator is k0 itself."""
+    monkeypatch.setenv("TOPO_MFMA", "1")
     for nu, h in ((0.3, 1.0), (0.45, 0.05)):
         prob = A.Problem(1, 1, 1, h=h, nu=nu, Emin=0.0, penal=1.0, bc=A.BC_CUSTOM,
                          fixed_mask=np.zeros(24, bool), load=np.zeros(24))
@@ -73,6 +91,21 @@ def test_element_apply_reproduces_k0_columns():
         x = gpu(np.ones(1))
         cols = np.stack([cpu(A.to_matvec(ctx, x, gpu(np.eye(24)[j]))) for j in range(24)], axis=1)
         assert np.max(np.abs(cols - element.k0(nu, h))) <= 1e-15
+        # float32 product of a float32-inner context with the matrix-core
+        # product requested: used at nu = 0.3, the vector-ALU fallback at
+        # nu = 0.45 (its element matrix is not exact in bfloat16)
+        ctx32 = A.to_create(A.Problem(1, 1, 1, h=h, nu=nu, Emin=0.0, penal=1.0, bc=A.BC_CUSTOM,
+                                      fixed_mask=np.zeros(24, bool), load=np.zeros(24),
+                                      precision=A.PREC_FP32_REFINE))
+        e32 = np.eye(24, dtype=np.float32)
+        cols = np.stack([cpu(A.to_matvec_f32(ctx32, x, gpu(e32[j]))) for j in range(24)], axis=1)
+        k0 = element.k0(nu, h)
+        assert np.max(np.abs(cols - k0)) <= 2e-7 * np.abs(k0).max()
+        # rigid translations are in the kernel exactly
+        for c in range(3):
+            t = np.zeros(24, np.float32)
+            t[c::3] = 1.7
+            assert np.all(cpu(A.to_matvec_f32(ctx32, x, gpu(t))) == 0.0)
 
 
 def test_matvec_full_size_sampled_rows():
@@ -137,22 +170,51 @@ def test_product_and_solve_256x128x128():
                                                                    info["rel_res"], c), flush=True)
 
 
+def _golden(name):
+    import json
+    import os
+    d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    meta = json.load(open(os.path.join(d, name + ".json")))
+    arr = np.load(os.path.join(d, name + ".npz"))
+    return meta, arr["u"], arr["dc"]
+
+
+def _phi_sample(phin, nn, rng, per_stratum=1000):
+    """Nodes for the brute-force distance check: half within 2h of the surface
+    (the search's first pass settles them), half beyond (the coarse-cell ring
+    walk settles them), and the ten farthest."""
+    near = np.flatnonzero(np.abs(phin) <= 2.0)
+    far = np.flatnonzero(np.abs(phin) > 2.0)
+    pick = [rng.choice(near, min(per_stratum, near.size), replace=False),
+            rng.choice(far, min(per_stratum, far.size), replace=False),
+            np.argsort(-np.abs(phin))[:10]]
+    return np.unique(np.concatenate(pick)), near.size, far.size
+
+
 def test_bench_step_96x48x48():
     """The benchmark's step at its full size and in its launch set-up
-    (cantilever 96 x 48 x 48, random field l = 6, kappa = 2, seed 1,
-    float32-inner / float64-refined solve), against the oracle on outputs it
-    can compute one by one: residual rows at sampled nodes; the compliance and
+    (cantilever 96 x 48 x 48, random field l = 6, kappa = 2, seed 1), at the
+    outer tolerance the benchmark times (1e-5, the loosest rung whose errors
+    meet the targets on its calibration seeds), in both precisions, against
+    the oracle's own solution of the same design (Jacobi-PCG to 1e-10, stored
+    by tests/golden/make_bench_golden.py): c and dc (2-norm) within 1e-6 and u
+    within 1e-6 in the energy norm of Eq. 2.  Then, on outputs the oracle can
+    compute one by one: residual rows at sampled nodes; the compliance and
     every sensitivity from the oracle's element energies of the returned u;
     both filters over the whole grid; the nodal densities, the triangle count,
-    brute-force distances at sampled and at the farthest nodes, and the volume
-    fraction of the returned field."""
+    brute-force distances (Eqs. 28-29) at 2000 nodes split between the
+    search's near pass and its ring walk, and the volume fraction of the
+    returned field."""
     nelx, nely, nelz = 96, 48, 48
     print("bench step", (nelx, nely, nelz), flush=True)
+    meta, u_or, dc_or = _golden("cantilever_96x48x48_seed1")
     x = inputs.random_field(nelx, nely, nelz, seed=1, ell=6.0, kappa=2.0)
     xg = gpu(x)
     E = fem.modulus(x, 1.0, 1e-9, 3.0)
     K0 = element.k0(0.3, 1.0)
+    K = fem.assemble(nelx, nely, nelz, E, K0)
     fixed, f = fem.problem_arrays(nelx, nely, nelz, A.BC_CANTILEVER)
+    c_or = meta["c"]
     NX, NY = nelx + 1, nely + 1
     nn = NX * NY * (nelz + 1)
     rng = np.random.default_rng(11)
@@ -160,17 +222,21 @@ def test_bench_step_96x48x48():
     picks += list(rng.choice(nn, 200, replace=False))
     # the float64 path (its own z chunks) first, then the benchmark's path
     for prec in (A.PREC_FP64, A.PREC_FP32_REFINE):
-        ctx = A.to_create(A.Problem(nelx, nely, nelz, precision=prec, rtol=1e-8))
+        ctx = A.to_create(A.Problem(nelx, nely, nelz, precision=prec, rtol=1e-5))
         u, info, st = A.to_solve(ctx, xg)
-        assert st == A.L.TO_OK and info["rel_res"] <= 1e-8
+        assert st == A.L.TO_OK and info["rel_res"] <= 1e-5
         un = cpu(u)
+        c, dc = A.to_compliance_sensitivity(ctx, xg, u)
+        dcn = cpu(dc)
+        e_c, e_dc, e_uK = abs(c - c_or) / abs(c_or), rel2(dcn, dc_or), knorm_rel(K, un, u_or)
+        print("prec %d rtol 1e-5: %d inner, err vs oracle c %.2e dc %.2e u_K %.2e u_2 %.2e"
+              % (prec, info["inner_iters"], e_c, e_dc, e_uK, rel2(un, u_or)), flush=True)
+        assert e_c <= 1e-6 and e_dc <= 1e-6 and e_uK <= 1e-6
         r = f.reshape(-1, 3)[picks] - fem.apply_rows(nelx, nely, nelz, E, K0, un, fixed, picks)
         r[fixed.reshape(-1, 3)[picks]] = 0.0
-        assert np.max(np.abs(r)) <= 1e-8 * np.linalg.norm(f)
-        c, dc = A.to_compliance_sensitivity(ctx, xg, u)
+        assert np.max(np.abs(r)) <= 1e-5 * np.linalg.norm(f)
         assert abs(c - fem.compliance(f, un)) <= 1e-12 * abs(c)
         dref = fem.sensitivity(x, fem.element_energy(nelx, nely, nelz, K0, un), 1.0, 1e-9, 3.0)
-        dcn = cpu(dc)
         assert np.max(np.abs(dcn - dref)) <= 1e-12 * np.abs(dref).max()
     xf = cpu(A.to_filter(ctx, 1.5, A.FILTER_DENS, xg))
     assert np.array_equal(xf, filters.density_filter(x, nelx, nely, nelz, 1.5))
@@ -182,13 +248,14 @@ def test_bench_step_96x48x48():
     assert np.array_equal(rhon, rho_r)
     T, _, _ = sdf.marching_tets(rho_r, nelx, nely, nelz, 1.0, 0.5)
     assert A.last_triangle_count(ctx) == len(T)
-    npk = np.concatenate([rng.choice(nn, 30, replace=False), np.argsort(-np.abs(phin))[:10]])
+    npk, n_near, n_far = _phi_sample(phin, nn, rng)
+    assert npk.size >= 2000
     pts = grid.node_coords(nelx, nely, nelz, 1.0)[npk]
     phi_r = sdf.signed_distance(sdf.unsigned_distance_vec(pts, T), rho_r[npk], 0.5)
     assert np.max(np.abs(phin[npk] - phi_r)) <= 1e-12
     assert np.max(np.abs(vfn - sdf.volume_fraction(phin, nelx, nely, nelz, 1.0))) <= 1e-12
-    print("bench step: %d inner iterations, c %.9e, %d triangles, max |phi| %.3f"
-          % (info["inner_iters"], c, len(T), np.abs(phin).max()), flush=True)
+    print("bench step: %d triangles, phi checked at %d nodes (%d near, %d far in the grid), "
+          "max |phi| %.3f" % (len(T), npk.size, n_near, n_far, np.abs(phin).max()), flush=True)
 
 
 def test_mbb_ersatz_pipeline_192x64x32():
@@ -210,7 +277,8 @@ def test_mbb_ersatz_pipeline_192x64x32():
     NX, NY = nelx + 1, nely + 1
     nn = NX * NY * (nelz + 1)
     rng = np.random.default_rng(12)
-    npk = np.concatenate([rng.choice(nn, 30, replace=False), np.argsort(-np.abs(phin))[:10]])
+    npk, n_near, n_far = _phi_sample(phin, nn, rng)
+    assert npk.size >= 2000
     pts = grid.node_coords(nelx, nely, nelz, 1.0)[npk]
     phi_r = sdf.signed_distance(sdf.unsigned_distance_vec(pts, T), rho_r[npk], 0.5)
     assert np.max(np.abs(phin[npk] - phi_r)) <= 1e-12
@@ -270,17 +338,19 @@ def test_solve_vs_oracle(name, dims, bc, kind, prec):
     assert info["rel_res"] <= rtol
     c, dc = A.to_compliance_sensitivity(ctx, xg, u)
     uref, cref, dcref = _oracle_solution(nelx, nely, nelz, x, prob)
-    # float64: u, c, dc <= 1e-8.  float32 inner + float64 refinement (CG
-    # directions stored in float32 or bfloat16): c and dc <= 1e-6; u only to
-    # 1e-5, because with E_min = 1e-9 the displacement of near-void regions is
-    # barely determined by the residual (their stiffness is below float32
-    # resolution next to solid elements) while it hardly enters c or dc.
+    # float64: u (2-norm), c, dc <= 1e-8.  float32 inner + float64 refinement
+    # (z stored in float32 or bfloat16): c, dc and u <= 1e-6, with u measured
+    # in the energy norm of Eq. 2, ||u - u_ref||_K / ||u_ref||_K; the 2-norm
+    # error of u is printed beside it.
     tol = 1e-8 if prec == A.PREC_FP64 else 1e-6
-    tol_u = 1e-8 if prec == A.PREC_FP64 else 1e-5
     un = cpu(u)
-    print("err_u %.2e err_c %.2e err_dc %.2e" % (rel2(un, uref), abs(c - cref) / abs(cref),
-                                                rel2(cpu(dc), dcref)))
-    assert rel2(un, uref) <= tol_u
+    K, _, _ = oracle_K(nelx, nely, nelz, x, prob)
+    err_u2, err_uK = rel2(un, uref), knorm_rel(K, un, uref)
+    print("err_u %.2e (K-norm %.2e) err_c %.2e err_dc %.2e"
+          % (err_u2, err_uK, abs(c - cref) / abs(cref), rel2(cpu(dc), dcref)), flush=True)
+    if prec == A.PREC_FP64:
+        assert err_u2 <= tol
+    assert err_uK <= tol
     assert abs(c - cref) <= tol * abs(cref)
     assert rel2(cpu(dc), dcref) <= tol
     fixed, _ = fem.problem_arrays(nelx, nely, nelz, bc)

@@ -1,5 +1,5 @@
-"""GPU parity of the relaxed shape derivative (Sec. 2.2.2, Eqs. 15-18) and the
-Hilbertian extension (Sec. 2.2.3, Eqs. 19-20), through the C ABI, against the
+"""GPU parity of the relaxed shape derivative (Sec. 2.2.5, Eqs. 15-18) and the
+Hilbertian extension (Sec. 2.2.6, Eqs. 19-20), through the C ABI, against the
 oracle on the same seeded inputs.
 
   * nodal vector: the same Gauss sums in another order (the GPU writes the

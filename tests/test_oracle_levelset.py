@@ -1,5 +1,5 @@
-"""Pins for the oracle's level-set evolution and reinitialisation (Sec. 2.2.4,
-Eqs. 21-22; Sec. 2.2.5, Eqs. 23-24).
+"""Pins for the oracle's level-set evolution and reinitialisation (Sec. 2.2.7,
+Eqs. 21-22; Sec. 2.2.8, Eqs. 23-24).
 
   * hand-worked single steps on a 1D profile (phi = x^2 with v = +1 and -1, a
     slope-2 line under reinitialisation), whose values follow from the

@@ -154,3 +154,41 @@ def test_triangle_counts_per_voxel_are_bounded():
     T, owner, counts = sdf.marching_tets(rho, nelx, nely, nelz)
     assert counts.max() <= 12 and counts.sum() == len(T)
     assert np.array_equal(np.bincount(owner, minlength=counts.size), counts)
+
+
+def test_tet_cases_hand_worked():
+    """Sec. 3.3 on one Kuhn tet, worked by hand.  Corners P0..P3 of the
+    x-y-z tet with values R; a corner is inside when R >= 0.5.  The cut point
+    on edge a -> b (a inside) is P_a + t (P_b - P_a), t = (0.5 - R_a)/(R_b - R_a).
+
+    2 in (0, 1), 2 out (2, 3), R = (1, 3/4, 0, 1/4):
+      p_ac: t = 1/2 on P0-P2 -> (1/2, 1/2, 0)
+      p_ad: t = 2/3 on P0-P3 -> (2/3, 2/3, 2/3)
+      p_bd: t = 1/2 on P1-P3 -> (1, 1/2, 1/2)
+      p_bc: t = 1/3 on P1-P2 -> (1, 1/3, 0)
+    and the quad is split along p_ac - p_bd: (p_ac, p_ad, p_bd), (p_ac, p_bd, p_bc).
+    The four points lie on the level plane 1 - x/4 - 3y/4 + z/4 = 1/2 of the
+    tet's linear interpolant, as every marching-tetrahedra quad does, so the
+    diagonal changes the triangle list but not the surface."""
+    P = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [1, 1, 1]], dtype=float)
+    tris = sdf.tet_triangles(P, np.array([1.0, 0.75, 0.0, 0.25]), 0.5)
+    pac, pad, pbd, pbc = ([0.5, 0.5, 0.0], [2 / 3, 2 / 3, 2 / 3], [1.0, 0.5, 0.5],
+                          [1.0, 1 / 3, 0.0])
+    expect = [[pac, pad, pbd], [pac, pbd, pbc]]
+    assert len(tris) == 2
+    for got, want in zip(tris, expect):
+        assert np.max(np.abs(np.array(got) - np.array(want))) <= 1e-15
+    level = lambda p: 1 - p[0] / 4 - 3 * p[1] / 4 + p[2] / 4
+    for p in (pac, pad, pbd, pbc):
+        assert abs(level(p) - 0.5) <= 1e-15
+    # 1 in (corner 2), R = (0, 0, 1, 1/4): cuts toward 0, 1, 3 at t = 1/2, 1/2, 2/3
+    tris = sdf.tet_triangles(P, np.array([0.0, 0.0, 1.0, 0.25]), 0.5)
+    want = [[0.5, 0.5, 0.0], [1.0, 0.5, 0.0], [1.0, 1.0, 2 / 3]]
+    assert len(tris) == 1 and np.max(np.abs(np.array(tris[0]) - np.array(want))) <= 1e-15
+    # 3 in (0, 1, 3), out 2, R = (1, 1, 0, 3/4): cuts toward 2 at t = 1/2, 1/2, 1/3
+    tris = sdf.tet_triangles(P, np.array([1.0, 1.0, 0.0, 0.75]), 0.5)
+    want = [[0.5, 0.5, 0.0], [1.0, 0.5, 0.0], [1.0, 1.0, 2 / 3]]
+    assert len(tris) == 1 and np.max(np.abs(np.array(tris[0]) - np.array(want))) <= 1e-15
+    # all in or all out: nothing
+    assert sdf.tet_triangles(P, np.array([1.0, 1.0, 0.5, 0.5]), 0.5) == []
+    assert sdf.tet_triangles(P, np.array([0.0, 0.1, 0.2, 0.49]), 0.5) == []

@@ -1,5 +1,5 @@
-"""Pins for the oracle's relaxed shape derivative (Sec. 2.2.2, Eqs. 15-18) and
-Hilbertian extension (Sec. 2.2.3, Eqs. 19-20).
+"""Pins for the oracle's relaxed shape derivative (Sec. 2.2.5, Eqs. 15-18) and
+Hilbertian extension (Sec. 2.2.6, Eqs. 19-20).
 
   * the shape functions are isoparametric on the local node order and
     differentiate to the stiffness gradients;
