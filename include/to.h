@@ -171,6 +171,24 @@ to_status to_filter(to_ctx *ctx, double rmin, int32_t mode, const double *d_x, c
 to_status to_density_to_sdf(to_ctx *ctx, const double *d_x, double rho_t, double *d_phi,
                             double *d_rho_nodes, double *d_vf);
 
+/* to_density_to_sdf for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same computation and results, bit for bit, with the
+ * triangles kept in a fixed device array of the library instead of a buffer
+ * the context grows.  The array holds TO_NOALLOC_MAX_TRIANGLES triangles
+ * (72 bytes each, 18.9 MB), one copy per GPU the library runs on, held until
+ * the process ends.  A design whose iso-surface needs more is rejected with
+ * TO_E_OOM after the counting pass (d_rho_nodes, if given, then holds the
+ * nodal densities; d_phi and d_vf are untouched); to_last_triangle_count()
+ * gives the number it needed.  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (contexts on different streams or threads)
+ * race and must be serialised by the caller.  No device memory is allocated
+ * or freed (the context's workspace and pinned host scalars come from
+ * to_create); on the host only an error path formats its message. */
+#define TO_NOALLOC_MAX_TRIANGLES 262144
+to_status to_density_to_sdf_noalloc(to_ctx *ctx, const double *d_x, double rho_t, double *d_phi,
+                                    double *d_rho_nodes, double *d_vf);
+
 /* Ersatz weights of a level set (Sec. 4.1: cut elements weighted by their
  * solid volume fraction): per element, the volume fraction where the
  * piecewise-linear interpolant of phi on the six-tet split is < 0 (the vf of

@@ -70,6 +70,7 @@ _SIGS = {
     "to_compliance_sensitivity": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(_D), _P]),
     "to_filter": (ctypes.c_int, [_P, _D, ctypes.c_int32, _P, _P, _P]),
     "to_density_to_sdf": (ctypes.c_int, [_P, _P, _D, _P, _P, _P]),
+    "to_density_to_sdf_noalloc": (ctypes.c_int, [_P, _P, _D, _P, _P, _P]),
     "to_volume_fraction": (ctypes.c_int, [_P, _P, _P]),
     "to_oc_update": (ctypes.c_int, [_P, _P, _P, _D, _D, _D, _P, ctypes.POINTER(ToOcInfo)]),
     "to_simp": (ctypes.c_int, [_P, ctypes.POINTER(ToSimpParams), _P, _P, _P, _P,

@@ -209,6 +209,24 @@ def to_density_to_sdf(ctx: Context, x, rho_t=0.5, phi=None, rho_nodes=None, vf=N
     return phi, rho_nodes, vf
 
 
+def to_density_to_sdf_noalloc(ctx: Context, x, phi, rho_nodes=None, vf=None, rho_t=0.5,
+                              raise_on_error=True):
+    """to_density_to_sdf without any device allocation: the triangles go to
+    the library's fixed device array (at most NOALLOC_TRI_MAX of them).  The
+    caller passes every output buffer.  Returns the status."""
+    p = ctx.prob
+    st = L.lib().to_density_to_sdf_noalloc(ctx.handle, _dev(x, torch.float64, p.nel, "x"),
+                                           float(rho_t), _dev(phi, torch.float64, p.nn, "phi"),
+                                           _dev(rho_nodes, torch.float64, p.nn, "rho_nodes"),
+                                           _dev(vf, torch.float64, p.nel, "vf"))
+    if raise_on_error:
+        _check(st, ctx.handle)
+    return st
+
+
+NOALLOC_TRI_MAX = 262144  # TO_NOALLOC_MAX_TRIANGLES of include/to.h
+
+
 def last_triangle_count(ctx: Context) -> int:
     return L.lib().to_last_triangle_count(ctx.handle)
 

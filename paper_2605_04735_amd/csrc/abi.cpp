@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -701,8 +702,15 @@ to_status to_filter(to_ctx *c, double rmin, int32_t mode, const double *d_x, con
   return TO_OK;
 }
 
-to_status to_density_to_sdf(to_ctx *c, const double *d_x, double rho_t, double *d_phi,
-                            double *d_rho_nodes, double *d_vf) {
+namespace {
+
+// Density -> SDF on a context.  tri_fixed == nullptr: triangles in the
+// context's buffer, grown by hipMalloc when a design needs more; otherwise
+// the caller's fixed device array of tri_max triangles, and a design that
+// needs more is rejected (after the count pass, before any triangle is
+// written).
+to_status density_to_sdf(to_ctx *c, const double *d_x, double rho_t, double *d_phi,
+                         double *d_rho_nodes, double *d_vf, double *tri_fixed, size_t tri_max) {
   if (!c) return fail(nullptr, TO_E_INVALID, "ctx is NULL");
   if (!d_x || !d_phi) return fail(c, TO_E_INVALID, "d_x and d_phi are required");
   if (!std::isfinite(rho_t)) return fail(c, TO_E_INVALID, "rho_t must be finite");
@@ -720,26 +728,86 @@ to_status to_density_to_sdf(to_ctx *c, const double *d_x, double rho_t, double *
   c->last_tri = total;
   if (total < 0) return fail(c, TO_E_INVALID, "triangle count overflow");
   if (total > 0) {
-    const size_t need = (size_t)total * 9;
-    if (need > c->tri_cap) {
-      if (c->tri) HIPCHK(hipFree(c->tri));
-      c->tri = nullptr;
-      c->tri_cap = 0;
-      const size_t cap = need + need / 4;
-      if (hipMalloc((void **)&c->tri, cap * sizeof(double)) != hipSuccess)
-        return fail(c, TO_E_OOM, "cannot allocate the triangle buffer");
-      c->tri_cap = cap;
+    double *tri = tri_fixed;
+    if (tri_fixed) {
+      if ((size_t)total > tri_max)
+        return fail(c, TO_E_OOM,
+                    "the design's iso-surface has " + std::to_string(total) +
+                        " triangles; to_density_to_sdf_noalloc holds at most " +
+                        std::to_string(tri_max) + " (use to_density_to_sdf)");
+    } else {
+      const size_t need = (size_t)total * 9;
+      if (need > c->tri_cap) {
+        if (c->tri) HIPCHK(hipFree(c->tri));
+        c->tri = nullptr;
+        c->tri_cap = 0;
+        const size_t cap = need + need / 4;
+        if (hipMalloc((void **)&c->tri, cap * sizeof(double)) != hipSuccess)
+          return fail(c, TO_E_OOM, "cannot allocate the triangle buffer");
+        c->tri_cap = cap;
+      }
+      tri = c->tri;
     }
-    HIPCHK(launch_mt_emit(g, rho, rho_t, c->p.h, c->toff, c->cnt, c->tri, c->stream));
+    HIPCHK(launch_mt_emit(g, rho, rho_t, c->p.h, c->toff, c->cnt, tri, c->stream));
     // the coarse occupancy bitmask reuses the filter scratch (nel doubles, far more than
     // the nel/2048 words it needs)
-    HIPCHK(launch_udist(g, c->p.h, c->cnt, c->toff, c->tri, (int *)c->ftmp, rho, rho_t, d_phi,
+    HIPCHK(launch_udist(g, c->p.h, c->cnt, c->toff, tri, (int *)c->ftmp, rho, rho_t, d_phi,
                         c->stream));
   } else {
     HIPCHK(launch_sign_inf(g, rho, rho_t, d_phi, c->stream));
   }
   if (d_vf) HIPCHK(launch_vf(g, d_phi, d_vf, c->stream));
   return TO_OK;
+}
+
+}  // namespace
+
+to_status to_density_to_sdf(to_ctx *c, const double *d_x, double rho_t, double *d_phi,
+                            double *d_rho_nodes, double *d_vf) {
+  return density_to_sdf(c, d_x, rho_t, d_phi, d_rho_nodes, d_vf, nullptr, 0);
+}
+
+// ---- the variant that allocates nothing.  Its triangles live in `scratch`,
+// a fixed device array that every GPU the library runs on holds until the
+// process ends.  In host code the array's name is only a host-side stand-in:
+// its device address, per device, comes from hipGetSymbolAddress on that
+// device's first call and is what kernels receive.
+namespace {
+constexpr size_t NOALLOC_TRI_MAX = TO_NOALLOC_MAX_TRIANGLES;  // 72 bytes each: 18.9 MB
+constexpr int NOALLOC_MAX_DEVICES = 64;
+}  // namespace
+
+static __device__ __align__(256) double scratch[NOALLOC_TRI_MAX * 9];
+
+namespace {
+std::mutex g_scratch_mu;
+double *g_scratch_dev[NOALLOC_MAX_DEVICES] = {};
+
+// device address of `scratch` on the current device c->device
+to_status scratch_address(to_ctx *c, double **out) {
+  if (c->device < 0 || c->device >= NOALLOC_MAX_DEVICES)
+    return fail(c, TO_E_INVALID, "device ordinal beyond the no-allocation variant's table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[c->device]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(c, TO_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[c->device] = (double *)ptr;
+  }
+  *out = g_scratch_dev[c->device];
+  return TO_OK;
+}
+}  // namespace
+
+to_status to_density_to_sdf_noalloc(to_ctx *c, const double *d_x, double rho_t, double *d_phi,
+                                    double *d_rho_nodes, double *d_vf) {
+  if (!c) return fail(nullptr, TO_E_INVALID, "ctx is NULL");
+  HIPCHK(hipSetDevice(c->device));
+  double *tri = nullptr;
+  const to_status st = scratch_address(c, &tri);
+  if (st != TO_OK) return st;
+  return density_to_sdf(c, d_x, rho_t, d_phi, d_rho_nodes, d_vf, tri, NOALLOC_TRI_MAX);
 }
 
 int32_t to_last_triangle_count(const to_ctx *c) { return c ? c->last_tri : 0; }
