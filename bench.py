@@ -12,11 +12,12 @@ HBM: state solve from a zero start (float32 inner Jacobi-PCG + float64 outer
 refinement), compliance and sensitivity, density filter (rmin 1.5) and
 sensitivity filter (R = 2), density -> SDF with the ersatz volume fraction.
 The plain float64 solve is timed the same way.  Both paths stop at the
-loosest outer residual that brings compliance and sensitivities within
-0.5e-6 of a tight float64 reference on calibration seeds (11, 12, 13),
-tightened by a further factor of 100 (the error/residual ratio varies a lot
-between designs), chosen before timing; the achieved errors on the timed
-design are reported.
+loosest outer residual that brings compliance, sensitivities and the
+displacement (in the energy norm of Eq. 2) within 0.5e-6 of a tight float64
+reference on calibration seeds (11, 12, 13), tightened by a further factor of
+10 (the error/residual ratio varies between designs), chosen before timing;
+the achieved errors of the timed design against the oracle's solution are
+reported.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -39,15 +40,20 @@ LARGE = (256, 128, 128)
 RTOL_LADDER = [1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 3e-6, 1e-6, 3e-7, 1e-7, 3e-8, 1e-8]
 TARGET = 1e-6
 CAL_MARGIN = 0.5          # calibrate to half the target: residuals are a loose proxy
-CAL_SAFETY = 1e-2         # and use a tolerance two decades below the calibrated rung,
+CAL_SAFETY = 1e-1         # and use a tolerance one decade below the calibrated rung,
 RTOL_FLOOR = 1e-8         # but not below 1e-8: float64 itself cannot resolve residuals much
                           # below ~1e-9 of designs whose stiff parts float in near-void
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per node of one float32 inner-CG iteration (large-grid
-# limit): the product reads r, the Jacobi diagonal, p_old, x and E and writes
-# p, q and x; the update reads r, q, the diagonal and the mask and writes r
-CG_PRODUCT_BYTES_F32 = 48
-CG_UPDATE_BYTES_F32 = 89
+
+
+def cg_bytes_f32(zfuse):
+    """Algorithmic bytes per node of one float32 inner-CG iteration, (product,
+    update); the product also reads 4 per element (E).  With z formed in the
+    product (zfuse) it reads r, the Jacobi diagonal and p_old (28) and writes
+    p and q (24); the update reads x, p, r, q, the diagonal and the mask byte
+    (53) and writes x and r (24).  With z stored, the product reads z instead
+    of r and the diagonal (24 + 24) and the update also writes z (53 + 36)."""
+    return (52, 77) if zfuse else (48, 89)
 
 
 def log(*a):
@@ -131,9 +137,14 @@ def probe(kind):
         torch.cuda.synchronize()
         log("level-set probe done")
         return
-    for f32 in (True, False):
+    # float32 (vector-ALU modal form), float32 on the matrix cores (opt-in
+    # variant, TOPO_MFMA=1), float64
+    for f32, mfma in ((True, False), (True, True), (False, False)):
+        if mfma:
+            os.environ["TOPO_MFMA"] = "1"
         p = A.Problem(*LARGE, precision=A.PREC_FP32_REFINE if f32 else A.PREC_FP64)
         ctx = A.to_create(p)
+        os.environ.pop("TOPO_MFMA", None)
         u = torch.randn(p.ndof, dtype=torch.float32 if f32 else torch.float64, device=dev)
         y = torch.empty_like(u)
         x = torch.from_numpy(inputs.random_field(*LARGE, seed=3, ell=6.0)).to(dev)
@@ -208,6 +219,12 @@ def _nodes(d):
     return (d[0] + 1) * (d[1] + 1) * (d[2] + 1), d[0] * d[1] * d[2]
 
 
+def cg_zfuse_dims(dims):
+    """Whether the library forms the CG z inside the product on grid `dims`."""
+    from paper_2605_04735_amd.api import cg_zfuse
+    return cg_zfuse(dims)
+
+
 def algorithmic_bytes(kernel, dims):
     """Bytes one launch of `kernel` must move on grid `dims` (nel voxels, nn
     nodes): every input read once, every output written once."""
@@ -216,9 +233,11 @@ def algorithmic_bytes(kernel, dims):
         ("k_matvec<float, 0>", 25, 4),         # read u (12) and the mask byte, E; write y (12)
         ("k_matvec_mfma<0>", 25, 4),
         ("k_matvec<double, 0>", 49, 8),
-        ("k_cg_matvec1<float, false>", CG_PRODUCT_BYTES_F32, 4),
-        ("k_cg_mfma1", CG_PRODUCT_BYTES_F32, 4),
-        ("k_cg_update1<float, false>", CG_UPDATE_BYTES_F32, 0),
+        ("k_cg_matvec1<float, false, false, 1>", cg_bytes_f32(True)[0], 4),
+        ("k_cg_matvec1<float, false, true, 1>", cg_bytes_f32(True)[0], 4),
+        ("k_cg_matvec1<float, false, false, 0>", cg_bytes_f32(False)[0], 4),
+        ("k_cg_matvec1<float, false, true, 0>", cg_bytes_f32(False)[0], 4),
+        ("k_cg_update1<float, false>", cg_bytes_f32(cg_zfuse_dims(dims))[1], 0),
         ("k_ls_advect", 24, 0), ("k_ls_reinit", 16, 0),
         ("k_hcg_apply", 17, 0), ("k_hcg_update", 56, 0), ("k_hcg_dir", 24, 0),
         ("__amd_rocclr_copyBuffer", None, None),
@@ -329,12 +348,14 @@ SUMMARIES = [
      "one fp32+refine solve of the 256x128x128 cantilever (random-field densities, seed 3) to "
      "rtol 1e-2: inner-CG product and update", LARGE, "cg3_trace", "cg3_fetch", "cg3_write",
      ("cg3_sq",), PRODUCT_SOURCES,
-     ("k_cg_matvec1<float, false>", "k_cg_mfma1", "k_cg_update1<float, false>")),
+     ("k_cg_matvec1<float, false, false, 1>", "k_cg_matvec1<float, false, true, 1>",
+      "k_cg_update1<float, false>")),
     ("pmc_cg_matvec_f32_cantilever_96x48x48.txt",
      "one fp32+refine solve of the 96x48x48 cantilever (seed 1) to rtol 1e-4: inner-CG product "
      "and update (working set resident in the 256 MB Infinity Cache)", DIMS, None, "cg_fetch",
      "cg_write", (), PRODUCT_SOURCES,
-     ("k_cg_matvec1<float, false>", "k_cg_mfma1", "k_cg_update1<float, false>")),
+     ("k_cg_matvec1<float, false, false, 0>", "k_cg_matvec1<float, false, true, 0>",
+      "k_cg_update1<float, false>")),
     ("levelset_256x128x128.txt",
      "level-set evolution (10 steps) and reinitialisation (to 1e-3, at most 40 pseudo-steps) on "
      "the 257x129x129 node grid; phi = 2.5 x the distance to three balls, smooth speed of both "
@@ -743,7 +764,7 @@ def main():
     # set (about 30 MB) sits in the 256 MB Infinity Cache and every launch is
     # a few microseconds, so that figure (given beside it) measures launch
     # latency, not HBM.
-    kern = A.cg_product_kernel_name()
+    kern = A.cg_product_kernel_name(DIMS)
     mv_us = 1e3 * res_m["mv_ms"] / max(res_m["mv_n"], 1)
     bytes_launch = algorithmic_bytes(kern, DIMS)
     achieved = bytes_launch / (mv_us * 1e-6) / 1e9
@@ -767,7 +788,11 @@ def main():
     gmeta, garr = golden("cantilever_96x48x48_seed1")
 
     def errs(u, c, dc, ur, cr, dcr):
-        return {"u": rel2(u, ur), "c": abs(c - cr) / abs(cr), "dc": rel2(dc, dcr),
+        # the energy norm with the float64 product (checked against the oracle's
+        # assembled operator to 1e-13 by the parity tests)
+        ut = torch.from_numpy(u).to(dev)
+        return {"u": rel2(u, ur), "u_energy": energy_norm_err(A, ctx_d, x, ut, ur),
+                "c": abs(c - cr) / abs(cr), "dc": rel2(dc, dcr),
                 "dc_max": float(np.abs(dc - dcr).max() / np.abs(dcr).max())}
     errors = {
         "vs_oracle": {
@@ -1202,7 +1227,7 @@ def workload_large(A, inputs, dev, copy_gbs):
         if prec == A.PREC_FP32_REFINE:
             mv_ms, mv_n = A.to_profile(ctx, False)
             mv_us = 1e3 * mv_ms / max(mv_n, 1)
-            kern = A.cg_product_kernel_name()
+            kern = A.cg_product_kernel_name(dims)
             byt = algorithmic_bytes(kern, dims)
             ach = byt / (mv_us * 1e-6) / 1e9
             out["roofline_cg_product"] = {
@@ -1212,8 +1237,8 @@ def workload_large(A, inputs, dev, copy_gbs):
                 "traffic": measured_traffic("kernel_trace_cg_256x128x128.txt", "void topo::" + kern),
                 "kernel": kern, "avg_us": round(mv_us, 3), "launches_sampled": mv_n,
                 "bytes_per_launch": byt}
-            out["cg_algorithmic_bytes_per_node_per_iteration"] = (CG_PRODUCT_BYTES_F32
-                                                                  + CG_UPDATE_BYTES_F32)
+            out["cg_algorithmic_bytes_per_node_per_iteration"] = sum(
+                cg_bytes_f32(cg_zfuse_dims(dims)))
         ctx.close()
         del u, dc
         torch.cuda.empty_cache()
@@ -1279,6 +1304,12 @@ def serving(nreq, cal):
     arrivals = np.cumsum(gaps) - gaps[0]
     served, t_served = run(list(arrivals))
     lat = np.array([served[k]["latency_ms"] for k in range(nreq)])
+    by_grid = {}
+    for k, dims, bc, x in reqs:
+        by_grid.setdefault("%dx%dx%d" % dims, []).append(served[k]["latency_ms"])
+    lat_by_grid = {g: {"n": len(v), "p50": float(np.percentile(v, 50)),
+                       "p99": float(np.percentile(v, 99)), "max": float(np.max(v))}
+                   for g, v in sorted(by_grid.items())}
     ok = all(served[k]["status"] == A.L.TO_OK for k in range(nreq))
     statuses = {}
     for k in range(nreq):
@@ -1322,6 +1353,7 @@ def serving(nreq, cal):
             "lambda_per_s": round(lam, 2), "solves_per_s": round(sps, 2),
             "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                            "max": float(lat.max())},
+            "latency_ms_by_grid": lat_by_grid,
             "fp64_sequential_solves_per_s": round(nreq / t_fp64, 2),
             "speedup_vs_fp64_sequential": round(sps * t_fp64 / nreq, 3),
             "max_rel_err_vs_tight_fp64_first32": errs,

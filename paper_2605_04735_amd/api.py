@@ -4,6 +4,7 @@ Argument marshalling only: torch tensors supply device memory and the current
 HIP stream; every step of the computation runs in the HIP library.
 """
 import ctypes
+import os
 from dataclasses import dataclass, field
 from typing import Optional
 
@@ -374,9 +375,28 @@ def product_kernel_name(f32=True):
     return "k_matvec<float, 0>" if f32 else "k_matvec<double, 0>"
 
 
-def cg_product_kernel_name():
-    """Name of the float32 inner-CG product kernel of the one-design solve."""
-    return "k_cg_matvec1<float, false>"
+# The library forms the CG z = D r inside the product (instead of storing z in
+# the update) on grids of at least this many nodes, or as TOPO_CG_ZFUSE=0/1
+# says; mirrored here to name the kernel a solve launches.
+ZFUSE_MIN_NODES = 1 << 19
+
+
+def cg_zfuse(dims):
+    e = os.environ.get("TOPO_CG_ZFUSE")
+    if e is not None:
+        return int(e) != 0
+    return (dims[0] + 1) * (dims[1] + 1) * (dims[2] + 1) >= ZFUSE_MIN_NODES
+
+
+def cg_product_kernel_name(dims):
+    """Name of the float32 inner-CG product kernel of the one-design solve on
+    grid `dims` (vector-ALU product)."""
+    return "k_cg_matvec1<float, false, false, %d>" % int(cg_zfuse(dims))
+
+
+def cg_update_kernel_name():
+    """Name of the float32 inner-CG update kernel of the one-design solve."""
+    return "k_cg_update1<float, false>"
 
 
 class Server:

@@ -309,6 +309,19 @@ to_status prepare_moduli(to_ctx *c, const double *d_x, bool check) {
   return TO_OK;
 }
 
+// Forming z = D r inside the product (instead of storing z in the update and
+// reading it back) saves 12 bytes per node and costs 4 plus a multiply per
+// staged node: it pays where the CG vectors stream from HBM, not where they
+// stay in the last-level cache.  TOPO_CG_ZFUSE=0/1 overrides the choice.
+}  // namespace
+
+int topo::cg_zfuse(const Grid &g) {
+  if (const char *e = std::getenv("TOPO_CG_ZFUSE")) return std::atoi(e) != 0;
+  return g.nn >= ZFUSE_MIN_NODES;
+}
+
+namespace {
+
 template <typename T>
 CgDesc<T> make_desc(to_ctx *c, T *const v[6], const T *E, const T *dinv, const Coef<T> &k) {
   const Grid &g = c->g;
@@ -327,6 +340,7 @@ CgDesc<T> make_desc(to_ctx *c, T *const v[6], const T *E, const T *dinv, const C
   d.nb_mv = c->nb_mv;
   d.nb_up = c->nb_up;
   d.zbf16 = sizeof(T) == 4 && c->p.precision == TO_PREC_FP32_REFINE_BF16;
+  d.zfuse = d.zbf16 ? 0 : cg_zfuse(g);
   d.nn = (long long)g.nn;
   d.k = k;
   d.E = E;

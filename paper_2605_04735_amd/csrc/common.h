@@ -100,6 +100,10 @@ struct MvArgs {
   Coef<T> k;
   const void *mA;        // matrix-core float32 product: the A operand (2 x 64 x 16 bytes)
   float mscale;          //   and the element scale h mu / 72 (times E_e)
+  // CG: with zfuse, `in` is the residual r and the product forms z = D r from
+  // the Jacobi inverse diagonal (otherwise `in` is the z the update stored)
+  const T *dinv;         // [nn]
+  int zfuse;
 };
 
 // One design of a batched inner CG solve (device resident).  The product
@@ -109,7 +113,8 @@ struct CgDesc {
   int nelx, nely, nelz, kz;
   int tx, ty;           // product tiles along x and y (blocks: tx * ty * tz)
   int nb_mv, nb_up;     // blocks of this design in the product / update kernels
-  int zbf16, pad_;      // float32 CG: z stored in bfloat16 (2 bytes per component)
+  int zbf16;           // float32 CG: z stored in bfloat16 (2 bytes per component)
+  int zfuse;           // the product forms z = D r (1) or reads the z the update stored (0)
   long long nn;
   Coef<T> k;
   const void *mA;       // float32: the matrix-core product's A operand, or NULL for the
@@ -250,6 +255,15 @@ template <typename T>
 hipError_t launch_cg_update(const CgDesc<T> *descs, const BlockEntry *bmap_up, int nb_up, int parity,
                             hipStream_t s);
 int update_blocks(size_t nn);
+// where the CG product gets z = D r: read as the update stored it, formed from
+// r and the Jacobi diagonal, or as the descriptor's zfuse says (batched)
+enum { ZF_READ = 0, ZF_FORM = 1, ZF_DESC = 2 };
+
+// CG z = D r formed inside the product from this many nodes up (where the
+// vectors stream from HBM); below, the update stores z and the product reads it
+constexpr size_t ZFUSE_MIN_NODES = size_t(1) << 19;
+int cg_zfuse(const Grid &g);
+
 template <typename T>
 hipError_t launch_axpy_out(const Grid &g, double *u, const T *d, const double *scal,
                            hipStream_t s);

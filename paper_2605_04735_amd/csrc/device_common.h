@@ -255,6 +255,17 @@ __device__ __forceinline__ T bload1(rsrc_t r, unsigned vo, unsigned so) {
   if constexpr (sizeof(T) == 4) return bload1f(r, vo, so);
   else return bload1d(r, vo, so);
 }
+// Product rounded on its own, never fused into a following add: the CG
+// product forms z = D r with exactly the value the update used for r^T z.
+// (Fused into p = z + beta p_old, the unrounded z would make r^T z and the
+// direction disagree by a rounding, which slowed the float32 CG by several
+// percent in iterations.)
+template <typename T>
+__device__ __forceinline__ T mul_rn(T a, T b) {
+#pragma clang fp contract(off)
+  return a * b;
+}
+
 // bfloat16 storage of float32 vectors (3 components of 2 bytes per node):
 // round to nearest even once, keep the rounded value in float32.
 __device__ __forceinline__ float bf16_round(float v) {

@@ -51,7 +51,8 @@ namespace topo {
 // LDS), along y through a 3-value LDS exchange with the next tile row.  Node
 // plane L+2 is fetched into registers while layer L computes.  The
 // summation order is fixed: the result is deterministic.
-template <typename T, int MODE, bool ZBF = false, typename PreFn, typename BetaFn>
+template <typename T, int MODE, bool ZBF = false, int ZF = ZF_READ, typename PreFn,
+          typename BetaFn>
 __device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int by, int bz,
                                                PreFn &&pre, BetaFn &&get_beta,
                                                T (*pl)[3][TPX * TPY], T (*ex)[MV_THREADS],
@@ -62,6 +63,10 @@ __device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int b
   // float32 directions).
   constexpr bool CG = MODE == MV_CG;
   static_assert(!ZBF || (CG && sizeof(T) == 4), "bfloat16 z: float32 CG only");
+  // CG without bfloat16 z under ZF_FORM (or ZF_DESC with the arguments'
+  // zfuse set): the input is r and z = D r is formed here
+  constexpr bool ZFC = CG && !ZBF && ZF != ZF_READ;  // z may be formed here
+  const bool zf = ZFC && (ZF == ZF_FORM || a.zfuse);
   constexpr unsigned SZ = ZBF ? 2u : sizeof(T);  // bytes per component of the input vector
   constexpr bool MASKED = !CG;
   constexpr unsigned S = sizeof(T);
@@ -114,6 +119,7 @@ __device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int b
     T in[2][3], po[2][3];
     unsigned m[2];
     T e;
+    T di[2];  // zf: Jacobi inverse diagonal
   };
   auto fetch = [&](Plane &R, int kp) {
     // a plane outside the grid reads through empty resources (all zeros):
@@ -126,12 +132,15 @@ __device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int b
     const rsrc_t rp = make_rsrc(a.pold, CG && inz ? 3u * nn * S : 0u);
     const rsrc_t rm = make_rsrc(a.mask, MASKED && inz ? nn : 0u);
     const rsrc_t re = make_rsrc(a.E, kp >= 0 && kp < a.nelz ? eplane * (unsigned)a.nelz * S : 0u);
+    const rsrc_t rd = make_rsrc(a.dinv, zf && inz ? nn * S : 0u);
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
       if constexpr (ZBF) bload3_bf16(ri, voZ[sl], sz, R.in[sl]);
       else bload3(ri, voZ[sl], sz, R.in[sl]);
       if constexpr (CG) bload3(rp, voN[sl], so, R.po[sl]);
       if constexpr (MASKED) R.m[sl] = bload_u8(rm, voM[sl], kc * plane);
+      if constexpr (ZFC)
+        R.di[sl] = bload1<T>(rd, voM[sl] == OOB ? OOB : voM[sl] * S, kc * plane * S);
     }
     R.e = bload1<T>(re, voE, kc * eplane * S);
   };
@@ -148,8 +157,15 @@ __device__ __forceinline__ double matvec_block(const MvArgs<T> &a, int bx, int b
       T v[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        if constexpr (CG) v[c] = R.in[sl][c] + beta * R.po[sl][c];
-        else v[c] = ((R.m[sl] >> c) & 1u) ? T(0) : R.in[sl][c];
+        if constexpr (CG) {
+          T z = R.in[sl][c];
+          if constexpr (ZFC) {
+            if (zf) z = mul_rn(R.di[sl], z);  // the z of the update's r^T z, bit for bit
+          }
+          v[c] = z + beta * R.po[sl][c];
+        } else {
+          v[c] = ((R.m[sl] >> c) & 1u) ? T(0) : R.in[sl][c];
+        }
         dst[c][idx] = v[c];
       }
       if (wr) bstore3(rPn, voP[sl], (unsigned)kp * plane * 3u * S, v);
@@ -294,9 +310,10 @@ void k_matvec(const MvArgs<T> a, int tx, int ty) {
 // Inner-CG product, local block lb of design d.  Every block first completes
 // the reduction of the previous update (r^T z and ||r||^2, partial set
 // parity^1): converged designs stop here; otherwise beta = (r^T z)_new /
-// (r^T z)_old, p = z + beta p_old, q = K p, and the block's p^T q partial is
-// written for the update kernel.
-template <typename T, bool ZBF = false, bool MF = false>
+// (r^T z)_old, p = z + beta p_old (z = D r formed here from r when the
+// descriptor's zfuse is set, else read as the update stored it), q = K p, and
+// the block's p^T q partial is written for the update kernel.
+template <typename T, bool ZBF = false, bool MF = false, int ZF = ZF_DESC>
 __device__ __forceinline__ void cg_matvec_block(const CgDesc<T> &d, double *scal, int *flags,
                                                 double *cgp, int nparts, int lb_in, int parity) {
   static_assert(!MF || (sizeof(T) == 4 && !ZBF), "matrix-core product: float32 CG, float32 z");
@@ -336,7 +353,9 @@ __device__ __forceinline__ void cg_matvec_block(const CgDesc<T> &d, double *scal
   a.nelz = d.nelz;
   a.kz = d.kz;
   a.E = d.E;
-  a.in = d.z;
+  a.zfuse = ZBF || ZF == ZF_READ ? 0 : ZF == ZF_FORM ? 1 : d.zfuse;
+  a.in = a.zfuse ? d.r : d.z;
+  a.dinv = d.dinv;
   T *const p0 = d.p[0], *const p1 = d.p[1];
   a.pold = parity ? p1 : p0;
   a.pout = parity ? p0 : p1;
@@ -351,7 +370,7 @@ __device__ __forceinline__ void cg_matvec_block(const CgDesc<T> &d, double *scal
   if (lb < 0) return;  // padding of the last band: nothing loaded is used
   asm volatile("" ::"s"(a.nelx), "s"(a.nely), "s"(a.nelz), "s"(a.kz), "s"(tx), "s"(ty), "s"(a.E),
                "s"(a.in), "s"(p0), "s"(p1), "s"(a.out), "s"(a.k.L2), "s"(a.k.M4), "s"(a.k.M2),
-               "s"(a.k.L2_3), "s"(a.k.M2_3), "s"(a.k.B9));
+               "s"(a.k.L2_3), "s"(a.k.M2_3), "s"(a.k.B9), "s"(a.dinv), "s"(a.zfuse));
   const int bx = lb % tx, by = (lb / tx) % ty, bz = lb / (tx * ty);
   auto get_beta = [&](T &beta) -> bool {
     double sums[NP];
@@ -384,11 +403,11 @@ __device__ __forceinline__ void cg_matvec_block(const CgDesc<T> &d, double *scal
   double s;
   if constexpr (MF) {
     __shared__ MfmaLds S;
-    s = mfma_block<MV_CG>(a, bx, by, bz, [] {}, get_beta, S, red);
+    s = mfma_block<MV_CG, ZF>(a, bx, by, bz, [] {}, get_beta, S, red);
   } else {
     __shared__ T pl[2][3][TPX * TPY];
     __shared__ T ex[6][MV_THREADS];
-    s = matvec_block<T, MV_CG, ZBF>(a, bx, by, bz, [] {}, get_beta, pl, ex, red);
+    s = matvec_block<T, MV_CG, ZBF, ZF>(a, bx, by, bz, [] {}, get_beta, pl, ex, red);
   }
   if (run && threadIdx.x == 0) cgp[CGP_PQ + lb] = s;
 }
@@ -406,18 +425,19 @@ __global__ __launch_bounds__(MV_THREADS) void k_cg_matvec(const CgDesc<T> *descs
 // sums, parity and partial count lead the arguments (8 dwords) so that they
 // arrive preloaded in SGPRs: the block's first loads (the previous reduction)
 // need no argument load before them.
-template <typename T, bool ZBF, bool MF = false>
+template <typename T, bool ZBF, bool MF = false, int ZF = ZF_READ>
 __global__ __launch_bounds__(MV_THREADS) void k_cg_matvec1(double *scal, int *flags, double *cgp,
                                                            int parity, int nparts,
                                                            const CgDesc<T> d) {
-  cg_matvec_block<T, ZBF, MF>(d, scal, flags, cgp, nparts, -1, parity);
+  cg_matvec_block<T, ZBF, MF, ZF>(d, scal, flags, cgp, nparts, -1, parity);
 }
 
 // Batched CG vector update: every block completes the p^T q reduction of the
-// product, alpha = (r^T z) / (p^T q), then x += alpha p; r -= alpha q (fixed
-// DOFs 0); z = D r, and the block's r^T z and ||r||^2 partials go to set
-// `parity` for the next product.  A thread's first two nodes are loaded before
-// the reduction, so their latency overlaps it.
+// product, alpha = (r^T z) / (p^T q), then x += alpha p; r -= alpha q
+// (fixed DOFs 0); z = D r, stored unless the product forms it (zfuse), and
+// the block's r^T z and ||r||^2 partials go to set `parity` for the next
+// product.  A thread's first two nodes are loaded before the reduction, so
+// their latency overlaps it.
 template <typename T, bool ZBF = false>
 __device__ __forceinline__ void cg_update_block(const CgDesc<T> &d, double *scal, int *flags,
                                                 double *cgp, int nparts, int lb, int parity) {
@@ -441,11 +461,12 @@ __device__ __forceinline__ void cg_update_block(const CgDesc<T> &d, double *scal
   T *const p0 = d.p[0], *const p1 = d.p[1];
   const T *const dinv = d.dinv;
   const uint8_t *const mask = d.mask;
-  const int nb_up = d.nb_up;
+  const int nb_up = d.nb_up, zfuse = d.zfuse;
   asm volatile("" ::"s"(nn), "s"(x), "s"(r), "s"(z), "s"(q), "s"(p0), "s"(p1), "s"(dinv),
-               "s"(mask), "s"(nb_up));
+               "s"(mask), "s"(nb_up), "s"(zfuse));
+  const bool zst = ZBF || !zfuse;  // z is stored for the product
   const rsrc_t rX = make_rsrc(x, 3u * nn * S), rR = make_rsrc(r, 3u * nn * S);
-  const rsrc_t rZ = make_rsrc(z, 3u * nn * SZ), rQ = make_rsrc(q, 3u * nn * S);
+  const rsrc_t rZ = make_rsrc(z, zst ? 3u * nn * SZ : 0u), rQ = make_rsrc(q, 3u * nn * S);
   const rsrc_t rP = make_rsrc(parity ? p0 : p1, 3u * nn * S);  // p[parity ^ 1]
   const rsrc_t rD = make_rsrc(dinv, nn * S), rM = make_rsrc(mask, nn);
   const unsigned stride = (unsigned)nb_up * 256u;
@@ -488,7 +509,7 @@ __device__ __forceinline__ void cg_update_block(const CgDesc<T> &d, double *scal
     for (int c = 0; c < 3; ++c) {
       xn[c] = v.x[c] + alpha * v.p[c];
       rn[c] = ((v.m >> c) & 1u) ? T(0) : v.r[c] - alpha * v.q[c];
-      zn[c] = v.di * rn[c];
+      zn[c] = mul_rn(v.di, rn[c]);
       if constexpr (ZBF) zn[c] = bf16_round(zn[c]);  // the z the next product reads
       rzs += (double)rn[c] * (double)zn[c];
       rrs += (double)rn[c] * (double)rn[c];
@@ -500,7 +521,7 @@ __device__ __forceinline__ void cg_update_block(const CgDesc<T> &d, double *scal
     bstore3(rX, v.vo, 0, xn);
     bstore3(rR, v.vo, 0, rn);
     if constexpr (ZBF) bstore3_bf16(rZ, v.vz, 0, zn);
-    else bstore3(rZ, v.vz, 0, zn);
+    else bstore3(rZ, v.vz, 0, zn);  // (an empty resource drops it under zfuse)
   };
   update(A);
   update(B);
@@ -627,39 +648,31 @@ hipError_t launch_cg_update(const CgDesc<T> *descs, const BlockEntry *bmap_up, i
 template hipError_t launch_matvec<double, MV_APPLY>(const MvArgs<double> &, int *, hipStream_t);
 template hipError_t launch_matvec<double, MV_RESID>(const MvArgs<double> &, int *, hipStream_t);
 template hipError_t launch_matvec<float, MV_APPLY>(const MvArgs<float> &, int *, hipStream_t);
+// the single-design product kernel for descriptor d: bfloat16 z, matrix-core
+// or vector-ALU product, z formed inside or read
+template <typename T>
+void *cg_matvec1_kernel(const CgDesc<T> &d) {
+  if constexpr (sizeof(T) == 4) {
+    if (d.zbf16) return (void *)k_cg_matvec1<T, true>;
+    if (d.mA)
+      return d.zfuse ? (void *)k_cg_matvec1<T, false, true, ZF_FORM>
+                     : (void *)k_cg_matvec1<T, false, true, ZF_READ>;
+  }
+  return d.zfuse ? (void *)k_cg_matvec1<T, false, false, ZF_FORM>
+                 : (void *)k_cg_matvec1<T, false, false, ZF_READ>;
+}
+
 template <typename T>
 hipError_t launch_cg_matvec1(const CgDesc<T> &d, int parity, hipStream_t s, hipEvent_t start,
                              hipEvent_t stop) {
-  if constexpr (sizeof(T) == 4) {
-    if (d.zbf16) {
-      if (start && stop)
-        hipExtLaunchKernelGGL((k_cg_matvec1<T, true>), dim3(mv_grid(d.tx * d.ty, d.nb_mv / (d.tx * d.ty))), dim3(MV_THREADS), 0, s, start,
-                              stop, 0, d.scal, d.flags, d.cgp, parity, d.nb_up, d);
-      else
-        hipLaunchKernelGGL((k_cg_matvec1<T, true>), dim3(mv_grid(d.tx * d.ty, d.nb_mv / (d.tx * d.ty))), dim3(MV_THREADS), 0, s, d.scal,
-                           d.flags, d.cgp, parity, d.nb_up, d);
-      return hipGetLastError();
-    }
-  }
   const dim3 grid(mv_grid(d.tx * d.ty, d.nb_mv / (d.tx * d.ty)));
-  if constexpr (sizeof(T) == 4) {
-    if (d.mA) {
-      if (start && stop)
-        hipExtLaunchKernelGGL((k_cg_matvec1<T, false, true>), grid, dim3(MV_THREADS), 0, s, start,
-                              stop, 0, d.scal, d.flags, d.cgp, parity, d.nb_up, d);
-      else
-        hipLaunchKernelGGL((k_cg_matvec1<T, false, true>), grid, dim3(MV_THREADS), 0, s, d.scal,
-                           d.flags, d.cgp, parity, d.nb_up, d);
-      return hipGetLastError();
-    }
-  }
-  if (start && stop)
-    hipExtLaunchKernelGGL((k_cg_matvec1<T, false>), grid, dim3(MV_THREADS), 0, s, start, stop, 0,
-                          d.scal, d.flags, d.cgp, parity, d.nb_up, d);
-  else
-    hipLaunchKernelGGL((k_cg_matvec1<T, false>), grid, dim3(MV_THREADS), 0, s, d.scal, d.flags,
-                       d.cgp, parity, d.nb_up, d);
-  return hipGetLastError();
+  double *scal = d.scal, *cgp = d.cgp;
+  int *flags = d.flags, nparts = d.nb_up;
+  CgDesc<T> dd = d;
+  void *args[] = {&scal, &flags, &cgp, &parity, &nparts, &dd};
+  // timestamps taken by the dispatch itself when events are given
+  return hipExtLaunchKernel(cg_matvec1_kernel(d), grid, dim3(MV_THREADS), args, 0, s, start, stop,
+                            0);
 }
 
 template <typename T>
@@ -685,14 +698,9 @@ hipError_t build_cg_graph(const CgDesc<T> &d, int parity0, int iters, hipGraphEx
   hipGraph_t g = nullptr;
   hipError_t e = hipGraphCreate(&g, 0);
   if (e != hipSuccess) return e;
-  void *fmv = (void *)k_cg_matvec1<T, false>, *fup = (void *)k_cg_update1<T, false>;
+  void *fmv = cg_matvec1_kernel(d), *fup = (void *)k_cg_update1<T, false>;
   if constexpr (sizeof(T) == 4) {
-    if (d.zbf16) {
-      fmv = (void *)k_cg_matvec1<T, true>;
-      fup = (void *)k_cg_update1<T, true>;
-    } else if (d.mA) {
-      fmv = (void *)k_cg_matvec1<T, false, true>;
-    }
+    if (d.zbf16) fup = (void *)k_cg_update1<T, true>;
   }
   hipGraphNode_t prev = nullptr;
   for (int i = 0; i < 2 * iters && e == hipSuccess; ++i) {

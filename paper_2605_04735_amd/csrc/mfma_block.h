@@ -41,7 +41,7 @@ __device__ __forceinline__ float shr1_row(float v) {
 // One block of the matrix-core product (MODE: MV_APPLY or MV_CG), tile (bx, by)
 // over node planes [bz kz, bz kz + kz).  Returns the block's p^T q partial in
 // thread 0 (MV_CG).  pre/get_beta: as for the vector-ALU product.
-template <int MODE, typename PreFn, typename BetaFn>
+template <int MODE, int ZF = ZF_READ, typename PreFn, typename BetaFn>
 __device__ __forceinline__ double mfma_block(const MvArgs<float> &a, int bx, int by, int bz,
                                              PreFn &&pre, BetaFn &&get_beta, MfmaLds &S,
                                              double *red) {
@@ -61,6 +61,9 @@ __device__ __forceinline__ double mfma_block(const MvArgs<float> &a, int bx, int
   const rsrc_t rPn = make_rsrc(a.pout, CG ? 3u * nn * F4 : 0u);
   const rsrc_t rIn = make_rsrc(a.in, 3u * nn * F4);
   const rsrc_t rM = make_rsrc(a.mask, MASKED ? nn : 0u);
+  // the input is r and z = D r is formed here (ZF_FORM, or ZF_DESC with zfuse)
+  constexpr bool ZFC = CG && ZF != ZF_READ;
+  const bool zf = ZFC && (ZF == ZF_FORM || a.zfuse);
 
   // the A operand (rows of M for az = 0 and az = 1), 16 bytes each
   bf16x8 A0, A1;
@@ -105,6 +108,7 @@ __device__ __forceinline__ double mfma_block(const MvArgs<float> &a, int bx, int
     float in[2][3], po[2][3];
     unsigned m[2];
     float e[4];
+    float di[2];  // zf: Jacobi inverse diagonal
   };
   auto fetch = [&](Plane &R, int kp) {
     const bool inz = kp >= 0 && kp < NZ;  // uniform
@@ -114,10 +118,15 @@ __device__ __forceinline__ double mfma_block(const MvArgs<float> &a, int bx, int
     const rsrc_t rp = make_rsrc(a.pold, CG && inz ? 3u * nn * F4 : 0u);
     const rsrc_t rm = make_rsrc(a.mask, MASKED && inz ? nn : 0u);
     const rsrc_t re = make_rsrc(a.E, kp >= 0 && kp < a.nelz ? eplane * (unsigned)a.nelz * F4 : 0u);
+    const rsrc_t rd = make_rsrc(a.dinv, zf && inz ? nn * F4 : 0u);
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
       bload3(ri, voN[sl], so, R.in[sl]);
-      if constexpr (CG) bload3(rp, voN[sl], so, R.po[sl]);
+      if constexpr (CG) {
+        bload3(rp, voN[sl], so, R.po[sl]);
+        if constexpr (ZFC)
+          R.di[sl] = bload1f(rd, voM[sl] == OOB ? OOB : voM[sl] * F4, kc * plane * F4);
+      }
       if constexpr (MASKED) R.m[sl] = bload_u8(rm, voM[sl], kc * plane);
     }
 #pragma unroll
@@ -125,7 +134,7 @@ __device__ __forceinline__ double mfma_block(const MvArgs<float> &a, int bx, int
   };
   float beta = 0.f;
   // plane kp into LDS slot kp % 3 (split into bfloat16 parts); CG: p = z +
-  // beta p_old, written out for the nodes this block owns
+  // beta p_old (z = D r under zf), written out for the nodes this block owns
   auto stage = [&](Plane &R, int kp, float (&E)[4]) {
     const int slot = (kp + 3) % 3;
     const bool wr = CG && kp >= k0 && kp < k1;
@@ -136,8 +145,13 @@ __device__ __forceinline__ double mfma_block(const MvArgs<float> &a, int bx, int
       float v[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        if constexpr (CG) v[c] = R.in[sl][c] + beta * R.po[sl][c];
-        else v[c] = ((R.m[sl] >> c) & 1u) ? 0.f : R.in[sl][c];
+        if constexpr (CG) {
+          float z = R.in[sl][c];
+          if constexpr (ZFC) {
+            if (zf) z = mul_rn(R.di[sl], z);
+          }
+          v[c] = z + beta * R.po[sl][c];
+        } else v[c] = ((R.m[sl] >> c) & 1u) ? 0.f : R.in[sl][c];
       }
       unsigned h[3], m[3], l[3];
 #pragma unroll

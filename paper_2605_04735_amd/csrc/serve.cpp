@@ -347,6 +347,7 @@ CgDesc<float> make_desc(const Slot &sl) {
   d.dinv = sl.dinv32;
   d.mask = sl.mask;
   d.x = sl.v[0];
+  d.zfuse = cg_zfuse(sl.g);
   d.r = sl.v[1];
   d.z = sl.v[2];
   d.p[0] = sl.v[3];

@@ -158,3 +158,18 @@ def test_served_graph_replays_equal_separate_launches(monkeypatch):
         assert eager[k]["status"] == A.L.TO_OK and graph[k]["status"] == A.L.TO_OK
         assert graph[k]["c"] == eager[k]["c"]
         assert np.array_equal(graph[k]["dc"], eager[k]["dc"])
+
+
+def test_served_z_formed_in_product_equals_z_stored(monkeypatch):
+    """The batched CG product reads each design's z source from its
+    descriptor; forming z = D r there gives the stored-z results bit for bit."""
+    reqs = _requests()
+    print("serving mix with z stored and z formed", flush=True)
+    monkeypatch.setenv("TOPO_CG_ZFUSE", "0")
+    stored = _serve(reqs)
+    monkeypatch.setenv("TOPO_CG_ZFUSE", "1")
+    formed = _serve(reqs)
+    for k, _, _ in reqs:
+        assert stored[k]["status"] == A.L.TO_OK and formed[k]["status"] == A.L.TO_OK
+        assert formed[k]["c"] == stored[k]["c"]
+        assert np.array_equal(formed[k]["dc"], stored[k]["dc"])
