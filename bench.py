@@ -47,13 +47,25 @@ HBM_PEAK_GBS = 8000.0
 
 
 def cg_bytes_f32(zfuse):
-    """Algorithmic bytes per node of one float32 inner-CG iteration, (product,
-    update); the product also reads 4 per element (E).  With z formed in the
-    product (zfuse) it reads r, the Jacobi diagonal and p_old (28) and writes
-    p and q (24); the update reads x, p, r, q, the diagonal and the mask byte
-    (53) and writes x and r (24).  With z stored, the product reads z instead
-    of r and the diagonal (24 + 24) and the update also writes z (53 + 36)."""
-    return (52, 77) if zfuse else (48, 89)
+    """Algorithmic bytes per node of the float32 inner-CG kernels: the product
+    (which also reads 4 per element, E) and the update by how it treats x.
+    With z formed in the product (zfuse) the product reads r, the Jacobi
+    diagonal and p_old (28) and writes p and q (24); with z stored it reads z
+    and p_old (24) and writes p and q, and every update also writes z (12).
+    The update reads r, q, the diagonal and the mask byte (29) and writes r
+    (12); advancing x every iteration adds x and p (24) read and x written
+    (12); with x grouped, three of four (one of two) updates skip x and the
+    fourth (second) reads x and all the group's directions and writes x."""
+    zs = 0 if zfuse else 12
+    return {"product": 52 if zfuse else 48, "each": 77 + zs, "skip": 41 + zs,
+            "flush2": 89 + zs, "flush4": 113 + zs}
+
+
+def cg_iteration_bytes_f32(zfuse):
+    """Per node and iteration, float32 CG as the solve runs it (x grouped by
+    two): the product plus the mean of a skipping and a grouped update."""
+    b = cg_bytes_f32(zfuse)
+    return b["product"] + (b["skip"] + b["flush2"]) / 2
 
 
 def log(*a):
@@ -233,11 +245,14 @@ def algorithmic_bytes(kernel, dims):
         ("k_matvec<float, 0>", 25, 4),         # read u (12) and the mask byte, E; write y (12)
         ("k_matvec_mfma<0>", 25, 4),
         ("k_matvec<double, 0>", 49, 8),
-        ("k_cg_matvec1<float, false, false, 1>", cg_bytes_f32(True)[0], 4),
-        ("k_cg_matvec1<float, false, true, 1>", cg_bytes_f32(True)[0], 4),
-        ("k_cg_matvec1<float, false, false, 0>", cg_bytes_f32(False)[0], 4),
-        ("k_cg_matvec1<float, false, true, 0>", cg_bytes_f32(False)[0], 4),
-        ("k_cg_update1<float, false>", cg_bytes_f32(cg_zfuse_dims(dims))[1], 0),
+        ("k_cg_matvec1<float, false, false, 1>", cg_bytes_f32(True)["product"], 4),
+        ("k_cg_matvec1<float, false, true, 1>", cg_bytes_f32(True)["product"], 4),
+        ("k_cg_matvec1<float, false, false, 0>", cg_bytes_f32(False)["product"], 4),
+        ("k_cg_matvec1<float, false, true, 0>", cg_bytes_f32(False)["product"], 4),
+        ("k_cg_update1<float, false, 0>", cg_bytes_f32(cg_zfuse_dims(dims))["each"], 0),
+        ("k_cg_update1<float, false, 1>", cg_bytes_f32(cg_zfuse_dims(dims))["skip"], 0),
+        ("k_cg_update1<float, false, 2>", cg_bytes_f32(cg_zfuse_dims(dims))["flush2"], 0),
+        ("k_cg_update1<float, false, 3>", cg_bytes_f32(cg_zfuse_dims(dims))["flush4"], 0),
         ("k_ls_advect", 24, 0), ("k_ls_reinit", 16, 0),
         ("k_hcg_apply", 17, 0), ("k_hcg_update", 56, 0), ("k_hcg_dir", 24, 0),
         ("__amd_rocclr_copyBuffer", None, None),
@@ -349,13 +364,13 @@ SUMMARIES = [
      "rtol 1e-2: inner-CG product and update", LARGE, "cg3_trace", "cg3_fetch", "cg3_write",
      ("cg3_sq",), PRODUCT_SOURCES,
      ("k_cg_matvec1<float, false, false, 1>", "k_cg_matvec1<float, false, true, 1>",
-      "k_cg_update1<float, false>")),
+      "k_cg_update1<float, false, 1>", "k_cg_update1<float, false, 2>")),
     ("pmc_cg_matvec_f32_cantilever_96x48x48.txt",
      "one fp32+refine solve of the 96x48x48 cantilever (seed 1) to rtol 1e-4: inner-CG product "
      "and update (working set resident in the 256 MB Infinity Cache)", DIMS, None, "cg_fetch",
      "cg_write", (), PRODUCT_SOURCES,
      ("k_cg_matvec1<float, false, false, 0>", "k_cg_matvec1<float, false, true, 0>",
-      "k_cg_update1<float, false>")),
+      "k_cg_update1<float, false, 1>", "k_cg_update1<float, false, 2>")),
     ("levelset_256x128x128.txt",
      "level-set evolution (10 steps) and reinitialisation (to 1e-3, at most 40 pseudo-steps) on "
      "the 257x129x129 node grid; phi = 2.5 x the distance to three balls, smooth speed of both "
@@ -1237,8 +1252,8 @@ def workload_large(A, inputs, dev, copy_gbs):
                 "traffic": measured_traffic("kernel_trace_cg_256x128x128.txt", "void topo::" + kern),
                 "kernel": kern, "avg_us": round(mv_us, 3), "launches_sampled": mv_n,
                 "bytes_per_launch": byt}
-            out["cg_algorithmic_bytes_per_node_per_iteration"] = sum(
-                cg_bytes_f32(cg_zfuse_dims(dims)))
+            out["cg_algorithmic_bytes_per_node_per_iteration"] = cg_iteration_bytes_f32(
+                cg_zfuse_dims(dims))
         ctx.close()
         del u, dc
         torch.cuda.empty_cache()

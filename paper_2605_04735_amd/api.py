@@ -394,10 +394,6 @@ def cg_product_kernel_name(dims):
     return "k_cg_matvec1<float, false, false, %d>" % int(cg_zfuse(dims))
 
 
-def cg_update_kernel_name():
-    """Name of the float32 inner-CG update kernel of the one-design solve."""
-    return "k_cg_update1<float, false>"
-
 
 class Server:
     """Continuous-batching compliance + sensitivity server (to_server_*).

@@ -25,6 +25,7 @@ namespace {
 thread_local std::string g_last_error;
 
 constexpr int MAXOFS = 1024;        // filter stencil capacity (rmin <= 6)
+constexpr int NCGV = 8;             // inner CG vectors of ndof entries
 constexpr double MAX_RMIN = 6.0;
 
 struct Layout {
@@ -52,8 +53,9 @@ struct to_ctx {
   double *E64 = nullptr, *dinv64 = nullptr, *f = nullptr, *r64 = nullptr;
   float *E32 = nullptr, *dinv32 = nullptr;
   uint8_t *mask = nullptr;
-  double *v64[6] = {};  // d, r, z, pA, pB, q  (float64 inner)
-  float *v32[6] = {};   // d, r, z, pA, pB, q  (float32 inner)
+  // inner CG vectors (float64 or float32 inner): x, r, z, p0, p1, q, p2, p3
+  double *v64[NCGV] = {};
+  float *v32[NCGV] = {};
   double *part = nullptr, *scal = nullptr;
   int *flags = nullptr;
   double *ftmp = nullptr, *fw = nullptr;
@@ -66,7 +68,7 @@ struct to_ctx {
   CgDesc<double> hd64{};
   double *cgp = nullptr;         // block partials of the batched CG kernels
   int nb_mv = 0, nb_up = 0;
-  int parity = 0;
+  int slot = 0;  // direction slot of the next inner-CG product (partial sets by slot & 1)
 
   double *tri = nullptr;  // triangles, grown on demand by to_density_to_sdf
   size_t tri_cap = 0;
@@ -99,11 +101,11 @@ struct to_ctx {
   long long prof_count = 0;
   int prof_every = 16;  // bracket one product launch in this many
   // a chunk of CG iterations as one graph launch, per precision and starting
-  // parity (built on first use); with timing on, one chunk in four runs as
+  // direction slot (built on first use); with timing on, one chunk in four runs as
   // separate launches so that product launches can be sampled
   bool use_graph = true;
   long long chunks = 0;
-  hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  hipGraphExec_t graph[2][CG_NP_MAX] = {};
   std::string err;
 };
 
@@ -190,11 +192,11 @@ size_t carve(to_ctx *c, const Grid &g, int precision, double nu, char *base) {
   const size_t oD64 = L.take<double>(g.nn), oD32 = L.take<float>(g.nn);
   const size_t oMask = L.take<uint8_t>(g.nn);
   const size_t oF = L.take<double>(g.ndof), oR64 = L.take<double>(g.ndof);
-  size_t ov[6];
+  size_t ov[NCGV];
   if (precision == TO_PREC_FP64)
-    for (int i = 0; i < 6; ++i) ov[i] = L.take<double>(g.ndof);
+    for (int i = 0; i < NCGV; ++i) ov[i] = L.take<double>(g.ndof);
   else
-    for (int i = 0; i < 6; ++i) ov[i] = L.take<float>(g.ndof);
+    for (int i = 0; i < NCGV; ++i) ov[i] = L.take<float>(g.ndof);
   const size_t oPart = L.take<double>(2 * (size_t)MAXB);
   const size_t oScal = L.take<double>(S_COUNT);
   const size_t oFlags = L.take<int>(F_COUNT);
@@ -217,7 +219,7 @@ size_t carve(to_ctx *c, const Grid &g, int precision, double nu, char *base) {
     c->mask = (uint8_t *)(base + oMask);
     c->f = (double *)(base + oF);
     c->r64 = (double *)(base + oR64);
-    for (int i = 0; i < 6; ++i) {
+    for (int i = 0; i < NCGV; ++i) {
       if (precision == TO_PREC_FP64) c->v64[i] = (double *)(base + ov[i]);
       else c->v32[i] = (float *)(base + ov[i]);
     }
@@ -323,7 +325,7 @@ int topo::cg_zfuse(const Grid &g) {
 namespace {
 
 template <typename T>
-CgDesc<T> make_desc(to_ctx *c, T *const v[6], const T *E, const T *dinv, const Coef<T> &k) {
+CgDesc<T> make_desc(to_ctx *c, T *const v[NCGV], const T *E, const T *dinv, const Coef<T> &k) {
   const Grid &g = c->g;
   CgDesc<T> d{};
   d.nelx = g.nelx;
@@ -351,7 +353,21 @@ CgDesc<T> make_desc(to_ctx *c, T *const v[6], const T *E, const T *dinv, const C
   d.z = v[2];
   d.p[0] = v[3];
   d.p[1] = v[4];
+  d.p[2] = v[6];
+  d.p[3] = v[7];
   d.q = v[5];
+  // grouped x unless z is stored in bfloat16, whose update advances x itself:
+  // groups of two in float32 (the two direction buffers; four gained no more
+  // there), of four in float64 (13% per iteration at 256 x 128 x 128 against
+  // 9% for two).  TOPO_XGROUP=0 / 2 / 4 selects x every iteration / groups
+  // of two / groups of four.
+  d.np = sizeof(T) == 8 ? 4 : 2;
+  d.xgroup = !d.zbf16;
+  if (const char *e = std::getenv("TOPO_XGROUP")) {
+    const int v = std::atoi(e);
+    d.xgroup = !d.zbf16 && v != 0;
+    d.np = d.xgroup && v == 4 ? 4 : 2;
+  }
   d.cgp = c->cgp;
   d.scal = c->scal;
   d.flags = c->flags;
@@ -362,37 +378,42 @@ CgDesc<T> make_desc(to_ctx *c, T *const v[6], const T *E, const T *dinv, const C
 // the batch-of-one case of the batched CG kernels (two launches per
 // iteration; the reductions finish in the last block of each kernel).
 template <typename T>
-to_status inner_pcg(to_ctx *c, T *const v[6], const T *dinv, double eta, int cap, int *iters,
+to_status inner_pcg(to_ctx *c, T *const v[NCGV], const T *dinv, double eta, int cap, int *iters,
                     int *status) {
   const Grid &g = c->g;
-  // the first product runs with parity c->parity and reads partial set parity ^ 1
-  const int slot = c->parity ^ 1;
-  const int zbf = sizeof(T) == 4 && c->p.precision == TO_PREC_FP32_REFINE_BF16;
-  HIPCHK(launch_cg_init<T>(g, c->r64, c->scal, v[0], v[1], v[2], v[3], v[4], dinv, c->mask, c->cgp,
-                           slot, c->nb_up, c->stream, zbf));
-  HIPCHK(launch_finish_init(c->cgp, c->nb_up, slot, eta * eta, cap, c->scal, c->flags, c->stream));
   const CgDesc<T> *hd;
   if constexpr (sizeof(T) == 4) hd = &c->hd32;
   else hd = &c->hd64;
+  const int np = hd->np == 4 ? 4 : 2;
+  c->slot %= np;
+  // the first product runs at direction slot c->slot and reads partial set
+  // (slot & 1) ^ 1; every direction slot starts at zero
+  const int pset = (c->slot & 1) ^ 1;
+  const int zbf = sizeof(T) == 4 && c->p.precision == TO_PREC_FP32_REFINE_BF16;
+  HIPCHK(launch_cg_init<T>(g, c->r64, c->scal, v[0], v[1], v[2], v[3], v[4], dinv, c->mask, c->cgp,
+                           pset, c->nb_up, c->stream, zbf, np == 4 ? v[6] : nullptr,
+                           np == 4 ? v[7] : nullptr));
+  HIPCHK(launch_finish_init(c->cgp, c->nb_up, pset, eta * eta, cap, c->scal, c->flags, c->stream,
+                            c->slot));
   int launched = 0;
   *iters = 0;
   *status = 0;
   for (;;) {
     const int n = std::min(c->chunk, cap - launched);
-    hipGraphExec_t &gx = c->graph[sizeof(T) == 8][c->parity];
+    hipGraphExec_t &gx = c->graph[sizeof(T) == 8][c->slot];
     const bool sample = c->prof && (c->chunks++ % 4 == 0);
-    if (c->use_graph && !sample && n == c->chunk && c->chunk % 2 == 0) {
-      if (!gx) HIPCHK(build_cg_graph<T>(*hd, c->parity, c->chunk, &gx));
-      HIPCHK(hipGraphLaunch(gx, c->stream));  // an even chunk keeps the parity
+    if (c->use_graph && !sample && n == c->chunk && c->chunk % np == 0) {
+      if (!gx) HIPCHK(build_cg_graph<T>(*hd, c->slot, c->chunk, &gx));
+      HIPCHK(hipGraphLaunch(gx, c->stream));  // a chunk of whole slot cycles keeps the slot
     } else {
       for (int it = 0; it < n; ++it) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         // sampled away from the first launch after a host synchronisation
         if (c->prof && (launched + it) % c->prof_every == c->prof_every / 2)
           HIPCHK(prof_pair(c, &e0, &e1));
-        HIPCHK(launch_cg_matvec1<T>(*hd, c->parity, c->stream, e0, e1));
-        HIPCHK(launch_cg_update1<T>(*hd, c->parity, c->stream));
-        c->parity ^= 1;
+        HIPCHK(launch_cg_matvec1<T>(*hd, c->slot, c->stream, e0, e1));
+        HIPCHK(launch_cg_update1<T>(*hd, c->slot, c->stream));
+        c->slot = (c->slot + 1) % np;
       }
     }
     launched += n;
@@ -410,9 +431,11 @@ to_status inner_pcg(to_ctx *c, T *const v[6], const T *dinv, double eta, int cap
   return TO_OK;
 }
 
+// u += the inner solution (with the grouped steps still pending)
 template <typename T>
-to_status axpy_correction(to_ctx *c, double *u, const T *d) {
-  HIPCHK(launch_axpy_out<T>(c->g, u, d, c->scal, c->stream));
+to_status axpy_correction(to_ctx *c, double *u, const CgDesc<T> &d) {
+  HIPCHK(launch_axpy_out<T>(c->g, u, d.x, c->scal, c->stream, d.np == 4 ? 4 : 2, d.xgroup, d.p,
+                            c->flags));
   return TO_OK;
 }
 
@@ -621,11 +644,11 @@ to_status to_solve(to_ctx *c, const double *d_x, const double *d_u0, double *d_u
       if (fp64) {
         st = inner_pcg<double>(c, c->v64, c->dinv64, eta, cap, &it, &status);
         if (st != TO_OK) return st;
-        st = axpy_correction<double>(c, d_u, c->v64[0]);
+        st = axpy_correction<double>(c, d_u, c->hd64);
       } else {
         st = inner_pcg<float>(c, c->v32, c->dinv32, eta, cap, &it, &status);
         if (st != TO_OK) return st;
-        st = axpy_correction<float>(c, d_u, c->v32[0]);
+        st = axpy_correction<float>(c, d_u, c->hd32);
       }
       if (st != TO_OK) return st;
       total_inner += it;

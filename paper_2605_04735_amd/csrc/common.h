@@ -25,7 +25,8 @@ enum Scal {
   S_RZ0,        // r^T z of the partial-sum set of parity 0 / 1 (batched CG)
   S_RZ1,
   S_RP,         // bfloat16 directions: r^T p_old of the current iterate (see CGP_RP)
-  S_COUNT = 16
+  S_AH,         // grouped x update: step length of the direction in slot j, S_AH + j
+  S_COUNT = S_AH + 4 + 4
 };
 enum Flag {
   F_DONE = 0,   // inner CG finished (converged, broke down or non-finite)
@@ -34,6 +35,7 @@ enum Flag {
   F_BADX,       // bit 0: some x outside [0,1]; bit 1: some x non-finite
   F_CAP,        // the inner CG stops (done) after this many iterations
   F_BADG,       // some sensitivity handed to the OC update is non-finite
+  F_SLOT0,      // direction slot of the first product of the current inner solve
   F_COUNT = 8
 };
 
@@ -106,8 +108,17 @@ struct MvArgs {
   int zfuse;
 };
 
-// One design of a batched inner CG solve (device resident).  The product
-// kernel reads p[parity] as the previous direction and writes p[parity ^ 1].
+// Direction slots of the inner CG: the product of slot s reads p[s] as the
+// previous direction and writes p[(s + 1) % np]; its partial sums alternate
+// with s & 1.  Without grouping every update advances x by alpha p.  With
+// grouped x the updates keep each step length and advance x once every np
+// iterations by the np steps together (the update of slot np - 2, when all np
+// directions are still in their slots): x += alpha p moves 36 bytes per node,
+// the grouped form 12 + 24 / np on average.
+constexpr int CG_NP_MAX = 4;
+enum XUpdate { XU_EACH = 0, XU_SKIP = 1, XU_FLUSH2 = 2, XU_FLUSH4 = 3 };
+
+// One design of a batched inner CG solve (device resident).
 template <typename T>
 struct CgDesc {
   int nelx, nely, nelz, kz;
@@ -115,16 +126,17 @@ struct CgDesc {
   int nb_mv, nb_up;     // blocks of this design in the product / update kernels
   int zbf16;           // float32 CG: z stored in bfloat16 (2 bytes per component)
   int zfuse;           // the product forms z = D r (1) or reads the z the update stored (0)
+  int np;              // direction slots: 2 (0 reads as 2) or 4
+  int xgroup;          // x advanced once per np iterations (1) or every iteration (0)
   long long nn;
   Coef<T> k;
   const void *mA;       // float32: the matrix-core product's A operand, or NULL for the
   float mscale;         //   vector-ALU product (then tx, ty, kz and nb_mv are its tiles')
-  int pad2_;
   const T *E;
   const T *dinv;
   const uint8_t *mask;
   T *x, *r, *z, *q;
-  T *p[2];
+  T *p[CG_NP_MAX];
   double *cgp;          // [CGP_SIZE] block partials: p^T q, then r^T z and ||r||^2 by parity
   double *scal;         // [S_COUNT]
   int *flags;           // [F_COUNT]
@@ -231,19 +243,20 @@ int vec_blocks(size_t nn);
 template <typename T>
 hipError_t launch_cg_init(const Grid &g, const double *b, const double *scal, T *x, T *r, T *z,
                           T *pA, T *pB, const T *dinv, const uint8_t *mask, double *cgp, int slot,
-                          int nb_up, hipStream_t s, int zbf = 0);  // zbf: z stored in bfloat16
+                          int nb_up, hipStream_t s, int zbf = 0,  // zbf: z stored in bfloat16
+                          T *pC = nullptr, T *pD = nullptr);  // further direction slots (zeroed)
 // One CG iteration for every design of a batch is the product kernel (with
 // its last-block step length) followed by the update kernel (last-block beta
 // and convergence test).  blockmaps: (design, local block) per block.
 // One design, descriptor by value (the single-solve path).
 template <typename T>
-hipError_t launch_cg_matvec1(const CgDesc<T> &d, int parity, hipStream_t s,
+hipError_t launch_cg_matvec1(const CgDesc<T> &d, int slot, hipStream_t s,
                              hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 template <typename T>
-hipError_t launch_cg_update1(const CgDesc<T> &d, int parity, hipStream_t s);
+hipError_t launch_cg_update1(const CgDesc<T> &d, int slot, hipStream_t s);
 // `iters` CG iterations of one design as an instantiated graph (see k_matvec.hip)
 template <typename T>
-hipError_t build_cg_graph(const CgDesc<T> &d, int parity0, int iters, hipGraphExec_t *out);
+hipError_t build_cg_graph(const CgDesc<T> &d, int slot0, int iters, hipGraphExec_t *out);
 template <typename T>
 hipError_t build_cg_graph_batched(const CgDesc<T> *descs, const BlockEntry *bmv, int nb_mv,
                                   const BlockEntry *bup, int nb_up, int parity0, int iters,
@@ -264,12 +277,17 @@ enum { ZF_READ = 0, ZF_FORM = 1, ZF_DESC = 2 };
 constexpr size_t ZFUSE_MIN_NODES = size_t(1) << 19;
 int cg_zfuse(const Grid &g);
 
+// u += (x + the pending grouped steps) / scal[S_SCALE]: the float64 solution
+// update of the outer refinement.  With grouped x (xgroup) the steps since
+// the last grouped update, sum_j alpha_j p[j] over j < (flags[F_SLOT0] +
+// flags[F_ITERS] + 1) % np, are still pending and are applied here.
 template <typename T>
 hipError_t launch_axpy_out(const Grid &g, double *u, const T *d, const double *scal,
-                           hipStream_t s);
+                           hipStream_t s, int np = 2, int xgroup = 0, T *const *p = nullptr,
+                           const int *flags = nullptr);
 
 hipError_t launch_finish_init(const double *cgp, int nb_up, int slot, double tol2_rel, int cap,
-                              double *scal, int *flags, hipStream_t s);
+                              double *scal, int *flags, hipStream_t s, int slot0 = 0);
 hipError_t launch_finish_sum(const double *part, int nb, int comp, double *scal, int idx,
                              hipStream_t s);
 hipError_t launch_fill(void *p, size_t bytes, hipStream_t s);

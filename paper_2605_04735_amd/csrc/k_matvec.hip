@@ -315,7 +315,8 @@ void k_matvec(const MvArgs<T> a, int tx, int ty) {
 // the block's p^T q partial is written for the update kernel.
 template <typename T, bool ZBF = false, bool MF = false, int ZF = ZF_DESC>
 __device__ __forceinline__ void cg_matvec_block(const CgDesc<T> &d, double *scal, int *flags,
-                                                double *cgp, int nparts, int lb_in, int parity) {
+                                                double *cgp, int nparts, int lb_in, int slot) {
+  const int parity = slot & 1;
   static_assert(!MF || (sizeof(T) == 4 && !ZBF), "matrix-core product: float32 CG, float32 z");
   __shared__ double red[16];
   bool run = false;
@@ -356,9 +357,11 @@ __device__ __forceinline__ void cg_matvec_block(const CgDesc<T> &d, double *scal
   a.zfuse = ZBF || ZF == ZF_READ ? 0 : ZF == ZF_FORM ? 1 : d.zfuse;
   a.in = a.zfuse ? d.r : d.z;
   a.dinv = d.dinv;
-  T *const p0 = d.p[0], *const p1 = d.p[1];
-  a.pold = parity ? p1 : p0;
-  a.pout = parity ? p0 : p1;
+  // the previous direction in slot s, the new one into slot s + 1 (mod np)
+  const int np = d.np == 4 ? 4 : 2;
+  T *const p0 = d.p[slot], *const p1 = d.p[slot + 1 == np ? 0 : slot + 1];
+  a.pold = p0;
+  a.pout = p1;
   a.out = d.q;
   a.mask = d.mask;
   a.k = d.k;
@@ -427,9 +430,9 @@ __global__ __launch_bounds__(MV_THREADS) void k_cg_matvec(const CgDesc<T> *descs
 // need no argument load before them.
 template <typename T, bool ZBF, bool MF = false, int ZF = ZF_READ>
 __global__ __launch_bounds__(MV_THREADS) void k_cg_matvec1(double *scal, int *flags, double *cgp,
-                                                           int parity, int nparts,
+                                                           int slot, int nparts,
                                                            const CgDesc<T> d) {
-  cg_matvec_block<T, ZBF, MF, ZF>(d, scal, flags, cgp, nparts, -1, parity);
+  cg_matvec_block<T, ZBF, MF, ZF>(d, scal, flags, cgp, nparts, -1, slot);
 }
 
 // Batched CG vector update: every block completes the p^T q reduction of the
@@ -438,10 +441,14 @@ __global__ __launch_bounds__(MV_THREADS) void k_cg_matvec1(double *scal, int *fl
 // the block's r^T z and ||r||^2 partials go to set `parity` for the next
 // product.  A thread's first two nodes are loaded before the reduction, so
 // their latency overlaps it.
-template <typename T, bool ZBF = false>
+template <typename T, bool ZBF = false, int XU = XU_EACH>
 __device__ __forceinline__ void cg_update_block(const CgDesc<T> &d, double *scal, int *flags,
-                                                double *cgp, int nparts, int lb, int parity) {
+                                                double *cgp, int nparts, int lb, int slot) {
+  static_assert(XU == XU_EACH || !ZBF, "grouped x: float32 or float64 z");
+  constexpr bool FL = XU == XU_FLUSH2 || XU == XU_FLUSH4;  // the grouped x update
+  constexpr int NG = XU == XU_FLUSH4 ? 4 : 2;               // its group size
   __shared__ double red[8];
+  const int parity = slot & 1;
   constexpr unsigned S = sizeof(T);
   constexpr unsigned SZ = ZBF ? 2u : sizeof(T);  // stored z component
   // first the loads that need nothing but the leading arguments
@@ -454,32 +461,65 @@ __device__ __forceinline__ void cg_update_block(const CgDesc<T> &d, double *scal
   // bfloat16 z (a preconditioner that varies with the rounding): the exact
   // line search along p, r^T p = r^T z + beta r^T p_old
   if constexpr (ZBF) rz += bload1d(rs, 8u * S_BETA, 0) * bload1d(rs, 8u * S_RP, 0);
+  // grouped x (the update of slot np - 2): the step lengths of slots 0 ..
+  // np - 2, kept by the updates before this one
+  double ah[3] = {0.0, 0.0, 0.0};
+  if constexpr (FL) {
+#pragma unroll
+    for (int j = 0; j < NG - 1; ++j) ah[j] = bload1d(rs, 8u * (S_AH + j), 0);
+  }
   __builtin_amdgcn_sched_barrier(0);  // keep those loads first
   // then the descriptor fields in one round trip
   const unsigned nn = (unsigned)d.nn;
   T *const x = d.x, *const r = d.r, *const z = d.z, *const q = d.q;
-  T *const p0 = d.p[0], *const p1 = d.p[1];
+  // the direction the product just wrote: slot s + 1 (mod np); the grouped
+  // update reads all np slots
+  T *const pn = d.p[slot ^ 1];  // np = 2: slot ^ 1 = slot + 1 (mod 2)
+  T *const pf0 = d.p[0], *const pf1 = d.p[1], *const pf2 = d.p[2], *const pf3 = d.p[NG - 1];
   const T *const dinv = d.dinv;
   const uint8_t *const mask = d.mask;
   const int nb_up = d.nb_up, zfuse = d.zfuse;
-  asm volatile("" ::"s"(nn), "s"(x), "s"(r), "s"(z), "s"(q), "s"(p0), "s"(p1), "s"(dinv),
-               "s"(mask), "s"(nb_up), "s"(zfuse));
+  if constexpr (XU == XU_FLUSH4)
+    asm volatile("" ::"s"(nn), "s"(x), "s"(r), "s"(z), "s"(q), "s"(pf0), "s"(pf1), "s"(pf2),
+                 "s"(pf3), "s"(dinv), "s"(mask), "s"(nb_up), "s"(zfuse));
+  else if constexpr (XU == XU_FLUSH2)
+    asm volatile("" ::"s"(nn), "s"(x), "s"(r), "s"(z), "s"(q), "s"(pf0), "s"(pf3), "s"(dinv),
+                 "s"(mask), "s"(nb_up), "s"(zfuse));
+  else if constexpr (XU == XU_EACH)
+    asm volatile("" ::"s"(nn), "s"(x), "s"(r), "s"(z), "s"(q), "s"(pn), "s"(dinv), "s"(mask),
+                 "s"(nb_up), "s"(zfuse));
+  else
+    asm volatile("" ::"s"(nn), "s"(r), "s"(z), "s"(q), "s"(dinv), "s"(mask), "s"(nb_up),
+                 "s"(zfuse));
   const bool zst = ZBF || !zfuse;  // z is stored for the product
-  const rsrc_t rX = make_rsrc(x, 3u * nn * S), rR = make_rsrc(r, 3u * nn * S);
+  constexpr bool XA = XU != XU_SKIP;  // x advances in this launch
+  const rsrc_t rX = make_rsrc(x, XA ? 3u * nn * S : 0u), rR = make_rsrc(r, 3u * nn * S);
   const rsrc_t rZ = make_rsrc(z, zst ? 3u * nn * SZ : 0u), rQ = make_rsrc(q, 3u * nn * S);
-  const rsrc_t rP = make_rsrc(parity ? p0 : p1, 3u * nn * S);  // p[parity ^ 1]
+  // the last direction of a group is the one just written: slot NG - 1
+  const rsrc_t rP = make_rsrc(FL ? pf3 : pn, XA ? 3u * nn * S : 0u);
+  const rsrc_t rP0 = make_rsrc(pf0, FL ? 3u * nn * S : 0u);
+  const rsrc_t rP1 = make_rsrc(pf1, XU == XU_FLUSH4 ? 3u * nn * S : 0u);
+  const rsrc_t rP2 = make_rsrc(pf2, XU == XU_FLUSH4 ? 3u * nn * S : 0u);
   const rsrc_t rD = make_rsrc(dinv, nn * S), rM = make_rsrc(mask, nn);
   const unsigned stride = (unsigned)nb_up * 256u;
   struct Node {
     T x[3], p[3], r[3], q[3], di;
+    T pg[3][3];  // grouped x: the directions of slots 0 .. NG - 2
     unsigned m, vo, vz;  // vz: offset of the node's z (SZ bytes per component)
   };
   auto load = [&](Node &v, unsigned n) {
-    const bool in = n < nn;
+    const bool in = n < nn;  // (n < nn + 4 stride: far below 2^32 for any accepted grid)
     v.vo = in ? 3u * S * n : OOB;
     v.vz = in ? 3u * SZ * n : OOB;
-    bload3(rX, v.vo, 0, v.x);
-    bload3(rP, v.vo, 0, v.p);
+    if constexpr (XA) {
+      bload3(rX, v.vo, 0, v.x);
+      bload3(rP, v.vo, 0, v.p);
+    }
+    if constexpr (FL) bload3(rP0, v.vo, 0, v.pg[0]);
+    if constexpr (XU == XU_FLUSH4) {
+      bload3(rP1, v.vo, 0, v.pg[1]);
+      bload3(rP2, v.vo, 0, v.pg[2]);
+    }
     bload3(rR, v.vo, 0, v.r);
     bload3(rQ, v.vo, 0, v.q);
     v.di = bload1<T>(rD, in ? S * n : OOB, 0);
@@ -502,12 +542,18 @@ __device__ __forceinline__ void cg_update_block(const CgDesc<T> &d, double *scal
     return;
   }
   const T alpha = (T)(rz / pq);
+  const T a0 = (T)ah[0], a1 = (T)ah[1], a2 = (T)ah[2];
   double rzs = 0.0, rrs = 0.0, rps = 0.0, zqs = 0.0;
   auto update = [&](const Node &v) {
     T xn[3], rn[3], zn[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      xn[c] = v.x[c] + alpha * v.p[c];
+      if constexpr (XU == XU_FLUSH4)  // the steps in the order they were taken
+        xn[c] = v.x[c] + a0 * v.pg[0][c] + a1 * v.pg[1][c] + a2 * v.pg[2][c] + alpha * v.p[c];
+      else if constexpr (XU == XU_FLUSH2)
+        xn[c] = v.x[c] + a0 * v.pg[0][c] + alpha * v.p[c];
+      else if constexpr (XU == XU_EACH)
+        xn[c] = v.x[c] + alpha * v.p[c];
       rn[c] = ((v.m >> c) & 1u) ? T(0) : v.r[c] - alpha * v.q[c];
       zn[c] = mul_rn(v.di, rn[c]);
       if constexpr (ZBF) zn[c] = bf16_round(zn[c]);  // the z the next product reads
@@ -518,18 +564,30 @@ __device__ __forceinline__ void cg_update_block(const CgDesc<T> &d, double *scal
         zqs += (double)zn[c] * (double)v.q[c];
       }
     }
-    bstore3(rX, v.vo, 0, xn);
+    if constexpr (XA) bstore3(rX, v.vo, 0, xn);
     bstore3(rR, v.vo, 0, rn);
     if constexpr (ZBF) bstore3_bf16(rZ, v.vz, 0, zn);
     else bstore3(rZ, v.vz, 0, zn);  // (an empty resource drops it under zfuse)
   };
-  update(A);
-  update(B);
-  for (unsigned n = n0 + 2u * stride; n < nn; n += 2u * stride) {
-    load(A, n);
-    load(B, n + stride);
+  // pairs of nodes, the next pair's loads in flight while a pair updates;
+  // every thread runs the same number of pairs (nodes past nn load 0 and
+  // their stores are dropped), so the loop has no divergent exit and its
+  // waits stay exact
+  const unsigned npair = (nn + 2u * stride - 1u) / (2u * stride);
+  Node C, D;
+  for (unsigned k = 0;; k += 2) {
+    const unsigned n1 = n0 + (k + 1) * 2u * stride;
+    load(C, n1);
+    load(D, n1 + stride);
     update(A);
     update(B);
+    if (k + 1 >= npair) break;
+    const unsigned n2 = n0 + (k + 2) * 2u * stride;
+    load(A, n2);
+    load(B, n2 + stride);
+    update(C);
+    update(D);
+    if (k + 2 >= npair) break;
   }
   double s1, s2, s3 = 0.0, s4 = 0.0;
   if constexpr (ZBF) {
@@ -549,6 +607,9 @@ __device__ __forceinline__ void cg_update_block(const CgDesc<T> &d, double *scal
     if (lb == 0) {
       scal[S_PQ] = pq;
       scal[S_ALPHA] = rz / pq;
+      // grouped x: the step of the direction in slot s + 1, for the flush or
+      // for the solution update if the CG stops before the flush
+      if constexpr (XU != XU_EACH) scal[S_AH + (slot + 1 == (d.np == 4 ? 4 : 2) ? 0 : slot + 1)] = rz / pq;
       flags[F_ITERS] = flags[F_ITERS] + 1;
     }
   }
@@ -562,10 +623,10 @@ __global__ __launch_bounds__(256) void k_cg_update(const CgDesc<T> *descs,
   cg_update_block<T>(descs[be.design], be.scal, be.flags, be.cgp, be.nparts, be.lb, parity);
 }
 
-template <typename T, bool ZBF>
+template <typename T, bool ZBF, int XU = XU_EACH>
 __global__ __launch_bounds__(256) void k_cg_update1(double *scal, int *flags, double *cgp,
-                                                    int parity, int nparts, const CgDesc<T> d) {
-  cg_update_block<T, ZBF>(d, scal, flags, cgp, nparts, blockIdx.x, parity);
+                                                    int slot, int nparts, const CgDesc<T> d) {
+  cg_update_block<T, ZBF, XU>(d, scal, flags, cgp, nparts, blockIdx.x, slot);
 }
 
 namespace {
@@ -663,56 +724,62 @@ void *cg_matvec1_kernel(const CgDesc<T> &d) {
 }
 
 template <typename T>
-hipError_t launch_cg_matvec1(const CgDesc<T> &d, int parity, hipStream_t s, hipEvent_t start,
+hipError_t launch_cg_matvec1(const CgDesc<T> &d, int slot, hipStream_t s, hipEvent_t start,
                              hipEvent_t stop) {
   const dim3 grid(mv_grid(d.tx * d.ty, d.nb_mv / (d.tx * d.ty)));
   double *scal = d.scal, *cgp = d.cgp;
   int *flags = d.flags, nparts = d.nb_up;
   CgDesc<T> dd = d;
-  void *args[] = {&scal, &flags, &cgp, &parity, &nparts, &dd};
+  void *args[] = {&scal, &flags, &cgp, &slot, &nparts, &dd};
   // timestamps taken by the dispatch itself when events are given
   return hipExtLaunchKernel(cg_matvec1_kernel(d), grid, dim3(MV_THREADS), args, 0, s, start, stop,
                             0);
 }
 
+// the single-design update kernel for descriptor d at direction slot `slot`
 template <typename T>
-hipError_t launch_cg_update1(const CgDesc<T> &d, int parity, hipStream_t s) {
+void *cg_update1_kernel(const CgDesc<T> &d, int slot) {
   if constexpr (sizeof(T) == 4) {
-    if (d.zbf16) {
-      hipLaunchKernelGGL((k_cg_update1<T, true>), dim3(d.nb_up), dim3(256), 0, s, d.scal, d.flags,
-                         d.cgp, parity, d.nb_mv, d);
-      return hipGetLastError();
-    }
+    if (d.zbf16) return (void *)k_cg_update1<T, true>;
   }
-  hipLaunchKernelGGL((k_cg_update1<T, false>), dim3(d.nb_up), dim3(256), 0, s, d.scal, d.flags,
-                     d.cgp, parity, d.nb_mv, d);
-  return hipGetLastError();
+  if (!d.xgroup) return (void *)k_cg_update1<T, false, XU_EACH>;
+  const int np = d.np == 4 ? 4 : 2;
+  if (slot != np - 2) return (void *)k_cg_update1<T, false, XU_SKIP>;
+  return np == 4 ? (void *)k_cg_update1<T, false, XU_FLUSH4>
+                 : (void *)k_cg_update1<T, false, XU_FLUSH2>;
 }
 
-// A graph of `iters` CG iterations (product then update, alternating parity
-// from parity0) for one design: the same launches as launch_cg_matvec1 /
+template <typename T>
+hipError_t launch_cg_update1(const CgDesc<T> &d, int slot, hipStream_t s) {
+  double *scal = d.scal, *cgp = d.cgp;
+  int *flags = d.flags, nparts = d.nb_mv;
+  CgDesc<T> dd = d;
+  void *args[] = {&scal, &flags, &cgp, &slot, &nparts, &dd};
+  return hipLaunchKernel(cg_update1_kernel(d, slot), dim3(d.nb_up), dim3(256), args, 0, s);
+}
+
+// A graph of `iters` CG iterations (product then update, direction slots from
+// slot0 on) for one design: the same launches as launch_cg_matvec1 /
 // launch_cg_update1, built as explicit kernel nodes in a chain.
 template <typename T>
-hipError_t build_cg_graph(const CgDesc<T> &d, int parity0, int iters, hipGraphExec_t *out) {
+hipError_t build_cg_graph(const CgDesc<T> &d, int slot0, int iters, hipGraphExec_t *out) {
   *out = nullptr;
   hipGraph_t g = nullptr;
   hipError_t e = hipGraphCreate(&g, 0);
   if (e != hipSuccess) return e;
-  void *fmv = cg_matvec1_kernel(d), *fup = (void *)k_cg_update1<T, false>;
-  if constexpr (sizeof(T) == 4) {
-    if (d.zbf16) fup = (void *)k_cg_update1<T, true>;
-  }
+  void *fmv = cg_matvec1_kernel(d);
+  const int np = d.np == 4 ? 4 : 2;
   hipGraphNode_t prev = nullptr;
   for (int i = 0; i < 2 * iters && e == hipSuccess; ++i) {
-    int parity = parity0 ^ ((i >> 1) & 1);
+    int slot = (slot0 + (i >> 1)) % np;
     const bool mv = (i & 1) == 0;
     int nparts = mv ? d.nb_up : d.nb_mv;
     double *scal = d.scal, *cgp = d.cgp;
     int *flags = d.flags;
     CgDesc<T> dd = d;
-    void *args[] = {&scal, &flags, &cgp, &parity, &nparts, &dd};
+    void *args[] = {&scal, &flags, &cgp, &slot, &nparts, &dd};
     hipKernelNodeParams kp{};
-    kp.func = mv ? fmv : fup;
+    kp.func = mv ? fmv : cg_update1_kernel(d, slot);
     kp.gridDim = dim3(mv ? mv_grid(d.tx * d.ty, d.nb_mv / (d.tx * d.ty)) : d.nb_up);
     kp.blockDim = dim3(mv ? MV_THREADS : 256);
     kp.sharedMemBytes = 0;

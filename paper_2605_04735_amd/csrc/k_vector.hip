@@ -251,6 +251,7 @@ __global__ __launch_bounds__(256) void k_cg_init(size_t nn, const double *__rest
                                                  const double *__restrict__ scal, T *__restrict__ x,
                                                  T *__restrict__ r, T *__restrict__ z,
                                                  T *__restrict__ p, T *__restrict__ p2,
+                                                 T *__restrict__ p3, T *__restrict__ p4,
                                                  const T *__restrict__ dinv,
                                                  const uint8_t *__restrict__ mask,
                                                  double *__restrict__ rzp, double *__restrict__ rrp,
@@ -282,6 +283,8 @@ __global__ __launch_bounds__(256) void k_cg_init(size_t nn, const double *__rest
       if (!zdone) z[i] = zv;
       p[i] = 0;
       p2[i] = 0;
+      if (p3) p3[i] = 0;
+      if (p4) p4[i] = 0;
       rz += (double)rv * (double)zv;
       rr += (double)rv * (double)rv;
     }
@@ -299,29 +302,49 @@ __global__ __launch_bounds__(256) void k_cg_init(size_t nn, const double *__rest
 template <typename T>
 hipError_t launch_cg_init(const Grid &g, const double *b, const double *scal, T *x, T *r, T *z,
                           T *pA, T *pB, const T *dinv, const uint8_t *mask, double *cgp, int slot,
-                          int nb_up, hipStream_t s, int zbf) {
+                          int nb_up, hipStream_t s, int zbf, T *pC, T *pD) {
   hipLaunchKernelGGL(k_cg_init<T>, dim3(nb_up), dim3(256), 0, s, g.nn, b, scal, x, r, z, pA, pB,
-                     dinv, mask, cgp + CGP_RZ + slot * MAXB, cgp + CGP_RR + slot * MAXB,
+                     pC, pD, dinv, mask, cgp + CGP_RZ + slot * MAXB, cgp + CGP_RR + slot * MAXB,
                      cgp + CGP_RP + slot * MAXB, cgp + CGP_ZQ + slot * MAXB, zbf);
   return hipGetLastError();
 }
 
-// u += d / scal[S_SCALE]  (float64 solution update of the outer refinement)
+template <typename T>
+struct PSlots {
+  const T *p[CG_NP_MAX];
+};
+
+// u += (x + pending steps) / scal[S_SCALE]  (float64 solution update of the
+// outer refinement; the pending steps in the same order as a grouped update)
 template <typename T>
 __global__ void k_axpy_out(size_t ndof, double *__restrict__ u, const T *__restrict__ d,
-                           const double *__restrict__ scal) {
+                           const double *__restrict__ scal, int np, const PSlots<T> ps,
+                           const int *__restrict__ flags) {
   const double a = 1.0 / scal[S_SCALE];
+  const int npend = np > 0 ? (flags[F_SLOT0] + flags[F_ITERS] + 1) % np : 0;
+  T al[CG_NP_MAX];
+#pragma unroll
+  for (int j = 0; j < CG_NP_MAX; ++j) al[j] = j < npend ? (T)scal[S_AH + j] : T(0);
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ndof;
-       i += (size_t)gridDim.x * blockDim.x)
-    u[i] += a * (double)d[i];
+       i += (size_t)gridDim.x * blockDim.x) {
+    T x = d[i];
+    for (int j = 0; j < npend; ++j) x = x + al[j] * ps.p[j][i];
+    u[i] += a * (double)x;
+  }
 }
 
 template <typename T>
 hipError_t launch_axpy_out(const Grid &g, double *u, const T *d, const double *scal,
-                           hipStream_t s) {
+                           hipStream_t s, int np, int xgroup, T *const *p, const int *flags) {
   int blocks = (int)((g.ndof + 255) / 256);
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_axpy_out<T>, dim3(blocks), dim3(256), 0, s, g.ndof, u, d, scal);
+  PSlots<T> ps{};
+  if (xgroup)
+    for (int j = 0; j < np; ++j) ps.p[j] = p[j];
+  else
+    np = 0;  // nothing pending
+  hipLaunchKernelGGL(k_axpy_out<T>, dim3(blocks), dim3(256), 0, s, g.ndof, u, d, scal, np, ps,
+                     flags);
   return hipGetLastError();
 }
 
@@ -345,7 +368,8 @@ __device__ double fixed_order_sum(const double *v, int nb) {
 
 __global__ __launch_bounds__(RED_THREADS) void k_finish_init(const double *cgp, int nb, int slot,
                                                              double tol2_rel, int cap,
-                                                             double *scal, int *flags) {
+                                                             double *scal, int *flags,
+                                                             int slot0) {
   const double rz = fixed_order_sum(cgp + CGP_RZ + slot * MAXB, nb);
   const double rr = fixed_order_sum(cgp + CGP_RR + slot * MAXB, nb);
   if (threadIdx.x == 0) {
@@ -358,6 +382,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_finish_init(const double *cgp, 
     flags[F_ITERS] = 0;
     flags[F_STATUS] = 0;
     flags[F_CAP] = cap;
+    flags[F_SLOT0] = slot0;
+    for (int j = 0; j < CG_NP_MAX; ++j) scal[S_AH + j] = 0.0;
     int done = (rr == 0.0) ? 1 : 0;
     if (!isfinite(rr) || !isfinite(rz)) {
       flags[F_STATUS] = 2;
@@ -374,9 +400,9 @@ __global__ __launch_bounds__(RED_THREADS) void k_finish_sum(const double *part, 
 }
 
 hipError_t launch_finish_init(const double *cgp, int nb_up, int slot, double tol2_rel, int cap,
-                              double *scal, int *flags, hipStream_t s) {
+                              double *scal, int *flags, hipStream_t s, int slot0) {
   hipLaunchKernelGGL(k_finish_init, dim3(1), dim3(RED_THREADS), 0, s, cgp, nb_up, slot, tol2_rel,
-                     cap, scal, flags);
+                     cap, scal, flags, slot0);
   return hipGetLastError();
 }
 hipError_t launch_finish_sum(const double *part, int nb, int comp, double *scal, int idx,
@@ -441,13 +467,16 @@ hipError_t launch_set_scale(double *scal, hipStream_t s) {
 
 template hipError_t launch_cg_init<double>(const Grid &, const double *, const double *, double *,
                                            double *, double *, double *, double *, const double *,
-                                           const uint8_t *, double *, int, int, hipStream_t, int);
+                                           const uint8_t *, double *, int, int, hipStream_t, int,
+                                           double *, double *);
 template hipError_t launch_cg_init<float>(const Grid &, const double *, const double *, float *,
                                           float *, float *, float *, float *, const float *,
-                                          const uint8_t *, double *, int, int, hipStream_t, int);
+                                          const uint8_t *, double *, int, int, hipStream_t, int,
+                                          float *, float *);
 template hipError_t launch_axpy_out<double>(const Grid &, double *, const double *,
-                                            const double *, hipStream_t);
+                                            const double *, hipStream_t, int, int,
+                                            double *const *, const int *);
 template hipError_t launch_axpy_out<float>(const Grid &, double *, const float *, const double *,
-                                           hipStream_t);
+                                           hipStream_t, int, int, float *const *, const int *);
 
 }  // namespace topo

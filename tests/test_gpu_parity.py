@@ -448,6 +448,34 @@ def test_cg_z_formed_in_product_equals_z_stored(prec, mfma, monkeypatch):
         assert torch.equal(res[0][0], res[1][0])
 
 
+@pytest.mark.parametrize("prec", [A.PREC_FP64, A.PREC_FP32_REFINE])
+def test_grouped_x_update_equals_update_every_iteration(prec, monkeypatch):
+    """The inner CG may advance x once per group of two or four iterations
+    (the steps kept, applied together in the order taken, and the pending
+    ones by the solution update): the same iterations and the same solution
+    as advancing x every iteration, in separate launches and in graph
+    chunks."""
+    nelx, nely, nelz = 40, 33, 19
+    x = gpu(inputs.random_field(nelx, nely, nelz, seed=6, ell=4.0))
+    ref = None
+    for graph in ("0", "1"):
+        monkeypatch.setenv("TOPO_GRAPH", graph)
+        for xg in ("0", "2", "4"):
+            print("x groups", xg, "graph", graph, "precision", prec, flush=True)
+            monkeypatch.setenv("TOPO_XGROUP", xg)
+            ctx = A.to_create(A.Problem(nelx, nely, nelz, precision=prec, rtol=1e-8))
+            u, info, _ = A.to_solve(ctx, x)
+            ctx.close()
+            if ref is None:
+                ref = (u, info["inner_iters"])
+                continue
+            assert info["inner_iters"] == ref[1]
+            # the same sums in the same order: equal up to how the compiler
+            # contracts them (seen bit-identical)
+            assert float((u - ref[0]).norm() / ref[0].norm()) <= 1e-12
+            print("  bit-identical:", bool(torch.equal(u, ref[0])), flush=True)
+
+
 def test_sensitivity_kernel_on_oracle_u():
     nelx, nely, nelz = 23, 14, 9
     x = inputs.random_field(nelx, nely, nelz, seed=4, ell=2.0)
