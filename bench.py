@@ -218,9 +218,11 @@ PROFILE_RUNS = {  # -o name: (rocprofv3 options, bench.py arguments)
     "ls_trace": ("--kernel-trace --stats", "--probe levelset"),
     "ls_fetch": ("--pmc FETCH_SIZE", "--probe levelset"),
     "ls_write": ("--pmc WRITE_SIZE", "--probe levelset"),
+    "ls_sq": ("--pmc " + SQ_COUNTERS, "--probe levelset"),
     "shape_trace": ("--kernel-trace --stats", "--probe shape"),
     "shape_fetch": ("--pmc FETCH_SIZE", "--probe shape"),
     "shape_write": ("--pmc WRITE_SIZE", "--probe shape"),
+    "shape_sq": ("--pmc " + SQ_COUNTERS, "--probe shape"),
 }
 PRODUCT_SOURCES = ("k_matvec.hip", "k_mfma.hip", "device_common.h", "common.h")
 LS_SOURCES = ("k_levelset.hip", "device_common.h", "common.h")
@@ -374,12 +376,12 @@ SUMMARIES = [
     ("levelset_256x128x128.txt",
      "level-set evolution (10 steps) and reinitialisation (to 1e-3, at most 40 pseudo-steps) on "
      "the 257x129x129 node grid; phi = 2.5 x the distance to three balls, smooth speed of both "
-     "signs, CFL number 1/2", LARGE, "ls_trace", "ls_fetch", "ls_write", (), LS_SOURCES,
+     "signs, CFL number 1/2", LARGE, "ls_trace", "ls_fetch", "ls_write", ("ls_sq",), LS_SOURCES,
      ("k_ls_advect", "k_ls_reinit")),
     ("shape_extension_256x128x128.txt",
      "shape-derivative vector and Hilbertian extension (ell = 2, extension CG to rtol 1e-8) on "
      "the 257x129x129 node grid; phi = 2.5 x the distance to three balls, seeded u", LARGE,
-     "shape_trace", "shape_fetch", "shape_write", (), SHAPE_SOURCES,
+     "shape_trace", "shape_fetch", "shape_write", ("shape_sq",), SHAPE_SOURCES,
      ("k_hcg_apply", "k_hcg_update", "k_hcg_dir", "k_shape_elem", "k_shape_gather")),
 ]
 
@@ -455,6 +457,12 @@ def summarize(root):
                     if rows:
                         sec.append("%s: %s" % (sq, ", ".join("%s=%.0f" % (c, _working(v))
                                                               for c, v in sorted(rows.items()))))
+                        if "SQ_INSTS_VALU" in rows and d:
+                            # one wave64 VALU instruction per CU per cycle (quarter-rate
+                            # transcendentals take longer): a lower bound on VALU time
+                            iss = _working(rows["SQ_INSTS_VALU"]) / 256.0 / 2400.0
+                            sec.append("valu_issue_us_lower_bound: %.1f (%.2f of the working "
+                                       "median)" % (iss, iss / _working(d)))
                 lines += sec
         lines += ["", "reading: traffic = FETCH_SIZE and WRITE_SIZE (KiB per dispatch, the median "
                   "of the working launches) times the copy-calibrated scales; SQ_INSTS_VALU counts "

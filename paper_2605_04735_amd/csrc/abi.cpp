@@ -192,11 +192,13 @@ size_t carve(to_ctx *c, const Grid &g, int precision, double nu, char *base) {
   const size_t oD64 = L.take<double>(g.nn), oD32 = L.take<float>(g.nn);
   const size_t oMask = L.take<uint8_t>(g.nn);
   const size_t oF = L.take<double>(g.ndof), oR64 = L.take<double>(g.ndof);
-  size_t ov[NCGV];
+  // float64 keeps four direction slots (x grouped by four), float32 two
+  const int ncgv = precision == TO_PREC_FP64 ? NCGV : NCGV - 2;
+  size_t ov[NCGV] = {};
   if (precision == TO_PREC_FP64)
-    for (int i = 0; i < NCGV; ++i) ov[i] = L.take<double>(g.ndof);
+    for (int i = 0; i < ncgv; ++i) ov[i] = L.take<double>(g.ndof);
   else
-    for (int i = 0; i < NCGV; ++i) ov[i] = L.take<float>(g.ndof);
+    for (int i = 0; i < ncgv; ++i) ov[i] = L.take<float>(g.ndof);
   const size_t oPart = L.take<double>(2 * (size_t)MAXB);
   const size_t oScal = L.take<double>(S_COUNT);
   const size_t oFlags = L.take<int>(F_COUNT);
@@ -219,7 +221,7 @@ size_t carve(to_ctx *c, const Grid &g, int precision, double nu, char *base) {
     c->mask = (uint8_t *)(base + oMask);
     c->f = (double *)(base + oF);
     c->r64 = (double *)(base + oR64);
-    for (int i = 0; i < NCGV; ++i) {
+    for (int i = 0; i < ncgv; ++i) {
       if (precision == TO_PREC_FP64) c->v64[i] = (double *)(base + ov[i]);
       else c->v32[i] = (float *)(base + ov[i]);
     }
@@ -368,6 +370,7 @@ CgDesc<T> make_desc(to_ctx *c, T *const v[NCGV], const T *E, const T *dinv, cons
     d.xgroup = !d.zbf16 && v != 0;
     d.np = d.xgroup && v == 4 ? 4 : 2;
   }
+  if (!v[6] || !v[7]) d.np = 2;  // four slots only where the workspace holds them
   d.cgp = c->cgp;
   d.scal = c->scal;
   d.flags = c->flags;
