@@ -69,7 +69,9 @@ constexpr int TEX = TOPO_TEX, TEY = TOPO_TEY;
 constexpr int TNX = TEX - 1, TNY = TEY - 1;
 constexpr int TPX = TEX + 1, TPY = TEY + 1;
 constexpr int MV_THREADS = TEX * TEY;
-static_assert(MV_THREADS == 256, "one 256-thread block per tile");
+static_assert(MV_THREADS == 256 || MV_THREADS == 512, "one 256- or 512-thread block per tile");
+// block-count targets below are for 256-thread blocks; scaled by this
+constexpr int MV_BLOCK_SCALE = MV_THREADS / 256;
 static_assert(TEX == 16 || TEX == 32 || TEX == 64, "x rows of 16, 32 or 64 lanes");
 static_assert(TPX * TPY <= 2 * MV_THREADS, "a node plane is staged in two slots per thread");
 
@@ -78,6 +80,7 @@ enum MvMode { MV_APPLY = 0, MV_CG = 1, MV_RESID = 2 };
 // Tile of the matrix-core (MFMA) float32 product: ME x ME elements per z
 // layer, MN x MN owned nodes (see k_mfma.hip).
 constexpr int ME = 16, MN = ME - 1;
+constexpr int MF_THREADS = 256;  // its blocks: 4 waves of 4 element rows
 
 // Unit-modulus coefficients of the factored hex8 stiffness (see k_matvec.hip),
 // already multiplied by h/32.
@@ -199,7 +202,7 @@ __host__ __device__ inline int band_local(int b, int tiles, int nchunks) {
 __host__ __device__ inline int band_grid(int tiles, int nchunks) {
   return NXCD * ((tiles + NXCD - 1) / NXCD) * nchunks;
 }
-constexpr int BAND_MIN_BLOCKS = 1536;
+constexpr int BAND_MIN_BLOCKS = 1536 / MV_BLOCK_SCALE;
 // the product's local block of launch block b (or -1), and its launch size
 __host__ __device__ inline int mv_local(int b, int tiles, int nchunks) {
   const int nb = tiles * nchunks;

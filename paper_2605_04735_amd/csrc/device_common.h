@@ -327,16 +327,16 @@ struct Partials {
 #pragma unroll
     for (int a = 0; a < NV; ++a) s[a] = wave_sum_d(s[a]);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    constexpr int nw = BS / 64;  // sh: nw * NV doubles
     __syncthreads();
     if (lane == 0)
 #pragma unroll
-      for (int a = 0; a < NV; ++a) sh[w + 4 * a] = s[a];
+      for (int a = 0; a < NV; ++a) sh[w + nw * a] = s[a];
     __syncthreads();
-    constexpr int nw = BS / 64;
 #pragma unroll
     for (int a = 0; a < NV; ++a) {
       out[a] = 0.0;
-      for (int i = 0; i < nw; ++i) out[a] += sh[i + 4 * a];
+      for (int i = 0; i < nw; ++i) out[a] += sh[i + nw * a];
     }
     __syncthreads();
   }

@@ -318,7 +318,8 @@ __device__ __forceinline__ void cg_matvec_block(const CgDesc<T> &d, double *scal
                                                 double *cgp, int nparts, int lb_in, int slot) {
   const int parity = slot & 1;
   static_assert(!MF || (sizeof(T) == 4 && !ZBF), "matrix-core product: float32 CG, float32 z");
-  __shared__ double red[16];
+  constexpr int BT = MF ? MF_THREADS : MV_THREADS;  // threads of this block
+  __shared__ double red[4 * (BT / 64)];
   bool run = false;
   // the r^T z and ||r||^2 partials are loaded before the first planes, the
   // flags and scalars in the same round trip; a finished design only costs
@@ -331,7 +332,7 @@ __device__ __forceinline__ void cg_matvec_block(const CgDesc<T> &d, double *scal
     parts[2] = cgp + CGP_RP + (parity ^ 1) * MAXB;
     parts[3] = cgp + CGP_ZQ + (parity ^ 1) * MAXB;
   }
-  Partials<2, NP> P;
+  Partials<2, NP, BT> P;
   int done = 0, iters = 0, cap = 0;
   double rz_old = 0.0, tol2 = 0.0, pq_old = 0.0;
   // first the loads that need nothing but the leading arguments
@@ -429,7 +430,7 @@ __global__ __launch_bounds__(MV_THREADS) void k_cg_matvec(const CgDesc<T> *descs
 // arrive preloaded in SGPRs: the block's first loads (the previous reduction)
 // need no argument load before them.
 template <typename T, bool ZBF, bool MF = false, int ZF = ZF_READ>
-__global__ __launch_bounds__(MV_THREADS) void k_cg_matvec1(double *scal, int *flags, double *cgp,
+__global__ __launch_bounds__(MF ? MF_THREADS : MV_THREADS) void k_cg_matvec1(double *scal, int *flags, double *cgp,
                                                            int slot, int nparts,
                                                            const CgDesc<T> d) {
   cg_matvec_block<T, ZBF, MF, ZF>(d, scal, flags, cgp, nparts, -1, slot);
@@ -661,9 +662,10 @@ int matvec_kz(const Grid &g, bool fp64, bool mfma) {
   //   still leaves about 2.5 blocks per CU;
   // - float64 (two resident per CU): about 512 blocks, one round of the
   //   resident blocks, with kz at most 12 (the large-grid optimum).
-  int kz = kz_for_target(NZ, tiles, 2048);
-  if (!fp64 && kz < 3 && tiles * ((NZ + 2) / 3) >= 640) kz = 3;
-  if (fp64) kz = std::max(kz, std::min(kz_for_target(NZ, tiles, 512), 12));
+  const int sc = mfma ? 1 : MV_BLOCK_SCALE;  // the targets are for 256-thread blocks
+  int kz = kz_for_target(NZ, tiles, 2048 / sc);
+  if (!fp64 && kz < 3 && tiles * ((NZ + 2) / 3) >= 640 / sc) kz = 3;
+  if (fp64) kz = std::max(kz, std::min(kz_for_target(NZ, tiles, 512 / sc), 12));
   // partial sums must fit (a grid whose tiles alone exceed the bound is
   // rejected before this is reached)
   while (kz < NZ && tiles * ((NZ + kz - 1) / kz) > MAXB) ++kz;
@@ -732,7 +734,7 @@ hipError_t launch_cg_matvec1(const CgDesc<T> &d, int slot, hipStream_t s, hipEve
   CgDesc<T> dd = d;
   void *args[] = {&scal, &flags, &cgp, &slot, &nparts, &dd};
   // timestamps taken by the dispatch itself when events are given
-  return hipExtLaunchKernel(cg_matvec1_kernel(d), grid, dim3(MV_THREADS), args, 0, s, start, stop,
+  return hipExtLaunchKernel(cg_matvec1_kernel(d), grid, dim3(d.mA ? MF_THREADS : MV_THREADS), args, 0, s, start, stop,
                             0);
 }
 
@@ -781,7 +783,7 @@ hipError_t build_cg_graph(const CgDesc<T> &d, int slot0, int iters, hipGraphExec
     hipKernelNodeParams kp{};
     kp.func = mv ? fmv : cg_update1_kernel(d, slot);
     kp.gridDim = dim3(mv ? mv_grid(d.tx * d.ty, d.nb_mv / (d.tx * d.ty)) : d.nb_up);
-    kp.blockDim = dim3(mv ? MV_THREADS : 256);
+    kp.blockDim = dim3(mv ? (d.mA ? MF_THREADS : MV_THREADS) : 256);
     kp.sharedMemBytes = 0;
     kp.kernelParams = args;
     kp.extra = nullptr;

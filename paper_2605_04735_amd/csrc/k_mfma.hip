@@ -109,9 +109,9 @@ bool mfma_operand_table(double nu, uint16_t out[2][64][8], float *mscale_unit) {
 }
 
 template <int MODE>
-__global__ __launch_bounds__(MV_THREADS) void k_matvec_mfma(const MvArgs<float> a, int tx, int ty) {
+__global__ __launch_bounds__(MF_THREADS) void k_matvec_mfma(const MvArgs<float> a, int tx, int ty) {
   __shared__ MfmaLds S;
-  __shared__ double red[MV_THREADS / 64];
+  __shared__ double red[MF_THREADS / 64];
   const int NZ = a.nelz + 1, tz = (NZ + a.kz - 1) / a.kz;
   const int lb = mv_local((int)blockIdx.x, tx * ty, tz);
   if (lb < 0) return;  // padding of the last band
@@ -123,7 +123,7 @@ hipError_t launch_matvec_mfma(const MvArgs<float> &a, int *nblocks, hipStream_t 
   const int NX = a.nelx + 1, NY = a.nely + 1, NZ = a.nelz + 1;
   const int tx = (NX + MN - 1) / MN, ty = (NY + MN - 1) / MN, tz = (NZ + a.kz - 1) / a.kz;
   if (nblocks) *nblocks = tx * ty * tz;
-  hipLaunchKernelGGL((k_matvec_mfma<MV_APPLY>), dim3(mv_grid(tx * ty, tz)), dim3(MV_THREADS), 0, s,
+  hipLaunchKernelGGL((k_matvec_mfma<MV_APPLY>), dim3(mv_grid(tx * ty, tz)), dim3(MF_THREADS), 0, s,
                      a, tx, ty);
   return hipGetLastError();
 }

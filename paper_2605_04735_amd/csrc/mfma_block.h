@@ -78,7 +78,7 @@ __device__ __forceinline__ double mfma_block(const MvArgs<float> &a, int bx, int
   unsigned voN[2], voM[2], voP[2];
 #pragma unroll
   for (int sl = 0; sl < 2; ++sl) {
-    const int idx = tid + sl * MV_THREADS;
+    const int idx = tid + sl * MF_THREADS;
     const int li = idx % MP, lj = idx / MP;
     const int gx = i0 - 1 + li, gy = j0 - 1 + lj;
     const bool v = idx < MPL && gx >= 0 && gx < NX && gy >= 0 && gy < NY;
@@ -140,7 +140,7 @@ __device__ __forceinline__ double mfma_block(const MvArgs<float> &a, int bx, int
     const bool wr = CG && kp >= k0 && kp < k1;
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
-      const int idx = tid + sl * MV_THREADS;
+      const int idx = tid + sl * MF_THREADS;
       if (idx >= MPL) continue;
       float v[3];
 #pragma unroll
