@@ -76,6 +76,14 @@ struct to_ctx {
 
   double *h_scal = nullptr;
   int *h_flags = nullptr;
+  // inner-CG chunk reads: two pinned slots (flags, then S_RR and S_TOL2) and
+  // their events, so that the next chunk can run while the host reads one
+  struct ChunkRead {
+    int flags[F_COUNT];
+    double rr_tol2[2];
+  };
+  ChunkRead *h_chunk = nullptr;
+  hipEvent_t chunk_ev[2] = {nullptr, nullptr};
 
   Coef<double> k64{};
   Coef<float> k32{};
@@ -398,38 +406,57 @@ to_status inner_pcg(to_ctx *c, T *const v[NCGV], const T *dinv, double eta, int 
                            np == 4 ? v[7] : nullptr));
   HIPCHK(launch_finish_init(c->cgp, c->nb_up, pset, eta * eta, cap, c->scal, c->flags, c->stream,
                             c->slot));
-  int launched = 0;
+  // Chunks are queued ahead: each is followed by an asynchronous copy of the
+  // flags and residual norms into one of two pinned slots and an event, and
+  // the host waits for chunk k's copy while chunk k + 1 already runs, so the
+  // GPU does not idle during the host's check.  A chunk queued after the CG
+  // has stopped does nothing (every launch reads the done flag first).  With
+  // timing samples on, one chunk at a time (their event pairs are recycled
+  // after each read).
+  const int ahead = c->prof ? 1 : 2;
+  int launched = 0, queued = 0, nread = 0;
   *iters = 0;
   *status = 0;
   for (;;) {
-    const int n = std::min(c->chunk, cap - launched);
-    hipGraphExec_t &gx = c->graph[sizeof(T) == 8][c->slot];
-    const bool sample = c->prof && (c->chunks++ % 4 == 0);
-    if (c->use_graph && !sample && n == c->chunk && c->chunk % np == 0) {
-      if (!gx) HIPCHK(build_cg_graph<T>(*hd, c->slot, c->chunk, &gx));
-      HIPCHK(hipGraphLaunch(gx, c->stream));  // a chunk of whole slot cycles keeps the slot
-    } else {
-      for (int it = 0; it < n; ++it) {
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        // sampled away from the first launch after a host synchronisation
-        if (c->prof && (launched + it) % c->prof_every == c->prof_every / 2)
-          HIPCHK(prof_pair(c, &e0, &e1));
-        HIPCHK(launch_cg_matvec1<T>(*hd, c->slot, c->stream, e0, e1));
-        HIPCHK(launch_cg_update1<T>(*hd, c->slot, c->stream));
-        c->slot = (c->slot + 1) % np;
+    while (queued - nread < ahead && launched < cap) {
+      const int n = std::min(c->chunk, cap - launched);
+      hipGraphExec_t &gx = c->graph[sizeof(T) == 8][c->slot];
+      const bool sample = c->prof && (c->chunks++ % 4 == 0);
+      if (c->use_graph && !sample && n == c->chunk && c->chunk % np == 0) {
+        if (!gx) HIPCHK(build_cg_graph<T>(*hd, c->slot, c->chunk, &gx));
+        HIPCHK(hipGraphLaunch(gx, c->stream));  // a chunk of whole slot cycles keeps the slot
+      } else {
+        for (int it = 0; it < n; ++it) {
+          hipEvent_t e0 = nullptr, e1 = nullptr;
+          // sampled away from the first launch after a host synchronisation
+          if (c->prof && (launched + it) % c->prof_every == c->prof_every / 2)
+            HIPCHK(prof_pair(c, &e0, &e1));
+          HIPCHK(launch_cg_matvec1<T>(*hd, c->slot, c->stream, e0, e1));
+          HIPCHK(launch_cg_update1<T>(*hd, c->slot, c->stream));
+          c->slot = (c->slot + 1) % np;
+        }
       }
+      launched += n;
+      to_ctx::ChunkRead &cr = c->h_chunk[queued % 2];
+      HIPCHK(hipMemcpyAsync(cr.flags, c->flags, F_COUNT * sizeof(int), hipMemcpyDeviceToHost,
+                            c->stream));
+      static_assert(S_TOL2 == S_RR + 1, "S_RR and S_TOL2 copied together");
+      HIPCHK(hipMemcpyAsync(cr.rr_tol2, c->scal + S_RR, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                            c->stream));
+      HIPCHK(hipEventRecord(c->chunk_ev[queued % 2], c->stream));
+      ++queued;
     }
-    launched += n;
-    to_status s = sync_read(c);
-    if (s != TO_OK) return s;
+    if (nread == queued) break;  // every chunk up to the cap has been read
+    HIPCHK(hipEventSynchronize(c->chunk_ev[nread % 2]));
+    const to_ctx::ChunkRead &cr = c->h_chunk[nread % 2];
+    ++nread;
     if (c->prof) prof_collect(c);
-    *iters = c->h_flags[F_ITERS];
-    *status = c->h_flags[F_STATUS];
+    *iters = cr.flags[F_ITERS];
+    *status = cr.flags[F_STATUS];
     if (c->trace)
-      std::fprintf(stderr, "[topo]   inner launched %d iters %d done %d status %d rr %.3e tol2 %.3e\n",
-                   launched, *iters, c->h_flags[F_DONE], *status, c->h_scal[S_RR],
-                   c->h_scal[S_TOL2]);
-    if (c->h_flags[F_DONE] || launched >= cap) break;
+      std::fprintf(stderr, "[topo]   inner chunk %d iters %d done %d status %d rr %.3e tol2 %.3e\n",
+                   nread, *iters, cr.flags[F_DONE], *status, cr.rr_tol2[0], cr.rr_tol2[1]);
+    if (cr.flags[F_DONE]) break;
   }
   return TO_OK;
 }
@@ -515,8 +542,13 @@ to_status to_create(const to_problem *prob, void *d_workspace, size_t bytes, voi
   if (hipHostMalloc((void **)&c->h_scal, (S_COUNT + OC_STATE + 8) * sizeof(double),
                     hipHostMallocDefault) !=
           hipSuccess ||
-      hipHostMalloc((void **)&c->h_flags, F_COUNT * sizeof(int), hipHostMallocDefault) != hipSuccess)
+      hipHostMalloc((void **)&c->h_flags, F_COUNT * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void **)&c->h_chunk, 2 * sizeof(to_ctx::ChunkRead), hipHostMallocDefault) !=
+          hipSuccess)
     return bail(TO_E_OOM, "hipHostMalloc failed");
+  for (hipEvent_t &e : c->chunk_ev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+      return bail(TO_E_HIP, "hipEventCreate failed");
   c->k64 = make_coef<double>(prob->nu, prob->h);
   c->k32 = make_coef<float>(prob->nu, prob->h);
   {
@@ -580,6 +612,9 @@ void to_destroy(to_ctx *c) {
   if (c->shp) hipFree(c->shp);
   if (c->h_scal) hipHostFree(c->h_scal);
   if (c->h_flags) hipHostFree(c->h_flags);
+  if (c->h_chunk) hipHostFree(c->h_chunk);
+  for (hipEvent_t e : c->chunk_ev)
+    if (e) hipEventDestroy(e);
   delete c;
 }
 
