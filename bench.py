@@ -198,6 +198,11 @@ def rel2(a, b):
 SQ_COUNTERS = ("SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_INSTS_SALU SQ_LDS_BANK_CONFLICT "
                "SQ_ACTIVE_INST_VALU SQ_BUSY_CYCLES SQ_WAVE_CYCLES")
 SQ_MFMA_COUNTERS = "SQ_INSTS_VALU_MFMA_MOPS_BF16 SQ_VALU_MFMA_BUSY_CYCLES SQ_INSTS_MFMA SQ_BUSY_CU_CYCLES"
+# the bench's large workloads only (products at 256x128x128, the config-2 MBB,
+# the 256x128x128 solves): the command whose live CG-product timing is the
+# top-level roofline
+BENCH_LARGE_ARGS = ("--steps 1 --warmup 1 --no-cpu-baseline --no-serving --no-simp --no-levelset "
+                    "--no-shape --no-paper --no-config0")
 BENCH_TRACE_ARGS = ("--steps 5 --warmup 1 --no-cpu-baseline --no-serving --no-large --no-simp "
                     "--no-levelset --no-shape --no-paper --no-config0")
 PROFILE_RUNS = {  # -o name: (rocprofv3 options, bench.py arguments)
@@ -215,6 +220,7 @@ PROFILE_RUNS = {  # -o name: (rocprofv3 options, bench.py arguments)
     "cg3_write": ("--pmc WRITE_SIZE", "--probe cg3"),
     "cg3_sq": ("--pmc " + SQ_COUNTERS, "--probe cg3"),
     "bench_trace": ("--kernel-trace --stats", BENCH_TRACE_ARGS),
+    "bench_large_trace": ("--kernel-trace --stats", BENCH_LARGE_ARGS),
     "ls_trace": ("--kernel-trace --stats", "--probe levelset"),
     "ls_fetch": ("--pmc FETCH_SIZE", "--probe levelset"),
     "ls_write": ("--pmc WRITE_SIZE", "--probe levelset"),
@@ -367,6 +373,13 @@ SUMMARIES = [
      ("cg3_sq",), PRODUCT_SOURCES,
      ("k_cg_matvec1<float, false, false, 1>", "k_cg_matvec1<float, false, true, 1>",
       "k_cg_update1<float, false, 1>", "k_cg_update1<float, false, 2>")),
+    ("kernel_trace_bench_large_256x128x128.txt",
+     "the bench's large workloads (products at 256x128x128, the config-2 MBB, the 256x128x128 "
+     "solves in three precisions), one step of the headline: the inner-CG kernels of the "
+     "fp32+refine 256x128x128 solve, the kernel behind the top-level roofline", LARGE,
+     "bench_large_trace", None, None, (), PRODUCT_SOURCES,
+     ("k_cg_matvec1<float, false, false, 1>", "k_cg_update1<float, false, 1>",
+      "k_cg_update1<float, false, 2>")),
     ("pmc_cg_matvec_f32_cantilever_96x48x48.txt",
      "one fp32+refine solve of the 96x48x48 cantilever (seed 1) to rtol 1e-4: inner-CG product "
      "and update (working set resident in the 256 MB Infinity Cache)", DIMS, None, "cg_fetch",
