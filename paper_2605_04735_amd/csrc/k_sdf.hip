@@ -444,14 +444,20 @@ __global__ __launch_bounds__(128) void k_udist(int nelx, int nely, int nelz, dou
             const size_t ue = uin ? (size_t)ui + (size_t)nelx * ((size_t)uj + (size_t)nely * uk) : 0;
             const int ucnt = uin ? count[ue] : 0;
             const int uoff = uin ? offset[ue] : 0;
-            for (int v = 0; v < CB * CB * CB; ++v) {
+            // only the cell's non-empty voxels (a wave-wide bit mask, lowest
+            // first), and only those some unfinished lane may find closer
+            unsigned long long live = __ballot(ucnt > 0);
+            while (live) {
+              const int v = __builtin_ctzll(live);  // the same for every lane
+              live &= live - 1;
               const int c = __builtin_amdgcn_readlane(ucnt, v);
-              if (c == 0) continue;
-              if (!need_voxel(ci * CB + (v & 3), cj * CB + ((v >> 2) & 3), ck * CB + (v >> 4), i, j,
-                              k, h, done, best))
-                continue;
-              const double *t = tri + 9 * (size_t)__builtin_amdgcn_readlane(uoff, v);
-              for (int q = 0; q < c; ++q, t += 9) best = fmin(best, tri_dist2(p, t, t + 3, t + 6));
+              const bool need = need_voxel(ci * CB + (v & 3), cj * CB + ((v >> 2) & 3),
+                                           ck * CB + (v >> 4), i, j, k, h, done, best);
+              if (__ballot(need) == 0) continue;
+              if (need) {
+                const double *t = tri + 9 * (size_t)__builtin_amdgcn_readlane(uoff, v);
+                for (int q = 0; q < c; ++q, t += 9) best = fmin(best, tri_dist2(p, t, t + 3, t + 6));
+              }
             }
           }
         }
