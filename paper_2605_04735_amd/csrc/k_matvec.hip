@@ -616,12 +616,15 @@ __device__ __forceinline__ void cg_update_block(const CgDesc<T> &d, double *scal
   }
 }
 
-template <typename T>
+// (x grouped by two over the batch: every design of a batch has np = 2 and
+// xgroup set, and the launch of parity 0 is the grouped x update)
+template <typename T, int XU = XU_EACH>
 __global__ __launch_bounds__(256) void k_cg_update(const CgDesc<T> *descs,
                                                    const BlockEntry *blockmap, int parity) {
   const BlockEntry be = blockmap[blockIdx.x];
   if (be.design < 0) return;  // padding entry
-  cg_update_block<T>(descs[be.design], be.scal, be.flags, be.cgp, be.nparts, be.lb, parity);
+  cg_update_block<T, false, XU>(descs[be.design], be.scal, be.flags, be.cgp, be.nparts, be.lb,
+                                parity);
 }
 
 template <typename T, bool ZBF, int XU = XU_EACH>
@@ -704,7 +707,12 @@ hipError_t launch_cg_matvec(const CgDesc<T> *descs, const BlockEntry *bmap_mv, i
 template <typename T>
 hipError_t launch_cg_update(const CgDesc<T> *descs, const BlockEntry *bmap_up, int nb_up, int parity,
                             hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_update<T>, dim3(nb_up), dim3(256), 0, s, descs, bmap_up, parity);
+  if (parity == 0)
+    hipLaunchKernelGGL((k_cg_update<T, XU_FLUSH2>), dim3(nb_up), dim3(256), 0, s, descs, bmap_up,
+                       parity);
+  else
+    hipLaunchKernelGGL((k_cg_update<T, XU_SKIP>), dim3(nb_up), dim3(256), 0, s, descs, bmap_up,
+                       parity);
   return hipGetLastError();
 }
 
@@ -815,7 +823,8 @@ hipError_t build_cg_graph_batched(const CgDesc<T> *descs, const BlockEntry *bmv,
     const BlockEntry *bp = mv ? bmv : bup;
     void *args[] = {&dp, &bp, &parity};
     hipKernelNodeParams kp{};
-    kp.func = mv ? (void *)k_cg_matvec<T> : (void *)k_cg_update<T>;
+    kp.func = mv ? (void *)k_cg_matvec<T>
+                 : parity == 0 ? (void *)k_cg_update<T, XU_FLUSH2> : (void *)k_cg_update<T, XU_SKIP>;
     kp.gridDim = dim3(mv ? nb_mv : nb_up);
     kp.blockDim = dim3(mv ? MV_THREADS : 256);
     kp.sharedMemBytes = 0;

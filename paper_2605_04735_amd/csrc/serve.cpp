@@ -353,6 +353,8 @@ CgDesc<float> make_desc(const Slot &sl) {
   d.p[0] = sl.v[3];
   d.p[1] = sl.v[4];
   d.q = sl.v[5];
+  d.np = 2;
+  d.xgroup = 1;  // x advanced by the parity-0 update, two steps at a time
   d.cgp = sl.cgp;
   d.scal = sl.scal;
   d.flags = sl.flags;
@@ -496,7 +498,11 @@ void server_loop(to_server *s) {
         sl.outer++;
         if (fl[F_STATUS] == 1 && fl[F_ITERS] == 0) sl.fail = TO_E_SINGULAR;
         if (fl[F_STATUS] == 2) sl.fail = TO_E_NONFINITE;
-        check(s, launch_axpy_out<float>(sl.g, sl.u, sl.v[0], sl.scal, s->stream));
+        {
+          float *const ps[2] = {sl.v[3], sl.v[4]};  // the steps since the last grouped update
+          check(s, launch_axpy_out<float>(sl.g, sl.u, sl.v[0], sl.scal, s->stream, 2, 1, ps,
+                                          sl.flags));
+        }
         launch_resid(s, sl);
         sl.state = RESID;
         s->batch_dirty = true;
@@ -543,7 +549,8 @@ void server_loop(to_server *s) {
                                      sl.v[4], sl.dinv32, sl.mask, sl.cgp, slot_set, sl.nb_up,
                                      s->stream));
       check(s, launch_finish_init(sl.cgp, sl.nb_up, slot_set, eta * eta,
-                                  p.max_iters - sl.inner_total, sl.scal, sl.flags, s->stream));
+                                  p.max_iters - sl.inner_total, sl.scal, sl.flags, s->stream,
+                                  s->parity));
       sl.state = INNER;
       s->batch_dirty = true;
     }

@@ -449,14 +449,16 @@ def test_cg_z_formed_in_product_equals_z_stored(prec, mfma, monkeypatch):
 
 
 @pytest.mark.parametrize("prec", [A.PREC_FP64, A.PREC_FP32_REFINE])
-def test_grouped_x_update_equals_update_every_iteration(prec, monkeypatch):
+@pytest.mark.parametrize("zfuse", ["0", "1"])
+def test_grouped_x_update_equals_update_every_iteration(prec, zfuse, monkeypatch):
     """The inner CG may advance x once per group of two or four iterations
     (the steps kept, applied together in the order taken, and the pending
     ones by the solution update): the same iterations and the same solution
     as advancing x every iteration, in separate launches and in graph
-    chunks."""
+    chunks, with z read from the update or formed in the product."""
     nelx, nely, nelz = 40, 33, 19
     x = gpu(inputs.random_field(nelx, nely, nelz, seed=6, ell=4.0))
+    monkeypatch.setenv("TOPO_CG_ZFUSE", zfuse)
     ref = None
     for graph in ("0", "1"):
         monkeypatch.setenv("TOPO_GRAPH", graph)
