@@ -169,11 +169,11 @@ def probe(kind):
     log("product probe done")
 
 
-def measured_traffic(summary, kernel):
+def measured_traffic(summary, kernel, profiles_dir=None):
     """HBM bytes per launch of `kernel` from a committed counter summary, or
     None when the product's sources changed since the counters were taken."""
     try:
-        text = open(os.path.join(ROOT, "profiles", summary)).read()
+        text = open(os.path.join(profiles_dir or PROFILES_DIR, summary)).read()
     except OSError:
         return None
     sha = _source_sha(PRODUCT_SOURCES)
@@ -184,6 +184,31 @@ def measured_traffic(summary, kernel):
         if sha not in fields.get("source", ""):
             return None
         return float(fields["traffic_bytes_per_launch"])
+    return None
+
+
+def profiled_avg_us(summary, kernel, profiles_dir=None):
+    """rocprofv3 average duration (us) of `kernel` from the kernel table of a
+    committed trace summary, or None when the product's sources changed since
+    the trace was taken."""
+    try:
+        lines = open(os.path.join(profiles_dir or PROFILES_DIR, summary)).read().splitlines()
+    except OSError:
+        return None
+    sha = _source_sha(PRODUCT_SOURCES)
+    if not any(l.startswith("source:") and sha in l for l in lines[:3]):
+        return None
+    cols = None
+    for l in lines:
+        if l.startswith("kernel ") and "avg_us" in l:
+            cols = l.split()[1:]
+            continue
+        if cols is None or not l.strip():
+            cols = None if not l.strip() else cols
+            continue
+        parts = l.rsplit(None, len(cols))
+        if len(parts) == len(cols) + 1 and (parts[0] == kernel or parts[0].startswith(kernel + "(")):
+            return float(dict(zip(cols, parts[1:]))["avg_us"])
     return None
 
 
@@ -230,6 +255,10 @@ PROFILE_RUNS = {  # -o name: (rocprofv3 options, bench.py arguments)
     "shape_write": ("--pmc WRITE_SIZE", "--probe shape"),
     "shape_sq": ("--pmc " + SQ_COUNTERS, "--probe shape"),
 }
+# the trace of the bench's large workloads: its average for the inner-CG
+# product is reported beside the live roofline figure
+LARGE_TRACE = "kernel_trace_bench_large_256x128x128.txt"
+PROFILES_DIR = os.path.join(ROOT, "profiles")
 PRODUCT_SOURCES = ("k_matvec.hip", "k_mfma.hip", "device_common.h", "common.h")
 LS_SOURCES = ("k_levelset.hip", "device_common.h", "common.h")
 SHAPE_SOURCES = ("k_shape.hip", "device_common.h", "common.h")
@@ -347,9 +376,9 @@ def _copy_scales(root):
             "kernel": kf[0], "dispatches": (len(f[kf[0]]), len(w[kw[0]]))}
 
 
-def _committed_scales():
+def _committed_scales(profiles_dir=None):
     try:
-        text = open(os.path.join(ROOT, "profiles", "pmc_copy_calibration.txt")).read()
+        text = open(os.path.join(profiles_dir or PROFILES_DIR, "pmc_copy_calibration.txt")).read()
     except OSError:
         return None
     out = {}
@@ -373,7 +402,7 @@ SUMMARIES = [
      ("cg3_sq",), PRODUCT_SOURCES,
      ("k_cg_matvec1<float, false, false, 1>", "k_cg_matvec1<float, false, true, 1>",
       "k_cg_update1<float, false, 1>", "k_cg_update1<float, false, 2>")),
-    ("kernel_trace_bench_large_256x128x128.txt",
+    (LARGE_TRACE,
      "the bench's large workloads (products at 256x128x128, the config-2 MBB, the 256x128x128 "
      "solves in three precisions), one step of the headline: the inner-CG kernels of the "
      "fp32+refine 256x128x128 solve, the kernel behind the top-level roofline", LARGE,
@@ -399,11 +428,11 @@ SUMMARIES = [
 ]
 
 
-def summarize(root):
-    """Writes the profiles/ summaries from the CSV output of the runs of
-    profile_commands() found under `root`; a summary whose runs are absent is
-    left as it is."""
-    out_dir = os.path.join(ROOT, "profiles")
+def summarize(root, out_dir=None):
+    """Writes the profiles/ summaries (into `out_dir`, profiles/ by default)
+    from the CSV output of the runs of profile_commands() found under `root`;
+    a summary whose runs are absent is left as it is."""
+    out_dir = out_dir or PROFILES_DIR
     cal = _copy_scales(root)
     if cal is not None:
         with open(os.path.join(out_dir, "pmc_copy_calibration.txt"), "w") as fh:
@@ -419,7 +448,7 @@ def summarize(root):
             fh.write("fetch_scale: %.4f\nwrite_scale: %.4f\n" % (cal["fetch_scale"],
                                                                  cal["write_scale"]))
         log("wrote profiles/pmc_copy_calibration.txt")
-    scales = cal or _committed_scales() or {"fetch_scale": 1.0, "write_scale": 1.0}
+    scales = cal or _committed_scales(out_dir) or {"fetch_scale": 1.0, "write_scale": 1.0}
     for (fname, title, dims, tr, fe, wr, sqs, srcs, kernels) in SUMMARIES:
         dur = _durations(root, tr) if tr else {}
         fet = _counter(root, fe, "FETCH_SIZE") if fe else {}
@@ -812,6 +841,14 @@ def main():
     if big is not None:
         roofline = dict(big)
         roofline["grid"] = "256x128x128 (inner-CG product inside the fp32+refine solve)"
+        prof_us = profiled_avg_us(LARGE_TRACE, "void topo::" + roofline["kernel"])
+        if prof_us:
+            roofline["rocprofv3"] = {
+                "summary": "profiles/" + LARGE_TRACE, "avg_us": prof_us,
+                "achieved": round(roofline["bytes_per_launch"] / (prof_us * 1e-6) / 1e9, 1),
+                "frac": round(roofline["bytes_per_launch"] / (prof_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                "note": "average over every launch of the same solve, graph replays included; "
+                        "the live figure samples separate dispatches"}
         roofline["cache_resident_96x48x48"] = small
     else:
         roofline = {"bound": "hbm", "achieved": small["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
