@@ -205,7 +205,9 @@ def test_bench_step_96x48x48():
     both filters over the whole grid; the nodal densities, the triangle count,
     brute-force distances (Eqs. 28-29) at 2000 nodes split between the
     search's near pass and its ring walk, and the volume fraction of the
-    returned field."""
+    returned field.  The float32 solve runs beside the density->SDF transfer
+    of a second context on its own stream, as in the benchmark, and both must
+    equal the same calls made alone bit for bit."""
     nelx, nely, nelz = 96, 48, 48
     print("bench step", (nelx, nely, nelz), flush=True)
     meta, u_or, dc_or = _golden("cantilever_96x48x48_seed1")
@@ -221,9 +223,19 @@ def test_bench_step_96x48x48():
     rng = np.random.default_rng(11)
     picks = [0, NX - 1, NX * NY - 1, nn - 1, 31 + NX * 7, 62 + NX * (14 + NY * 30)]
     picks += list(rng.choice(nn, 200, replace=False))
-    # the float64 path (its own z chunks) first, then the benchmark's path
+    # the float64 path (its own z chunks) first, then the benchmark's path.
+    # As in the benchmark, the density->SDF transfer runs on a second context
+    # with its own stream, issued before the solve and joined after it.
+    sdf_stream = torch.cuda.Stream()
+    geo = A.to_create(A.Problem(nelx, nely, nelz), stream=sdf_stream)
+    f64 = dict(dtype=torch.float64, device="cuda")
+    phi, rho, vf = torch.empty(nn, **f64), torch.empty(nn, **f64), torch.empty(nelx * nely * nelz, **f64)
+    done = torch.cuda.Event()
     for prec in (A.PREC_FP64, A.PREC_FP32_REFINE):
         ctx = A.to_create(A.Problem(nelx, nely, nelz, precision=prec, rtol=1e-5))
+        if prec == A.PREC_FP32_REFINE:
+            A.to_density_to_sdf(geo, xg, 0.5, phi=phi, rho_nodes=rho, vf=vf)
+            done.record(sdf_stream)
         u, info, st = A.to_solve(ctx, xg)
         assert st == A.L.TO_OK and info["rel_res"] <= 1e-5
         un = cpu(u)
@@ -243,12 +255,18 @@ def test_bench_step_96x48x48():
     assert np.array_equal(xf, filters.density_filter(x, nelx, nely, nelz, 1.5))
     dcf = cpu(A.to_filter(ctx, 2.0, A.FILTER_SENS, dc, x=xg))
     assert np.array_equal(dcf, filters.sensitivity_filter(x, dcn, nelx, nely, nelz, 2.0))
-    phi, rho, vf = A.to_density_to_sdf(ctx, xg, 0.5)
+    torch.cuda.current_stream().wait_event(done)
+    # the solve beside the transfer equals the solve alone, bit for bit, and
+    # the transfer beside the solve equals the transfer alone
+    u_alone, _, st = A.to_solve(ctx, xg)
+    assert st == A.L.TO_OK and torch.equal(u_alone, u)
+    phi_a, rho_a, vf_a = A.to_density_to_sdf(ctx, xg, 0.5)
+    assert torch.equal(phi_a, phi) and torch.equal(rho_a, rho) and torch.equal(vf_a, vf)
     phin, rhon, vfn = cpu(phi), cpu(rho), cpu(vf)
     rho_r = sdf.nodal_density_mean(x, nelx, nely, nelz)
     assert np.array_equal(rhon, rho_r)
     T, _, _ = sdf.marching_tets(rho_r, nelx, nely, nelz, 1.0, 0.5)
-    assert A.last_triangle_count(ctx) == len(T)
+    assert A.last_triangle_count(geo) == len(T) and A.last_triangle_count(ctx) == len(T)
     npk, n_near, n_far = _phi_sample(phin, nn, rng)
     assert npk.size >= 2000
     pts = grid.node_coords(nelx, nely, nelz, 1.0)[npk]
