@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -104,10 +105,13 @@ struct to_ctx {
   // optional HIP-event timing of every CG-mode product launch
   bool prof = false;
   std::vector<hipEvent_t> ev;  // start/stop pairs
-  size_t ev_used = 0;
+  std::vector<int> ev_iter;    // the CG iteration of each pair's product launch
+  size_t ev_used = 0;           // events handed out in this inner solve
+  size_t ev_done = 0;           // of which read
+  size_t ev_mark[2] = {0, 0};   // ev_used after each queued chunk (by chunk slot)
   double prof_ms = 0.0;
   long long prof_count = 0;
-  int prof_every = 16;  // bracket one product launch in this many
+  int prof_every = 16;  // in a sampled chunk, bracket one product launch in this many
   // a chunk of CG iterations as one graph launch, per precision and starting
   // direction slot (built on first use); with timing on, one chunk in four runs as
   // separate launches so that product launches can be sampled
@@ -280,29 +284,36 @@ to_status sync_read(to_ctx *c) {
   return TO_OK;
 }
 
-// Accumulates the elapsed times of the recorded event pairs (the stream has
-// been synchronised) and recycles the events.
-void prof_collect(to_ctx *c) {
-  for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+// Accumulates the elapsed times of the event pairs [ev_done, upto), whose
+// chunk has completed.  Only launches of iterations below `limit` count: a
+// launch at or after the iteration where the CG stopped returned at once.
+void prof_collect(to_ctx *c, size_t upto, int limit) {
+  for (size_t i = c->ev_done; i + 1 < upto; i += 2) {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]) == hipSuccess) {
+    if (c->ev_iter[i / 2] < limit && hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]) == hipSuccess) {
       c->prof_ms += ms;
       c->prof_count += 1;
     }
   }
-  c->ev_used = 0;
+  c->ev_done = std::max(c->ev_done, upto);
 }
 
 // Hands out the next start/stop event pair (created on first use).  The pair
 // is attached to one product dispatch, so the elapsed time is that kernel's
-// execution alone, without the latency of separate event packets.
-hipError_t prof_pair(to_ctx *c, hipEvent_t *start, hipEvent_t *stop) {
+// execution alone, without the latency of separate event packets.  The events
+// carry no system-scope fence: with one, the timed dispatch also wrote back
+// and invalidated the caches, which made it run about 8 us longer at
+// 256x128x128.  They are read only after the chunk's own event (with the
+// default fence), recorded later on the same stream, has completed.
+hipError_t prof_pair(to_ctx *c, int iter, hipEvent_t *start, hipEvent_t *stop) {
   while (c->ev_used + 2 > c->ev.size()) {
     hipEvent_t e;
-    hipError_t r = hipEventCreate(&e);
+    hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
     if (r != hipSuccess) return r;
     c->ev.push_back(e);
   }
+  c->ev_iter.resize(c->ev.size() / 2);
+  c->ev_iter[c->ev_used / 2] = iter;
   *start = c->ev[c->ev_used++];
   *stop = c->ev[c->ev_used++];
   return hipSuccess;
@@ -410,11 +421,11 @@ to_status inner_pcg(to_ctx *c, T *const v[NCGV], const T *dinv, double eta, int 
   // flags and residual norms into one of two pinned slots and an event, and
   // the host waits for chunk k's copy while chunk k + 1 already runs, so the
   // GPU does not idle during the host's check.  A chunk queued after the CG
-  // has stopped does nothing (every launch reads the done flag first).  With
-  // timing samples on, one chunk at a time (their event pairs are recycled
-  // after each read).
-  const int ahead = c->prof ? 1 : 2;
+  // has stopped does nothing (every launch reads the done flag first).  Timing
+  // samples are read chunk by chunk as their chunks complete.
+  const int ahead = 2;
   int launched = 0, queued = 0, nread = 0;
+  c->ev_used = c->ev_done = 0;
   *iters = 0;
   *status = 0;
   for (;;) {
@@ -426,11 +437,16 @@ to_status inner_pcg(to_ctx *c, T *const v[NCGV], const T *dinv, double eta, int 
         if (!gx) HIPCHK(build_cg_graph<T>(*hd, c->slot, c->chunk, &gx));
         HIPCHK(hipGraphLaunch(gx, c->stream));  // a chunk of whole slot cycles keeps the slot
       } else {
-        for (int it = 0; it < n; ++it) {
+        for (int it = 0, k = 0; it < n; ++it) {
           hipEvent_t e0 = nullptr, e1 = nullptr;
-          // sampled away from the first launch after a host synchronisation
-          if (c->prof && (launched + it) % c->prof_every == c->prof_every / 2)
-            HIPCHK(prof_pair(c, &e0, &e1));
+          // sampled away from the first launch after a host synchronisation,
+          // at positions of both slot parities (the product after a grouped
+          // x update and the one after a skipping update differ)
+          const int at = c->prof_every / 2 + k * c->prof_every + (k & 1);
+          if (sample && it == at) {
+            HIPCHK(prof_pair(c, launched + it, &e0, &e1));
+            ++k;
+          }
           HIPCHK(launch_cg_matvec1<T>(*hd, c->slot, c->stream, e0, e1));
           HIPCHK(launch_cg_update1<T>(*hd, c->slot, c->stream));
           c->slot = (c->slot + 1) % np;
@@ -444,19 +460,28 @@ to_status inner_pcg(to_ctx *c, T *const v[NCGV], const T *dinv, double eta, int 
       HIPCHK(hipMemcpyAsync(cr.rr_tol2, c->scal + S_RR, 2 * sizeof(double), hipMemcpyDeviceToHost,
                             c->stream));
       HIPCHK(hipEventRecord(c->chunk_ev[queued % 2], c->stream));
+      c->ev_mark[queued % 2] = c->ev_used;
       ++queued;
     }
     if (nread == queued) break;  // every chunk up to the cap has been read
     HIPCHK(hipEventSynchronize(c->chunk_ev[nread % 2]));
     const to_ctx::ChunkRead &cr = c->h_chunk[nread % 2];
+    if (c->prof)
+      prof_collect(c, c->ev_mark[nread % 2], cr.flags[F_DONE] ? cr.flags[F_ITERS] : INT_MAX);
     ++nread;
-    if (c->prof) prof_collect(c);
     *iters = cr.flags[F_ITERS];
     *status = cr.flags[F_STATUS];
     if (c->trace)
       std::fprintf(stderr, "[topo]   inner chunk %d iters %d done %d status %d rr %.3e tol2 %.3e\n",
                    nread, *iters, cr.flags[F_DONE], *status, cr.rr_tol2[0], cr.rr_tol2[1]);
     if (cr.flags[F_DONE]) break;
+  }
+  if (c->prof) {  // samples of a chunk still queued, then the pairs are free again
+    if (c->ev_done < c->ev_used) {
+      HIPCHK(hipEventSynchronize(c->chunk_ev[(queued - 1) % 2]));
+      prof_collect(c, c->ev_used, *iters);
+    }
+    c->ev_used = c->ev_done = 0;
   }
   return TO_OK;
 }
@@ -519,7 +544,7 @@ to_status to_create(const to_problem *prob, void *d_workspace, size_t bytes, voi
   if (const char *e = std::getenv("TOPO_INNER_ETA")) c->eta = std::atof(e);
   if (const char *e = std::getenv("TOPO_CHUNK")) c->chunk = std::max(1, std::atoi(e));
   if (const char *e = std::getenv("TOPO_TRACE")) c->trace = std::atoi(e) != 0;
-  if (const char *e = std::getenv("TOPO_PROF_EVERY")) c->prof_every = std::max(1, std::atoi(e));
+  if (const char *e = std::getenv("TOPO_PROF_EVERY")) c->prof_every = std::max(2, std::atoi(e));
   if (const char *e = std::getenv("TOPO_GRAPH")) c->use_graph = std::atoi(e) != 0;
   auto bail = [&](to_status s, const std::string &m) {
     to_status r = fail(nullptr, s, m);
@@ -1212,7 +1237,7 @@ to_status to_profile(to_ctx *c, int32_t enable, double *h_ms, int64_t *h_count) 
   c->prof = enable != 0;
   c->prof_ms = 0.0;
   c->prof_count = 0;
-  c->ev_used = 0;
+  c->ev_used = c->ev_done = 0;
   return TO_OK;
 }
 

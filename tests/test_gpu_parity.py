@@ -496,6 +496,29 @@ def test_grouped_x_update_equals_update_every_iteration(prec, zfuse, monkeypatch
             print("  bit-identical:", bool(torch.equal(u, ref[0])), flush=True)
 
 
+@pytest.mark.parametrize("prec", [A.PREC_FP64, A.PREC_FP32_REFINE])
+def test_timing_samples_leave_the_solve_unchanged(prec):
+    """With the product's timing samples on (one chunk in four as separate
+    launches, two of them bracketed by events, the chunks still queued two
+    ahead), the solve takes the same iterations to the same solution, and
+    samples are taken only of launches that did work."""
+    nelx, nely, nelz = 48, 24, 24
+    x = gpu(inputs.random_field(nelx, nely, nelz, seed=8, ell=4.0))
+    ctx = A.to_create(A.Problem(nelx, nely, nelz, precision=prec, rtol=1e-8))
+    u0, info0, _ = A.to_solve(ctx, x)
+    A.to_profile(ctx, True)
+    u1, info1, _ = A.to_solve(ctx, x)
+    ms, n = A.to_profile(ctx, False)
+    ctx.close()
+    print("precision", prec, "iterations", info1["inner_iters"], "samples", n,
+          "avg us %.2f" % (1e3 * ms / max(n, 1)), flush=True)
+    assert info1["inner_iters"] == info0["inner_iters"] and torch.equal(u1, u0)
+    # at most two samples per sampled chunk of 32 iterations, one chunk in
+    # four, with at most one chunk queued after each pass's stop
+    assert 0 < n <= info1["inner_iters"] / 64 + info1["outer_iters"] + 2
+    assert ms > 0.0
+
+
 def test_sensitivity_kernel_on_oracle_u():
     nelx, nely, nelz = 23, 14, 9
     x = inputs.random_field(nelx, nely, nelz, seed=4, ell=2.0)
