@@ -1340,8 +1340,17 @@ def workload_large(A, inputs, dev, copy_gbs):
                 "traffic": measured_traffic("kernel_trace_cg_256x128x128.txt", "void topo::" + kern),
                 "kernel": kern, "avg_us": round(mv_us, 3), "launches_sampled": mv_n,
                 "bytes_per_launch": byt}
-            out["cg_algorithmic_bytes_per_node_per_iteration"] = cg_iteration_bytes_f32(
-                cg_zfuse_dims(dims))
+            bpn = cg_iteration_bytes_f32(cg_zfuse_dims(dims))
+            out["cg_algorithmic_bytes_per_node_per_iteration"] = bpn
+            # the whole iteration (product and update) against the HBM roofline:
+            # the per-node bytes plus the moduli's 4 B per element
+            nn, nel = _nodes(dims)
+            it_bytes = bpn * nn + 4 * nel
+            it_gbs = it_bytes / (out[name]["us_per_cg_iter"] * 1e-6) / 1e9
+            out["roofline_cg_iteration"] = {
+                "bytes_per_iteration": int(it_bytes), "achieved": round(it_gbs, 1),
+                "unit": "GB/s", "frac": round(it_gbs / HBM_PEAK_GBS, 4),
+                "frac_of_measured_copy": round(it_gbs / copy_gbs, 4)}
         ctx.close()
         del u, dc
         torch.cuda.empty_cache()
