@@ -421,10 +421,16 @@ to_status inner_pcg(to_ctx *c, T *const v[NCGV], const T *dinv, double eta, int 
   // flags and residual norms into one of two pinned slots and an event, and
   // the host waits for chunk k's copy while chunk k + 1 already runs, so the
   // GPU does not idle during the host's check.  A chunk queued after the CG
-  // has stopped does nothing (every launch reads the done flag first).  Timing
-  // samples are read chunk by chunk as their chunks complete.
-  const int ahead = 2;
+  // has stopped does nothing (every launch reads the done flag first), so
+  // once the residual's decay over the last chunks predicts the stop within
+  // the chunk already queued, no further chunk is queued until that one has
+  // been read: a wrong guess costs one host round trip, a right one saves a
+  // chunk of launches that return at once.  Timing samples are read chunk by
+  // chunk as their chunks complete.
+  int ahead = 2;
   int launched = 0, queued = 0, nread = 0;
+  double prev_rr = 0.0;
+  int prev_iters = -1;
   c->ev_used = c->ev_done = 0;
   *iters = 0;
   *status = 0;
@@ -475,6 +481,17 @@ to_status inner_pcg(to_ctx *c, T *const v[NCGV], const T *dinv, double eta, int 
       std::fprintf(stderr, "[topo]   inner chunk %d iters %d done %d status %d rr %.3e tol2 %.3e\n",
                    nread, *iters, cr.flags[F_DONE], *status, cr.rr_tol2[0], cr.rr_tol2[1]);
     if (cr.flags[F_DONE]) break;
+    // the predicted iterations to the stop, from the decay of ||r||^2 since
+    // the previous chunk's end
+    const double rr = cr.rr_tol2[0], tol2 = cr.rr_tol2[1];
+    ahead = 2;
+    if (prev_iters >= 0 && *iters > prev_iters && rr > 0.0 && rr < prev_rr && tol2 > 0.0) {
+      const double slope = std::log(rr / prev_rr) / (double)(*iters - prev_iters);
+      const double remaining = std::log(tol2 / rr) / slope;
+      if (remaining <= (double)(launched - *iters)) ahead = 1;
+    }
+    prev_rr = rr;
+    prev_iters = *iters;
   }
   if (c->prof) {  // samples of a chunk still queued, then the pairs are free again
     if (c->ev_done < c->ev_used) {
