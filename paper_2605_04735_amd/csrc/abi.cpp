@@ -396,9 +396,10 @@ CgDesc<T> make_desc(to_ctx *c, T *const v[NCGV], const T *E, const T *dinv, cons
   return d;
 }
 
-// One inner Jacobi-PCG solve of K d = r64 / ||r64|| in precision T, run as
-// the batch-of-one case of the batched CG kernels (two launches per
-// iteration; the reductions finish in the last block of each kernel).
+// One inner Jacobi-PCG solve of K d = r64 / ||r64|| in precision T: two
+// launches per iteration (the product with the direction update, then the
+// vector update), each of whose blocks first sums the other kernel's block
+// partials in a fixed order.
 template <typename T>
 to_status inner_pcg(to_ctx *c, T *const v[NCGV], const T *dinv, double eta, int cap, int *iters,
                     int *status) {
