@@ -369,9 +369,12 @@ void to_server_destroy(to_server *srv); /* NULL-safe; waits for the worker to st
  * to_last_triangle_count: triangles of the last to_density_to_sdf call.
  * to_profile: returns the accumulated HIP-event time (ms) and count of the
  *   inner-CG product launches recorded since the previous to_profile call,
- *   then resets them and turns recording on (enable != 0) or off.  Recording
- *   brackets one in every 16 such launches with events on the context stream
- *   (the events slow the launch stream down; sampling keeps that small). */
+ *   then resets them and turns recording on (enable != 0) or off.  While
+ *   recording, one chunk of CG iterations in four runs as separate launches
+ *   (not as a graph), and two of its product launches (one of each direction
+ *   slot) carry start/stop events taken from the dispatch's own timestamps,
+ *   without a system-scope fence.  Only launches of iterations before the
+ *   CG's stop are counted.  The solve's results do not change. */
 double to_last_energy_sum(const to_ctx *ctx);
 int32_t to_last_triangle_count(const to_ctx *ctx);
 to_status to_profile(to_ctx *ctx, int32_t enable, double *h_ms, int64_t *h_count);
