@@ -769,6 +769,7 @@ def main():
     res_d = timed(ctx_d, "fp64")
     c_d, dc_d, u_d = res_d["c"], bufs["dc"].cpu().numpy(), bufs["u"].cpu().numpy()
     ntri = A.last_triangle_count(ctx_sdf)
+    ctx_sdf.close()
 
     # ---------------------------------------------------------- products
     def product_rate(ctx, prob, f32, reps=200):
