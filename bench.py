@@ -198,13 +198,14 @@ def profiled_avg_us(summary, kernel, profiles_dir=None):
     sha = _source_sha(PRODUCT_SOURCES)
     if not any(l.startswith("source:") and sha in l for l in lines[:3]):
         return None
-    cols = None
+    cols = None  # the column names while inside the kernel table (it ends at a blank line)
     for l in lines:
         if l.startswith("kernel ") and "avg_us" in l:
             cols = l.split()[1:]
             continue
-        if cols is None or not l.strip():
-            cols = None if not l.strip() else cols
+        if not l.strip():
+            cols = None
+        if cols is None:
             continue
         parts = l.rsplit(None, len(cols))
         if len(parts) == len(cols) + 1 and (parts[0] == kernel or parts[0].startswith(kernel + "(")):
