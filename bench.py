@@ -357,7 +357,7 @@ def _source_line(files):
                                                                            _source_sha(files))
 
 
-def _cmd_lines(names, outdir="gpurun_out/prof"):
+def _cmd_lines(names, outdir):
     return ["  rocprofv3 %s --output-format csv -d %s -o %s -- python3 bench.py %s"
             % (PROFILE_RUNS[n][0], outdir, n, PROFILE_RUNS[n][1]) for n in names]
 
@@ -439,7 +439,7 @@ def summarize(root, out_dir=None):
         with open(os.path.join(out_dir, "pmc_copy_calibration.txt"), "w") as fh:
             fh.write("# HBM traffic calibration (plain device copy of known size)\n")
             fh.write("commands (from the repository root, TMPDIR=/tmp):\n")
-            fh.write("\n".join(_cmd_lines(("copy_fetch", "copy_write"))) + "\n")
+            fh.write("\n".join(_cmd_lines(("copy_fetch", "copy_write"), root)) + "\n")
             fh.write("copy: torch copy_ of %d bytes (reads %d, writes %d) -> %s, %d/%d dispatches\n"
                      % (COPY_BYTES, COPY_BYTES, COPY_BYTES, cal["kernel"], *cal["dispatches"]))
             fh.write("FETCH_SIZE_KiB_per_dispatch: %.1f   (expected %.1f) -> fetch_scale %.4f\n"
@@ -458,7 +458,7 @@ def summarize(root, out_dir=None):
             continue
         runs = [r for r in (tr, fe, wr) + tuple(sqs) if r]
         lines = ["# " + title, _source_line(srcs),
-                 "commands (from the repository root, TMPDIR=/tmp):"] + _cmd_lines(runs)
+                 "commands (from the repository root, TMPDIR=/tmp):"] + _cmd_lines(runs, root)
         lines.append("counter scaling (pmc_copy_calibration.txt): FETCH_SIZE x %.4f, WRITE_SIZE x %.4f"
                      % (scales["fetch_scale"], scales["write_scale"]))
         if dur:
@@ -519,7 +519,7 @@ def summarize(root, out_dir=None):
         lines = ["# rocprofv3 kernel trace of the bench step (cantilever 96x48x48, random-field "
                  "densities, seed 1): calibration, 1 warm-up and 5 timed steps of each precision "
                  "path, product timings at 96x48x48", _source_line(PRODUCT_SOURCES),
-                 "command (from the repository root, TMPDIR=/tmp):"] + _cmd_lines(("bench_trace",))
+                 "command (from the repository root, TMPDIR=/tmp):"] + _cmd_lines(("bench_trace",), root)
         lines += ["", "%-62s %7s %10s %10s %10s %7s" % ("kernel", "calls", "avg_us", "median_us",
                                                         "total_ms", "pct")]
         tot = sum(sum(v) for v in bt.values())
@@ -686,8 +686,8 @@ def main():
         summarize(args.summarize)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (requests shard "
-              "across GPUs with no communication; see the design notes). Run with --gpus 1.",
+        print("bench.py measures one GPU only: the library has no multi-GPU path (independent "
+              "designs would shard across GPUs with no communication). Run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
     import torch
