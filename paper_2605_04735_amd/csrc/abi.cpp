@@ -1052,16 +1052,29 @@ to_status to_ls_reinit(to_ctx *c, double *d_phi, double gamma, double tol, int32
   double *state = c->part + LS_STATE_OFS, *hs = c->h_scal + S_COUNT;
   double *buf[2] = {d_phi, c->rho_scratch};
   // one launch per pseudo-step plus the one that sees the stop; the host
-  // looks at the state once per batch
-  int k = 0;
+  // looks at the state once per batch of at most 64.  Launches after the stop
+  // return at once, so once the decay of the largest change between two looks
+  // predicts the stop, the next batch is cut to the predicted count (a short
+  // guess costs one more host round trip).
+  int k = 0, batch = 64, k_prev = -1;
+  double ch_prev = 0.0;
   for (;;) {
-    for (int b = 0; b < 64; ++b, ++k)
+    for (int b = 0; b < batch; ++b, ++k)
       HIPCHK(launch_ls_reinit(c->g, h, dtau, tol, max_steps, k, buf[k & 1], buf[(k + 1) & 1],
                               slots, state, c->stream));
-    HIPCHK(hipMemcpyAsync(hs, state, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(hs, state, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     if (hs[0] != 0.0) break;
     if (k > max_steps + 128) return fail(c, TO_E_HIP, "reinitialisation state did not advance");
+    // hs[3]: the largest change of step k - 1 (taken by launch k - 1)
+    const double ch = hs[3];
+    batch = 64;
+    if (k_prev >= 0 && std::isfinite(ch) && ch > 0.0 && ch < ch_prev) {
+      const double remaining = std::log(tol / ch) / (std::log(ch / ch_prev) / (double)(k - k_prev));
+      batch = (int)std::min(64.0, std::max(4.0, std::ceil(1.1 * remaining) + 2.0));
+    }
+    k_prev = k;
+    ch_prev = ch;
   }
   const int steps = (int)hs[1];
   if (steps & 1)
@@ -1119,9 +1132,13 @@ to_status to_hilbert_extend(to_ctx *c, double ell, const double *d_g, double *d_
   uint8_t *gm = (uint8_t *)c->rho_scratch;
   double *scal = c->part + HCG_SCAL_OFS, *hs = c->h_scal + S_COUNT;
   HIPCHK(launch_fill(c->flags, F_COUNT * sizeof(int), c->stream));
-  int it = 0;
+  // chunks of at most 32 iterations; launches after the stop return at once,
+  // so once the residual's mean decay so far predicts the stop, the next
+  // chunk is cut to the predicted count (a short guess costs one more host
+  // round trip)
+  int it = 0, n_next = 32;
   for (;;) {
-    const int n = std::min(32, max_iters + 1 - it);
+    const int n = std::min(n_next, max_iters + 1 - it);
     HIPCHK(launch_hilbert(c->g, c->p.h, ell, rtol, max_iters, c->f, d_g, d_v, vec, gm, c->part,
                           scal, c->flags, it, n, c->stream));
     it += n;
@@ -1130,6 +1147,12 @@ to_status to_hilbert_extend(to_ctx *c, double ell, const double *d_g, double *d_
     HIPCHK(hipStreamSynchronize(c->stream));
     if (c->h_flags[0] != 0) break;
     if (it > max_iters) return fail(c, TO_E_HIP, "extension CG state did not advance");
+    // hs: [0] the stopping r^T r, [1] r^T r after [2] iterations, [3] the first r^T r
+    n_next = 32;
+    if (hs[2] > 0.0 && hs[1] > 0.0 && hs[1] < hs[3] && hs[0] > 0.0) {
+      const double remaining = std::log(hs[0] / hs[1]) / (std::log(hs[1] / hs[3]) / hs[2]);
+      n_next = (int)std::min(32.0, std::max(1.0, std::ceil(1.1 * remaining) + 1.0));
+    }
   }
   const int st = c->h_flags[0];
   if (h_iters) *h_iters = (int32_t)hs[2];

@@ -202,9 +202,10 @@ __global__ __launch_bounds__(LS_BLOCK) void k_ls_advect(int NX, int NY, int NZ, 
 // per lane, then a wave max): below tol the loop has converged; at
 // k == max_steps without that it is capped.  state[0]: 0 running,
 // 1 converged, 2 capped; state[1]: steps computed; state[2]: the last step's
-// largest |change|.  Only block 0 writes the state, and its first wave also
-// clears set (k + 1) % 3 for the next launch (that set was last read by
-// launch k - 1).
+// largest |change|; while running, state[3]: the previous step's largest
+// |change| (written by every launch).  Only block 0 writes the state, and its
+// first wave also clears set (k + 1) % 3 for the next launch (that set was
+// last read by launch k - 1).
 template <bool P2>
 __global__ __launch_bounds__(LS_BLOCK) void k_ls_reinit(
     int NX, int NY, int NZ, int kz, double h, double inv_h, double dtau, double tol, int max_steps,
@@ -228,10 +229,14 @@ __global__ __launch_bounds__(LS_BLOCK) void k_ls_reinit(
   const double prev = prev_sh;
   const bool conv = prev < tol;
   const bool capped = !conv && k_launch >= max_steps;
-  if (block0 && t == 0 && st == 0.0 && (conv || capped)) {
-    state[0] = conv ? 1.0 : 2.0;
-    state[1] = (double)k_launch;
-    state[2] = prev;
+  if (block0 && t == 0 && st == 0.0) {
+    if (conv || capped) {
+      state[0] = conv ? 1.0 : 2.0;
+      state[1] = (double)k_launch;
+      state[2] = prev;
+    } else {
+      state[3] = prev;  // progress, for the host's choice of batch
+    }
   }
   if (st != 0.0 || conv || capped) return;
   const Tile tl = ls_tile(NX, NY, NZ, kz);

@@ -534,6 +534,10 @@ __global__ __launch_bounds__(256) void k_hcg_dir(HcgArgs A, int it) {
     }
     return;
   }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {  // progress, for the host's choice of chunk
+    A.scal[1] = rr;
+    A.scal[2] = (double)(it + 1);
+  }
   const double beta = rzn / rzo;
   const size_t nn = (size_t)A.NX * A.NY * A.NZ;
   for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < nn;
