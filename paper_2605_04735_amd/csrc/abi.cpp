@@ -17,6 +17,7 @@
 
 #include "common.h"
 #include "refine_rule.h"
+#include "stop_predict.h"
 #include "to.h"
 
 using namespace topo;
@@ -486,11 +487,9 @@ to_status inner_pcg(to_ctx *c, T *const v[NCGV], const T *dinv, double eta, int 
     // the previous chunk's end
     const double rr = cr.rr_tol2[0], tol2 = cr.rr_tol2[1];
     ahead = 2;
-    if (prev_iters >= 0 && *iters > prev_iters && rr > 0.0 && rr < prev_rr && tol2 > 0.0) {
-      const double slope = std::log(rr / prev_rr) / (double)(*iters - prev_iters);
-      const double remaining = std::log(tol2 / rr) / slope;
-      if (remaining <= (double)(launched - *iters)) ahead = 1;
-    }
+    if (prev_iters >= 0 &&
+        predicted_steps(prev_rr, prev_iters, rr, *iters, tol2) <= (double)(launched - *iters))
+      ahead = 1;
     prev_rr = rr;
     prev_iters = *iters;
   }
@@ -1069,8 +1068,8 @@ to_status to_ls_reinit(to_ctx *c, double *d_phi, double gamma, double tol, int32
     // hs[3]: the largest change of step k - 1 (taken by launch k - 1)
     const double ch = hs[3];
     batch = 64;
-    if (k_prev >= 0 && std::isfinite(ch) && ch > 0.0 && ch < ch_prev) {
-      const double remaining = std::log(tol / ch) / (std::log(ch / ch_prev) / (double)(k - k_prev));
+    if (k_prev >= 0) {
+      const double remaining = predicted_steps(ch_prev, k_prev, ch, k, tol);
       batch = (int)std::min(64.0, std::max(4.0, std::ceil(1.1 * remaining) + 2.0));
     }
     k_prev = k;
@@ -1148,11 +1147,8 @@ to_status to_hilbert_extend(to_ctx *c, double ell, const double *d_g, double *d_
     if (c->h_flags[0] != 0) break;
     if (it > max_iters) return fail(c, TO_E_HIP, "extension CG state did not advance");
     // hs: [0] the stopping r^T r, [1] r^T r after [2] iterations, [3] the first r^T r
-    n_next = 32;
-    if (hs[2] > 0.0 && hs[1] > 0.0 && hs[1] < hs[3] && hs[0] > 0.0) {
-      const double remaining = std::log(hs[0] / hs[1]) / (std::log(hs[1] / hs[3]) / hs[2]);
-      n_next = (int)std::min(32.0, std::max(1.0, std::ceil(1.1 * remaining) + 1.0));
-    }
+    const double remaining = predicted_steps(hs[3], 0.0, hs[1], hs[2], hs[0]);
+    n_next = (int)std::min(32.0, std::max(1.0, std::ceil(1.1 * remaining) + 1.0));
   }
   const int st = c->h_flags[0];
   if (h_iters) *h_iters = (int32_t)hs[2];

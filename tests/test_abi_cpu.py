@@ -170,3 +170,52 @@ def test_refinement_stagnation_rule(tmp_path):
     assert first_stall([1.0, 0.9, 0.8, 0.7, float("nan")]) == 4
     # fewer than five records never stall
     assert first_stall([1.0, 1.0, 1.0, 1.0]) == -1
+
+
+PREDICT_DRIVER = r"""
+#include <cstdio>
+#include <cstdlib>
+#include "stop_predict.h"
+int main(int argc, char **argv) {
+  // q0 s0 q1 s1 target
+  const double v = topo::predicted_steps(std::atof(argv[1]), std::atof(argv[2]), std::atof(argv[3]),
+                                         std::atof(argv[4]), std::atof(argv[5]));
+  std::printf("%.17g\n", v);
+  return 0;
+}
+"""
+
+
+def test_stop_prediction(tmp_path):
+    """The host's guess of the remaining steps of a device loop (the inner CG,
+    the extension CG and reinitialisation queue about that many launches),
+    compiled on its own from the header the library uses: exact for a
+    geometric sequence, and no guess (+inf) where nothing decays."""
+    src = tmp_path / "predict.cpp"
+    src.write_text(PREDICT_DRIVER)
+    exe = tmp_path / "predict"
+    subprocess.run(["g++", "-std=c++17", "-I", os.path.join(ROOT, "paper_2605_04735_amd", "csrc"),
+                    str(src), "-o", str(exe)], check=True)
+
+    def steps(q0, s0, q1, s1, target):
+        out = subprocess.run([str(exe)] + ["%.17g" % v for v in (q0, s0, q1, s1, target)],
+                             capture_output=True, text=True, check=True).stdout
+        return float(out)
+
+    # q = 2^-s seen at steps 10 and 20: 2^-30 is 10 steps away, 2^-25 five
+    assert abs(steps(2.0 ** -10, 10, 2.0 ** -20, 20, 2.0 ** -30) - 10.0) < 1e-9
+    assert abs(steps(2.0 ** -10, 10, 2.0 ** -20, 20, 2.0 ** -25) - 5.0) < 1e-9
+    # slower decay, 0.9 per step from step 0: 0.9^100 from 0.9^32 is 68 steps
+    assert abs(steps(1.0, 0, 0.9 ** 32, 32, 0.9 ** 100) - 68.0) < 1e-9
+    # already at or below the target: no steps left
+    assert steps(1.0, 0, 1e-3, 10, 1e-2) < 0.0
+    assert steps(1.0, 0, 1e-3, 10, 1e-3) == 0.0
+    inf = float("inf")
+    # nothing to extrapolate: no decay, no step between the looks, bad values
+    assert steps(1.0, 0, 1.0, 10, 1e-3) == inf
+    assert steps(1.0, 0, 2.0, 10, 1e-3) == inf
+    assert steps(1.0, 10, 0.5, 10, 1e-3) == inf
+    assert steps(0.0, 0, 0.5, 10, 1e-3) == inf
+    assert steps(inf, 0, 0.5, 10, 1e-3) == inf
+    assert steps(1.0, 0, 0.5, 10, 0.0) == inf
+    assert steps(float("nan"), 0, 0.5, 10, 1e-3) == inf
