@@ -22,6 +22,11 @@
  *    before anything is queued.  to_last_error(ctx) gives a message; with a
  *    NULL ctx it gives the calling thread's last error.  The context stays
  *    usable after any error.  One context per thread (not thread-safe).
+ *  - Concurrency: contexts share no device state (each has its own workspace
+ *    and stream; the one exception is the fixed array of
+ *    to_density_to_sdf_noalloc), so calls on different contexts may overlap
+ *    on the GPU, from one thread or several; the caller orders their streams
+ *    where one call's output is another's input.
  */
 #ifndef TO_H_
 #define TO_H_
