@@ -306,6 +306,30 @@ __device__ double tri_dist2(const double *p, const double *a, const double *b, c
   return dot3(q, q);
 }
 
+// Smallest squared distance from p to the c triangles stored from t on (9
+// coordinates each).  When t is the same for the whole wave (UNIFORM), the
+// triangles arrive as scalar loads, which complete in any order, so a test
+// waits for every load in flight: they are taken two per round, both loads
+// issued before the first test waits, so a pair costs one memory round trip.
+// fmin is exact, so the order does not change the result.
+template <bool UNIFORM>
+__device__ __forceinline__ double voxel_dist2(const double *p, const double *t, int c) {
+  double m = INFINITY;
+  int q = 0;
+  if constexpr (UNIFORM) {
+    for (; q + 1 < c; q += 2, t += 18) {
+      double a[18];
+#pragma unroll
+      for (int i = 0; i < 18; ++i) a[i] = t[i];
+      // both triangles' values are needed here, so their loads issue together
+      asm volatile("" ::"s"(a[0]), "s"(a[3]), "s"(a[6]), "s"(a[9]), "s"(a[12]), "s"(a[15]));
+      m = fmin(m, fmin(tri_dist2(p, a, a + 3, a + 6), tri_dist2(p, a + 9, a + 12, a + 15)));
+    }
+  }
+  for (; q < c; ++q, t += 9) m = fmin(m, tri_dist2(p, t, t + 3, t + 6));
+  return m;
+}
+
 constexpr int CB = 4;  // coarse cell edge (voxels) of the occupancy grid
 
 // occupancy of the CB^3 coarse cells as a bitmask: bit (c & 31) of word c / 32
@@ -354,7 +378,7 @@ __device__ __forceinline__ void scan_voxel(int vi, int vj, int vk, int nelx, int
   const int c = count[e];
   if (c == 0) return;
   const double *t = tri + 9 * (size_t)offset[e];
-  for (int q = 0; q < c; ++q, t += 9) best = fmin(best, tri_dist2(p, t, t + 3, t + 6));
+  best = fmin(best, voxel_dist2<false>(p, t, c));
 }
 
 // whether the node (i, j, k) still needs voxel (vi, vj, vk) in phase 2: not
@@ -382,13 +406,11 @@ __device__ __forceinline__ bool need_voxel(int vi, int vj, int vk, int i, int j,
 // one voxel per lane, read back voxel by voxel with readlane.  Each lane keeps
 // its own best distance, its own voxel pruning and its own stop rule; the
 // wave leaves the ring loop when every lane has stopped.
-__global__ __launch_bounds__(128) void k_udist(int nelx, int nely, int nelz, double h,
-                                               const int *__restrict__ count,
-                                               const int *__restrict__ offset,
-                                               const double *__restrict__ tri,
-                                               const unsigned *__restrict__ occ,
-                                               const double *__restrict__ rho, double rho_t,
-                                               double *__restrict__ phi, int occ_lds_allowed) {
+__global__ __launch_bounds__(128) void k_udist(
+    int nelx, int nely, int nelz, double h, const int *__restrict__ count,
+    const int *__restrict__ offset, const double *__restrict__ tri,
+    const unsigned *__restrict__ occ, const double *__restrict__ rho, double rho_t,
+    double *__restrict__ phi, int occ_lds_allowed) {
   const int NX = nelx + 1, NY = nely + 1, NZ = nelz + 1;
   const int cx = (nelx + CB - 1) / CB, cy = (nely + CB - 1) / CB, cz = (nelz + CB - 1) / CB;
   const int Rmax = max(cx, max(cy, cz));
@@ -456,7 +478,7 @@ __global__ __launch_bounds__(128) void k_udist(int nelx, int nely, int nelz, dou
               if (__ballot(need) == 0) continue;
               if (need) {
                 const double *t = tri + 9 * (size_t)__builtin_amdgcn_readlane(uoff, v);
-                for (int q = 0; q < c; ++q, t += 9) best = fmin(best, tri_dist2(p, t, t + 3, t + 6));
+                best = fmin(best, voxel_dist2<true>(p, t, c));
               }
             }
           }
